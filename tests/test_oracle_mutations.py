@@ -1,0 +1,151 @@
+"""Planted mistakes: each test plants one plausible error in the oracle (on the
+CPU, through monkeypatch) and checks that at least one pin of
+test_oracle_pins.py then fails.  This shows the pins are sharp enough that a
+dropped term, a wrong sign or index or a transposed operand cannot pass."""
+import numpy as np
+import pytest
+
+import oracle as O
+import test_oracle_pins as P
+
+X = O.xf_oracle
+
+
+def _patch(monkeypatch, name, value):
+    """plant `value` under `name` in the oracle module and the package that
+    re-exports it (the pins call through the package)"""
+    monkeypatch.setattr(X, name, value)
+    if hasattr(O, name):
+        monkeypatch.setattr(O, name, value)
+
+
+def _fails(fn, *a, **k):
+    try:
+        fn(*a, **k)
+    except AssertionError:
+        return True
+    return False
+
+
+def test_wrong_linear_weights_caught(monkeypatch):
+    _patch(monkeypatch, "WENO_D", (0.3, 0.6, 0.1))
+    assert _fails(P.test_fifth_order_convergence_smooth_wave)
+
+
+def test_wrong_smoothness_coefficient_caught(monkeypatch, rng):
+    orig = X.weno5_smoothness
+
+    def bad(a, b, c, d, e):
+        b0, b1, b2 = orig(a, b, c, d, e)
+        return b0, b1 - 1.0 / 12.0 * (b - 2.0 * c + d) ** 2, b2
+    _patch(monkeypatch, "weno5_smoothness", bad)
+    assert _fails(P.test_weno_smoothness_matches_integral_definition, rng)
+
+
+def test_weight_power_one_caught(monkeypatch):
+    def bad(a, b, c, d, e):
+        q = X.weno5_candidates(a, b, c, d, e)
+        be = X.weno5_smoothness(a, b, c, d, e)
+        al = [X.WENO_D[k] / (X.WENO_EPS + be[k]) for k in range(3)]
+        s = sum(al)
+        return sum(al[k] / s * q[k] for k in range(3))
+    _patch(monkeypatch, "weno5", bad)
+    assert _fails(P.test_weno_essentially_non_oscillatory)
+
+
+def test_dropped_RT_in_species_energy_caught(monkeypatch, rng):
+    _patch(monkeypatch, "species_e", lambda th, T: th.R * X.h_over_R(th, T))
+    assert _fails(P.test_single_gas_matches_textbook_solver, rng)
+
+
+def test_swapped_roe_weights_caught(monkeypatch, rng):
+    orig = X.roe_state
+
+    def bad(th, pL, pR):
+        # weight the left state with the right density's share
+        sL, sR = np.sqrt(pL["rho"]), np.sqrt(pR["rho"])
+        fake = dict(pL)
+        fake["rho"] = pR["rho"]
+        fakeR = dict(pR)
+        fakeR["rho"] = pL["rho"]
+        return orig(th, fake, fakeR)
+    _patch(monkeypatch, "roe_state", bad)
+    assert _fails(P.test_single_gas_matches_textbook_solver, rng)
+
+
+def test_tangential_row_sign_caught(monkeypatch, rng):
+    orig = X.eigen_L
+
+    def bad(th, roe, d):
+        L = orig(th, roe, d)
+        L[..., th.ns + 1, :th.ns] *= -1.0
+        return L
+    _patch(monkeypatch, "eigen_L", bad)
+    assert _fails(P.test_left_right_inverse, 2, rng)
+
+
+def test_transposed_left_matrix_caught(monkeypatch, rng):
+    orig = X.eigen_L
+    _patch(monkeypatch, "eigen_L", lambda th, roe, d: np.swapaxes(orig(th, roe, d), -1, -2))
+    assert _fails(P.test_left_right_inverse, 2, rng)
+
+
+def test_dropped_RT_in_chi_caught(monkeypatch, rng):
+    orig = X.roe_state
+
+    def bad(th, pL, pR):
+        r = orig(th, pL, pR)
+        r["chi"] = r["chi"] - th.R * r["T"][..., None]
+        r["c2"] = np.sum(r["Y"] * r["chi"], axis=-1) + r["Gam"] * (r["H"] - r["q2"])
+        r["c"] = np.sqrt(r["c2"])
+        return r
+    _patch(monkeypatch, "roe_state", bad)
+    assert _fails(P.test_flux_jacobian_eigenvectors, 3, rng)
+
+
+def test_flux_sign_caught(monkeypatch):
+    orig = X.face_flux
+
+    def bad(*a, **k):
+        F, al, c2 = orig(*a, **k)
+        return -F, al, c2
+    _patch(monkeypatch, "face_flux", bad)
+    assert _fails(P.test_fifth_order_convergence_smooth_wave)
+
+
+def test_wrong_acoustic_eigenvalue_caught(monkeypatch, rng):
+    orig = X.eigenvalues
+
+    def bad(th, prim, d):
+        lam = orig(th, prim, d)
+        return np.concatenate([lam[-1:], lam[1:]], axis=0)   # u+c used for the u-c field
+    _patch(monkeypatch, "eigenvalues", bad)
+    assert _fails(P.test_single_gas_matches_textbook_solver, rng)
+
+
+def test_wrong_rk3_stage_weight_caught(monkeypatch):
+    def bad(L, U, dt):
+        U1 = U + dt * L(U)
+        U2 = 0.5 * U + 0.5 * (U1 + dt * L(U1))
+        return U / 3.0 + 2.0 / 3.0 * (U2 + dt * L(U2))
+    _patch(monkeypatch, "ssp_rk3", bad)
+    assert _fails(P.test_ssp_rk3_linear_stability_polynomial)
+
+
+def test_wrong_outflow_ghost_caught(monkeypatch, rng):
+    orig = X.fill_ghosts
+
+    def bad(grid, U):
+        V = orig(grid, U)
+        V[:, :, 0, :] = V[:, :, 4, :]     # -y outflow copied from the second interior row
+        return V
+    _patch(monkeypatch, "fill_ghosts", bad)
+    assert _fails(P.test_ghost_fill_matches_numpy_pad, rng)
+
+
+def test_newton_with_cp_denominator_still_converges_but_energy_with_cp_caught(monkeypatch, rng):
+    """A Newton step with the wrong derivative converges to the same root (so
+    the round trip cannot see it), but an energy map that uses h instead of e
+    changes the EOS and the textbook comparison fails."""
+    _patch(monkeypatch, "mixture_e", lambda th, Y, T: np.sum(Y * th.R * X.h_over_R(th, T), axis=-1))
+    assert _fails(P.test_single_gas_matches_textbook_solver, rng)

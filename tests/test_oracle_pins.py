@@ -1,0 +1,624 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed forms,
+polynomial exactness and the integral definition of the WENO smoothness
+indicators, the eigenvector identities L R = I and A R = R Lambda (A by complex
+step of the physical flux), an independent textbook single-gas solver, the
+exact Sod Riemann solution, invariances (energy reference, mirror, axis and
+species permutation), discrete conservation and measured fifth-order
+convergence.  No GPU is used.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+from numpy.polynomial import Polynomial
+
+import oracle as O
+from conftest import oracle_objects
+from paper_2403_05910_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# helpers (the tests' own, independent of the oracle)
+# ---------------------------------------------------------------------------
+def cell_averages(poly, edges):
+    P = poly.integ()
+    return (P(edges[1:]) - P(edges[:-1])) / np.diff(edges)
+
+
+def random_mixture_prims(th, rng, shape, T_range=(250.0, 2500.0), u_max=300.0):
+    ns = th.ns
+    Y = rng.dirichlet(np.ones(ns), size=shape)             # (..., ns)
+    Y = np.moveaxis(Y, -1, 0)
+    T = rng.uniform(*T_range, size=shape)
+    rho = rng.uniform(0.2, 5.0, size=shape)
+    u = rng.uniform(-u_max, u_max, size=(3,) + shape)
+    return rho, u, T, Y
+
+
+def uniform_case(th, n, bc, rng):
+    rho, u, T, Y = random_mixture_prims(th, rng, ())
+    g = O.Grid(n[0], n[1], n[2], 1.0 / n[0], 1.0 / n[1], 1.0 / n[2], bc)
+    Uc = O.conservative(th, rho, u, T, Y)
+    U = np.broadcast_to(Uc.reshape(-1, 1, 1, 1), (th.ns + 4,) + g.padded).copy()
+    return g, U
+
+
+def thermal_table(ns, seed=0):
+    tab = W.sampled_table(list(np.linspace(2.0, 40.0, ns)), seed)
+    return O.Thermo(tab.W, tab.a, tab.T_lo, tab.T_hi)
+
+
+def rel_field_err(a, b, scale):
+    return np.max(np.abs(a - b).reshape(a.shape[0], -1), axis=1) / np.maximum(scale, 1e-300)
+
+
+# ---------------------------------------------------------------------------
+# WENO5-JS
+# ---------------------------------------------------------------------------
+def test_weno_candidates_exact_for_quadratics(rng):
+    """Each third-order candidate reproduces the interface value of any
+    quadratic whose cell averages are the data (the flux-splitting reading)."""
+    for _ in range(50):
+        poly = Polynomial(rng.standard_normal(3) * 10)
+        h = rng.uniform(0.01, 0.5)
+        edges = h * (np.arange(6) - 2.5)      # cells centred at -2h..2h; cell c at 0
+        f = cell_averages(poly, edges)
+        exact = poly(0.5 * h)
+        for q in O.weno5_candidates(*f):
+            assert abs(q - exact) <= 1e-12 * max(1.0, abs(exact))
+        assert abs(O.weno5(*f) - exact) <= 1e-12 * max(1.0, abs(exact))
+
+
+def test_weno_linear_weights_give_fifth_order_exactness(rng):
+    """sum_k d_k q_k is exact for quartics: pins the linear weights d."""
+    for _ in range(50):
+        poly = Polynomial(rng.standard_normal(5))
+        h = rng.uniform(0.05, 0.5)
+        f = cell_averages(poly, h * (np.arange(6) - 2.5))
+        q = O.weno5_candidates(*f)
+        val = sum(O.WENO_D[k] * q[k] for k in range(3))
+        assert abs(val - poly(0.5 * h)) <= 1e-12 * max(1.0, abs(poly(0.5 * h)))
+
+
+def test_weno_smoothness_matches_integral_definition(rng):
+    """beta_k = sum_{l=1,2} h^(2l-1) int_cell (d^l p_k / dx^l)^2 dx, with p_k
+    the quadratic that has the sub-stencil's data as cell averages (h = 1)."""
+    for _ in range(30):
+        f = rng.standard_normal(5) * 3
+        beta = O.weno5_smoothness(*f)
+        for k in range(3):
+            # unknown coefficients c0 + c1 x + c2 x^2; averages over [j-1/2, j+1/2]
+            A = np.zeros((3, 3))
+            for r, j in enumerate(range(k, k + 3)):
+                for pw in range(3):
+                    A[r, pw] = ((j + 0.5) ** (pw + 1) - (j - 0.5) ** (pw + 1)) / (pw + 1)
+            p = Polynomial(np.linalg.solve(A, f[k:k + 3]))
+            d1, d2 = p.deriv(1), p.deriv(2)
+            ref = (d1 * d1).integ()(2.5) - (d1 * d1).integ()(1.5) + (d2 * d2).integ()(2.5) - (d2 * d2).integ()(1.5)
+            assert abs(beta[k] - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+def test_weno_essentially_non_oscillatory():
+    """Across a jump the scheme keeps only the smooth sub-stencil; with p = 2
+    and eps = 1e-6 the leak is O((eps/beta)^2) ~ 1e-12."""
+    assert abs(O.weno5(0.0, 0.0, 0.0, 1.0, 1.0)) < 1e-10
+    assert abs(O.weno5(1.0, 1.0, 1.0, 1.0, 0.0) - 1.0) < 1e-10
+    assert abs(O.weno5(5.0, 5.0, 5.0, 5.0, 5.0) - 5.0) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# thermodynamics and Newton (Eq. 7, Eq. 21)
+# ---------------------------------------------------------------------------
+def test_enthalpy_is_integral_of_cp():
+    from scipy.integrate import quad
+    th = thermal_table(5)
+    for s in range(th.ns):
+        for (T1, T2) in ((250.0, 600.0), (300.0, 3900.0)):
+            ref, _ = quad(lambda T: O.cp_over_R(th, T)[s], T1, T2, epsabs=0, epsrel=1e-13)
+            got = O.h_over_R(th, T2)[s] - O.h_over_R(th, T1)[s]
+            assert abs(got - ref) <= 1e-12 * abs(ref)
+
+
+def test_calorically_perfect_closed_forms():
+    th = O.Thermo([0.02896, 0.004003], [[3.5, 0, 0, 0, 0, 0], [1.667 / 0.667, 0, 0, 0, 0, 0]])
+    T = np.array([0.003, 300.0, 1234.5])
+    e = O.species_e(th, T)
+    ref = th.R * T[:, None] / (np.array([1.4, 1.667]) - 1.0)
+    assert np.allclose(e, ref, rtol=1e-14, atol=0)
+    Y = np.array([[0.3, 0.7]] * 3)
+    Tn, nc = O.temperature_newton(th, Y, O.mixture_e(th, Y, T))
+    assert not nc.any()
+    assert np.allclose(Tn, T, rtol=2e-15, atol=0)
+
+
+def test_newton_roundtrip(rng):
+    th = thermal_table(9)
+    Y = rng.dirichlet(np.ones(9), size=2000)
+    T = rng.uniform(210.0, 3900.0, size=2000)
+    e = O.mixture_e(th, Y, T)
+    Tn, nc = O.temperature_newton(th, Y, e)
+    assert not nc.any()
+    assert np.max(np.abs(Tn - T) / T) <= 1e-13
+    assert np.max(np.abs(O.mixture_e(th, Y, Tn) - e) / np.abs(e)) <= 1e-14
+
+
+def test_newton_flags_out_of_range(rng):
+    th = thermal_table(3)
+    Y = np.array([[0.2, 0.3, 0.5]])
+    e_hot = O.mixture_e(th, Y, np.array([6000.0]))
+    rho = np.array([1.0])
+    U = np.concatenate([rho * Y.T, np.zeros((3, 1)), (rho * e_hot)[None]], axis=0)
+    P = O.primitives(th, U)
+    assert P["flags"][0] & O.FLAG_TRANGE
+    U2 = U.copy()
+    U2[0] = -0.1
+    assert O.primitives(th, U2)["flags"][0] & (O.FLAG_RHO | O.FLAG_Y)
+
+
+# ---------------------------------------------------------------------------
+# eigensystem
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("ns", [1, 2, 5, 9])
+def test_left_right_inverse(ns, rng):
+    """L R = I at 1000 random Roe states built from random L/R cell pairs."""
+    th = thermal_table(ns)
+    nf = 1000
+    pr = []
+    for _ in range(2):
+        rho, u, T, Y = random_mixture_prims(th, rng, (nf,))
+        pr.append(O.primitives(th, O.conservative(th, rho, u, T, Y)))
+    roe = O.roe_state(th, pr[0], pr[1])
+    for d in range(3):
+        L = O.eigen_L(th, roe, d)
+        R = O.eigen_R(th, roe, d)
+        LR = L @ R
+        scale = np.abs(L) @ np.abs(R)
+        err = np.abs(LR - np.eye(ns + 4)) / np.where(scale > 0, scale, 1.0)
+        assert err.max() <= 1e-13, (d, err.max())
+
+
+@pytest.mark.parametrize("ns", [1, 3, 9])
+def test_flux_jacobian_eigenvectors(ns, rng):
+    """A R = R Lambda at a single state (Roe state of two equal cells); A =
+    dF/dU by complex step of the oracle's physical flux (through the Newton
+    temperature), Lambda = diag(u_n - c, u_n ..., u_n + c)."""
+    th = thermal_table(ns)
+    nv = ns + 4
+    for trial in range(3):
+        rho, u, T, Y = random_mixture_prims(th, rng, (1,))
+        U0 = O.conservative(th, rho, u, T, Y)[:, 0]
+        P0 = O.primitives(th, U0[:, None])
+        roe = O.roe_state(th, P0, P0)
+        for d in range(3):
+            A = np.zeros((nv, nv))
+            h = 1e-30
+            for j in range(nv):
+                Uc = U0.astype(complex)
+                Uc[j] += 1j * h * max(1.0, abs(U0[j]))
+                Pc = O.primitives(th, Uc[:, None])
+                F = O.physical_flux(th, Uc[:, None], Pc, d)[:, 0]
+                A[:, j] = F.imag / (h * max(1.0, abs(U0[j])))
+            R = O.eigen_R(th, roe, d)[0]
+            lam = O.eigenvalues(th, P0, d)[:, 0]
+            lhs = A @ R
+            rhs_ = R * lam[None, :]
+            scale = np.abs(A) @ np.abs(R) + np.abs(rhs_)
+            assert np.max(np.abs(lhs - rhs_) / np.where(scale > 0, scale, 1.0)) <= 1e-12
+
+
+def test_roe_sound_speed_limits(rng):
+    """Equal states: the face c^2 equals the cell (1 + Rbar/cv) Rbar T.
+    Single calorically perfect gas: c^2 = (gamma - 1)(H - |u|^2/2) (classic Roe)."""
+    th = thermal_table(4)
+    rho, u, T, Y = random_mixture_prims(th, rng, (200,))
+    P = O.primitives(th, O.conservative(th, rho, u, T, Y))
+    roe = O.roe_state(th, P, P)
+    assert np.allclose(roe["c2"], P["c"] ** 2, rtol=1e-13, atol=0)
+    g = 1.4
+    th1 = O.Thermo([0.02896], [[g / (g - 1), 0, 0, 0, 0, 0]])
+    pr = []
+    for _ in range(2):
+        rho, u, T, Y = random_mixture_prims(th1, rng, (200,))
+        pr.append(O.primitives(th1, O.conservative(th1, rho, u, T, Y)))
+    roe = O.roe_state(th1, pr[0], pr[1])
+    sl, sr = np.sqrt(pr[0]["rho"]), np.sqrt(pr[1]["rho"])
+    Ht = (sl * pr[0]["H"] + sr * pr[1]["H"]) / (sl + sr)
+    ut = (sl * pr[0]["u"] + sr * pr[1]["u"]) / (sl + sr)
+    ref = (g - 1) * (Ht - 0.5 * np.sum(ut * ut, axis=0))
+    assert np.allclose(roe["c2"], ref, rtol=1e-12, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# independent textbook single-gas solver (ideal-gas Roe eigenvectors)
+# ---------------------------------------------------------------------------
+def _weno_textbook(v):
+    """WENO5-JS on five values, written in the tests' own candidate/weight form."""
+    C = ((1 / 3, -7 / 6, 11 / 6), (-1 / 6, 5 / 6, 1 / 3), (1 / 3, 5 / 6, -1 / 6))
+    q = [C[k][0] * v[k] + C[k][1] * v[k + 1] + C[k][2] * v[k + 2] for k in range(3)]
+    b = [13 / 12 * (v[k] - 2 * v[k + 1] + v[k + 2]) ** 2 for k in range(3)]
+    b[0] += 0.25 * (v[0] - 4 * v[1] + 3 * v[2]) ** 2
+    b[1] += 0.25 * (v[1] - v[3]) ** 2
+    b[2] += 0.25 * (3 * v[2] - 4 * v[3] + v[4]) ** 2
+    w = [dk / (1e-6 + bk) ** 2 for dk, bk in zip((0.1, 0.6, 0.3), b)]
+    return sum(wk * qk for wk, qk in zip(w, q)) / sum(w)
+
+
+def textbook_rhs_1d(gamma, U, n, dx):
+    """Characteristic WENO5 + component-wise LLF x-flux difference for one
+    ideal gas with state (rho, rho u, rho v, rho w, E); U padded with 3 ghosts.
+    Right eigenvectors from the classical ideal-gas form (Toro, Ch. 3):
+    K1 = (1, u-c, v, w, H-uc), K2 = (1, u, v, w, q^2/2), K3 = (0,0,1,0,v),
+    K4 = (0,0,0,1,w), K5 = (1, u+c, v, w, H+uc); left ones by matrix inverse."""
+    rho = U[0]
+    u, v, w = U[1] / rho, U[2] / rho, U[3] / rho
+    E = U[4]
+    p = (gamma - 1) * (E - 0.5 * rho * (u * u + v * v + w * w))
+    c = np.sqrt(gamma * p / rho)
+    H = (E + p) / rho
+    F = np.stack([rho * u, rho * u * u + p, rho * u * v, rho * u * w, (E + p) * u])
+    flux = np.zeros((5, n + 1))
+    for k in range(n + 1):
+        i = k + 2
+        sL, sR = np.sqrt(rho[i]), np.sqrt(rho[i + 1])
+        avg = lambda a: (sL * a[i] + sR * a[i + 1]) / (sL + sR)
+        ut, vt, wt, Ht = avg(u), avg(v), avg(w), avg(H)
+        q2 = ut * ut + vt * vt + wt * wt
+        ct = np.sqrt((gamma - 1) * (Ht - 0.5 * q2))
+        K = np.array([[1, 1, 0, 0, 1],
+                      [ut - ct, ut, 0, 0, ut + ct],
+                      [vt, vt, 1, 0, vt],
+                      [wt, wt, 0, 1, wt],
+                      [Ht - ut * ct, 0.5 * q2, vt, wt, Ht + ut * ct]])
+        Kinv = np.linalg.inv(K)
+        cells = range(i - 2, i + 4)
+        lam = np.array([[abs(u[m] - c[m]), abs(u[m]), abs(u[m]), abs(u[m]), abs(u[m] + c[m])] for m in cells])
+        al = lam.max(axis=0)
+        fc = np.array([Kinv @ F[:, m] for m in cells])
+        uc = np.array([Kinv @ U[:, m] for m in cells])
+        gp = 0.5 * (fc + al * uc)
+        gm = 0.5 * (fc - al * uc)
+        hat = np.array([_weno_textbook(gp[0:5, j]) + _weno_textbook(gm[5:0:-1, j]) for j in range(5)])
+        flux[:, k] = K @ hat
+    return -(flux[:, 1:] - flux[:, :-1]) / dx
+
+
+def _single_gas_case(rng, n=40, gamma=1.4, jump=True):
+    Wg = 0.02896
+    th = O.Thermo([Wg], [[gamma / (gamma - 1), 0, 0, 0, 0, 0]])
+    x = (np.arange(n) + 0.5) / n
+    rho = 1.0 + 0.3 * np.sin(2 * np.pi * x) + (0.8 * (x > 0.5) if jump else 0)
+    p = 1e5 * (1.0 + 0.2 * np.cos(2 * np.pi * x) + (1.5 * (x > 0.5) if jump else 0))
+    vel = np.stack([60 * np.sin(4 * np.pi * x) + 30, 20 * np.cos(2 * np.pi * x), -15 * np.sin(2 * np.pi * x)])
+    T = p / (rho * th.R[0])
+    U = np.zeros((5, 1, 1, n + 6))
+    U[:, 0, 0, 3:-3] = O.conservative(th, rho, vel, T, np.ones((1, n)))
+    g = O.Grid(n, 1, 1, 1.0 / n, 1.0, 1.0, (0,) * 6)
+    return th, g, O.fill_ghosts(g, U)
+
+
+def test_single_gas_matches_textbook_solver(rng):
+    th, g, U = _single_gas_case(rng)
+    r, aux = O.rhs(th, g, U, return_aux=True)
+    ref = textbook_rhs_1d(1.4, U[:, 0, 0, :], g.nx, g.dx)
+    err = rel_field_err(r[:, 0, 0, 3:-3], ref, aux["scale"])
+    assert err.max() <= 1e-13, err
+
+
+def test_two_species_with_absent_second_reduces_to_single(rng):
+    th, g, U = _single_gas_case(rng)
+    th2 = thermal_table(2)
+    th2 = O.Thermo([th.W[0], th2.W[1]], [th.a[0], th2.a[1]])
+    U2 = np.concatenate([U[:1], np.zeros_like(U[:1]), U[1:]], axis=0)
+    r1, aux = O.rhs(th, g, U, return_aux=True)
+    r2 = O.rhs(th2, g, U2)
+    assert np.all(r2[1] == 0.0)
+    err = rel_field_err(np.delete(r2, 1, axis=0), r1, aux["scale"])
+    assert err.max() <= 1e-13, err
+
+
+# ---------------------------------------------------------------------------
+# exact Riemann solution (Sod)
+# ---------------------------------------------------------------------------
+def exact_riemann(gamma, L, R, xi):
+    """Exact solution of the ideal-gas Riemann problem at similarity
+    coordinates xi = (x - x0)/t (Toro, Ch. 4): Newton for p*, then sampling."""
+    rl, ul, pl = L
+    rr, ur, pr = R
+    cl, cr = np.sqrt(gamma * pl / rl), np.sqrt(gamma * pr / rr)
+    g1 = (gamma - 1) / (2 * gamma)
+
+    def fk(p, rk, pk, ck):
+        if p > pk:
+            A, B = 2 / ((gamma + 1) * rk), (gamma - 1) / (gamma + 1) * pk
+            f = (p - pk) * np.sqrt(A / (p + B))
+            df = np.sqrt(A / (B + p)) * (1 - (p - pk) / (2 * (B + p)))
+        else:
+            f = 2 * ck / (gamma - 1) * ((p / pk) ** g1 - 1)
+            df = 1 / (rk * ck) * (p / pk) ** (-(gamma + 1) / (2 * gamma))
+        return f, df
+
+    p = 0.5 * (pl + pr)
+    for _ in range(100):
+        f1, d1 = fk(p, rl, pl, cl)
+        f2, d2 = fk(p, rr, pr, cr)
+        dp = (f1 + f2 + ur - ul) / (d1 + d2)
+        p = max(p - dp, 1e-12)
+        if abs(dp) < 1e-15 * p:
+            break
+    us = 0.5 * (ul + ur) + 0.5 * (fk(p, rr, pr, cr)[0] - fk(p, rl, pl, cl)[0])
+    rsl = rl * (p / pl) ** (1 / gamma) if p <= pl else rl * ((p / pl + (gamma - 1) / (gamma + 1)) / ((gamma - 1) / (gamma + 1) * p / pl + 1))
+    rsr = rr * (p / pr) ** (1 / gamma) if p <= pr else rr * ((p / pr + (gamma - 1) / (gamma + 1)) / ((gamma - 1) / (gamma + 1) * p / pr + 1))
+    out = np.zeros((3, len(xi)))
+    for k, s in enumerate(xi):
+        if s <= us:   # left of contact
+            if p > pl:
+                S = ul - cl * np.sqrt((gamma + 1) / (2 * gamma) * p / pl + g1)
+                out[:, k] = (rl, ul, pl) if s < S else (rsl, us, p)
+            else:
+                csl = cl * (p / pl) ** g1
+                if s < ul - cl:
+                    out[:, k] = (rl, ul, pl)
+                elif s > us - csl:
+                    out[:, k] = (rsl, us, p)
+                else:
+                    uu = 2 / (gamma + 1) * (cl + (gamma - 1) / 2 * ul + s)
+                    cc = 2 / (gamma + 1) * (cl + (gamma - 1) / 2 * (ul - s))
+                    rr_ = rl * (cc / cl) ** (2 / (gamma - 1))
+                    out[:, k] = (rr_, uu, pl * (cc / cl) ** (1 / g1))
+        else:
+            if p > pr:
+                S = ur + cr * np.sqrt((gamma + 1) / (2 * gamma) * p / pr + g1)
+                out[:, k] = (rr, ur, pr) if s > S else (rsr, us, p)
+            else:
+                csr = cr * (p / pr) ** g1
+                if s > ur + cr:
+                    out[:, k] = (rr, ur, pr)
+                elif s < us + csr:
+                    out[:, k] = (rsr, us, p)
+                else:
+                    uu = 2 / (gamma + 1) * (-cr + (gamma - 1) / 2 * ur + s)
+                    cc = 2 / (gamma + 1) * (cr - (gamma - 1) / 2 * (ur - s))
+                    rr_ = rr * (cc / cr) ** (2 / (gamma - 1))
+                    out[:, k] = (rr_, uu, pr * (cc / cr) ** (1 / g1))
+    return out, (p, us, rsl, rsr)
+
+
+def test_exact_riemann_solver_matches_textbook_star_state():
+    gold = json.load(open(os.path.join(GOLDEN, "sod_star_state.json")))
+    _, (ps, us, rsl, rsr) = exact_riemann(1.4, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), np.array([0.0]))
+    for got, key in ((ps, "p_star"), (us, "u_star"), (rsl, "rho_star_left"), (rsr, "rho_star_right")):
+        assert abs(got - gold[key]) <= 0.6e-5 * max(1.0, abs(gold[key])) * 1.0 + 1e-5
+
+
+def _run_sod(n, t_end=0.2, cfl=0.5):
+    case = W.sod(n)
+    th, g = oracle_objects(case)
+    U = O.fill_ghosts(g, case.U)
+    t = 0.0
+    while t < t_end - 1e-14:
+        dt = min(O.cfl_dt(th, g, U, cfl), t_end - t)
+        U = O.rk3_step(th, g, U, dt)
+        t += dt
+    return U[0, 0, 0, 3:-3], (np.arange(n) + 0.5) / n
+
+
+def test_sod_against_exact_solution():
+    errs = []
+    for n in (100, 200, 400):
+        rho, x = _run_sod(n)
+        ex, _ = exact_riemann(1.4, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), (x - 0.5) / 0.2)
+        errs.append(np.mean(np.abs(rho - ex[0])))
+    assert errs[-1] <= 5e-3, errs
+    assert errs[0] > errs[1] > errs[2], errs
+    order = np.log2(errs[0] / errs[2]) / 2
+    assert order >= 0.6, (errs, order)
+
+
+# ---------------------------------------------------------------------------
+# whole-scheme invariants
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("ns", [1, 2, 5, 9])
+@pytest.mark.parametrize("bc", [(0,) * 6, (1,) * 6])
+def test_freestream_preserved(ns, bc, rng):
+    th = thermal_table(ns)
+    g, U = uniform_case(th, (7, 6, 5), bc, rng)
+    U = O.fill_ghosts(g, U)
+    r, aux = O.rhs(th, g, U, return_aux=True)
+    assert aux["flags"] == 0
+    assert np.all(np.abs(r).reshape(ns + 4, -1).max(axis=1) <= 1e-14 * aux["scale"])
+
+
+def test_discrete_conservation_periodic():
+    tab = W.sampled_table([2.0, 28.0, 40.0], 3)
+    case = W.random_smooth_state(tab, (12, 10, 8), seed=5, jump=True)
+    th, g = oracle_objects(case)
+    U = O.fill_ghosts(g, case.U)
+    r, aux = O.rhs(th, g, U, return_aux=True)
+    tot = np.sum(r, axis=(1, 2, 3))
+    ncell = np.prod(g.n)
+    assert np.all(np.abs(tot) <= 1e-14 * ncell * aux["scale"]), (tot, aux["scale"])
+    # and the residual is far from trivially zero
+    assert np.all(np.abs(r).reshape(len(tot), -1).max(axis=1) > 1e-6 * aux["scale"])
+
+
+def _wave_exact_U(x, tab):
+    """closed form of the advected two-species wave: u = 1 and p = 1 uniform,
+    so rho E = p sum_s Y_s R_s/(gamma_s - 1) / Rbar + rho/2"""
+    gam = np.array([1.4, 1.667])
+    Rs = W.R_UNIVERSAL / tab.W
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * x)
+    Y1 = 0.5 + 0.4 * np.sin(2 * np.pi * x)
+    Y = np.stack([Y1, 1.0 - Y1])
+    Rbar = Rs[0] * Y[0] + Rs[1] * Y[1]
+    rhoe = (Y[0] * Rs[0] / (gam[0] - 1) + Y[1] * Rs[1] / (gam[1] - 1)) / Rbar
+    return np.stack([rho * Y[0], rho * Y[1], rho, 0 * x, 0 * x, rhoe + 0.5 * rho])
+
+
+def _wave_truncation_error(n):
+    case = W.wave_1d(n)
+    th, g = oracle_objects(case)
+    x = (np.arange(n) + 0.5) / n
+    # the generator's state equals the closed form at the cell centres
+    assert np.allclose(case.U[:, 0, 0, 3:-3], _wave_exact_U(x, case.thermo), rtol=1e-14, atol=1e-14)
+    U = O.fill_ghosts(g, case.U)
+    r = O.rhs(th, g, U)[:, 0, 0, 3:-3]
+    h = 1e-30
+    dUdx = _wave_exact_U(x + 1j * h, case.thermo).imag / h
+    exact = -dUdx          # -dF/dx with F = u U + p (0,0,1,0,0,1), u = 1, p = 1
+    e = np.abs(r - exact)
+    return np.mean(e[[0, 1, 2, 5]]), np.max(e[[0, 1, 2, 5]])
+
+
+def test_fifth_order_convergence_smooth_wave():
+    ns_ = (25, 50, 100, 200, 400, 800)
+    e = np.array([_wave_truncation_error(n) for n in ns_])
+    o1 = np.log2(e[:-1, 0] / e[1:, 0])
+    oinf = np.log2(e[:-1, 1] / e[1:, 1])
+    assert o1[-2:].min() >= 4.8, (e, o1)
+    assert oinf[-2:].min() >= 4.5, (e, oinf)
+
+
+def test_energy_reference_invariance():
+    """Shifting every species energy by a constant (a5) maps U -> M U with
+    E' = E + sum_s rho_s R_s da5_s; the residual transforms the same way."""
+    tab = W.sampled_table([2.0, 28.0, 40.0], 7)
+    case = W.random_smooth_state(tab, (9, 8, 7), seed=11, jump=True)
+    th, g = oracle_objects(case)
+    U = O.fill_ghosts(g, case.U)
+    r, aux = O.rhs(th, g, U, return_aux=True)
+    da5 = np.array([120.0, -300.0, 75.0])
+    th2 = O.Thermo(th.W, th.a + np.concatenate([np.zeros((3, 5)), da5[:, None]], axis=1), th.T_lo, th.T_hi)
+    shift = th.R * da5
+    U2 = U.copy()
+    U2[-1] += np.tensordot(shift, U[:3], axes=(0, 0))
+    r2 = O.rhs(th2, g, U2)
+    Mr = r.copy()
+    Mr[-1] += np.tensordot(shift, r[:3], axes=(0, 0))
+    scale = aux["scale"].copy()
+    scale[-1] += np.abs(shift) @ aux["scale"][:3]
+    assert rel_field_err(r2, Mr, scale).max() <= 1e-11
+
+
+def _sym_case():
+    tab = W.sampled_table([2.0, 28.0, 40.0], 9)
+    case = W.random_smooth_state(tab, (8, 8, 6), seed=3, jump=True)
+    th, g = oracle_objects(case)
+    return th, g, O.fill_ghosts(g, case.U)
+
+
+def test_mirror_symmetry():
+    th, g, U = _sym_case()
+    r, aux = O.rhs(th, g, U, return_aux=True)
+    Um = U[..., ::-1].copy()
+    Um[th.ns] *= -1
+    rm = O.rhs(th, g, Um)[..., ::-1].copy()
+    rm[th.ns] *= -1
+    assert rel_field_err(rm, r, aux["scale"]).max() <= 1e-13
+
+
+def test_axis_permutation_symmetry():
+    th, g, U = _sym_case()
+    r, aux = O.rhs(th, g, U, return_aux=True)
+    Ut = np.swapaxes(U, 2, 3).copy()          # x <-> y
+    Ut[[th.ns, th.ns + 1]] = Ut[[th.ns + 1, th.ns]]
+    gt = O.Grid(g.ny, g.nx, g.nz, g.dy, g.dx, g.dz, (g.bc[2], g.bc[3], g.bc[0], g.bc[1], g.bc[4], g.bc[5]))
+    rt = np.swapaxes(O.rhs(th, gt, Ut), 2, 3).copy()
+    rt[[th.ns, th.ns + 1]] = rt[[th.ns + 1, th.ns]]
+    assert rel_field_err(rt, r, aux["scale"]).max() <= 1e-13
+
+
+def test_species_permutation_symmetry():
+    th, g, U = _sym_case()
+    r, aux = O.rhs(th, g, U, return_aux=True)
+    perm = [2, 0, 1]
+    thp = O.Thermo(th.W[perm], th.a[perm], th.T_lo, th.T_hi)
+    Up = np.concatenate([U[perm], U[th.ns:]], axis=0)
+    rp = O.rhs(thp, g, Up)
+    back = np.concatenate([r[perm], r[th.ns:]], axis=0)
+    sc = np.concatenate([aux["scale"][perm], aux["scale"][th.ns:]])
+    assert rel_field_err(rp, back, sc).max() <= 1e-13
+
+
+# ---------------------------------------------------------------------------
+# time stepping, CFL, ghosts, rhs at sampled cells
+# ---------------------------------------------------------------------------
+def test_ssp_rk3_linear_stability_polynomial():
+    for z in (-0.3, -1.0, -2.5, 0.7, 0.1 + 1.2j, -1.1 - 0.4j):
+        lam = z / 0.1
+        got = O.ssp_rk3(lambda U: lam * U, np.array([1.0 + 0j]), 0.1)[0]
+        assert abs(got - (1 + z + z * z / 2 + z ** 3 / 6)) <= 1e-15 * max(1, abs(got))
+
+
+def test_cfl_closed_form_uniform_state():
+    gam = 1.4
+    th = O.Thermo([0.02896], [[gam / (gam - 1), 0, 0, 0, 0, 0]])
+    g = O.Grid(6, 5, 4, 0.1, 0.2, 0.05, (0,) * 6)
+    rho, p, u = 1.3, 2e5, np.array([30.0, -40.0, 10.0])
+    T = p / (rho * th.R[0])
+    Uc = O.conservative(th, np.array(rho), u, np.array(T), np.ones(1))
+    U = np.broadcast_to(Uc.reshape(-1, 1, 1, 1), (5,) + g.padded).copy()
+    c = np.sqrt(gam * p / rho)
+    ref = 0.5 / sum((abs(u[d]) + c) / g.d[d] for d in range(3))
+    assert abs(O.cfl_dt(th, g, U, 0.5) - ref) <= 1e-14 * ref
+
+
+def test_ghost_fill_matches_numpy_pad(rng):
+    g = O.Grid(5, 4, 6, 1, 1, 1, (0, 0, 1, 1, 0, 1))
+    core = rng.standard_normal((2, 6, 4, 5))
+    U = np.zeros((2,) + g.padded)
+    U[:, 3:-3, 3:-3, 3:-3] = core
+    got = O.fill_ghosts(g, U)
+    ref = np.pad(core, ((0, 0), (0, 0), (0, 0), (3, 3)), mode="wrap")
+    ref = np.pad(ref, ((0, 0), (0, 0), (3, 3), (0, 0)), mode="edge")
+    lo = np.pad(ref, ((0, 0), (3, 0), (0, 0), (0, 0)), mode="wrap")[:, :3]
+    ref = np.concatenate([ref[:, -3:], ref], axis=1)  # z periodic at -z
+    ref = np.concatenate([ref, np.repeat(ref[:, -1:], 3, axis=1)], axis=1)  # z outflow at +z
+    del lo
+    assert np.array_equal(got, ref)
+
+
+def test_rhs_at_matches_full_rhs():
+    tab = W.sampled_table([2.0, 28.0], 2)
+    case = W.random_smooth_state(tab, (9, 7, 6), seed=4, jump=True, bc=(1, 1, 0, 0, 0, 0))
+    th, g = oracle_objects(case)
+    U = O.fill_ghosts(g, case.U)
+    r = O.rhs(th, g, U)
+    cells = np.array([[0, 0, 0], [8, 6, 5], [4, 3, 2], [0, 6, 3]])
+    ra = O.rhs_at(th, g, U, cells)
+    ref = r[:, cells[:, 2] + 3, cells[:, 1] + 3, cells[:, 0] + 3]
+    assert np.array_equal(ra, ref) or np.max(np.abs(ra - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------------------
+# the input generators' shock jumps (Eq. 33 and its thermally perfect analogue)
+# ---------------------------------------------------------------------------
+def test_rankine_hugoniot_residuals():
+    tab = W.sampled_table(W.W9, 0)
+    Y = np.zeros(9)
+    Y[8] = 1.0
+    rho1, u1, p1, T1 = W.post_shock_thermal(tab, Y, 2.0, 300.0, 101325.0)
+    th = O.Thermo(tab.W, tab.a, tab.T_lo, tab.T_hi)
+    Rb = float(th.R @ Y)
+    rho0 = 101325.0 / (Rb * 300.0)
+    P0 = O.primitives(th, O.conservative(th, np.array([rho0]), np.zeros((3, 1)), np.array([300.0]), Y[:, None]))
+    Wsh = 2.0 * P0["c"][0]
+    h = lambda T: float(O.mixture_e(th, Y, np.array(T)) + Rb * T)
+    v0, v1 = Wsh, Wsh - u1
+    assert abs(rho0 * v0 - rho1 * v1) <= 1e-12 * rho0 * v0
+    assert abs(101325.0 + rho0 * v0 ** 2 - p1 - rho1 * v1 ** 2) <= 1e-12 * (101325.0 + rho0 * v0 ** 2)
+    assert abs(h(300.0) + v0 ** 2 / 2 - h(T1) - v1 ** 2 / 2) <= 1e-11 * (h(300.0) + v0 ** 2 / 2)
+    assert abs(p1 - rho1 * Rb * T1) <= 1e-12 * p1
+    # calorically perfect closed form, Eq. 33
+    g_ = 1.4
+    rho1, u1, p1 = W.post_shock_perfect(g_, 1.22, 1.2, 101325.0, np.sqrt(g_ * 101325.0 / 1.2))
+    c0 = np.sqrt(g_ * 101325.0 / 1.2)
+    v0, v1 = 1.22 * c0, 1.22 * c0 - u1
+    hh = lambda p, r: g_ / (g_ - 1) * p / r
+    assert abs(1.2 * v0 - rho1 * v1) <= 1e-12 * 1.2 * v0
+    assert abs(101325.0 + 1.2 * v0 ** 2 - p1 - rho1 * v1 ** 2) <= 1e-12 * (101325.0 + 1.2 * v0 ** 2)
+    assert abs(hh(101325.0, 1.2) + v0 ** 2 / 2 - hh(p1, rho1) - v1 ** 2 / 2) <= 1e-12 * hh(101325.0, 1.2)
