@@ -1,0 +1,238 @@
+#!/usr/bin/env python
+"""Throughput of the convective right-hand side on one MI355X.
+
+A step is one pass of the whole hot path over the state: the CFL time step
+(reduced on the device), then one SSP-RK3 step, i.e. three times ghost fill,
+primitives with the Newton temperature, the x/y/z Roe-characteristic
+WENO5-LLF flux differences and the stage update.  The metric is interior
+cell-RHS evaluations per second (3 per cell per step), FP64.  Beside it the
+same line reports the FP32-mixed path (throughput and its per-field error
+against FP64), the adjoint (VJP) throughput and adjoint/forward time ratios,
+the roofline of the dominant kernel (timed live with HIP events on the stream
+it runs on) and the CPU oracle on a bounded crop of the same state.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    "nine_species_sbi_256": ("nine_species_sbi", dict(n=256)),
+    "inert_sbi_128": ("inert_sbi", dict(n=128)),
+    "two_bubble_sbi_512x256x256": ("two_bubble_sbi", dict()),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_case(name):
+    from paper_2403_05910_amd import workloads as W
+    fn, kw = WORKLOADS[name]
+    return getattr(W, fn)(**kw)
+
+
+def run_steps(ctx, U, dt_dev, steps, cfl):
+    for _ in range(steps):
+        ctx.cfl_dt(U, cfl, out=dt_dev)
+        ctx.rk3_step(U, dt_dev)
+
+
+def timed_steps(torch, ctx, U, dt_dev, steps, cfl):
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_steps(ctx, U, dt_dev, steps, cfl)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.timing(False)
+    return t1 - t0, ctx.timing_read()
+
+
+def roofline_of(kernels, case, precision):
+    """dominant kernel class by total time; flops per launch from the
+    algorithmic count; achieved = flops per launch / average launch time"""
+    from paper_2403_05910_amd import perfmodel as pm
+    ns = case.thermo.ns
+    sweeps = {"sweep_x": 0, "sweep_y": 1, "sweep_z": 2}
+    name = max(sweeps, key=lambda k: kernels[k][0])
+    ms, launches = kernels[name]
+    flops = pm.sweep_flops(ns, case.n, sweeps[name])
+    avg_s = ms / launches / 1e3
+    achieved = flops / avg_s / 1e12
+    peak = pm.PEAK["fp32_vector_TFLOPs" if precision == "mixed" else "fp64_vector_TFLOPs"]
+    return {"kernel": name, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": None, "avg_launch_ms": ms / launches, "launches": launches,
+            "flops_per_launch": flops}
+
+
+def cpu_baseline(case, crop=40):
+    """the oracle as it stands, on a crop^3 block of the same state (its
+    halo taken from the neighbouring cells), straddling the shock and bubble"""
+    import oracle as O
+    t = case.thermo
+    th = O.Thermo(t.W, t.a, t.T_lo, t.T_hi)
+    nx, ny, nz = case.n
+    x0 = max(0, min(nx - crop, int(0.15 * nx) - crop // 2))
+    y0 = (ny - crop) // 2
+    z0 = (nz - crop) // 2
+    sub = case.U[:, z0:z0 + crop + 6, y0:y0 + crop + 6, x0:x0 + crop + 6]
+    g = O.Grid(crop, crop, crop, *case.d, (0,) * 6)
+    t0 = time.perf_counter()
+    O.rhs(th, g, np.ascontiguousarray(sub))
+    dt = time.perf_counter() - t0
+    return {"value": crop ** 3 / dt, "unit": "cell-RHS evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"one FP64 RHS of a {crop}^3 crop (with its 3-cell halo) of the same state, "
+                      f"x0={x0}, y0={y0}, z0={z0}; numpy, single thread",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="nine_species_sbi_256", choices=list(WORKLOADS))
+    ap.add_argument("--cfl", type=float, default=0.5)
+    ap.add_argument("--no-extras", action="store_true", help="FP64 step throughput only")
+    ap.add_argument("--no-cpu", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU: the path is built and measured for one MI355X "
+              f"(asked for --gpus {a.gpus}); see the design notes for how it would shard.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2403_05910_amd import perfmodel as pm
+    from paper_2403_05910_amd import xf
+
+    torch.cuda.set_device(0)
+    log(f"[bench] building workload {a.workload}")
+    case = make_case(a.workload)
+    cells = case.cells
+    ns = case.thermo.ns
+    log(f"[bench] {case.n} cells={cells} species={ns}")
+
+    ctx = xf.Context.from_case(case, "fp64")
+    U0 = ctx.state_from_numpy(case.U)
+    U = U0.clone()
+    dt_dev = torch.zeros(1, dtype=torch.float64, device=U.device)
+    ctx.fill_ghosts(U)
+    run_steps(ctx, U, dt_dev, a.warmup, a.cfl)
+    torch.cuda.synchronize()
+    log("[bench] fp64 warmup done")
+    secs, kern = timed_steps(torch, ctx, U, dt_dev, a.steps, a.cfl)
+    flags = ctx.status()
+    value = 3 * cells * a.steps / secs
+    log(f"[bench] fp64: {secs / a.steps * 1e3:.2f} ms/step, {value:.3e} cell-RHS/s, flags={flags}")
+    roof = roofline_of(kern, case, "fp64")
+    kernels_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in kern.items() if v[1]}
+
+    out = {
+        "metric": "cell-RHS evals/s (FP64)",
+        "value": value,
+        "unit": "cell-RHS evals/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": secs / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "grid": list(case.n), "species": ns, "cells": cells,
+                   "step": "CFL dt on device + one SSP-RK3 step (3 RHS evaluations)"},
+        "status_flags": flags,
+        "kernel_avg_ms": kernels_ms,
+        "roofline": roof,
+        "hbm_frac_algorithmic": value / 3 * pm.rk3_step_bytes_per_cell(ns) / 1e9 / pm.PEAK["hbm_GBs"],
+    }
+
+    if not a.no_extras:
+        # FP32-mixed path: same workload, same step
+        ctxm = xf.Context.from_case(case, "mixed")
+        Um = U0.clone()
+        ctxm.fill_ghosts(Um)
+        run_steps(ctxm, Um, dt_dev, a.warmup, a.cfl)
+        torch.cuda.synchronize()
+        secs_m, kern_m = timed_steps(torch, ctxm, Um, dt_dev, a.steps, a.cfl)
+        vm = 3 * cells * a.steps / secs_m
+        log(f"[bench] mixed: {secs_m / a.steps * 1e3:.2f} ms/step, {vm:.3e} cell-RHS/s")
+        # per-field error of one mixed RHS against the FP64 RHS of the same state
+        V = U0.clone()
+        ctx.fill_ghosts(V)
+        r64 = ctx.rhs(V)
+        r32 = ctxm.rhs(V)
+        d = (r32 - r64).abs()
+        nv = ns + 4
+        scale = r64.abs().reshape(nv, -1).amax(dim=1)
+        linf = (d.reshape(nv, -1).amax(dim=1) / scale).cpu().numpy()
+        l1 = (d.reshape(nv, -1).sum(dim=1) / r64.abs().reshape(nv, -1).sum(dim=1)).cpu().numpy()
+        del r32, d
+        out["mixed"] = {"value": vm, "unit": "cell-RHS evals/s", "ms_per_step": secs_m / a.steps * 1e3,
+                        "speedup_vs_fp64": vm / value,
+                        "rhs_rel_err_linf_per_field": [float(x) for x in linf],
+                        "rhs_rel_err_l1_per_field": [float(x) for x in l1],
+                        "roofline": roofline_of(kern_m, case, "mixed"),
+                        "flags": ctxm.status()}
+        ctxm.close()
+        del Um
+        # adjoint: one RHS VJP per evaluation, against one forward RHS
+        rb = torch.randn_like(r64)
+        Ub = torch.zeros_like(r64)
+        for _ in range(2):
+            ctx.rhs_vjp(V, rb, Ub)
+            ctx.rhs(V, out=r64)
+        reps = max(3, a.steps // 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.rhs(V, out=r64)
+        torch.cuda.synchronize()
+        t_fwd = (time.perf_counter() - t0) / reps
+        ctx.timing(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.rhs_vjp(V, rb, Ub)
+        torch.cuda.synchronize()
+        t_vjp = (time.perf_counter() - t0) / reps
+        ctx.timing(False)
+        kv = ctx.timing_read()
+        out["adjoint"] = {"value": cells / t_vjp, "unit": "cell adjoint-evals/s", "ms_per_vjp": t_vjp * 1e3,
+                          "ms_per_rhs": t_fwd * 1e3, "adjoint_over_forward": t_vjp / t_fwd,
+                          "kernel_avg_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kv.items() if v[1]}}
+        log(f"[bench] vjp {t_vjp * 1e3:.2f} ms vs rhs {t_fwd * 1e3:.2f} ms")
+        # checkpointed RK3 adjoint step vs forward step
+        try:
+            lam = torch.randn_like(r64)
+            ctx.rk3_step_vjp(V, 1e-9, lam)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(2):
+                ctx.rk3_step_vjp(V, 1e-9, lam)
+            torch.cuda.synchronize()
+            t_rk3v = (time.perf_counter() - t0) / 2
+            out["adjoint"]["ms_per_rk3_step_vjp"] = t_rk3v * 1e3
+            out["adjoint"]["rk3_adjoint_over_forward_step"] = t_rk3v / (secs / a.steps)
+        except Exception as e:  # workspace too large for the device
+            out["adjoint"]["rk3_step_vjp_error"] = str(e)
+    if not a.no_cpu:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(case)
+        out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

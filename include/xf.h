@@ -1,0 +1,204 @@
+/*
+ * xf.h -- C ABI of libxf.so: the convective right-hand side of the
+ * multicomponent compressible Euler/Navier-Stokes system of XFluids
+ * (arXiv 2403.05910), hand-written HIP for gfx950 (MI355X).
+ *
+ * What the library computes (paper section / equation):
+ *   state U = (rho Y_1..rho Y_N, rho u, rho v, rho w, rho E)   Sec. II.A, Eq. 1-2
+ *   mixture EOS p = rho Rbar T                                  Eq. 7
+ *   T from internal energy by Newton iteration                  Sec. II.C.3, Eq. 21
+ *   Roe-averaged characteristic projection, LLF splitting       Sec. II.C.1, Eq. 14
+ *   WENO5-JS reconstruction, back-projection                    Eq. 15
+ *   flux difference L(U) = -sum_d (F^_{i+1/2} - F^_{i-1/2})/dx_d  Eq. 13
+ *   SSP-RK3 update                                              Eq. 16
+ *   CFL time step                                               Eq. 17
+ * plus a hand-written vector-Jacobian product of the right-hand side (the
+ * LLF wave speeds held fixed), which the paper does not have.
+ *
+ * Layout.  Every state-shaped buffer is FP64, structure of arrays,
+ * field-major: [Nv][Z][Y][X] with x fastest, Nv = N + 4.  Each dimension with
+ * n_d > 1 is active and carries 3 ghost layers on both sides
+ * (X = nx + 6, ...); an inactive dimension (n_d == 1) has no ghosts and no
+ * flux.  Cell (i, j, k) of the interior sits at padded (i+gx, j+gy, k+gz).
+ * Ghost layers follow the block/halo layout of Sec. III.A (Fig. 3).
+ *
+ * Ownership.  The caller owns every device buffer (state, rhs, cotangents,
+ * workspace).  The library allocates device memory only inside xf_create (a
+ * status word); no call after that allocates device memory (HIP events for
+ * the optional per-kernel timing are created only while timing is enabled).
+ * Workspace sizes come from
+ * xf_workspace_bytes; workspace contents need not be initialised and are not
+ * preserved between calls.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void*; NULL means the null
+ * stream.  Every call except xf_create, xf_destroy and xf_status is
+ * asynchronous on that stream and never synchronises the host.
+ *
+ * Errors.  Functions return an int status: XF_OK (0) or a negative code.
+ * Argument errors are detected on the host before anything is enqueued.
+ * Non-physical states met by the kernels (rho <= 0, p <= 0, T out of its
+ * bracket, Newton not converged, Roe c^2 <= 0, NaN) set bits in a device
+ * status word that xf_status reads (and clears); the kernels never trap.
+ * Kernel launch failures return XF_EDEVICE.
+ */
+#ifndef XF_H
+#define XF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct xf_ctx xf_ctx;
+
+enum {
+    XF_OK = 0,
+    XF_EINVAL = -1,        /* bad argument (null pointer, size, enum value)       */
+    XF_EDEVICE = -2,       /* HIP runtime error (launch, copy, no device)          */
+    XF_ENOMEM = -3,        /* allocation inside xf_create failed                  */
+    XF_ENONPHYS = -4,      /* xf_status: a non-physical state was flagged          */
+    XF_EUNSUPPORTED = -5   /* valid request this build does not provide (e.g. N)  */
+};
+
+enum { XF_BC_PERIODIC = 0, XF_BC_OUTFLOW = 1 };
+enum { XF_PREC_FP64 = 0, XF_PREC_MIXED = 1 };
+enum { XF_OP_RHS = 0, XF_OP_RK3 = 1, XF_OP_VJP = 2, XF_OP_RK3_VJP = 3 };
+
+/* status-word bits (xf_status) */
+enum {
+    XF_FLAG_RHO = 1,       /* rho <= 0 in a cell the stencils read               */
+    XF_FLAG_Y = 2,         /* some Y_s < -1e-12                                  */
+    XF_FLAG_P = 4,         /* p <= 0 or T <= 0                                   */
+    XF_FLAG_TRANGE = 8,    /* T outside [T_lo, T_hi] (bracketed tables only)    */
+    XF_FLAG_NEWTON = 16,   /* Newton not converged in 50 iterations              */
+    XF_FLAG_C2 = 32,       /* Roe-averaged face c^2 <= 0                         */
+    XF_FLAG_NAN = 64       /* NaN or Inf in the state or a result                */
+};
+
+#define XF_MAX_SPECIES 9
+
+/* Uniform Cartesian grid (Sec. III.A, Fig. 3).  n_d >= 1; a dimension with
+ * n_d > 1 needs n_d >= 3.  bc order: -x, +x, -y, +y, -z, +z; XF_BC_PERIODIC
+ * wraps, XF_BC_OUTFLOW copies the nearest interior cell (zero gradient).
+ * Periodic sides must come in pairs. */
+typedef struct {
+    int nx, ny, nz;
+    double dx, dy, dz;
+    int bc[6];
+} xf_grid;
+
+/* Per-species thermo tables (Sec. II.C.3; the NASA-polynomial form named
+ * there): molar mass W[s] in kg/mol and a[s*6 + k], k = 0..5, with
+ *   cp_s/R_s = a0 + a1 T + a2 T^2 + a3 T^3 + a4 T^4,
+ *   h_s/R_s  = a0 T + a1 T^2/2 + a2 T^3/3 + a3 T^4/4 + a4 T^5/5 + a5,
+ *   e_s = h_s - R_s T,  R_s = 8.314462618 / W_s.
+ * [T_lo, T_hi] brackets the Newton temperature solve; T_hi <= 0 means no
+ * bracket (use it for calorically perfect tables).  Host pointers; the
+ * library copies them in xf_create. 1 <= ns <= XF_MAX_SPECIES. */
+typedef struct {
+    int ns;
+    const double *W;
+    const double *a;
+    double T_lo, T_hi;
+} xf_thermo;
+
+/* Create a context on the current HIP device.  precision: XF_PREC_FP64, or
+ * XF_PREC_MIXED (characteristic projection, WENO weights and fluxes in FP32;
+ * internal energy, Newton T, pressure and all stored values in FP64).
+ * Allocates the device status word.  On error *out is NULL. */
+int xf_create(const xf_grid *grid, const xf_thermo *thermo, int precision, xf_ctx **out);
+int xf_destroy(xf_ctx *ctx);
+
+/* Number of doubles in one padded state: Nv * Z * Y * X. */
+size_t xf_state_elems(const xf_ctx *ctx);
+
+/* Bytes of device workspace needed by an operation (XF_OP_*). */
+size_t xf_workspace_bytes(const xf_ctx *ctx, int op);
+
+/* Fill the 3 ghost layers of every active side of U in place: periodic wrap
+ * or zero-gradient outflow (the boundary treatment of Sec. III.B.4), for all
+ * fields; dimensions in the order x, y, z over the full padded extent of the
+ * other axes, so edges and corners are filled consistently. */
+int xf_fill_ghosts(xf_ctx *ctx, double *U, void *stream);
+
+/* rhs = L(U) = -sum_d (F^_{i+1/2} - F^_{i-1/2}) / dx_d on the interior (Eq. 13
+ * with the flux of Eq. 14-15); ghost cells of rhs are set to zero.  U's ghost
+ * layers must be valid (xf_fill_ghosts).  U and rhs must not overlap.
+ * ws: xf_workspace_bytes(ctx, XF_OP_RHS) bytes. */
+int xf_rhs(xf_ctx *ctx, const double *U, double *rhs, void *ws, void *stream);
+
+/* dt = cfl / max_i sum_{d active} (|u_d| + c)_i / dx_d over the interior
+ * (Eq. 17 per direction, summed), written to the device double *dt_dev.
+ * ws: xf_workspace_bytes(ctx, XF_OP_RHS) bytes. */
+int xf_cfl_dt(xf_ctx *ctx, const double *U, double cfl, double *dt_dev, void *ws, void *stream);
+
+/* One SSP-RK3 step of Eq. 16 in place on U (ghosts are filled before each
+ * stage and after the step).  The step is dt, or *dt_dev when dt_dev is not
+ * NULL (a device scalar, e.g. from xf_cfl_dt, so no host round trip).
+ * Stage combinations are accumulated in FP64 in both precisions.
+ * ws: xf_workspace_bytes(ctx, XF_OP_RK3) bytes. */
+int xf_rk3_step(xf_ctx *ctx, double *U, double dt, const double *dt_dev, void *ws, void *stream);
+
+/* Vector-Jacobian product of the right-hand side: U_bar += J(U)^T rhs_bar,
+ * J = d rhs / dU on the padded state with ghost values treated as independent
+ * inputs (compose with xf_fill_ghosts_vjp for the map from the interior).
+ * The LLF wave speeds are held fixed (their dependence on U is not
+ * differentiated); T(U) is differentiated through the converged Newton
+ * solve by the implicit-function rule dT = (de - sum_s e_s dY_s) / C_v.
+ * rhs_bar ghost entries are ignored.  U_bar is read and updated.
+ * ws: xf_workspace_bytes(ctx, XF_OP_VJP) bytes. */
+int xf_rhs_vjp(xf_ctx *ctx, const double *U, const double *rhs_bar, double *U_bar,
+               void *ws, void *stream);
+
+/* Adjoint of xf_fill_ghosts: adds every ghost entry of U_bar onto the
+ * interior cell it was copied from (reverse order z, y, x) and zeroes the
+ * ghost entries. */
+int xf_fill_ghosts_vjp(xf_ctx *ctx, double *U_bar, void *stream);
+
+/* Adjoint of one xf_rk3_step with a fixed dt: given U_n (the state before
+ * the step, ghosts need not be valid) and U_bar = dJ/dU_{n+1} (padded), it
+ * recomputes the stage states from U_n and overwrites U_bar with dJ/dU_n.
+ * The LLF wave speeds of every stage are held fixed.
+ * ws: xf_workspace_bytes(ctx, XF_OP_RK3_VJP) bytes. */
+int xf_rk3_step_vjp(xf_ctx *ctx, const double *U_n, double dt, double *U_bar,
+                    void *ws, void *stream);
+
+/* Kernel classes of the per-kernel timing below. */
+enum {
+    XF_K_PRIMS = 0,        /* primitives + Newton temperature                    */
+    XF_K_SWEEP_X = 1,      /* x flux difference                                  */
+    XF_K_SWEEP_Y = 2,      /* y flux difference                                  */
+    XF_K_SWEEP_Z = 3,      /* z flux difference                                  */
+    XF_K_FILL = 4,         /* ghost fill (all active directions of one call)     */
+    XF_K_STAGE = 5,        /* SSP-RK3 stage combination                          */
+    XF_K_CFL = 6,          /* CFL reduction                                      */
+    XF_K_ZERO = 7,         /* zeroing of rhs ghosts / VJP scratch                */
+    XF_K_VJP_X = 8,        /* x flux-difference VJP                              */
+    XF_K_VJP_Y = 9,
+    XF_K_VJP_Z = 10,
+    XF_K_PRIMS_VJP = 11,   /* implicit-function VJP of (p, T)(U)                  */
+    XF_K_FILL_VJP = 12,    /* adjoint of the ghost fill                          */
+    XF_K_COUNT = 13
+};
+
+/* Per-kernel timing for profiling.  While enabled, every kernel launch of
+ * this context is bracketed by two HIP events recorded on the launch stream
+ * (events are created on demand and reused; nothing else changes).
+ * xf_timing_read synchronises `stream`, adds the elapsed time of every
+ * completed launch of class k to ms[k] and its count to launches[k]
+ * (arrays of XF_K_COUNT entries, overwritten), and forgets the records. */
+int xf_timing(xf_ctx *ctx, int enable);
+int xf_timing_read(xf_ctx *ctx, void *stream, double *ms, long long *launches);
+
+/* Synchronise `stream`, return the accumulated status bits in *flags_out
+ * and clear them.  Returns XF_ENONPHYS when any bit was set, else XF_OK. */
+int xf_status(xf_ctx *ctx, void *stream, unsigned *flags_out);
+
+/* Static description of a status code. */
+const char *xf_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XF_H */

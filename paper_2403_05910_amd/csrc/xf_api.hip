@@ -1,0 +1,450 @@
+// xf_api.hip -- the C ABI of libxf.so (declared in include/xf.h): argument
+// checks on the host, then asynchronous launches on the caller's stream.
+#include <stdint.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "xf_common.hpp"
+
+namespace xf {
+template <int N>
+const NsOps *ops_ns();
+
+const NsOps *ops_for_ns(int ns) {
+    switch (ns) {
+        case 1: return ops_ns<1>();
+        case 2: return ops_ns<2>();
+        case 3: return ops_ns<3>();
+        case 4: return ops_ns<4>();
+        case 5: return ops_ns<5>();
+        case 6: return ops_ns<6>();
+        case 7: return ops_ns<7>();
+        case 8: return ops_ns<8>();
+        case 9: return ops_ns<9>();
+        default: return nullptr;
+    }
+}
+}  // namespace xf
+
+struct xf_ctx {
+    xf::LaunchCtx lc;
+    int ns, nv;
+    const xf::NsOps *ops;
+    int device;
+    // per-kernel timing (off unless xf_timing enabled it)
+    bool timing;
+    struct Rec {
+        int cls;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+using xf::LaunchCtx;
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+
+// Workspace carve-up (byte offsets); every piece 256-byte aligned.
+struct Layout {
+    size_t P, Pbar, mx, L, U0, V0, V1, V2, lam0, mu, total;
+};
+
+Layout layout(const xf_ctx *c, int op) {
+    const size_t cell = (size_t)c->lc.g.cells * sizeof(double);
+    const size_t state = cell * c->nv;
+    Layout l{};
+    size_t o = 0;
+    l.P = o;
+    o += align_up(4 * cell);
+    l.mx = o;
+    o += kAlign;
+    if (op == XF_OP_VJP || op == XF_OP_RK3_VJP) {
+        l.Pbar = o;
+        o += align_up(2 * cell);
+    }
+    if (op == XF_OP_RK3 || op == XF_OP_RK3_VJP) {
+        l.L = o;
+        o += align_up(state);
+        l.U0 = o;
+        o += align_up(state);
+    }
+    if (op == XF_OP_RK3_VJP) {
+        l.V0 = o;
+        o += align_up(state);
+        l.V1 = o;
+        o += align_up(state);
+        l.V2 = o;
+        o += align_up(state);
+        l.lam0 = l.U0;   // the forward stage buffer doubles as the adjoint accumulator
+        l.mu = o;
+        o += align_up(state);
+    }
+    l.total = o;
+    return l;
+}
+
+template <typename T>
+T *at(void *ws, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+int dev_err(hipError_t e) { return e == hipSuccess ? XF_OK : XF_EDEVICE; }
+
+#define XF_TRY(expr)                                  \
+    do {                                              \
+        const hipError_t _e = (expr);                 \
+        if (_e != hipSuccess) return XF_EDEVICE;      \
+    } while (0)
+
+hipError_t take_event(xf_ctx *c, hipEvent_t *e) {
+    if (!c->pool.empty()) {
+        *e = c->pool.back();
+        c->pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
+}
+
+// Run one launch (a callable returning hipError_t), bracketed by events
+// when timing is on.
+template <class F>
+hipError_t timed(xf_ctx *c, int cls, hipStream_t s, F &&launch) {
+    if (!c->timing) return launch();
+    xf_ctx::Rec r{cls, nullptr, nullptr};
+    hipError_t e = take_event(c, &r.a);
+    if (e != hipSuccess) return e;
+    if ((e = take_event(c, &r.b)) != hipSuccess) return e;
+    if ((e = hipEventRecord(r.a, s)) != hipSuccess) return e;
+    if ((e = launch()) != hipSuccess) return e;
+    if ((e = hipEventRecord(r.b, s)) != hipSuccess) return e;
+    c->recs.push_back(r);
+    return hipSuccess;
+}
+
+int rhs_into(xf_ctx *c, const double *U, double *rhs, double *P, hipStream_t s) {
+    const LaunchCtx &lc = c->lc;
+    const int n[3] = {lc.g.nx, lc.g.ny, lc.g.nz};
+    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(lc, U, P, s); }));
+    bool first = true;
+    for (int d = 0; d < 3; ++d) {
+        if (n[d] <= 1) continue;
+        const int acc = first ? 0 : 1;
+        XF_TRY(timed(c, XF_K_SWEEP_X + d, s, [&] { return c->ops->sweep(lc, d, acc, U, P, rhs, s); }));
+        first = false;
+    }
+    if (first) XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero(lc.g.cells * c->nv, rhs, s); }));
+    XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero_ghosts(lc, c->nv, rhs, s); }));
+    return XF_OK;
+}
+
+int rhs_vjp_into(xf_ctx *c, const double *U, const double *rbar, double *Ubar, double *P, double *Pbar,
+                 hipStream_t s) {
+    const LaunchCtx &lc = c->lc;
+    const int n[3] = {lc.g.nx, lc.g.ny, lc.g.nz};
+    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(lc, U, P, s); }));
+    XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero(2 * lc.g.cells, Pbar, s); }));
+    for (int d = 0; d < 3; ++d) {
+        if (n[d] <= 1) continue;
+        XF_TRY(timed(c, XF_K_VJP_X + d, s,
+                     [&] { return c->ops->sweep_vjp(lc, d, U, P, rbar, Ubar, Pbar, s); }));
+    }
+    XF_TRY(timed(c, XF_K_PRIMS_VJP, s, [&] { return c->ops->prims_vjp(lc, U, P, Pbar, Ubar, s); }));
+    return XF_OK;
+}
+
+hipError_t fill(xf_ctx *c, double *U, hipStream_t s) {
+    return timed(c, XF_K_FILL, s, [&] { return xf::launch_fill_ghosts(c->lc, c->nv, U, s); });
+}
+
+hipError_t fill_vjp(xf_ctx *c, double *Ub, hipStream_t s) {
+    return timed(c, XF_K_FILL_VJP, s, [&] { return xf::launch_fill_ghosts_vjp(c->lc, c->nv, Ub, s); });
+}
+
+bool grid_ok(const xf_grid *g) {
+    const int n[3] = {g->nx, g->ny, g->nz};
+    const double d[3] = {g->dx, g->dy, g->dz};
+    for (int k = 0; k < 3; ++k) {
+        if (n[k] < 1) return false;
+        if (n[k] > 1) {
+            if (n[k] < 3) return false;
+            if (!(d[k] > 0.0)) return false;
+            const int a = g->bc[2 * k], b = g->bc[2 * k + 1];
+            if ((a != XF_BC_PERIODIC && a != XF_BC_OUTFLOW) || (b != XF_BC_PERIODIC && b != XF_BC_OUTFLOW))
+                return false;
+            if ((a == XF_BC_PERIODIC) != (b == XF_BC_PERIODIC)) return false;
+        }
+    }
+    const double cells = (double)(n[0] + (n[0] > 1 ? 6 : 0)) * (n[1] + (n[1] > 1 ? 6 : 0)) *
+                         (n[2] + (n[2] > 1 ? 6 : 0));
+    return cells < 9.0e18 / 16.0;
+}
+
+template <typename R>
+void fill_thermo(xf::ThermoK<R> &t, const xf_thermo *th) {
+    memset(&t, 0, sizeof(t));
+    for (int s = 0; s < th->ns; ++s) {
+        const double Rs = xf::kRu / th->W[s];
+        const double *a = th->a + 6 * s;
+        t.Rs[s] = (R)Rs;
+        t.cv[s][0] = (R)(Rs * (a[0] - 1.0));
+        t.cv[s][1] = (R)(Rs * a[1]);
+        t.cv[s][2] = (R)(Rs * a[2]);
+        t.cv[s][3] = (R)(Rs * a[3]);
+        t.cv[s][4] = (R)(Rs * a[4]);
+        t.e[s][0] = (R)(Rs * a[5]);
+        t.e[s][1] = (R)(Rs * (a[0] - 1.0));
+        t.e[s][2] = (R)(Rs * a[1] / 2.0);
+        t.e[s][3] = (R)(Rs * a[2] / 3.0);
+        t.e[s][4] = (R)(Rs * a[3] / 4.0);
+        t.e[s][5] = (R)(Rs * a[4] / 5.0);
+    }
+    t.bracket = th->T_hi > 0.0 ? 1 : 0;
+    t.T_lo = th->T_lo;
+    t.T_hi = th->T_hi;
+    t.T_ref = t.bracket ? 0.5 * (th->T_lo + th->T_hi) : 1.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int xf_create(const xf_grid *grid, const xf_thermo *thermo, int precision, xf_ctx **out) {
+    if (!out) return XF_EINVAL;
+    *out = nullptr;
+    if (!grid || !thermo || !grid_ok(grid)) return XF_EINVAL;
+    if (precision != XF_PREC_FP64 && precision != XF_PREC_MIXED) return XF_EINVAL;
+    if (thermo->ns < 1 || !thermo->W || !thermo->a) return XF_EINVAL;
+    if (thermo->ns > XF_MAX_SPECIES) return XF_EUNSUPPORTED;
+    for (int s = 0; s < thermo->ns; ++s)
+        if (!(thermo->W[s] > 0.0)) return XF_EINVAL;
+    if (thermo->T_hi > 0.0 && !(thermo->T_lo < thermo->T_hi)) return XF_EINVAL;
+    const xf::NsOps *ops = xf::ops_for_ns(thermo->ns);
+    if (!ops) return XF_EUNSUPPORTED;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return XF_EDEVICE;
+    xf_ctx *c = new (std::nothrow) xf_ctx();
+    if (!c) return XF_ENOMEM;
+    c->timing = false;
+    xf::Geo &g = c->lc.g;
+    g.nx = grid->nx;
+    g.ny = grid->ny;
+    g.nz = grid->nz;
+    g.gx = g.nx > 1 ? 3 : 0;
+    g.gy = g.ny > 1 ? 3 : 0;
+    g.gz = g.nz > 1 ? 3 : 0;
+    g.px = g.nx + 2 * g.gx;
+    g.py = g.ny + 2 * g.gy;
+    g.pz = g.nz + 2 * g.gz;
+    g.sy = g.px;
+    g.sz = (long long)g.px * g.py;
+    g.cells = g.sz * g.pz;
+    g.dx = grid->dx;
+    g.dy = grid->dy;
+    g.dz = grid->dz;
+    g.idx = g.nx > 1 ? 1.0 / grid->dx : 0.0;
+    g.idy = g.ny > 1 ? 1.0 / grid->dy : 0.0;
+    g.idz = g.nz > 1 ? 1.0 / grid->dz : 0.0;
+    for (int k = 0; k < 6; ++k) g.bc[k] = grid->bc[k];
+    fill_thermo(c->lc.th64, thermo);
+    fill_thermo(c->lc.th32, thermo);
+    c->lc.precision = precision;
+    c->ns = thermo->ns;
+    c->nv = thermo->ns + 4;
+    c->ops = ops;
+    c->device = dev;
+    if (hipMalloc(reinterpret_cast<void **>(&c->lc.status), kAlign) != hipSuccess) {
+        delete c;
+        return XF_ENOMEM;
+    }
+    if (hipMemset(c->lc.status, 0, kAlign) != hipSuccess) {
+        (void)hipFree(c->lc.status);
+        delete c;
+        return XF_EDEVICE;
+    }
+    *out = c;
+    return XF_OK;
+}
+
+int xf_destroy(xf_ctx *c) {
+    if (!c) return XF_EINVAL;
+    for (auto &r : c->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : c->pool) (void)hipEventDestroy(e);
+    const hipError_t e = hipFree(c->lc.status);
+    delete c;
+    return dev_err(e);
+}
+
+int xf_timing(xf_ctx *c, int enable) {
+    if (!c) return XF_EINVAL;
+    c->timing = enable != 0;
+    return XF_OK;
+}
+
+int xf_timing_read(xf_ctx *c, void *stream, double *ms, long long *launches) {
+    if (!c || !ms || !launches) return XF_EINVAL;
+    XF_TRY(hipStreamSynchronize((hipStream_t)stream));
+    for (int k = 0; k < XF_K_COUNT; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (auto &r : c->recs) {
+        float t = 0.0f;
+        XF_TRY(hipEventElapsedTime(&t, r.a, r.b));
+        ms[r.cls] += t;
+        launches[r.cls] += 1;
+        c->pool.push_back(r.a);
+        c->pool.push_back(r.b);
+    }
+    c->recs.clear();
+    return XF_OK;
+}
+
+size_t xf_state_elems(const xf_ctx *c) { return c ? (size_t)c->lc.g.cells * c->nv : 0; }
+
+size_t xf_workspace_bytes(const xf_ctx *c, int op) {
+    if (!c || op < XF_OP_RHS || op > XF_OP_RK3_VJP) return 0;
+    return layout(c, op).total;
+}
+
+int xf_fill_ghosts(xf_ctx *c, double *U, void *stream) {
+    if (!c || !U || !aligned8(U)) return XF_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    return dev_err(fill(c, U, s));
+}
+
+int xf_fill_ghosts_vjp(xf_ctx *c, double *Ub, void *stream) {
+    if (!c || !Ub || !aligned8(Ub)) return XF_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    return dev_err(fill_vjp(c, Ub, s));
+}
+
+int xf_rhs(xf_ctx *c, const double *U, double *rhs, void *ws, void *stream) {
+    if (!c || !U || !rhs || !ws || U == rhs || !aligned8(U) || !aligned8(rhs) || !aligned8(ws))
+        return XF_EINVAL;
+    const Layout l = layout(c, XF_OP_RHS);
+    return rhs_into(c, U, rhs, at<double>(ws, l.P), (hipStream_t)stream);
+}
+
+int xf_cfl_dt(xf_ctx *c, const double *U, double cfl, double *dt_dev, void *ws, void *stream) {
+    if (!c || !U || !dt_dev || !ws || !(cfl > 0.0) || !aligned8(U) || !aligned8(ws)) return XF_EINVAL;
+    const Layout l = layout(c, XF_OP_RHS);
+    const hipStream_t s = (hipStream_t)stream;
+    double *P = at<double>(ws, l.P);
+    unsigned long long *mx = at<unsigned long long>(ws, l.mx);
+    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, P, s); }));
+    XF_TRY(timed(c, XF_K_CFL, s, [&] {
+        hipError_t e = xf::launch_cfl_reset(mx, s);
+        if (e == hipSuccess) e = c->ops->cfl(c->lc, U, P, mx, s);
+        if (e == hipSuccess) e = xf::launch_cfl_finish(mx, cfl, dt_dev, s);
+        return e;
+    }));
+    return XF_OK;
+}
+
+int xf_rk3_step(xf_ctx *c, double *U, double dt, const double *dt_dev, void *ws, void *stream) {
+    if (!c || !U || !ws || !aligned8(U) || !aligned8(ws)) return XF_EINVAL;
+    if (!dt_dev && !(dt >= 0.0)) return XF_EINVAL;
+    const Layout l = layout(c, XF_OP_RK3);
+    const hipStream_t s = (hipStream_t)stream;
+    double *P = at<double>(ws, l.P), *L = at<double>(ws, l.L), *U0 = at<double>(ws, l.U0);
+    for (int stage = 1; stage <= 3; ++stage) {
+        XF_TRY(fill(c, U, s));
+        const int r = rhs_into(c, U, L, P, s);
+        if (r != XF_OK) return r;
+        XF_TRY(timed(c, XF_K_STAGE, s,
+                     [&] { return xf::launch_rk3_stage(c->lc, c->nv, stage, U, U0, L, dt, dt_dev, s); }));
+    }
+    XF_TRY(fill(c, U, s));
+    return XF_OK;
+}
+
+int xf_rhs_vjp(xf_ctx *c, const double *U, const double *rbar, double *Ubar, void *ws, void *stream) {
+    if (!c || !U || !rbar || !Ubar || !ws || Ubar == U || Ubar == rbar || !aligned8(U) || !aligned8(rbar) ||
+        !aligned8(Ubar) || !aligned8(ws))
+        return XF_EINVAL;
+    const Layout l = layout(c, XF_OP_VJP);
+    return rhs_vjp_into(c, U, rbar, Ubar, at<double>(ws, l.P), at<double>(ws, l.Pbar), (hipStream_t)stream);
+}
+
+int xf_rk3_step_vjp(xf_ctx *c, const double *Un, double dt, double *Ubar, void *ws, void *stream) {
+    if (!c || !Un || !Ubar || !ws || Un == Ubar || !aligned8(Un) || !aligned8(Ubar) || !aligned8(ws) ||
+        !(dt >= 0.0))
+        return XF_EINVAL;
+    const Layout l = layout(c, XF_OP_RK3_VJP);
+    const hipStream_t s = (hipStream_t)stream;
+    const LaunchCtx &lc = c->lc;
+    const long long n = lc.g.cells * c->nv;
+    double *P = at<double>(ws, l.P), *Pbar = at<double>(ws, l.Pbar), *L = at<double>(ws, l.L);
+    double *V0 = at<double>(ws, l.V0), *V1 = at<double>(ws, l.V1), *V2 = at<double>(ws, l.V2);
+    double *lam0 = at<double>(ws, l.lam0), *mu = at<double>(ws, l.mu);
+    int r;
+    // forward stage states V0 = G(U_n), V1 = G(V0 + dt L(V0)), V2 = G(3/4 V0 + 1/4 (V1 + dt L(V1)))
+    XF_TRY(timed(c, XF_K_STAGE, s, [&] { return xf::launch_copy(n, Un, V0, s); }));
+    XF_TRY(fill(c, V0, s));
+    if ((r = rhs_into(c, V0, L, P, s)) != XF_OK) return r;
+    XF_TRY(timed(c, XF_K_STAGE, s, [&] {
+        hipError_t e = xf::launch_copy(n, V0, V1, s);
+        if (e == hipSuccess) e = xf::launch_axpy_state(n, dt, L, 1.0, V1, s);
+        return e;
+    }));
+    XF_TRY(fill(c, V1, s));
+    if ((r = rhs_into(c, V1, L, P, s)) != XF_OK) return r;
+    XF_TRY(timed(c, XF_K_STAGE, s, [&] {
+        hipError_t e = xf::launch_copy(n, V1, V2, s);
+        if (e == hipSuccess) e = xf::launch_axpy_state(n, dt, L, 1.0, V2, s);
+        if (e == hipSuccess) e = xf::launch_axpy_state(n, 0.75, V0, 0.25, V2, s);
+        return e;
+    }));
+    XF_TRY(fill(c, V2, s));
+    // reverse sweep through the stages
+    double *const Vs[3] = {V0, V1, V2};
+    XF_TRY(fill_vjp(c, Ubar, s));
+    for (int stage = 3; stage >= 1; --stage) {
+        XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero(n, mu, s); }));
+        if ((r = rhs_vjp_into(c, Vs[stage - 1], Ubar, mu, P, Pbar, s)) != XF_OK) return r;
+        XF_TRY(timed(c, XF_K_STAGE, s,
+                     [&] { return xf::launch_rk3_stage_vjp(lc, c->nv, stage, Ubar, lam0, mu, nullptr, dt, s); }));
+        if (stage > 1) XF_TRY(fill_vjp(c, Ubar, s));
+    }
+    XF_TRY(fill_vjp(c, lam0, s));
+    XF_TRY(timed(c, XF_K_STAGE, s, [&] { return xf::launch_copy(n, lam0, Ubar, s); }));
+    return XF_OK;
+}
+
+int xf_status(xf_ctx *c, void *stream, unsigned *flags_out) {
+    if (!c || !flags_out) return XF_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    unsigned h = 0;
+    const unsigned zero = 0;
+    XF_TRY(hipMemcpyAsync(&h, c->lc.status, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    XF_TRY(hipMemcpyAsync(c->lc.status, &zero, sizeof(unsigned), hipMemcpyHostToDevice, s));
+    XF_TRY(hipStreamSynchronize(s));
+    *flags_out = h;
+    return h ? XF_ENONPHYS : XF_OK;
+}
+
+const char *xf_strerror(int code) {
+    switch (code) {
+        case XF_OK: return "success";
+        case XF_EINVAL: return "invalid argument";
+        case XF_EDEVICE: return "HIP runtime error";
+        case XF_ENOMEM: return "device allocation failed";
+        case XF_ENONPHYS: return "non-physical state flagged by the kernels";
+        case XF_EUNSUPPORTED: return "unsupported request (species count or operation)";
+        default: return "unknown status code";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// xf_common.hpp -- host/device shared definitions of libxf (gfx950).
+//
+// Kernel-argument structs (grid geometry, thermo coefficient tables) and the
+// per-species-count operation table the C ABI dispatches through.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/xf.h"
+
+namespace xf {
+
+constexpr double kRu = 8.314462618;      // J/(mol K)
+constexpr int kMaxNs = XF_MAX_SPECIES;
+constexpr double kNewtonTol = 1e-11;
+constexpr int kNewtonMaxIt = 50;
+
+// Geometry of one padded SoA field: x fastest, 3 ghost layers per active axis.
+struct Geo {
+    int nx, ny, nz;      // interior cells
+    int gx, gy, gz;      // ghost widths (3 or 0)
+    int px, py, pz;      // padded extents
+    long long sy, sz;    // strides of y and z in a field
+    long long cells;     // px * py * pz: stride between fields
+    double dx, dy, dz;
+    double idx, idy, idz;
+    int bc[6];
+};
+
+// Species thermo in the form the kernels evaluate (Horner in T):
+//   cv_s(T) = sum_k cv[s][k] T^k  (k = 0..4),  C_v,s = C_p,s - R_s
+//   e_s(T)  = sum_k e[s][k] T^k   (k = 0..5),  e_s = h_s - R_s T
+// For a table a[0..5] (cp/R = sum a_k T^k, h/R = sum a_k T^(k+1)/(k+1) + a5):
+//   cv = R_s (a0 - 1, a1, a2, a3, a4),  e = R_s (a5, a0 - 1, a1/2, a2/3, a3/4, a4/5).
+template <typename R>
+struct ThermoK {
+    R Rs[kMaxNs];
+    R cv[kMaxNs][5];
+    R e[kMaxNs][6];
+    double T_lo, T_hi, T_ref;
+    int bracket;
+};
+
+// Everything a launch needs besides buffers.
+struct LaunchCtx {
+    Geo g;
+    ThermoK<double> th64;
+    ThermoK<float> th32;
+    unsigned *status;    // device status word (atomicOr of XF_FLAG_*)
+    int precision;       // XF_PREC_*
+};
+
+// Per species-count entry points (one translation unit per N).
+struct NsOps {
+    // primitive variables (T, p, c, 1/rho) of every cell a stencil reads
+    hipError_t (*prims)(const LaunchCtx &, const double *U, double *P, hipStream_t);
+    // one direction of the convective flux difference; accumulate: rhs += or rhs =
+    hipError_t (*sweep)(const LaunchCtx &, int dir, int accumulate, const double *U,
+                        const double *P, double *rhs, hipStream_t);
+    // VJP of one direction: Ubar_direct += (dF/dU)^T ..., Pbar += (dF/d(p, T))^T ...
+    hipError_t (*sweep_vjp)(const LaunchCtx &, int dir, const double *U, const double *P,
+                            const double *rbar, double *Ubar, double *Pbar, hipStream_t);
+    // VJP of the primitive map: Ubar += (d(p, T)/dU)^T Pbar
+    hipError_t (*prims_vjp)(const LaunchCtx &, const double *U, const double *P,
+                            const double *Pbar, double *Ubar, hipStream_t);
+    // CFL partial reduction: max_i sum_d (|u_d| + c)/dx_d -> atomicMax on *mx (uint64 bits)
+    hipError_t (*cfl)(const LaunchCtx &, const double *U, const double *P,
+                      unsigned long long *mx, hipStream_t);
+};
+
+const NsOps *ops_for_ns(int ns);
+
+// Species-independent launches (xf_misc.hip).
+hipError_t launch_fill_ghosts(const LaunchCtx &, int nv, double *U, hipStream_t);
+hipError_t launch_fill_ghosts_vjp(const LaunchCtx &, int nv, double *Ubar, hipStream_t);
+hipError_t launch_zero_ghosts(const LaunchCtx &, int nv, double *A, hipStream_t);
+hipError_t launch_rk3_stage(const LaunchCtx &, int nv, int stage, double *U, double *U0,
+                            const double *L, double dt, const double *dt_dev, hipStream_t);
+hipError_t launch_rk3_stage_vjp(const LaunchCtx &, int nv, int stage, double *lam, double *lam0,
+                                double *mu, const double *dt_dev, double dt, hipStream_t);
+hipError_t launch_axpy_state(long long n, double a, const double *x, double b, double *y,
+                             hipStream_t);
+hipError_t launch_cfl_reset(unsigned long long *mx, hipStream_t);
+hipError_t launch_cfl_finish(const unsigned long long *mx, double cfl, double *dt_dev,
+                             hipStream_t);
+hipError_t launch_copy(long long n, const double *src, double *dst, hipStream_t);
+hipError_t launch_zero(long long n, double *dst, hipStream_t);
+
+// Number of grid blocks of the marching (y/z) sweeps and their segment length.
+void march_shape(const Geo &g, int dir, int *nseg, int *seglen);
+
+}  // namespace xf

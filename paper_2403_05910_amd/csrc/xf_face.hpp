@@ -1,0 +1,282 @@
+// xf_face.hpp -- device code of one face of the convective flux (gfx950).
+//
+// Computes the numerical flux F^_{i+1/2} of Eq. 14-15 of XFluids (arXiv
+// 2403.05910) at one face from the six cells m = i-2..i+3 of its stencil:
+//
+//   1. Roe-averaged face state of cells i, i+1 (sqrt(rho) weights on u, H,
+//      Y_s and T), species thermo at the averaged T, Gamma = Rbar / C_v,
+//      chi_s = Gamma (|u|^2/2 - e_s) + R_s T and the face sound speed
+//      c^2 = sum_s Y_s chi_s + Gamma (H - |u|^2).
+//   2. Component-wise LLF speeds: max over the six cells of |u_n - c|,
+//      |u_n|, |u_n + c| for the u-c, middle and u+c characteristic fields.
+//   3. Projection of F_m and U_m onto the characteristic fields, split
+//      F_m^pm = 1/2 (L F_m +- alpha L U_m) (Eq. 14).
+//   4. WENO5-JS of the plus side over m = i-2..i+2 and of the minus side
+//      mirrored over m = i+3..i-1 (Eq. 15).
+//   5. Back-projection F^ = R (F^+ + F^-) (Eq. 15).
+//
+// The left/right eigenvectors are never stored.  They are identity plus a few
+// rank-one terms, so each projection costs O(N):
+//   dp(v)     = sum_s chi_s v_rho_s - Gamma u.v_m + Gamma v_E
+//   l_-+ . v  = [dp(v) -+ c (n.v_m - u_n sigma(v))] / (2 c^2),  sigma = sum_s v_rho_s
+//   l_s  . v  = v_rho_s - Y_s dp(v) / c^2
+//   l_ta . v  = t_a . v_m - (u.t_a) sigma(v)
+//   r_-+ = (Y, u -+ c n, H -+ u_n c),  r_s = (e_s, u, |u|^2 - chi_s/Gamma),
+//   r_ta = (0, t_a, u.t_a).
+// Field order of the characteristic vector: u-c, species 1..N, t1, t2, u+c,
+// with (t1, t2) = (y, z) for an x face, (x, z) for y, (x, y) for z.  The
+// characteristic fields are streamed one at a time (acoustic pair first, then
+// the tangential pair, then the species), so registers hold O(N) values.
+#pragma once
+
+#include <cmath>
+
+#include "xf_common.hpp"
+
+// Face code is compiled for the device and, for CPU checks of its arithmetic,
+// for the host as well.
+#define XF_HD __host__ __device__ __forceinline__
+
+namespace xf {
+
+XF_HD double xsqrt(double a) { return sqrt(a); }
+XF_HD float xsqrt(float a) { return sqrtf(a); }
+
+template <typename R>
+XF_HD R rmax(R a, R b) { return a > b ? a : b; }
+
+template <typename R>
+XF_HD R rabs(R a) { return a < R(0) ? -a : a; }
+
+// Horner evaluations of the species tables.
+template <typename R>
+XF_HD R cv_species(const ThermoK<R> &th, int s, R T) {
+    return (((th.cv[s][4] * T + th.cv[s][3]) * T + th.cv[s][2]) * T + th.cv[s][1]) * T + th.cv[s][0];
+}
+template <typename R>
+XF_HD R e_species(const ThermoK<R> &th, int s, R T) {
+    return ((((th.e[s][5] * T + th.e[s][4]) * T + th.e[s][3]) * T + th.e[s][2]) * T + th.e[s][1]) * T
+           + th.e[s][0];
+}
+
+// WENO5-JS value at the right edge of the cell holding c (linear weights
+// 1/10, 6/10, 3/10; absolute eps = 1e-6; weights (eps + beta)^-2).  Written
+// with one division: alpha_k / sum alpha = d_k prod_{j!=k} s_j / sum(...),
+// s_k = (eps + beta_k)^2.
+XF_HD double weno5(double a, double b, double c, double d, double e) {
+    const double q0 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
+    const double q1 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
+    const double q2 = (2.0 * c + 5.0 * d - e) * (1.0 / 6.0);
+    const double t0 = a - 2.0 * b + c, u0 = a - 4.0 * b + 3.0 * c;
+    const double t1 = b - 2.0 * c + d, u1 = b - d;
+    const double t2 = c - 2.0 * d + e, u2 = 3.0 * c - 4.0 * d + e;
+    double s0 = 1e-6 + ((13.0 / 12.0) * t0 * t0 + 0.25 * u0 * u0);
+    double s1 = 1e-6 + ((13.0 / 12.0) * t1 * t1 + 0.25 * u1 * u1);
+    double s2 = 1e-6 + ((13.0 / 12.0) * t2 * t2 + 0.25 * u2 * u2);
+    s0 *= s0;
+    s1 *= s1;
+    s2 *= s2;
+    const double w0 = 0.1 * (s1 * s2), w1 = 0.6 * (s0 * s2), w2 = 0.3 * (s0 * s1);
+    return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+}
+
+// FP32 form.  The (eps + beta)^2 products can overflow FP32, so the three
+// (eps + beta) are first scaled by the same power of two (exact, no rounding),
+// which leaves the weights unchanged.
+XF_HD float weno5(float a, float b, float c, float d, float e) {
+    const float q0 = (2.0f * a - 7.0f * b + 11.0f * c) * (1.0f / 6.0f);
+    const float q1 = (-b + 5.0f * c + 2.0f * d) * (1.0f / 6.0f);
+    const float q2 = (2.0f * c + 5.0f * d - e) * (1.0f / 6.0f);
+    const float t0 = a - 2.0f * b + c, u0 = a - 4.0f * b + 3.0f * c;
+    const float t1 = b - 2.0f * c + d, u1 = b - d;
+    const float t2 = c - 2.0f * d + e, u2 = 3.0f * c - 4.0f * d + e;
+    float s0 = 1e-6f + ((13.0f / 12.0f) * t0 * t0 + 0.25f * u0 * u0);
+    float s1 = 1e-6f + ((13.0f / 12.0f) * t1 * t1 + 0.25f * u1 * u1);
+    float s2 = 1e-6f + ((13.0f / 12.0f) * t2 * t2 + 0.25f * u2 * u2);
+    const float smax = fmaxf(s0, fmaxf(s1, s2));
+    int ex;
+    frexpf(smax, &ex);
+    s0 = ldexpf(s0, -ex);
+    s1 = ldexpf(s1, -ex);
+    s2 = ldexpf(s2, -ex);
+    s0 *= s0;
+    s1 *= s1;
+    s2 *= s2;
+    const float w0 = 0.1f * (s1 * s2), w1 = 0.6f * (s0 * s2), w2 = 0.3f * (s0 * s1);
+    return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+}
+
+// Read-only view of a 6-cell stencil along one axis.
+struct Stencil {
+    const double *__restrict__ U;
+    const double *__restrict__ P;   // [4][cells]: T, p, c, 1/rho
+    long long base;                 // padded index of stencil cell 0 (= i-2)
+    long long step;                 // index stride along the sweep axis
+    long long cells;                // field stride
+    XF_HD double u(int f, int m) const { return U[f * cells + base + m * step]; }
+    XF_HD double p(int k, int m) const { return P[k * cells + base + m * step]; }
+};
+
+template <int DIR>
+struct Axes {
+    // momentum component of the normal and of the two tangents
+    static constexpr int n = DIR;
+    static constexpr int t1 = (DIR == 0) ? 1 : 0;
+    static constexpr int t2 = (DIR == 2) ? 1 : 2;
+};
+
+// Numerical flux at one face.  Fh[0..NS+3] receives F^ in conservative field
+// order.  flags collects XF_FLAG_C2 if the face c^2 is not positive.
+template <int NS, typename R, int DIR>
+XF_HD void face_flux(const Stencil &st, const ThermoK<R> &th, R *__restrict__ Fh,
+                                          unsigned &flags) {
+    constexpr int IM = NS;
+    constexpr int IE = NS + 3;
+    constexpr int IN = NS + Axes<DIR>::n;
+    constexpr int I1 = NS + Axes<DIR>::t1;
+    constexpr int I2 = NS + Axes<DIR>::t2;
+
+    // ---- 1. Roe-averaged face state ------------------------------------
+    R rL = R(0), rR = R(0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        rL += R(st.u(s, 2));
+        rR += R(st.u(s, 3));
+    }
+    const R sL = xsqrt(rL), sR = xsqrt(rR);
+    const R wL = sL / (sL + sR);
+    const R wR = R(1) - wL;
+    const R aL = wL * R(st.p(3, 2)), aR = wR * R(st.p(3, 3));   // weights on conservative values
+    R ut[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ut[k] = aL * R(st.u(IM + k, 2)) + aR * R(st.u(IM + k, 3));
+    const R Ht = aL * (R(st.u(IE, 2)) + R(st.p(1, 2))) + aR * (R(st.u(IE, 3)) + R(st.p(1, 3)));
+    const R Tt = wL * R(st.p(0, 2)) + wR * R(st.p(0, 3));
+    R Yt[NS], chi[NS];
+    R Rb = R(0), cvb = R(0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        Yt[s] = aL * R(st.u(s, 2)) + aR * R(st.u(s, 3));
+        Rb += Yt[s] * th.Rs[s];
+        cvb += Yt[s] * cv_species(th, s, Tt);
+        chi[s] = e_species(th, s, Tt);   // e_s(T~) for now
+    }
+    const R Gam = Rb / cvb;
+    const R q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+    R c2 = Gam * (Ht - q2);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        chi[s] = Gam * (R(0.5) * q2 - chi[s]) + th.Rs[s] * Tt;
+        c2 += Yt[s] * chi[s];
+    }
+    if (!(c2 > R(0))) flags |= XF_FLAG_C2;
+    const R ct = xsqrt(c2);
+    const R ic2 = R(1) / c2;
+    const R cih = R(0.5) * ct * ic2;      // c / (2 c^2)
+    const R utn = ut[Axes<DIR>::n], ut1 = ut[Axes<DIR>::t1], ut2 = ut[Axes<DIR>::t2];
+
+    // ---- 2./3. per-cell scalars of the projections, LLF speeds ----------
+    R un[6], DU[6], DF[6], rh[6];
+    R aM = R(0), a0 = R(0), aP = R(0);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        R sc = R(0), sr = R(0);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const R r = R(st.u(s, m));
+            sc += chi[s] * r;
+            sr += r;
+        }
+        const R rinv = R(st.p(3, m)), pm = R(st.p(1, m)), cm = R(st.p(2, m));
+        const R E = R(st.u(IE, m));
+        const R unm = R(st.u(IN, m)) * rinv;
+        const R um = ut[0] * R(st.u(IM, m)) + ut[1] * R(st.u(IM + 1, m)) + ut[2] * R(st.u(IM + 2, m));
+        // dp of U_m and of F_m = (rho_s u_n, m u_n + p n, (E + p) u_n)
+        const R dpU = sc - Gam * um + Gam * E;
+        const R dpF = unm * sc - Gam * (unm * um + pm * utn) + Gam * ((E + pm) * unm);
+        un[m] = unm;
+        DU[m] = dpU * ic2;
+        DF[m] = dpF * ic2;
+        rh[m] = sr;
+        aM = rmax(aM, rabs(unm - cm));
+        a0 = rmax(a0, rabs(unm));
+        aP = rmax(aP, rabs(unm + cm));
+    }
+
+    // ---- acoustic pair ----------------------------------------------------
+    R hm, hp;
+    {
+        R gMp[6], gMm[6], gPp[6], gPm[6];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            const R mn = R(st.u(IN, m));
+            const R XU = mn - utn * rh[m];
+            const R XF = (mn * un[m] + R(st.p(1, m))) - utn * (rh[m] * un[m]);
+            const R wUm = R(0.5) * DU[m] - cih * XU, wFm = R(0.5) * DF[m] - cih * XF;
+            const R wUp = R(0.5) * DU[m] + cih * XU, wFp = R(0.5) * DF[m] + cih * XF;
+            gMp[m] = R(0.5) * (wFm + aM * wUm);
+            gMm[m] = R(0.5) * (wFm - aM * wUm);
+            gPp[m] = R(0.5) * (wFp + aP * wUp);
+            gPm[m] = R(0.5) * (wFp - aP * wUp);
+        }
+        hm = weno5(gMp[0], gMp[1], gMp[2], gMp[3], gMp[4]) + weno5(gMm[5], gMm[4], gMm[3], gMm[2], gMm[1]);
+        hp = weno5(gPp[0], gPp[1], gPp[2], gPp[3], gPp[4]) + weno5(gPm[5], gPm[4], gPm[3], gPm[2], gPm[1]);
+    }
+    const R Asum = hm + hp, Dif = hp - hm;
+
+    // ---- tangential pair --------------------------------------------------
+    R h1, h2;
+    {
+        R gp[6], gm[6];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            const R wU = R(st.u(I1, m)) - ut1 * rh[m];
+            const R wF = un[m] * wU;
+            gp[m] = R(0.5) * (wF + a0 * wU);
+            gm[m] = R(0.5) * (wF - a0 * wU);
+        }
+        h1 = weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            const R wU = R(st.u(I2, m)) - ut2 * rh[m];
+            const R wF = un[m] * wU;
+            gp[m] = R(0.5) * (wF + a0 * wU);
+            gm[m] = R(0.5) * (wF - a0 * wU);
+        }
+        h2 = weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
+    }
+
+    // ---- species fields, back-projected as they come ----------------------
+    const R iGam = R(1) / Gam;
+    R gsum = R(0), gE = R(0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        R gp[6], gm[6];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            const R r = R(st.u(s, m));
+            const R wU = r - Yt[s] * DU[m];
+            const R wF = r * un[m] - Yt[s] * DF[m];
+            gp[m] = R(0.5) * (wF + a0 * wU);
+            gm[m] = R(0.5) * (wF - a0 * wU);
+        }
+        const R hs = weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
+        Fh[s] = Yt[s] * Asum + hs;
+        gsum += hs;
+        gE += (q2 - chi[s] * iGam) * hs;
+    }
+
+    // ---- momentum and energy of F^ = R h ----------------------------------
+    R Fm[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Fm[k] = ut[k] * (Asum + gsum);
+    Fm[Axes<DIR>::n] += ct * Dif;
+    Fm[Axes<DIR>::t1] += h1;
+    Fm[Axes<DIR>::t2] += h2;
+    Fh[IM + 0] = Fm[0];
+    Fh[IM + 1] = Fm[1];
+    Fh[IM + 2] = Fm[2];
+    Fh[IE] = Ht * Asum + utn * ct * Dif + ut1 * h1 + ut2 * h2 + gE;
+}
+
+}  // namespace xf

@@ -1,0 +1,241 @@
+// xf_forward.hpp -- forward kernels of the convective right-hand side.
+//
+//   k_prims       primitive recovery with the Newton temperature (Eq. 7, 21)
+//   k_sweep_x     x-direction flux difference, one face per thread
+//   k_sweep_march y/z-direction flux difference, one column per thread
+//   k_cfl         CFL reduction (Eq. 17), wavefront max + one 64-bit atomic
+#pragma once
+
+#include "xf_face.hpp"
+
+namespace xf {
+
+// ---------------------------------------------------------------------------
+// primitive variables and Newton temperature (always FP64)
+// ---------------------------------------------------------------------------
+template <int NS>
+XF_HD void mix_e_cv(const ThermoK<double> &th, const double *Y, double T, double &e,
+                                         double &cv) {
+    e = 0.0;
+    cv = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        e += Y[s] * e_species(th, s, T);
+        cv += Y[s] * cv_species(th, s, T);
+    }
+}
+
+// Newton on e(T) = e (Eq. 21): T <- T + (e - e(T)) / C_v(T).  Cold start
+// T0 = e / C_v(T_ref) clamped into the bracket; with a bracket, every
+// evaluation narrows [lo, hi] (e(T) > e: hi = T, else lo = T) and a step that
+// leaves the closed bracket is replaced by bisection.  Stop when
+// |dT| <= 1e-11 |T|, then one more Newton update.  Returns false if not
+// converged in 50 iterations.
+template <int NS>
+XF_HD bool newton_T(const ThermoK<double> &th, const double *Y, double e, double &T) {
+    double ee, cv;
+    double cv0 = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) cv0 += Y[s] * cv_species(th, s, th.T_ref);
+    T = e / cv0;
+    double lo = th.T_lo, hi = th.T_hi;
+    if (th.bracket) T = T < th.T_lo ? th.T_lo : (T > th.T_hi ? th.T_hi : T);
+    for (int it = 0; it < kNewtonMaxIt; ++it) {
+        mix_e_cv<NS>(th, Y, T, ee, cv);
+        const double f = ee - e;
+        double Tn = T - f / cv;
+        if (th.bracket) {
+            if (f > 0.0)
+                hi = fmin(hi, T);
+            else
+                lo = fmax(lo, T);
+            if (Tn < lo || Tn > hi) Tn = 0.5 * (lo + hi);
+        }
+        const bool conv = fabs(Tn - T) <= kNewtonTol * fabs(T);
+        T = Tn;
+        if (conv) {
+            mix_e_cv<NS>(th, Y, T, ee, cv);
+            T = T - (ee - e) / cv;
+            return true;
+        }
+    }
+    return false;
+}
+
+// P[0..3][cell] = (T, p, c, 1/rho) for every cell with at most one
+// coordinate in a ghost layer (the cells axis-aligned stencils read).
+template <int NS>
+__global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, double *__restrict__ P, Geo g,
+                                               ThermoK<double> th, unsigned *status) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.cells) return;
+    const int x = (int)(idx % g.px);
+    const long long r = idx / g.px;
+    const int y = (int)(r % g.py);
+    const int z = (int)(r / g.py);
+    const int ng = (x < g.gx || x >= g.gx + g.nx) + (y < g.gy || y >= g.gy + g.ny) +
+                   (z < g.gz || z >= g.gz + g.nz);
+    if (ng > 1) return;
+    const long long C = g.cells;
+    double Y[NS];
+    double rho = 0.0;
+    bool finite = true;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        Y[s] = U[s * C + idx];
+        rho += Y[s];
+        finite = finite && isfinite(Y[s]);
+    }
+    const double rinv = 1.0 / rho;
+    unsigned flags = 0;
+    bool yneg = false;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        Y[s] *= rinv;
+        yneg = yneg || (Y[s] < -1e-12);
+    }
+    const double mx = U[NS * C + idx], my = U[(NS + 1) * C + idx], mz = U[(NS + 2) * C + idx];
+    const double E = U[(NS + 3) * C + idx];
+    finite = finite && isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(E);
+    const double u = mx * rinv, v = my * rinv, w = mz * rinv;
+    const double e = E * rinv - 0.5 * (u * u + v * v + w * w);
+    double T;
+    const bool conv = newton_T<NS>(th, Y, e, T);
+    double Rb = 0.0, cv = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        Rb += Y[s] * th.Rs[s];
+        cv += Y[s] * cv_species(th, s, T);
+    }
+    const double p = rho * Rb * T;
+    const double c = sqrt((1.0 + Rb / cv) * Rb * T);
+    if (!(rho > 0.0)) flags |= XF_FLAG_RHO;
+    if (yneg) flags |= XF_FLAG_Y;
+    if (!(p > 0.0) || !(T > 0.0)) flags |= XF_FLAG_P;
+    if (th.bracket && (T < th.T_lo || T > th.T_hi)) flags |= XF_FLAG_TRANGE;
+    if (!conv) flags |= XF_FLAG_NEWTON;
+    if (!finite || !isfinite(T) || !isfinite(c)) flags |= XF_FLAG_NAN;
+    P[idx] = T;
+    P[C + idx] = p;
+    P[2 * C + idx] = c;
+    P[3 * C + idx] = rinv;
+    if (flags) atomicOr(status, flags);
+}
+
+// ---------------------------------------------------------------------------
+// x sweep: faces linearised over interior rows (face i of row r = the face
+// between interior cells i-1 and i, i = 0..nx).  A block of 256 threads takes
+// 256 consecutive faces and blocks overlap by one face, so every cell whose
+// two faces lie in a block gets rhs = (F^_{i-1/2} - F^_{i+1/2}) / dx there
+// (the neighbour flux comes through LDS).  x is the first active sweep, so it
+// writes rhs rather than accumulating.
+// ---------------------------------------------------------------------------
+constexpr int kXBlock = 256;
+
+template <int NS, typename R>
+__global__ __launch_bounds__(kXBlock) void k_sweep_x(const double *__restrict__ U, const double *__restrict__ P,
+                                                     double *__restrict__ rhs, Geo g, ThermoK<R> th,
+                                                     unsigned *status) {
+    constexpr int NV = NS + 4;
+    __shared__ R sF[NV][kXBlock];
+    const int t = threadIdx.x;
+    const long long nfx = (long long)g.nx + 1;
+    const long long f = (long long)blockIdx.x * (kXBlock - 1) + t;
+    const long long nfaces = nfx * g.ny * g.nz;
+    const bool valid = f < nfaces;
+    long long row = 0;
+    int i = 0;
+    R F[NV];
+    unsigned flags = 0;
+    long long rowbase = 0;
+    if (valid) {
+        row = f / nfx;
+        i = (int)(f - row * nfx);
+        const int j = (int)(row % g.ny), k = (int)(row / g.ny);
+        rowbase = (long long)(g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + g.gx;
+        Stencil st{U, P, rowbase + i - 3, 1, g.cells};
+        face_flux<NS, R, 0>(st, th, F, flags);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) sF[q][t] = F[q];
+    }
+    __syncthreads();
+    if (valid && t > 0 && i > 0) {
+        const R id = R(g.idx);
+        const long long cell = rowbase + i - 1;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) rhs[q * g.cells + cell] = double((sF[q][t - 1] - F[q]) * id);
+    }
+    if (flags) atomicOr(status, flags);
+}
+
+// ---------------------------------------------------------------------------
+// y/z sweeps: lanes run along x (coalesced), each thread marches one column
+// through a segment of the sweep axis, computing faces j-1/2 for
+// j = j0..j1 and updating cells j0..j1-1 with the previous face's flux held in
+// registers.  Segments are disjoint, so every cell is written by one thread.
+// ---------------------------------------------------------------------------
+template <int NS, typename R, int DIR>
+__global__ __launch_bounds__(256) void k_sweep_march(const double *__restrict__ U, const double *__restrict__ P,
+                                                     double *__restrict__ rhs, Geo g, ThermoK<R> th,
+                                                     int seglen, int accumulate, unsigned *status) {
+    constexpr int NV = NS + 4;
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int tr = blockIdx.y * 4 + threadIdx.y;
+    const int ntr = (DIR == 1) ? g.nz : g.ny;
+    const int nsw = (DIR == 1) ? g.ny : g.nz;
+    if (x >= g.nx || tr >= ntr) return;
+    const int j0 = blockIdx.z * seglen;
+    if (j0 >= nsw) return;
+    const int j1 = min(j0 + seglen, nsw);
+    const long long step = (DIR == 1) ? g.sy : g.sz;
+    const int gs = (DIR == 1) ? g.gy : g.gz;
+    const long long col = (long long)(g.gx + x) +
+                          ((DIR == 1) ? (long long)(g.gz + tr) * g.sz : (long long)(g.gy + tr) * g.sy);
+    const R id = R((DIR == 1) ? g.idy : g.idz);
+    R Fp[NV], F[NV];
+    unsigned flags = 0;
+    for (int j = j0; j <= j1; ++j) {
+        Stencil st{U, P, col + (long long)(gs + j - 3) * step, step, g.cells};
+        face_flux<NS, R, DIR>(st, th, F, flags);
+        if (j > j0) {
+            const long long cell = col + (long long)(gs + j - 1) * step;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                const double d = double((Fp[q] - F[q]) * id);
+                double *o = rhs + q * g.cells + cell;
+                *o = accumulate ? *o + d : d;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Fp[q] = F[q];
+    }
+    if (flags) atomicOr(status, flags);
+}
+
+// ---------------------------------------------------------------------------
+// CFL: max over interior cells of sum_d (|u_d| + c) / dx_d; positive doubles
+// order like their bit patterns, so the max is one 64-bit atomicMax per wave.
+// ---------------------------------------------------------------------------
+template <int NS>
+__global__ __launch_bounds__(256) void k_cfl(const double *__restrict__ U, const double *__restrict__ P, Geo g,
+                                             unsigned long long *mx) {
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (q < n) {
+        const int i = (int)(q % g.nx);
+        const long long r = q / g.nx;
+        const int j = (int)(r % g.ny), k = (int)(r / g.ny);
+        const long long idx = (long long)(g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + (g.gx + i);
+        const double rinv = P[3 * g.cells + idx], c = P[2 * g.cells + idx];
+        if (g.nx > 1) s += (fabs(U[NS * g.cells + idx] * rinv) + c) * g.idx;
+        if (g.ny > 1) s += (fabs(U[(NS + 1) * g.cells + idx] * rinv) + c) * g.idy;
+        if (g.nz > 1) s += (fabs(U[(NS + 2) * g.cells + idx] * rinv) + c) * g.idz;
+        if (!(s >= 0.0)) s = 0.0;   // NaN never wins the max (it is flagged by k_prims)
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s = fmax(s, __shfl_xor(s, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(mx, (unsigned long long)__double_as_longlong(s));
+}
+
+}  // namespace xf

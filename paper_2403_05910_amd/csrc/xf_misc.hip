@@ -1,0 +1,251 @@
+// xf_misc.hip -- species-independent kernels: boundary ghosts and their
+// adjoint, ghost zeroing, SSP-RK3 stage combinations (Eq. 16) and their
+// adjoint, CFL finish, copies.
+#include "xf_common.hpp"
+
+namespace xf {
+namespace {
+
+unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// Ghost layers of direction d: one thread per (field, other two padded
+// coordinates), both sides and all three layers in that thread.  The other
+// two coordinates are enumerated with the faster one first so that y and z
+// fills are coalesced along x.
+__device__ __forceinline__ void ghost_geometry(const Geo &g, int d, long long o, long long &base, long long &step,
+                                               int &n) {
+    if (d == 0) {
+        const long long y = o % g.py, z = o / g.py;
+        base = z * g.sz + y * g.sy;
+        step = 1;
+        n = g.nx;
+    } else if (d == 1) {
+        const long long x = o % g.px, z = o / g.px;
+        base = z * g.sz + x;
+        step = g.sy;
+        n = g.ny;
+    } else {
+        const long long x = o % g.px, y = o / g.px;
+        base = y * g.sy + x;
+        step = g.sz;
+        n = g.nz;
+    }
+}
+
+__device__ __forceinline__ long long others(const Geo &g, int d) {
+    return d == 0 ? (long long)g.py * g.pz : (d == 1 ? (long long)g.px * g.pz : (long long)g.px * g.py);
+}
+
+// padded source index of ghost layer l on side sd (0 low, 1 high), n interior
+__device__ __forceinline__ int ghost_src(int bc, int sd, int l, int n) {
+    if (sd == 0) return bc == XF_BC_PERIODIC ? n + l : 3;
+    return bc == XF_BC_PERIODIC ? 3 + l : 3 + n - 1;
+}
+__device__ __forceinline__ int ghost_dst(int sd, int l, int n) { return sd == 0 ? l : 3 + n + l; }
+
+__global__ __launch_bounds__(256) void k_fill(double *U, Geo g, int nv, int d) {
+    const long long no = others(g, d);
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= no * nv) return;
+    const long long f = q / no, o = q - f * no;
+    long long base, step;
+    int n;
+    ghost_geometry(g, d, o, base, step, n);
+    double *u = U + f * g.cells + base;
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+        const int bc = g.bc[2 * d + sd];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) u[ghost_dst(sd, l, n) * step] = u[ghost_src(bc, sd, l, n) * step];
+    }
+}
+
+// Adjoint of k_fill: every ghost cotangent is added to its source and zeroed,
+// in the reverse order of the forward copies.
+__global__ __launch_bounds__(256) void k_fill_vjp(double *Ub, Geo g, int nv, int d) {
+    const long long no = others(g, d);
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= no * nv) return;
+    const long long f = q / no, o = q - f * no;
+    long long base, step;
+    int n;
+    ghost_geometry(g, d, o, base, step, n);
+    double *u = Ub + f * g.cells + base;
+#pragma unroll
+    for (int sd = 1; sd >= 0; --sd) {
+        const int bc = g.bc[2 * d + sd];
+#pragma unroll
+        for (int l = 2; l >= 0; --l) {
+            const long long dst = ghost_dst(sd, l, n) * step;
+            const double v = u[dst];
+            u[dst] = 0.0;
+            u[ghost_src(bc, sd, l, n) * step] += v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zero_ghosts(double *A, Geo g, int nv) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= g.cells * nv) return;
+    const long long idx = q % g.cells;
+    const int x = (int)(idx % g.px);
+    const long long r = idx / g.px;
+    const int y = (int)(r % g.py), z = (int)(r / g.py);
+    const bool ghost = x < g.gx || x >= g.gx + g.nx || y < g.gy || y >= g.gy + g.ny || z < g.gz ||
+                       z >= g.gz + g.nz;
+    if (ghost) A[q] = 0.0;
+}
+
+// Stage k of Eq. 16 over the whole padded state (ghosts are refilled before
+// the next use):  1: U0 = U, U = U + dt L;  2: U = 3/4 U0 + 1/4 (U + dt L);
+// 3: U = 1/3 U0 + 2/3 (U + dt L).
+__global__ __launch_bounds__(256) void k_rk3_stage(double *U, double *U0, const double *L, long long n, int stage,
+                                                   double dt, const double *dt_dev) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const double h = dt_dev ? *dt_dev : dt;
+    const double u = U[q];
+    const double v = u + h * L[q];
+    if (stage == 1) {
+        U0[q] = u;
+        U[q] = v;
+    } else if (stage == 2) {
+        U[q] = 0.75 * U0[q] + 0.25 * v;
+    } else {
+        U[q] = U0[q] / 3.0 + 2.0 / 3.0 * v;
+    }
+}
+
+// y = a x + b y (b == 0 ignores the old y, so y may hold anything)
+__global__ __launch_bounds__(256) void k_axpby(long long n, double a, const double *x, double b, double *y) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    y[q] = b == 0.0 ? a * x[q] : a * x[q] + b * y[q];
+}
+
+// Adjoint of one stage given the stage cotangent lam (of the stage output)
+// and mu = J(V)^T lam (the rhs-VJP at that stage's input V):
+//   stage 3 (U = 1/3 V0 + 2/3 (V2 + dt L(V2))): lam0 = lam/3;      lam = 2/3 (lam + dt mu)
+//   stage 2 (U = 3/4 V0 + 1/4 (V1 + dt L(V1))): lam0 += 3/4 lam;   lam = 1/4 (lam + dt mu)
+//   stage 1 (U = V0 + dt L(V0)):                lam0 += lam + dt mu
+__global__ __launch_bounds__(256) void k_rk3_stage_vjp(double *lam, double *lam0, const double *mu, long long n,
+                                                       int stage, double dt, const double *dt_dev) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const double h = dt_dev ? *dt_dev : dt;
+    const double l = lam[q];
+    if (stage == 3) {
+        lam0[q] = l / 3.0;
+        lam[q] = 2.0 / 3.0 * (l + h * mu[q]);
+    } else if (stage == 2) {
+        lam0[q] += 0.75 * l;
+        lam[q] = 0.25 * (l + h * mu[q]);
+    } else {
+        lam0[q] += l + h * mu[q];
+    }
+}
+
+__global__ void k_cfl_reset(unsigned long long *mx) { *mx = 0ull; }
+
+__global__ void k_cfl_finish(const unsigned long long *mx, double cfl, double *dt) {
+    *dt = cfl / __longlong_as_double((long long)*mx);
+}
+
+__global__ __launch_bounds__(256) void k_copy(long long n, const double *src, double *dst) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) dst[q] = src[q];
+}
+
+__global__ __launch_bounds__(256) void k_zero(long long n, double *dst) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) dst[q] = 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_fill_ghosts(const LaunchCtx &c, int nv, double *U, hipStream_t s) {
+    const Geo &g = c.g;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    for (int d = 0; d < 3; ++d) {
+        if (n[d] <= 1) continue;
+        const long long no = d == 0 ? (long long)g.py * g.pz : (d == 1 ? (long long)g.px * g.pz : (long long)g.px * g.py);
+        hipLaunchKernelGGL(k_fill, dim3(blocks_for(no * nv, 256)), dim3(256), 0, s, U, g, nv, d);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_fill_ghosts_vjp(const LaunchCtx &c, int nv, double *Ub, hipStream_t s) {
+    const Geo &g = c.g;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    for (int d = 2; d >= 0; --d) {
+        if (n[d] <= 1) continue;
+        const long long no = d == 0 ? (long long)g.py * g.pz : (d == 1 ? (long long)g.px * g.pz : (long long)g.px * g.py);
+        hipLaunchKernelGGL(k_fill_vjp, dim3(blocks_for(no * nv, 256)), dim3(256), 0, s, Ub, g, nv, d);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_zero_ghosts(const LaunchCtx &c, int nv, double *A, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_ghosts, dim3(blocks_for(c.g.cells * nv, 256)), dim3(256), 0, s, A, c.g, nv);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk3_stage(const LaunchCtx &c, int nv, int stage, double *U, double *U0, const double *L,
+                            double dt, const double *dt_dev, hipStream_t s) {
+    const long long n = c.g.cells * nv;
+    hipLaunchKernelGGL(k_rk3_stage, dim3(blocks_for(n, 256)), dim3(256), 0, s, U, U0, L, n, stage, dt, dt_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk3_stage_vjp(const LaunchCtx &c, int nv, int stage, double *lam, double *lam0, double *mu,
+                                const double *dt_dev, double dt, hipStream_t s) {
+    const long long n = c.g.cells * nv;
+    hipLaunchKernelGGL(k_rk3_stage_vjp, dim3(blocks_for(n, 256)), dim3(256), 0, s, lam, lam0, mu, n, stage, dt,
+                       dt_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_state(long long n, double a, const double *x, double b, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpby, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, a, x, b, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_cfl_reset(unsigned long long *mx, hipStream_t s) {
+    hipLaunchKernelGGL(k_cfl_reset, dim3(1), dim3(1), 0, s, mx);
+    return hipGetLastError();
+}
+
+hipError_t launch_cfl_finish(const unsigned long long *mx, double cfl, double *dt_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_cfl_finish, dim3(1), dim3(1), 0, s, mx, cfl, dt_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(long long n, const double *src, double *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(long long n, double *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, dst);
+    return hipGetLastError();
+}
+
+void march_shape(const Geo &g, int dir, int *nseg, int *seglen) {
+    // enough waves to fill 256 CUs several times over, segments of >= 8 cells
+    const int nsw = dir == 1 ? g.ny : g.nz;
+    const int ntr = dir == 1 ? g.nz : g.ny;
+    const long long waves_per_seg = (long long)((g.nx + 63) / 64) * ntr;
+    long long segs = (8192 + waves_per_seg - 1) / waves_per_seg;
+    long long maxsegs = nsw / 8 > 0 ? nsw / 8 : 1;
+    if (segs > maxsegs) segs = maxsegs;
+    if (segs < 1) segs = 1;
+    int L = (int)((nsw + segs - 1) / segs);
+    *seglen = L;
+    *nseg = (nsw + L - 1) / L;
+}
+
+}  // namespace xf

@@ -1,0 +1,138 @@
+// xf_ns.hip -- launchers of the species-templated kernels for one species
+// count.  Compiled once per N with -DXF_NS=N; each object exports
+// xf::ops_ns<N>(), which the C ABI collects into its dispatch table.
+#include "xf_forward.hpp"
+#include "xf_vjp.hpp"
+
+#ifndef XF_NS
+#error "compile with -DXF_NS=<species count>"
+#endif
+
+namespace xf {
+namespace {
+
+constexpr int NS = XF_NS;
+
+unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t prims(const LaunchCtx &c, const double *U, double *P, hipStream_t s) {
+    hipLaunchKernelGGL(k_prims<NS>, dim3(blocks_for(c.g.cells, 256)), dim3(256), 0, s, U, P, c.g, c.th64,
+                       c.status);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumulate, const double *U,
+                   const double *P, double *rhs, hipStream_t s) {
+    const Geo &g = c.g;
+    if (dir == 0) {
+        const long long nf = (long long)(g.nx + 1) * g.ny * g.nz;
+        const unsigned nb = (unsigned)((nf - 1 + (kXBlock - 2)) / (kXBlock - 1));   // blocks overlap by one face
+        hipLaunchKernelGGL((k_sweep_x<NS, R>), dim3(nb), dim3(kXBlock), 0, s, U, P, rhs, g, th, c.status);
+        return hipGetLastError();
+    }
+    int nseg, seglen;
+    march_shape(g, dir, &nseg, &seglen);
+    const int ntr = dir == 1 ? g.nz : g.ny;
+    dim3 grid((g.nx + 63) / 64, (ntr + 3) / 4, nseg), block(64, 4);
+    if (dir == 1)
+        hipLaunchKernelGGL((k_sweep_march<NS, R, 1>), grid, block, 0, s, U, P, rhs, g, th, seglen, accumulate,
+                           c.status);
+    else
+        hipLaunchKernelGGL((k_sweep_march<NS, R, 2>), grid, block, 0, s, U, P, rhs, g, th, seglen, accumulate,
+                           c.status);
+    return hipGetLastError();
+}
+
+hipError_t sweep(const LaunchCtx &c, int dir, int accumulate, const double *U, const double *P, double *rhs,
+                 hipStream_t s) {
+    if (c.precision == XF_PREC_MIXED) return sweep_t<float>(c, c.th32, dir, accumulate, U, P, rhs, s);
+    return sweep_t<double>(c, c.th64, dir, accumulate, U, P, rhs, s);
+}
+
+MarchGeo march_geo(const Geo &g, int dir) {
+    MarchGeo m;
+    m.origin = (long long)g.gz * g.sz + (long long)g.gy * g.sy + g.gx;
+    if (dir == 0) {
+        m.sl = g.sy; m.nl = g.ny;
+        m.st = g.sz; m.nt = g.nz;
+        m.ss = 1;    m.nsw = g.nx;
+    } else if (dir == 1) {
+        m.sl = 1;    m.nl = g.nx;
+        m.st = g.sz; m.nt = g.nz;
+        m.ss = g.sy; m.nsw = g.ny;
+    } else {
+        m.sl = 1;    m.nl = g.nx;
+        m.st = g.sy; m.nt = g.ny;
+        m.ss = g.sz; m.nsw = g.nz;
+    }
+    return m;
+}
+
+template <typename R>
+hipError_t sweep_vjp_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, const double *U, const double *P,
+                       const double *rbar, double *Ubar, double *Pbar, hipStream_t s) {
+    const Geo &g = c.g;
+    const MarchGeo mg = march_geo(g, dir);
+    const double id = dir == 0 ? g.idx : (dir == 1 ? g.idy : g.idz);
+    // segments of at least 8 faces (two segments a column apart never touch
+    // the same cell); enough of them to fill the chip
+    const long long cols = (long long)mg.nl * mg.nt;
+    const int nfaces = mg.nsw + 1;
+    int seglen = nfaces;
+    const long long want = 16384;   // threads in flight per launch
+    if (cols < want) {
+        const long long segs = (want + cols - 1) / cols;
+        seglen = (int)((nfaces + segs - 1) / segs);
+        if (seglen < 8) seglen = 8;
+    }
+    const int nseg = (nfaces + seglen - 1) / seglen;
+    dim3 grid((mg.nl + 63) / 64, (mg.nt + 3) / 4, (nseg + 1) / 2), block(64, 4);
+    for (int parity = 0; parity < 2; ++parity) {
+        if (dir == 0)
+            hipLaunchKernelGGL((k_sweep_vjp<NS, R, 0>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, g.cells, mg,
+                               th, id, seglen, parity);
+        else if (dir == 1)
+            hipLaunchKernelGGL((k_sweep_vjp<NS, R, 1>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, g.cells, mg,
+                               th, id, seglen, parity);
+        else
+            hipLaunchKernelGGL((k_sweep_vjp<NS, R, 2>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, g.cells, mg,
+                               th, id, seglen, parity);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t sweep_vjp(const LaunchCtx &c, int dir, const double *U, const double *P, const double *rbar,
+                     double *Ubar, double *Pbar, hipStream_t s) {
+    if (c.precision == XF_PREC_MIXED) return sweep_vjp_t<float>(c, c.th32, dir, U, P, rbar, Ubar, Pbar, s);
+    return sweep_vjp_t<double>(c, c.th64, dir, U, P, rbar, Ubar, Pbar, s);
+}
+
+hipError_t prims_vjp(const LaunchCtx &c, const double *U, const double *P, const double *Pbar, double *Ubar,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_prims_vjp<NS>, dim3(blocks_for(c.g.cells, 256)), dim3(256), 0, s, U, P, Pbar, Ubar, c.g,
+                       c.th64);
+    return hipGetLastError();
+}
+
+hipError_t cfl(const LaunchCtx &c, const double *U, const double *P, unsigned long long *mx, hipStream_t s) {
+    const long long n = (long long)c.g.nx * c.g.ny * c.g.nz;
+    hipLaunchKernelGGL(k_cfl<NS>, dim3(blocks_for(n, 256)), dim3(256), 0, s, U, P, c.g, mx);
+    return hipGetLastError();
+}
+
+const NsOps kOps = {prims, sweep, sweep_vjp, prims_vjp, cfl};
+
+}  // namespace
+
+template <int N>
+const NsOps *ops_ns();
+
+template <>
+const NsOps *ops_ns<NS>() {
+    return &kOps;
+}
+
+}  // namespace xf

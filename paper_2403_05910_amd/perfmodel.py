@@ -1,0 +1,68 @@
+"""Algorithmic work of the convective right-hand side, for roofline figures.
+
+Flops are those of the algorithm as implemented (rank-structured projections,
+one-division WENO5-JS), counted as 1 per add, subtract, multiply, divide,
+square root, abs or max (a fused multiply-add counts 2).  Bytes are the
+algorithmic HBM traffic: every input read once, every output written once.
+
+Per face of one direction, N species (count of the operations in the face
+routine, step by step):
+  Roe state and thermo at the averaged T          34 N +  36
+  per-cell projection scalars and LLF speeds       18 N + 180
+  acoustic pair (splitting 150, 4 WENO 276, sums 4)        430
+  tangential pair (splitting 96, 4 WENO 276, sums 2)       374
+  species fields (splitting 60, 2 WENO 138, rest 8) 206 N
+  1 / Gamma and back-projection of momentum and energy      18
+  -> F(N) = 258 N + 1038 flops per face   (one WENO5-JS = 69 flops)
+plus the flux difference 2 (N + 4) per cell and direction.
+"""
+
+WENO_FLOPS = 69
+
+
+def face_flops(ns):
+    return 258 * ns + 1038
+
+
+def sweep_flops_per_cell(ns):
+    """one direction: one face (the cell's left face; the extra face per row
+    is counted in `sweep_flops`) plus the flux difference of N + 4 fields"""
+    return face_flops(ns) + 2 * (ns + 4)
+
+
+def sweep_flops(ns, n, direction):
+    """flops of one sweep launch over a grid n = (nx, ny, nz)"""
+    nx, ny, nz = n
+    cells = nx * ny * nz
+    faces = cells + cells // n[direction]
+    return faces * face_flops(ns) + cells * 2 * (ns + 4)
+
+
+def rhs_flops_per_cell(ns, active=3):
+    return active * sweep_flops_per_cell(ns)
+
+
+def rhs_bytes_per_cell(ns):
+    """read U, write rhs (FP64, N + 4 fields)"""
+    return 16 * (ns + 4)
+
+
+def sweep_bytes_per_cell(ns, first):
+    """a sweep reads U (N + 4 fields) and the primitives T, p, c, 1/rho and
+    writes rhs (the first sweep) or reads and writes it (the others)"""
+    nv = ns + 4
+    return 8 * (nv + 4) + (8 * nv if first else 16 * nv)
+
+
+def rk3_step_bytes_per_cell(ns):
+    """one fused-free RK3 step, algorithmic: 3 x (RHS read U + write L) plus
+    3 stage updates (read U^n, U^(k-1), L; write U^(k))"""
+    nv = ns + 4
+    return 3 * 16 * nv + 3 * 32 * nv
+
+
+PEAK = {
+    "hbm_GBs": 8000.0,
+    "fp64_vector_TFLOPs": 78.6,
+    "fp32_vector_TFLOPs": 157.3,
+}

@@ -248,12 +248,14 @@ def _bubble_phi(X, Y, Z, centre, r0, width, radius_fn=None):
     (the interface function of Eq. 32, with the interface about two cells wide)."""
     dx, dy, dz = X - centre[0], Y - centre[1], Z - centre[2]
     rr = np.sqrt(dx * dx + dy * dy + dz * dz)
-    if radius_fn is None:
-        r = r0
-    else:
-        theta = np.arccos(np.clip(dz / np.maximum(rr, 1e-300), -1.0, 1.0))
-        phi = np.mod(np.arctan2(dy, dx), 2 * np.pi)
-        r = r0 * radius_fn(theta, phi)
+    r = np.full(rr.shape, float(r0))
+    if radius_fn is not None:
+        # the perturbed radius matters only near the interface: beyond 16
+        # interface widths tanh has saturated to within 2e-14
+        near = np.abs(rr - r0) < 16.0 * width
+        theta = np.arccos(np.clip(dz[near] / np.maximum(rr[near], 1e-300), -1.0, 1.0))
+        phi = np.mod(np.arctan2(dy[near], dx[near]), 2 * np.pi)
+        r[near] = r0 * radius_fn(theta, phi)
     return 0.5 * (1.0 - np.tanh((rr - r) / width))
 
 

@@ -1,0 +1,386 @@
+"""Python binding of libxf.so (include/xf.h).
+
+The functions named xf_* mirror the C ABI one to one and only marshal
+arguments (raw device pointers, sizes, the stream).  `Context` wraps a context
+and its workspaces for torch tensors; `rhs` is a torch.autograd.Function whose
+backward calls xf_rhs_vjp; `rollout` runs SSP-RK3 steps with checkpoints and
+differentiates them with xf_rk3_step_vjp.  Every arithmetic step runs in the
+library's HIP kernels; torch provides device memory and the current stream.
+If libxf.so is missing this module raises on import: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxf.so")
+
+XF_OK, XF_EINVAL, XF_EDEVICE, XF_ENOMEM, XF_ENONPHYS, XF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+XF_BC_PERIODIC, XF_BC_OUTFLOW = 0, 1
+XF_PREC_FP64, XF_PREC_MIXED = 0, 1
+XF_OP_RHS, XF_OP_RK3, XF_OP_VJP, XF_OP_RK3_VJP = 0, 1, 2, 3
+FLAGS = {1: "rho<=0", 2: "Y<0", 4: "p<=0 or T<=0", 8: "T out of range", 16: "Newton not converged",
+         32: "Roe c^2<=0", 64: "NaN/Inf"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2403_05910_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_c_int, _c_double, _c_size_t, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class xf_grid(ctypes.Structure):
+    _fields_ = [("nx", _c_int), ("ny", _c_int), ("nz", _c_int),
+                ("dx", _c_double), ("dy", _c_double), ("dz", _c_double),
+                ("bc", _c_int * 6)]
+
+
+class xf_thermo(ctypes.Structure):
+    _fields_ = [("ns", _c_int), ("W", _dp), ("a", _dp), ("T_lo", _c_double), ("T_hi", _c_double)]
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_create = _sig("xf_create", _c_int, ctypes.POINTER(xf_grid), ctypes.POINTER(xf_thermo), _c_int, ctypes.POINTER(_vp))
+_destroy = _sig("xf_destroy", _c_int, _vp)
+_state_elems = _sig("xf_state_elems", _c_size_t, _vp)
+_ws_bytes = _sig("xf_workspace_bytes", _c_size_t, _vp, _c_int)
+_fill = _sig("xf_fill_ghosts", _c_int, _vp, _vp, _vp)
+_fill_vjp = _sig("xf_fill_ghosts_vjp", _c_int, _vp, _vp, _vp)
+_rhs = _sig("xf_rhs", _c_int, _vp, _vp, _vp, _vp, _vp)
+_cfl = _sig("xf_cfl_dt", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
+_rk3 = _sig("xf_rk3_step", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
+_rhs_vjp = _sig("xf_rhs_vjp", _c_int, _vp, _vp, _vp, _vp, _vp, _vp)
+_rk3_vjp = _sig("xf_rk3_step_vjp", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
+_status = _sig("xf_status", _c_int, _vp, _vp, ctypes.POINTER(ctypes.c_uint))
+_timing = _sig("xf_timing", _c_int, _vp, _c_int)
+_timing_read = _sig("xf_timing_read", _c_int, _vp, _vp, _dp, ctypes.POINTER(ctypes.c_longlong))
+_strerror = _sig("xf_strerror", ctypes.c_char_p, _c_int)
+
+EXPORTED = ["xf_create", "xf_destroy", "xf_state_elems", "xf_workspace_bytes", "xf_fill_ghosts",
+            "xf_fill_ghosts_vjp", "xf_rhs", "xf_cfl_dt", "xf_rk3_step", "xf_rhs_vjp", "xf_rk3_step_vjp",
+            "xf_status", "xf_strerror", "xf_timing", "xf_timing_read"]
+KERNEL_CLASSES = ["prims", "sweep_x", "sweep_y", "sweep_z", "fill", "stage", "cfl", "zero",
+                  "vjp_x", "vjp_y", "vjp_z", "prims_vjp", "fill_vjp"]
+
+
+class XfError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {xf_strerror(code)} ({code})")
+        self.code = code
+
+
+def _check(code, what):
+    if code != XF_OK:
+        raise XfError(code, what)
+    return code
+
+
+# ---------------------------------------------------------------------------
+# one-to-one wrappers of the C ABI (pointers are ints; streams are ints)
+# ---------------------------------------------------------------------------
+def xf_strerror(code):
+    return _strerror(code).decode()
+
+
+def xf_create(grid: xf_grid, thermo: xf_thermo, precision: int):
+    h = _vp()
+    _check(_create(ctypes.byref(grid), ctypes.byref(thermo), precision, ctypes.byref(h)), "xf_create")
+    return h.value
+
+
+def xf_destroy(ctx):
+    return _check(_destroy(ctx), "xf_destroy")
+
+
+def xf_state_elems(ctx):
+    return int(_state_elems(ctx))
+
+
+def xf_workspace_bytes(ctx, op):
+    return int(_ws_bytes(ctx, op))
+
+
+def xf_fill_ghosts(ctx, U, stream):
+    return _check(_fill(ctx, U, stream), "xf_fill_ghosts")
+
+
+def xf_fill_ghosts_vjp(ctx, Ubar, stream):
+    return _check(_fill_vjp(ctx, Ubar, stream), "xf_fill_ghosts_vjp")
+
+
+def xf_rhs(ctx, U, rhs, ws, stream):
+    return _check(_rhs(ctx, U, rhs, ws, stream), "xf_rhs")
+
+
+def xf_cfl_dt(ctx, U, cfl, dt_dev, ws, stream):
+    return _check(_cfl(ctx, U, cfl, dt_dev, ws, stream), "xf_cfl_dt")
+
+
+def xf_rk3_step(ctx, U, dt, dt_dev, ws, stream):
+    return _check(_rk3(ctx, U, dt, dt_dev, ws, stream), "xf_rk3_step")
+
+
+def xf_rhs_vjp(ctx, U, rhs_bar, U_bar, ws, stream):
+    return _check(_rhs_vjp(ctx, U, rhs_bar, U_bar, ws, stream), "xf_rhs_vjp")
+
+
+def xf_rk3_step_vjp(ctx, U_n, dt, U_bar, ws, stream):
+    return _check(_rk3_vjp(ctx, U_n, dt, U_bar, ws, stream), "xf_rk3_step_vjp")
+
+
+def xf_timing(ctx, enable):
+    return _check(_timing(ctx, int(bool(enable))), "xf_timing")
+
+
+def xf_timing_read(ctx, stream):
+    """{class name: (total ms, launches)} of the launches since the last read"""
+    n = len(KERNEL_CLASSES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_longlong * n)()
+    _check(_timing_read(ctx, stream, ms, cnt), "xf_timing_read")
+    return {KERNEL_CLASSES[k]: (ms[k], cnt[k]) for k in range(n)}
+
+
+def xf_status(ctx, stream):
+    """returns (code, flags); code is XF_ENONPHYS when flags != 0"""
+    f = ctypes.c_uint(0)
+    code = _status(ctx, stream, ctypes.byref(f))
+    if code not in (XF_OK, XF_ENONPHYS):
+        raise XfError(code, "xf_status")
+    return code, int(f.value)
+
+
+# ---------------------------------------------------------------------------
+# torch-facing context
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    """A libxf context on the current torch device plus its workspaces.
+
+    n = (nx, ny, nz), d = (dx, dy, dz), bc = 6 ints (-x,+x,-y,+y,-z,+z),
+    W (ns,) kg/mol, a (ns, 6) thermo coefficients, [T_lo, T_hi] Newton bracket
+    (T_hi <= 0: none), precision "fp64" or "mixed".
+    """
+
+    def __init__(self, n, d, bc, W, a, T_lo=0.0, T_hi=0.0, precision="fp64"):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libxf needs a HIP device")
+        self.n = tuple(int(v) for v in n)
+        self.d = tuple(float(v) for v in d)
+        self.bc = tuple(int(v) for v in bc)
+        self.W = np.ascontiguousarray(W, dtype=np.float64)
+        self.a = np.ascontiguousarray(a, dtype=np.float64).reshape(len(self.W), 6)
+        self.ns = len(self.W)
+        self.nv = self.ns + 4
+        self.precision = precision
+        g = [3 if k > 1 else 0 for k in self.n]
+        self.shape = (self.nv, self.n[2] + 2 * g[2], self.n[1] + 2 * g[1], self.n[0] + 2 * g[0])
+        self.interior = (slice(None), slice(g[2], g[2] + self.n[2]), slice(g[1], g[1] + self.n[1]),
+                         slice(g[0], g[0] + self.n[0]))
+        grid = xf_grid(self.n[0], self.n[1], self.n[2], self.d[0], self.d[1], self.d[2], (_c_int * 6)(*self.bc))
+        th = xf_thermo(self.ns, self.W.ctypes.data_as(_dp), self.a.ctypes.data_as(_dp), float(T_lo), float(T_hi))
+        prec = {"fp64": XF_PREC_FP64, "mixed": XF_PREC_MIXED}[precision]
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.handle = xf_create(grid, th, prec)
+        assert xf_state_elems(self.handle) == int(np.prod(self.shape))
+        self._ws = {}
+
+    @classmethod
+    def from_case(cls, case, precision="fp64"):
+        t = case.thermo
+        return cls(case.n, case.d, case.bc, t.W, t.a, t.T_lo, t.T_hi, precision)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            xf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- buffers --------------------------------------------------------
+    def workspace(self, op):
+        torch = _torch()
+        if op not in self._ws:
+            nb = xf_workspace_bytes(self.handle, op)
+            self._ws[op] = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        return self._ws[op].data_ptr()
+
+    def new_state(self):
+        torch = _torch()
+        return torch.zeros(self.shape, dtype=torch.float64, device=self.device)
+
+    def state_from_numpy(self, U):
+        torch = _torch()
+        assert tuple(U.shape) == self.shape, (U.shape, self.shape)
+        return torch.from_numpy(np.ascontiguousarray(U, dtype=np.float64)).to(self.device)
+
+    def _ptr(self, t):
+        torch = _torch()
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == self.shape):
+            raise ValueError(f"expected a contiguous float64 device tensor of shape {self.shape}")
+        return t.data_ptr()
+
+    @staticmethod
+    def _stream():
+        return _torch().cuda.current_stream().cuda_stream
+
+    # -- operations -----------------------------------------------------
+    def fill_ghosts(self, U):
+        xf_fill_ghosts(self.handle, self._ptr(U), self._stream())
+        return U
+
+    def fill_ghosts_vjp(self, Ubar):
+        xf_fill_ghosts_vjp(self.handle, self._ptr(Ubar), self._stream())
+        return Ubar
+
+    def rhs(self, U, out=None):
+        out = self.new_state() if out is None else out
+        xf_rhs(self.handle, self._ptr(U), self._ptr(out), self.workspace(XF_OP_RHS), self._stream())
+        return out
+
+    def cfl_dt(self, U, cfl, out=None):
+        torch = _torch()
+        out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
+        xf_cfl_dt(self.handle, self._ptr(U), float(cfl), out.data_ptr(), self.workspace(XF_OP_RHS), self._stream())
+        return out
+
+    def rk3_step(self, U, dt):
+        """dt: a float, or a one-element float64 device tensor (no host round trip)"""
+        torch = _torch()
+        if isinstance(dt, torch.Tensor):
+            xf_rk3_step(self.handle, self._ptr(U), 0.0, dt.data_ptr(), self.workspace(XF_OP_RK3), self._stream())
+        else:
+            xf_rk3_step(self.handle, self._ptr(U), float(dt), None, self.workspace(XF_OP_RK3), self._stream())
+        return U
+
+    def rhs_vjp(self, U, rhs_bar, U_bar=None):
+        U_bar = self.new_state() if U_bar is None else U_bar
+        xf_rhs_vjp(self.handle, self._ptr(U), self._ptr(rhs_bar), self._ptr(U_bar), self.workspace(XF_OP_VJP),
+                   self._stream())
+        return U_bar
+
+    def rk3_step_vjp(self, U_n, dt, U_bar):
+        xf_rk3_step_vjp(self.handle, self._ptr(U_n), float(dt), self._ptr(U_bar), self.workspace(XF_OP_RK3_VJP),
+                        self._stream())
+        return U_bar
+
+    def timing(self, enable=True):
+        xf_timing(self.handle, enable)
+
+    def timing_read(self):
+        return xf_timing_read(self.handle, self._stream())
+
+    def status(self):
+        """synchronises; returns the accumulated non-physical-state bits (and clears them)"""
+        return xf_status(self.handle, self._stream())[1]
+
+
+# ---------------------------------------------------------------------------
+# autograd
+# ---------------------------------------------------------------------------
+def _make_functions():
+    torch = _torch()
+
+    class RhsFunction(torch.autograd.Function):
+        """L(G(U)): ghost fill then the right-hand side; backward is
+        G^T J^T (xf_rhs_vjp then xf_fill_ghosts_vjp), LLF speeds held fixed."""
+
+        @staticmethod
+        def forward(fctx, ctx, U):
+            V = U.detach().clone()
+            ctx.fill_ghosts(V)
+            out = ctx.rhs(V)
+            fctx.ctx = ctx
+            fctx.save_for_backward(V)
+            return out
+
+        @staticmethod
+        def backward(fctx, g):
+            (V,) = fctx.saved_tensors
+            ctx = fctx.ctx
+            Ub = ctx.rhs_vjp(V, g.contiguous())
+            ctx.fill_ghosts_vjp(Ub)
+            return None, Ub
+
+    class RolloutFunction(torch.autograd.Function):
+        """nsteps SSP-RK3 steps of fixed dt from U0; states are kept every
+        ckpt_every steps and the backward recomputes each segment from its
+        checkpoint, then runs xf_rk3_step_vjp step by step in reverse."""
+
+        @staticmethod
+        def forward(fctx, ctx, U0, dt, nsteps, ckpt_every):
+            U = U0.detach().clone()
+            ckpts = []
+            for k in range(nsteps):
+                if k % ckpt_every == 0:
+                    ckpts.append(U.clone())
+                ctx.rk3_step(U, dt)
+            fctx.ctx, fctx.dt, fctx.nsteps, fctx.every = ctx, dt, nsteps, ckpt_every
+            fctx.ckpts = ckpts
+            return U
+
+        @staticmethod
+        def backward(fctx, g):
+            ctx, dt, nsteps, every = fctx.ctx, fctx.dt, fctx.nsteps, fctx.every
+            lam = g.detach().clone().contiguous()
+            for seg in reversed(range(len(fctx.ckpts))):
+                k0 = seg * every
+                k1 = min(k0 + every, nsteps)
+                states = [fctx.ckpts[seg]]
+                for k in range(k0, k1 - 1):
+                    states.append(ctx.rk3_step(states[-1].clone(), dt))
+                for st in reversed(states):
+                    ctx.rk3_step_vjp(st, dt, lam)
+            fctx.ckpts = None
+            return None, lam, None, None, None
+
+    return RhsFunction, RolloutFunction
+
+
+_FUNCS = None
+
+
+def _funcs():
+    global _FUNCS
+    if _FUNCS is None:
+        _FUNCS = _make_functions()
+    return _FUNCS
+
+
+def rhs(ctx: Context, U):
+    """differentiable L(G(U)) for a padded state U (ghost values are replaced)"""
+    return _funcs()[0].apply(ctx, U)
+
+
+def rollout(ctx: Context, U0, dt, nsteps, ckpt_every=8):
+    """differentiable state after nsteps SSP-RK3 steps of fixed dt"""
+    return _funcs()[1].apply(ctx, U0, float(dt), int(nsteps), int(ckpt_every))
+
+
+def rollout_memory_bytes(ctx: Context, nsteps, ckpt_every):
+    """device memory of a checkpointed rollout and its backward: checkpoints,
+    one segment of step states, the rollout output/cotangent and the RK3 and
+    RK3-VJP workspaces"""
+    S = int(np.prod(ctx.shape)) * 8
+    C = (nsteps + ckpt_every - 1) // ckpt_every
+    return C * S + ckpt_every * S + 2 * S + xf_workspace_bytes(ctx.handle, XF_OP_RK3) + \
+        xf_workspace_bytes(ctx.handle, XF_OP_RK3_VJP)

@@ -1,0 +1,238 @@
+"""GPU parity of the forward path against the CPU oracle, through the C ABI.
+
+Bar: per field, max |rhs_gpu - rhs_oracle| <= 1e-12 S_f, S_f = max |F^_f| /
+min dx (the flux-divergence scale; plain relative error is meaningless where
+the residual vanishes, e.g. in a uniform region).  Copies (ghost fill) must be
+bit-exact.  Sizes span several x-sweep blocks (256 faces), ragged wavefronts
+(nx not a multiple of 64), single active axes, and every boundary type; the
+full-size shock-bubble states are checked on sampled cells.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from conftest import oracle_objects
+from paper_2403_05910_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+TOL = 1e-12
+
+
+def _xf():
+    from paper_2403_05910_amd import xf
+    return xf
+
+
+def gpu_rhs(case, precision="fp64"):
+    xf = _xf()
+    ctx = xf.Context.from_case(case, precision)
+    U = ctx.state_from_numpy(case.U)
+    ctx.fill_ghosts(U)
+    r = ctx.rhs(U)
+    flags = ctx.status()
+    out = r.cpu().numpy(), flags, U.cpu().numpy()
+    ctx.close()
+    return out
+
+
+def oracle_rhs(case):
+    th, g = oracle_objects(case)
+    U = O.fill_ghosts(g, case.U)
+    r, aux = O.rhs(th, g, U, return_aux=True)
+    return r, aux, U
+
+
+def field_err(a, b, scale):
+    """per-field max |a - b| / scale; a field with zero scale (a flux that
+    vanishes identically, e.g. transverse momentum in 1D) must match exactly"""
+    nv = a.shape[0]
+    e = np.abs(a - b).reshape(nv, -1).max(axis=1)
+    return np.where(scale > 0, e / np.where(scale > 0, scale, 1.0), np.where(e == 0, 0.0, np.inf))
+
+
+def _cases():
+    tp3 = W.sampled_table([2.0, 28.0, 40.0], 1)
+    tp9 = W.sampled_table(W.W9, 0)
+    tp1 = W.sampled_table([28.0], 4)
+    return {
+        "wave1d_600": W.wave_1d(600),
+        "sod_400": W.sod(400),
+        "ragged3d_n3_outflow_x": W.random_smooth_state(tp3, (37, 19, 11), seed=1, jump=True, bc=(1, 1, 0, 0, 0, 0)),
+        "n9_3d_mixed_bc": W.random_smooth_state(tp9, (24, 20, 18), seed=2, jump=True, bc=(1, 1, 0, 0, 1, 1)),
+        "n1_thermal_3d": W.random_smooth_state(tp1, (16, 12, 10), seed=3, jump=True),
+        "plane2d_n3": W.random_smooth_state(tp3, (70, 30, 1), seed=4, jump=True, bc=(1, 1, 0, 0, 0, 0)),
+        "y_only_n3": W.random_smooth_state(tp3, (1, 40, 1), seed=5, bc=(0, 0, 1, 1, 0, 0)),
+        "z_only_n3": W.random_smooth_state(tp3, (1, 1, 33), seed=6),
+        "yz_plane_n3": W.random_smooth_state(tp3, (1, 21, 17), seed=7, jump=False),
+        "periodic_mixture_24": W.periodic_mixture(24),
+        "inert_sbi_32": W.inert_sbi(32),
+        "nine_sbi_32": W.nine_species_sbi(32),
+    }
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_rhs_fp64_matches_oracle(name):
+    case = CASES[name]
+    print(f"[parity] {name} n={case.n} ns={case.thermo.ns}", flush=True)
+    r_gpu, flags, U_gpu = gpu_rhs(case)
+    r_ora, aux, U_ora = oracle_rhs(case)
+    assert np.array_equal(U_gpu, U_ora), "ghost fill must be an exact copy"
+    assert flags == aux["flags"] == 0
+    err = field_err(r_gpu, r_ora, aux["scale"])
+    print(f"[parity] {name} max err / S_f = {err.max():.3e}", flush=True)
+    assert err.max() <= TOL, err
+    # ghosts of the result are zero
+    iz, iy, ix = O.Grid(*case.n, *case.d, case.bc).interior()
+    mask = np.ones(r_gpu.shape[1:], dtype=bool)
+    mask[iz, iy, ix] = False
+    assert np.all(r_gpu[:, mask] == 0.0)
+
+
+def test_rhs_is_deterministic():
+    case = CASES["n9_3d_mixed_bc"]
+    a, _, _ = gpu_rhs(case)
+    b, _, _ = gpu_rhs(case)
+    assert np.array_equal(a, b)
+
+
+def test_freestream_exactly_zero_on_gpu():
+    tab = W.sampled_table(W.W9, 0)
+    case = W.random_smooth_state(tab, (20, 9, 7), seed=8, amp=0.0, u_scale=0.0)
+    # uniform: overwrite with one cell's state, add a uniform velocity
+    U = case.U.copy()
+    g = [3, 3, 3]
+    c = U[:, 3, 3, 3].copy()
+    c[9:12] = c[:9].sum() * np.array([31.0, -12.0, 7.0])
+    c[12] += 0.5 * (31.0 ** 2 + 12.0 ** 2 + 7.0 ** 2) * c[:9].sum()
+    U[:] = c[:, None, None, None]
+    case.U = U
+    r, flags, _ = gpu_rhs(case)
+    assert flags == 0
+    assert np.all(r == 0.0)
+
+
+@pytest.mark.parametrize("bc", [(0,) * 6, (1,) * 6, (1, 1, 0, 0, 1, 1)])
+def test_ghost_fill_bit_exact(bc):
+    xf = _xf()
+    tab = W.sampled_table([2.0, 28.0], 0)
+    case = W.random_smooth_state(tab, (13, 7, 5), seed=9, bc=bc)
+    rng = np.random.default_rng(0)
+    case.U = rng.standard_normal(case.U.shape)       # garbage everywhere, ghosts included
+    ctx = xf.Context.from_case(case)
+    U = ctx.state_from_numpy(case.U)
+    ctx.fill_ghosts(U)
+    th, g = oracle_objects(case)
+    assert np.array_equal(U.cpu().numpy(), O.fill_ghosts(g, case.U))
+
+
+def test_cfl_dt_matches_oracle():
+    xf = _xf()
+    case = CASES["nine_sbi_32"]
+    ctx = xf.Context.from_case(case)
+    U = ctx.state_from_numpy(case.U)
+    ctx.fill_ghosts(U)
+    dt = ctx.cfl_dt(U, 0.5).item()
+    th, g = oracle_objects(case)
+    ref = O.cfl_dt(th, g, O.fill_ghosts(g, case.U), 0.5)
+    assert abs(dt - ref) <= 1e-14 * ref
+
+
+@pytest.mark.parametrize("name,steps", [("inert_sbi_32", 5), ("wave1d_600", 10), ("n9_3d_mixed_bc", 3)])
+def test_rk3_steps_match_oracle(name, steps):
+    xf = _xf()
+    case = CASES[name]
+    th, g = oracle_objects(case)
+    Uo = O.fill_ghosts(g, case.U)
+    dt = 0.5 * O.cfl_dt(th, g, Uo, 0.5)
+    ctx = xf.Context.from_case(case)
+    U = ctx.state_from_numpy(case.U)
+    dt_dev = torch.tensor([dt], dtype=torch.float64, device=U.device)
+    for k in range(steps):
+        Uo = O.rk3_step(th, g, Uo, dt)
+        if k % 2:
+            ctx.rk3_step(U, dt)
+        else:
+            ctx.rk3_step(U, dt_dev)
+    assert ctx.status() == 0
+    Ug = U.cpu().numpy()
+    scale = np.abs(Uo).reshape(Uo.shape[0], -1).max(axis=1)
+    err = field_err(Ug, Uo, scale)
+    print(f"[parity] rk3 {name} {steps} steps max err {err.max():.3e}", flush=True)
+    assert err.max() <= 1e-12, err
+
+
+def test_status_flags_match_oracle():
+    xf = _xf()
+    tab = W.sampled_table([2.0, 28.0, 40.0], 1)
+    base = W.random_smooth_state(tab, (12, 10, 8), seed=10)
+    th, g = oracle_objects(base)
+    cases = []
+    U = base.U.copy()
+    U[0, 5, 6, 7] = -abs(U[0, 5, 6, 7]) - U[1:3, 5, 6, 7].sum() - 1e-3   # rho < 0
+    cases.append((U, O.FLAG_RHO))
+    U = base.U.copy()
+    U[4, 6, 6, 6] = np.nan
+    cases.append((U, O.FLAG_NAN))
+    U = base.U.copy()
+    U[-1, 7, 5, 4] *= 30.0                                                # T far above the bracket
+    cases.append((U, O.FLAG_TRANGE))
+    for U, bit in cases:
+        ctx = xf.Context.from_case(base)
+        Ut = ctx.state_from_numpy(U)
+        ctx.fill_ghosts(Ut)
+        ctx.rhs(Ut)
+        flags = ctx.status()
+        _, aux = O.rhs(th, g, O.fill_ghosts(g, U), return_aux=True)
+        assert flags & bit, (flags, bit)
+        assert flags & ~O.FLAG_C2 == aux["flags"] & ~O.FLAG_C2, (flags, aux["flags"])
+        assert ctx.status() == 0                 # reading clears the word
+
+
+def _sample_cells(case, n_random, seed):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = case.n
+    cells = [rng.integers(0, [nx, ny, nz]) for _ in range(n_random)]
+    # boundaries, corners and the shock / interface neighbourhoods
+    for x in (0, 1, 2, nx - 3, nx - 2, nx - 1, int(0.15 * nx), int(0.15 * nx) + 1, int(0.2 * nx), int(0.5 * nx)):
+        for y, z in ((0, 0), (ny - 1, nz - 1), (ny // 2, nz // 2), (rng.integers(ny), rng.integers(nz))):
+            cells.append((x, y, z))
+    return np.array(cells)
+
+
+def flux_scale(th, grid, U, stride=4):
+    """S_f = max |F_f| / min dx from the oracle's physical fluxes on a strided
+    subsample of the interior (numerical and physical fluxes agree to
+    truncation error; the subsample spans the shock and interface regions)."""
+    iz, iy, ix = grid.interior()
+    sub = U[:, iz, iy, ix][:, ::stride, ::stride, ::stride]
+    flat = sub.reshape(sub.shape[0], -1)
+    P = O.primitives(th, flat)
+    fm = np.zeros(flat.shape[0])
+    for d in grid.active():
+        fm = np.maximum(fm, np.abs(O.physical_flux(th, flat, P, d)).max(axis=1))
+    return fm / min(grid.d[d] for d in grid.active())
+
+
+@pytest.mark.parametrize("which", ["inert_sbi_128", "nine_species_sbi_256"])
+def test_full_size_sampled_parity(which):
+    """Full-size shock-bubble states (the benchmark launch configuration):
+    GPU RHS on the whole grid, oracle on sampled cells (boundaries, shock,
+    interface and random cells)."""
+    case = W.inert_sbi(128) if which == "inert_sbi_128" else W.nine_species_sbi(256)
+    print(f"[parity] full-size {which} {case.n}", flush=True)
+    r_gpu, flags, U_gpu = gpu_rhs(case)
+    assert flags == 0
+    th, g = oracle_objects(case)
+    U_ora = O.fill_ghosts(g, case.U)
+    assert np.array_equal(U_gpu, U_ora)
+    cells = _sample_cells(case, 150, 11)
+    ro = O.rhs_at(th, g, U_ora, cells)
+    rg = r_gpu[:, cells[:, 2] + 3, cells[:, 1] + 3, cells[:, 0] + 3]
+    scale = flux_scale(th, g, U_ora)
+    err = field_err(rg, ro, scale)
+    print(f"[parity] {which} sampled max err / S_f = {err.max():.3e}", flush=True)
+    assert err.max() <= TOL, err

@@ -1,0 +1,273 @@
+"""GPU VJP (adjoint) against the CPU oracle.
+
+The adjoint holds the LLF wave speeds fixed.  The oracle's complex-step
+derivatives do the same by construction (its max/abs act on real parts), and
+its central differences are taken with the speeds frozen at the base state.
+Checks are dot products <rbar, J w> = <J^T rbar, w> with random directions,
+plus the ghost-fill adjoint, the RK3-step adjoint and a checkpointed rollout
+gradient.  FP64 bar 1e-12 relative (complex step) / 1e-7 (central FD with
+h = 1e-6 relative); the mixed path is held to a declared 1e-4.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from conftest import oracle_objects
+from paper_2403_05910_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _xf():
+    from paper_2403_05910_amd import xf
+    return xf
+
+
+def interior_random(shape, grid, rng, scale=None):
+    v = np.zeros(shape)
+    iz, iy, ix = grid.interior()
+    blk = rng.standard_normal(v[:, iz, iy, ix].shape)
+    if scale is not None:
+        blk *= scale.reshape(-1, 1, 1, 1)
+    v[:, iz, iy, ix] = blk
+    return v
+
+
+def _field_scale(U, grid):
+    iz, iy, ix = grid.interior()
+    return np.abs(U[:, iz, iy, ix]).reshape(U.shape[0], -1).max(axis=1)
+
+
+def vjp_dot_check(case, precision, seed, fold=True):
+    """GPU <J^T rbar, w> versus oracle <rbar, J w> by complex step.
+    fold=True: J of L(G(U)) w.r.t. interior U; fold=False: J of L(U) with
+    ghost values as independent inputs (U's ghosts already hold values)."""
+    xf = _xf()
+    th, g = oracle_objects(case)
+    rng = np.random.default_rng(seed)
+    Ubase = O.fill_ghosts(g, case.U) if fold else case.U
+    r0, aux = O.rhs(th, g, Ubase, return_aux=True)
+    sc = np.where(aux["scale"] > 0, aux["scale"], 1.0)
+    rbar = interior_random(case.U.shape, g, rng, 1.0 / sc)
+    fs = _field_scale(Ubase, g)
+    w = interior_random(case.U.shape, g, rng, fs)
+    if not fold:  # perturb the ghosts too
+        iz, iy, ix = g.interior()
+        mask = np.ones(case.U.shape[1:], bool)
+        mask[iz, iy, ix] = False
+        w[:, mask] = rng.standard_normal((case.U.shape[0], mask.sum())) * fs[:, None]
+    h = 1e-30
+    Uc = Ubase + 1j * h * w
+    rc = O.rhs(th, g, O.fill_ghosts(g, Uc) if fold else Uc)
+    ref = np.sum(rbar * rc.imag) / h
+
+    ctx = xf.Context.from_case(case, precision)
+    U = ctx.state_from_numpy(Ubase)
+    if fold:
+        ctx.fill_ghosts(U)
+    Ub = ctx.rhs_vjp(U, ctx.state_from_numpy(rbar))
+    if fold:
+        ctx.fill_ghosts_vjp(Ub)
+    assert ctx.status() == 0
+    got = float(np.sum(Ub.cpu().numpy() * w))
+    ctx.close()
+    return got, ref
+
+
+VJP_CASES = {
+    "n3_outflow_x": lambda: W.random_smooth_state(W.sampled_table([2.0, 28.0, 40.0], 1), (10, 8, 6), seed=21,
+                                                  jump=True, bc=(1, 1, 0, 0, 0, 0)),
+    "n9_periodic": lambda: W.random_smooth_state(W.sampled_table(W.W9, 0), (8, 7, 6), seed=22, jump=True),
+    "n1_outflow_all": lambda: W.random_smooth_state(W.sampled_table([28.0], 4), (9, 6, 5), seed=23, jump=True,
+                                                    bc=(1,) * 6),
+    "wave1d": lambda: W.wave_1d(40),
+    "plane2d_n2": lambda: W.random_smooth_state(W.sampled_table([4.0, 30.0], 2), (17, 9, 1), seed=24, jump=True),
+    "inert_sbi_16": lambda: W.inert_sbi(16),
+}
+
+
+@pytest.mark.parametrize("name", list(VJP_CASES))
+def test_rhs_vjp_fp64_dot_product_complex_step(name):
+    case = VJP_CASES[name]()
+    for seed in (1, 2):
+        got, ref = vjp_dot_check(case, "fp64", seed)
+        rel = abs(got - ref) / abs(ref)
+        print(f"[vjp] {name} seed {seed}: rel {rel:.3e}", flush=True)
+        assert rel <= 1e-12, (got, ref, rel)
+
+
+@pytest.mark.parametrize("name", ["n3_outflow_x", "n9_periodic", "inert_sbi_16"])
+def test_rhs_vjp_mixed_dot_product(name):
+    case = VJP_CASES[name]()
+    got, ref = vjp_dot_check(case, "mixed", 3)
+    rel = abs(got - ref) / abs(ref)
+    print(f"[vjp] mixed {name}: rel {rel:.3e}", flush=True)
+    assert rel <= 1e-4, (got, ref, rel)
+
+
+def _c4_crop():
+    """16^3 interior crop [24, 40)^3 of the 64^3 periodic mixture with a
+    3-cell ghost shell copied from the surrounding field"""
+    full = W.periodic_mixture(64)
+    sub = full.U[:, 24:46, 24:46, 24:46].copy()
+    return W.Case("c4crop", (16, 16, 16), full.d, (0,) * 6, full.thermo, sub)
+
+
+def test_rhs_vjp_c4_crop_complex_step_ghosts_independent():
+    case = _c4_crop()
+    got, ref = vjp_dot_check(case, "fp64", 5, fold=False)
+    rel = abs(got - ref) / abs(ref)
+    print(f"[vjp] c4 crop 16^3: rel {rel:.3e}", flush=True)
+    assert rel <= 1e-12, (got, ref, rel)
+
+
+def test_rhs_vjp_c4_full_grid_central_fd():
+    """64^3 periodic 5-species mixture: central differences of the oracle with
+    the LLF speeds frozen at the base state, h = 1e-6 relative per field."""
+    xf = _xf()
+    case = W.periodic_mixture(64)
+    th, g = oracle_objects(case)
+    U0 = O.fill_ghosts(g, case.U)
+    rng = np.random.default_rng(3)
+    r0, aux = O.rhs(th, g, U0, return_aux=True)
+    rbar = interior_random(U0.shape, g, rng, 1.0 / aux["scale"])
+    w = interior_random(U0.shape, g, rng, _field_scale(U0, g))
+    h = 1e-6
+    rp = O.rhs(th, g, O.fill_ghosts(g, U0 + h * w), alpha=aux["alpha"])
+    rm = O.rhs(th, g, O.fill_ghosts(g, U0 - h * w), alpha=aux["alpha"])
+    ref = np.sum(rbar * (rp - rm)) / (2 * h)
+    ctx = xf.Context.from_case(case)
+    U = ctx.state_from_numpy(U0)
+    Ub = ctx.rhs_vjp(U, ctx.state_from_numpy(rbar))
+    ctx.fill_ghosts_vjp(Ub)
+    got = float(np.sum(Ub.cpu().numpy() * w))
+    rel = abs(got - ref) / abs(ref)
+    print(f"[vjp] c4 64^3 central FD: rel {rel:.3e}", flush=True)
+    assert rel <= 1e-7, (got, ref, rel)
+
+
+@pytest.mark.parametrize("bc", [(0,) * 6, (1,) * 6, (1, 1, 0, 0, 1, 1)])
+def test_fill_ghosts_vjp_is_the_transpose(bc):
+    xf = _xf()
+    tab = W.sampled_table([2.0, 28.0], 0)
+    case = W.random_smooth_state(tab, (7, 5, 4), seed=1, bc=bc)
+    th, g = oracle_objects(case)
+    rng = np.random.default_rng(7)
+    ctx = xf.Context.from_case(case)
+    for _ in range(3):
+        lam = rng.standard_normal(case.U.shape)
+        v = rng.standard_normal(case.U.shape)
+        L = ctx.state_from_numpy(lam)
+        ctx.fill_ghosts_vjp(L)
+        Lh = L.cpu().numpy()
+        lhs = np.sum(Lh * v)
+        rhs_ = np.sum(lam * O.fill_ghosts(g, v))
+        assert abs(lhs - rhs_) <= 1e-13 * np.sum(np.abs(lam) * np.abs(O.fill_ghosts(g, v)))
+        iz, iy, ix = g.interior()
+        mask = np.ones(case.U.shape[1:], bool)
+        mask[iz, iy, ix] = False
+        assert np.all(Lh[:, mask] == 0.0)
+
+
+def test_rk3_step_vjp_complex_step():
+    xf = _xf()
+    case = W.random_smooth_state(W.sampled_table([2.0, 28.0, 40.0], 1), (9, 8, 6), seed=31, jump=True,
+                                 bc=(1, 1, 0, 0, 0, 0))
+    th, g = oracle_objects(case)
+    U0 = O.fill_ghosts(g, case.U)
+    dt = 0.4 * O.cfl_dt(th, g, U0, 0.5)
+    rng = np.random.default_rng(4)
+    fs = _field_scale(U0, g)
+    lam = interior_random(U0.shape, g, rng, 1.0 / fs)
+    w = interior_random(U0.shape, g, rng, fs)
+    h = 1e-30
+    Uc = O.rk3_step(th, g, U0 + 1j * h * w, dt)
+    ref = np.sum(lam * Uc.imag) / h
+    ctx = xf.Context.from_case(case)
+    U = ctx.state_from_numpy(U0)
+    L = ctx.state_from_numpy(lam)
+    ctx.rk3_step_vjp(U, dt, L)
+    assert ctx.status() == 0
+    got = float(np.sum(L.cpu().numpy() * w))
+    rel = abs(got - ref) / abs(ref)
+    print(f"[vjp] rk3 step: rel {rel:.3e}", flush=True)
+    assert rel <= 1e-12, (got, ref, rel)
+
+
+def _mixing_functional(torch_mod, ctx, U):
+    """J = sum over the interior of Y1 (1 - Y1) dV"""
+    Ui = U[ctx.interior]
+    rho = Ui[:ctx.ns].sum(dim=0)
+    Y1 = Ui[0] / rho
+    dV = ctx.d[0] * ctx.d[1] * ctx.d[2]
+    return (Y1 * (1 - Y1)).sum() * dV
+
+
+def test_checkpointed_rollout_gradient_complex_step():
+    """gradient of the mixing functional after 6 RK3 steps (checkpoints every
+    2) w.r.t. the initial state, along a random direction of the species
+    densities, versus the complex-step derivative of the oracle's rollout"""
+    xf = _xf()
+    case = W.random_smooth_state(W.sampled_table([2.0, 28.0, 40.0], 1), (8, 8, 8), seed=41, jump=False)
+    th, g = oracle_objects(case)
+    U0 = O.fill_ghosts(g, case.U)
+    dt = 0.5 * O.cfl_dt(th, g, U0, 0.5)
+    nsteps = 6
+    rng = np.random.default_rng(9)
+    w = np.zeros_like(U0)
+    iz, iy, ix = g.interior()
+    w[:3, iz, iy, ix] = rng.standard_normal((3, 8, 8, 8)) * np.abs(U0[:3, iz, iy, ix])
+
+    def J_np(U):
+        Ui = U[:, iz, iy, ix]
+        Y1 = Ui[0] / Ui[:3].sum(axis=0)
+        return np.sum(Y1 * (1 - Y1)) * g.dx * g.dy * g.dz
+
+    h = 1e-30
+    Uc = U0 + 1j * h * w
+    for _ in range(nsteps):
+        Uc = O.rk3_step(th, g, Uc, dt)
+    ref = J_np(Uc).imag / h
+
+    ctx = xf.Context.from_case(case)
+    grads = []
+    for every in (2, 1, 6):
+        Ut = ctx.state_from_numpy(U0).requires_grad_(True)
+        out = xf.rollout(ctx, Ut, dt, nsteps, ckpt_every=every)
+        _mixing_functional(torch, ctx, out).backward()
+        grads.append(Ut.grad.cpu().numpy())
+    got = float(np.sum(grads[0] * w))
+    rel = abs(got - ref) / abs(ref)
+    print(f"[vjp] rollout: rel {rel:.3e}", flush=True)
+    assert rel <= 1e-10, (got, ref, rel)
+    # recomputation is deterministic: the checkpoint spacing does not change the gradient
+    assert np.array_equal(grads[0], grads[1]) and np.array_equal(grads[0], grads[2])
+
+
+def test_rhs_autograd_function_matches_explicit_calls():
+    xf = _xf()
+    case = VJP_CASES["n3_outflow_x"]()
+    ctx = xf.Context.from_case(case)
+    U = ctx.state_from_numpy(case.U).requires_grad_(True)
+    r = xf.rhs(ctx, U)
+    g_out = torch.randn_like(r)
+    (r * g_out).sum().backward()
+    V = ctx.state_from_numpy(case.U)
+    ctx.fill_ghosts(V)
+    Ub = ctx.rhs_vjp(V, g_out)
+    ctx.fill_ghosts_vjp(Ub)
+    assert torch.equal(U.grad, Ub)
+    assert torch.equal(r.detach(), ctx.rhs(V))
+
+
+def test_vjp_is_deterministic():
+    xf = _xf()
+    case = VJP_CASES["n9_periodic"]()
+    ctx = xf.Context.from_case(case)
+    U = ctx.state_from_numpy(case.U)
+    ctx.fill_ghosts(U)
+    rb = torch.randn_like(U)
+    a = ctx.rhs_vjp(U, rb)
+    b = ctx.rhs_vjp(U, rb)
+    assert torch.equal(a, b)
