@@ -43,8 +43,7 @@ def make_case(name):
 
 def run_steps(ctx, U, dt_dev, steps, cfl):
     for _ in range(steps):
-        ctx.cfl_dt(U, cfl, out=dt_dev)
-        ctx.rk3_step(U, dt_dev)
+        ctx.rk3_step_cfl(U, cfl, dt_dev)
 
 
 def timed_steps(torch, ctx, U, dt_dev, steps, cfl):
@@ -105,6 +104,8 @@ def main():
     ap.add_argument("--cfl", type=float, default=0.5)
     ap.add_argument("--no-extras", action="store_true", help="FP64 step throughput only")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib", action="store_true",
+                    help="first run a plain device copy of 1 GiB (counter calibration for rocprofv3 --pmc)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU: the path is built and measured for one MI355X "
@@ -116,6 +117,14 @@ def main():
     from paper_2403_05910_amd import xf
 
     torch.cuda.set_device(0)
+    if a.calib:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 3 x 1 GiB read + 1 GiB written")
+        del src, dst
     log(f"[bench] building workload {a.workload}")
     case = make_case(a.workload)
     cells = case.cells
@@ -184,6 +193,7 @@ def main():
                         "rhs_rel_err_linf_per_field": [float(x) for x in linf],
                         "rhs_rel_err_l1_per_field": [float(x) for x in l1],
                         "roofline": roofline_of(kern_m, case, "mixed"),
+                        "kernel_avg_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kern_m.items() if v[1]},
                         "flags": ctxm.status()}
         ctxm.close()
         del Um

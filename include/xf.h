@@ -140,6 +140,13 @@ int xf_cfl_dt(xf_ctx *ctx, const double *U, double cfl, double *dt_dev, void *ws
  * ws: xf_workspace_bytes(ctx, XF_OP_RK3) bytes. */
 int xf_rk3_step(xf_ctx *ctx, double *U, double dt, const double *dt_dev, void *ws, void *stream);
 
+/* xf_rk3_step with the time step of Eq. 17 computed on the device from U^n
+ * (the same reduction as xf_cfl_dt, reusing the first stage's primitives)
+ * and written to the device double *dt_dev before the stages use it.  This
+ * is one full time step of the convective system with no host round trip.
+ * ws: xf_workspace_bytes(ctx, XF_OP_RK3) bytes. */
+int xf_rk3_step_cfl(xf_ctx *ctx, double *U, double cfl, double *dt_dev, void *ws, void *stream);
+
 /* Vector-Jacobian product of the right-hand side: U_bar += J(U)^T rhs_bar,
  * J = d rhs / dU on the padded state with ghost values treated as independent
  * inputs (compose with xf_fill_ghosts_vjp for the map from the interior).

@@ -564,14 +564,16 @@ def rhs(th, grid, U, alpha=None, return_aux=False):
     return (out, aux) if return_aux else out
 
 
-def rhs_at(th, grid, U, cells):
+def rhs_at(th, grid, U, cells, return_fmax=False):
     """L(U) at selected interior cells only.  cells: (K, 3) integer array of
     interior indices (i, j, k) = (x, y, z).  Computes the two faces of each
-    cell in every active direction from their own stencils.  Returns (Nv, K)."""
+    cell in every active direction from their own stencils.  Returns (Nv, K)
+    and, with return_fmax, the per-field max |F^| over those faces."""
     cells = np.asarray(cells, dtype=np.int64).reshape(-1, 3)
     nv = th.ns + 4
     K = len(cells)
     out = np.zeros((nv, K))
+    fmax = np.zeros(nv)
     gx, gy, gz = grid.g(0), grid.g(1), grid.g(2)
     pz, py, px = cells[:, 2] + gz, cells[:, 1] + gy, cells[:, 0] + gx
     for d in grid.active():
@@ -590,8 +592,9 @@ def rhs_at(th, grid, U, cells):
             with np.errstate(all="ignore"):
                 Fh, _, _ = face_flux(th, d, Ust, Pst)
             fl.append(Fh)
+            fmax = np.maximum(fmax, np.max(np.abs(Fh.real), axis=1))
         out -= (fl[1] - fl[0]) / grid.d[d]
-    return out
+    return (out, fmax) if return_fmax else out
 
 
 # ---------------------------------------------------------------------------

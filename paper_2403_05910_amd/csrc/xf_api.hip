@@ -53,7 +53,7 @@ size_t align_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace carve-up (byte offsets); every piece 256-byte aligned.
 struct Layout {
-    size_t P, Pbar, mx, L, U0, V0, V1, V2, lam0, mu, total;
+    size_t P, Pbar, mx, L, U0, S2, V0, V1, V2, lam0, mu, total;
 };
 
 Layout layout(const xf_ctx *c, int op) {
@@ -73,6 +73,10 @@ Layout layout(const xf_ctx *c, int op) {
         l.L = o;
         o += align_up(state);
         l.U0 = o;
+        o += align_up(state);
+    }
+    if (op == XF_OP_RK3) {
+        l.S2 = o;
         o += align_up(state);
     }
     if (op == XF_OP_RK3_VJP) {
@@ -130,19 +134,35 @@ hipError_t timed(xf_ctx *c, int cls, hipStream_t s, F &&launch) {
     return hipSuccess;
 }
 
-int rhs_into(xf_ctx *c, const double *U, double *rhs, double *P, hipStream_t s) {
+// Primitives, then the active sweeps.  Without a fused stage the residual
+// goes to rhs (ghosts zeroed); with one, the last sweep writes the stage
+// combination and rhs only holds the partial sums of the earlier sweeps.
+int sweeps_into(xf_ctx *c, const double *U, double *rhs, const double *P, const xf::StageArgs &stage,
+                hipStream_t s) {
     const LaunchCtx &lc = c->lc;
     const int n[3] = {lc.g.nx, lc.g.ny, lc.g.nz};
-    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(lc, U, P, s); }));
+    int last = -1;
+    for (int d = 0; d < 3; ++d)
+        if (n[d] > 1) last = d;
+    xf::StageArgs off{};
     bool first = true;
     for (int d = 0; d < 3; ++d) {
         if (n[d] <= 1) continue;
         const int acc = first ? 0 : 1;
-        XF_TRY(timed(c, XF_K_SWEEP_X + d, s, [&] { return c->ops->sweep(lc, d, acc, U, P, rhs, s); }));
+        const xf::StageArgs &sa = d == last ? stage : off;
+        XF_TRY(timed(c, XF_K_SWEEP_X + d, s, [&] { return c->ops->sweep(lc, d, acc, U, P, rhs, sa, s); }));
         first = false;
     }
-    if (first) XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero(lc.g.cells * c->nv, rhs, s); }));
-    XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero_ghosts(lc, c->nv, rhs, s); }));
+    if (last < 0) return XF_EUNSUPPORTED;   // no active dimension (rejected by xf_create)
+    return XF_OK;
+}
+
+int rhs_into(xf_ctx *c, const double *U, double *rhs, double *P, hipStream_t s) {
+    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, P, s); }));
+    const xf::StageArgs off{};
+    const int r = sweeps_into(c, U, rhs, P, off, s);
+    if (r != XF_OK) return r;
+    XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero_ghosts(c->lc, c->nv, rhs, s); }));
     return XF_OK;
 }
 
@@ -183,6 +203,7 @@ bool grid_ok(const xf_grid *g) {
             if ((a == XF_BC_PERIODIC) != (b == XF_BC_PERIODIC)) return false;
         }
     }
+    if (n[0] <= 1 && n[1] <= 1 && n[2] <= 1) return false;
     const double cells = (double)(n[0] + (n[0] > 1 ? 6 : 0)) * (n[1] + (n[1] > 1 ? 6 : 0)) *
                          (n[2] + (n[2] > 1 ? 6 : 0));
     return cells < 9.0e18 / 16.0;
@@ -353,21 +374,52 @@ int xf_cfl_dt(xf_ctx *c, const double *U, double cfl, double *dt_dev, void *ws, 
     return XF_OK;
 }
 
-int xf_rk3_step(xf_ctx *c, double *U, double dt, const double *dt_dev, void *ws, void *stream) {
-    if (!c || !U || !ws || !aligned8(U) || !aligned8(ws)) return XF_EINVAL;
-    if (!dt_dev && !(dt >= 0.0)) return XF_EINVAL;
+// One SSP-RK3 step with the stage combinations fused into the last sweep of
+// each right-hand side (ping-pong stage buffers S1, S2; stage 3 writes U in
+// place, each cell read and written by one thread).  With cfl > 0 the time
+// step is reduced on the device from the stage-1 primitives of U^n and
+// written to *dt_dev before it is used.
+int rk3_step(xf_ctx *c, double *U, double dt, const double *dt_in, double cfl, double *dt_out, void *ws,
+             hipStream_t s) {
     const Layout l = layout(c, XF_OP_RK3);
-    const hipStream_t s = (hipStream_t)stream;
-    double *P = at<double>(ws, l.P), *L = at<double>(ws, l.L), *U0 = at<double>(ws, l.U0);
-    for (int stage = 1; stage <= 3; ++stage) {
-        XF_TRY(fill(c, U, s));
-        const int r = rhs_into(c, U, L, P, s);
+    double *P = at<double>(ws, l.P), *L = at<double>(ws, l.L);
+    double *S1 = at<double>(ws, l.U0), *S2 = at<double>(ws, l.S2);
+    unsigned long long *mx = at<unsigned long long>(ws, l.mx);
+    const double *h = dt_in;
+    double *in[3] = {U, S1, S2};
+    double *out[3] = {S1, S2, U};
+    const double a[3] = {0.0, 0.75, 1.0 / 3.0};
+    const double b[3] = {1.0, 0.25, 2.0 / 3.0};
+    for (int k = 0; k < 3; ++k) {
+        XF_TRY(fill(c, in[k], s));
+        XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, in[k], P, s); }));
+        if (k == 0 && cfl > 0.0) {
+            XF_TRY(timed(c, XF_K_CFL, s, [&] {
+                hipError_t e = xf::launch_cfl_reset(mx, s);
+                if (e == hipSuccess) e = c->ops->cfl(c->lc, U, P, mx, s);
+                if (e == hipSuccess) e = xf::launch_cfl_finish(mx, cfl, dt_out, s);
+                return e;
+            }));
+            h = dt_out;
+        }
+        const xf::StageArgs sa{U, in[k], out[k], a[k], b[k], dt, h, 1};
+        const int r = sweeps_into(c, in[k], L, P, sa, s);
         if (r != XF_OK) return r;
-        XF_TRY(timed(c, XF_K_STAGE, s,
-                     [&] { return xf::launch_rk3_stage(c->lc, c->nv, stage, U, U0, L, dt, dt_dev, s); }));
     }
     XF_TRY(fill(c, U, s));
     return XF_OK;
+}
+
+int xf_rk3_step(xf_ctx *c, double *U, double dt, const double *dt_dev, void *ws, void *stream) {
+    if (!c || !U || !ws || !aligned8(U) || !aligned8(ws)) return XF_EINVAL;
+    if (!dt_dev && !(dt >= 0.0)) return XF_EINVAL;
+    return rk3_step(c, U, dt, dt_dev, 0.0, nullptr, ws, (hipStream_t)stream);
+}
+
+int xf_rk3_step_cfl(xf_ctx *c, double *U, double cfl, double *dt_dev, void *ws, void *stream) {
+    if (!c || !U || !ws || !dt_dev || !(cfl > 0.0) || !aligned8(U) || !aligned8(ws) || !aligned8(dt_dev))
+        return XF_EINVAL;
+    return rk3_step(c, U, 0.0, nullptr, cfl, dt_dev, ws, (hipStream_t)stream);
 }
 
 int xf_rhs_vjp(xf_ctx *c, const double *U, const double *rbar, double *Ubar, void *ws, void *stream) {

@@ -42,6 +42,18 @@ struct ThermoK {
     int bracket;
 };
 
+// Optional fused SSP-RK3 stage on the last sweep of a right-hand side:
+// instead of rhs, write Uout = a U0 + b (Uin + dt L) with L the finished
+// residual (a == 0 skips U0).  dt is *dt_dev when dt_dev is set.
+struct StageArgs {
+    const double *U0;
+    const double *Uin;
+    double *Uout;
+    double a, b, dt;
+    const double *dt_dev;
+    int on;
+};
+
 // Everything a launch needs besides buffers.
 struct LaunchCtx {
     Geo g;
@@ -57,14 +69,14 @@ struct NsOps {
     hipError_t (*prims)(const LaunchCtx &, const double *U, double *P, hipStream_t);
     // one direction of the convective flux difference; accumulate: rhs += or rhs =
     hipError_t (*sweep)(const LaunchCtx &, int dir, int accumulate, const double *U,
-                        const double *P, double *rhs, hipStream_t);
+                        const double *P, double *rhs, const StageArgs &stage, hipStream_t);
     // VJP of one direction: Ubar_direct += (dF/dU)^T ..., Pbar += (dF/d(p, T))^T ...
     hipError_t (*sweep_vjp)(const LaunchCtx &, int dir, const double *U, const double *P,
                             const double *rbar, double *Ubar, double *Pbar, hipStream_t);
     // VJP of the primitive map: Ubar += (d(p, T)/dU)^T Pbar
     hipError_t (*prims_vjp)(const LaunchCtx &, const double *U, const double *P,
                             const double *Pbar, double *Ubar, hipStream_t);
-    // CFL partial reduction: max_i sum_d (|u_d| + c)/dx_d -> atomicMax on *mx (uint64 bits)
+    // CFL reduction: max_i sum_d (|u_d| + c)/dx_d -> atomicMax on *mx (uint64 bits)
     hipError_t (*cfl)(const LaunchCtx &, const double *U, const double *P,
                       unsigned long long *mx, hipStream_t);
 };

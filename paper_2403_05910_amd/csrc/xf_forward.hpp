@@ -109,9 +109,9 @@ __global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, dou
     }
     const double p = rho * Rb * T;
     const double c = sqrt((1.0 + Rb / cv) * Rb * T);
-    if (!(rho > 0.0)) flags |= XF_FLAG_RHO;
+    if (rho <= 0.0) flags |= XF_FLAG_RHO;
     if (yneg) flags |= XF_FLAG_Y;
-    if (!(p > 0.0) || !(T > 0.0)) flags |= XF_FLAG_P;
+    if (p <= 0.0 || T <= 0.0) flags |= XF_FLAG_P;
     if (th.bracket && (T < th.T_lo || T > th.T_hi)) flags |= XF_FLAG_TRANGE;
     if (!conv) flags |= XF_FLAG_NEWTON;
     if (!finite || !isfinite(T) || !isfinite(c)) flags |= XF_FLAG_NAN;
@@ -132,10 +132,23 @@ __global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, dou
 // ---------------------------------------------------------------------------
 constexpr int kXBlock = 256;
 
+// Write the finished residual d of one field at one cell: to rhs, or, when
+// the stage is fused, the stage combination to Uout.
+__device__ __forceinline__ void put_result(double *__restrict__ rhs, const StageArgs &sa, long long o, double d,
+                                           double h, int accumulate) {
+    const double L = accumulate ? rhs[o] + d : d;
+    if (!sa.on) {
+        rhs[o] = L;
+        return;
+    }
+    const double v = sa.Uin[o] + h * L;
+    sa.Uout[o] = sa.a == 0.0 ? sa.b * v : sa.a * sa.U0[o] + sa.b * v;
+}
+
 template <int NS, typename R>
 __global__ __launch_bounds__(kXBlock) void k_sweep_x(const double *__restrict__ U, const double *__restrict__ P,
                                                      double *__restrict__ rhs, Geo g, ThermoK<R> th,
-                                                     unsigned *status) {
+                                                     StageArgs sa, unsigned *status) {
     constexpr int NV = NS + 4;
     __shared__ R sF[NV][kXBlock];
     const int t = threadIdx.x;
@@ -162,8 +175,10 @@ __global__ __launch_bounds__(kXBlock) void k_sweep_x(const double *__restrict__ 
     if (valid && t > 0 && i > 0) {
         const R id = R(g.idx);
         const long long cell = rowbase + i - 1;
+        const double h = sa.on ? (sa.dt_dev ? *sa.dt_dev : sa.dt) : 0.0;
 #pragma unroll
-        for (int q = 0; q < NV; ++q) rhs[q * g.cells + cell] = double((sF[q][t - 1] - F[q]) * id);
+        for (int q = 0; q < NV; ++q)
+            put_result(rhs, sa, q * g.cells + cell, double((sF[q][t - 1] - F[q]) * id), h, 0);
     }
     if (flags) atomicOr(status, flags);
 }
@@ -177,7 +192,7 @@ __global__ __launch_bounds__(kXBlock) void k_sweep_x(const double *__restrict__ 
 template <int NS, typename R, int DIR>
 __global__ __launch_bounds__(256) void k_sweep_march(const double *__restrict__ U, const double *__restrict__ P,
                                                      double *__restrict__ rhs, Geo g, ThermoK<R> th,
-                                                     int seglen, int accumulate, unsigned *status) {
+                                                     int seglen, int accumulate, StageArgs sa, unsigned *status) {
     constexpr int NV = NS + 4;
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int tr = blockIdx.y * 4 + threadIdx.y;
@@ -192,6 +207,7 @@ __global__ __launch_bounds__(256) void k_sweep_march(const double *__restrict__ 
     const long long col = (long long)(g.gx + x) +
                           ((DIR == 1) ? (long long)(g.gz + tr) * g.sz : (long long)(g.gy + tr) * g.sy);
     const R id = R((DIR == 1) ? g.idy : g.idz);
+    const double h = sa.on ? (sa.dt_dev ? *sa.dt_dev : sa.dt) : 0.0;
     R Fp[NV], F[NV];
     unsigned flags = 0;
     for (int j = j0; j <= j1; ++j) {
@@ -200,11 +216,8 @@ __global__ __launch_bounds__(256) void k_sweep_march(const double *__restrict__ 
         if (j > j0) {
             const long long cell = col + (long long)(gs + j - 1) * step;
 #pragma unroll
-            for (int q = 0; q < NV; ++q) {
-                const double d = double((Fp[q] - F[q]) * id);
-                double *o = rhs + q * g.cells + cell;
-                *o = accumulate ? *o + d : d;
-            }
+            for (int q = 0; q < NV; ++q)
+                put_result(rhs, sa, q * g.cells + cell, double((Fp[q] - F[q]) * id), h, accumulate);
         }
 #pragma unroll
         for (int q = 0; q < NV; ++q) Fp[q] = F[q];
@@ -220,22 +233,29 @@ template <int NS>
 __global__ __launch_bounds__(256) void k_cfl(const double *__restrict__ U, const double *__restrict__ P, Geo g,
                                              unsigned long long *mx) {
     const long long n = (long long)g.nx * g.ny * g.nz;
-    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double s = 0.0;
-    if (q < n) {
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x) {
         const int i = (int)(q % g.nx);
         const long long r = q / g.nx;
         const int j = (int)(r % g.ny), k = (int)(r / g.ny);
         const long long idx = (long long)(g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + (g.gx + i);
         const double rinv = P[3 * g.cells + idx], c = P[2 * g.cells + idx];
-        if (g.nx > 1) s += (fabs(U[NS * g.cells + idx] * rinv) + c) * g.idx;
-        if (g.ny > 1) s += (fabs(U[(NS + 1) * g.cells + idx] * rinv) + c) * g.idy;
-        if (g.nz > 1) s += (fabs(U[(NS + 2) * g.cells + idx] * rinv) + c) * g.idz;
-        if (!(s >= 0.0)) s = 0.0;   // NaN never wins the max (it is flagged by k_prims)
+        double v = 0.0;
+        if (g.nx > 1) v += (fabs(U[NS * g.cells + idx] * rinv) + c) * g.idx;
+        if (g.ny > 1) v += (fabs(U[(NS + 1) * g.cells + idx] * rinv) + c) * g.idy;
+        if (g.nz > 1) v += (fabs(U[(NS + 2) * g.cells + idx] * rinv) + c) * g.idz;
+        if (v > s) s = v;   // NaN never wins (it is flagged by k_prims)
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s = fmax(s, __shfl_xor(s, off, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(mx, (unsigned long long)__double_as_longlong(s));
+    __shared__ double wmax[4];
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+        atomicMax(mx, (unsigned long long)__double_as_longlong(m));
+    }
 }
 
 }  // namespace xf

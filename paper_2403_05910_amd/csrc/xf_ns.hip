@@ -23,12 +23,12 @@ hipError_t prims(const LaunchCtx &c, const double *U, double *P, hipStream_t s) 
 
 template <typename R>
 hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumulate, const double *U,
-                   const double *P, double *rhs, hipStream_t s) {
+                   const double *P, double *rhs, const StageArgs &sa, hipStream_t s) {
     const Geo &g = c.g;
     if (dir == 0) {
         const long long nf = (long long)(g.nx + 1) * g.ny * g.nz;
         const unsigned nb = (unsigned)((nf - 1 + (kXBlock - 2)) / (kXBlock - 1));   // blocks overlap by one face
-        hipLaunchKernelGGL((k_sweep_x<NS, R>), dim3(nb), dim3(kXBlock), 0, s, U, P, rhs, g, th, c.status);
+        hipLaunchKernelGGL((k_sweep_x<NS, R>), dim3(nb), dim3(kXBlock), 0, s, U, P, rhs, g, th, sa, c.status);
         return hipGetLastError();
     }
     int nseg, seglen;
@@ -37,17 +37,17 @@ hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumu
     dim3 grid((g.nx + 63) / 64, (ntr + 3) / 4, nseg), block(64, 4);
     if (dir == 1)
         hipLaunchKernelGGL((k_sweep_march<NS, R, 1>), grid, block, 0, s, U, P, rhs, g, th, seglen, accumulate,
-                           c.status);
+                           sa, c.status);
     else
         hipLaunchKernelGGL((k_sweep_march<NS, R, 2>), grid, block, 0, s, U, P, rhs, g, th, seglen, accumulate,
-                           c.status);
+                           sa, c.status);
     return hipGetLastError();
 }
 
 hipError_t sweep(const LaunchCtx &c, int dir, int accumulate, const double *U, const double *P, double *rhs,
-                 hipStream_t s) {
-    if (c.precision == XF_PREC_MIXED) return sweep_t<float>(c, c.th32, dir, accumulate, U, P, rhs, s);
-    return sweep_t<double>(c, c.th64, dir, accumulate, U, P, rhs, s);
+                 const StageArgs &sa, hipStream_t s) {
+    if (c.precision == XF_PREC_MIXED) return sweep_t<float>(c, c.th32, dir, accumulate, U, P, rhs, sa, s);
+    return sweep_t<double>(c, c.th64, dir, accumulate, U, P, rhs, sa, s);
 }
 
 MarchGeo march_geo(const Geo &g, int dir) {
@@ -119,7 +119,9 @@ hipError_t prims_vjp(const LaunchCtx &c, const double *U, const double *P, const
 
 hipError_t cfl(const LaunchCtx &c, const double *U, const double *P, unsigned long long *mx, hipStream_t s) {
     const long long n = (long long)c.g.nx * c.g.ny * c.g.nz;
-    hipLaunchKernelGGL(k_cfl<NS>, dim3(blocks_for(n, 256)), dim3(256), 0, s, U, P, c.g, mx);
+    long long nb = blocks_for(n, 256);
+    if (nb > 2048) nb = 2048;   // grid-stride: one atomic per block
+    hipLaunchKernelGGL(k_cfl<NS>, dim3((unsigned)nb), dim3(256), 0, s, U, P, c.g, mx);
     return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ namespace xf {
 // weno5(a..e):  dW/dx = sum_k w_k dq_k/dx - 2 sum_k w_k (q_k - W)/(eps + beta_k)
 // dbeta_k/dx, w_k the normalised nonlinear weights.
 template <typename R>
-XF_HD void weno5_bwd(R a, R b, R c, R d, R e, R hb, R &ab, R &bb, R &cb, R &db, R &eb) {
+XF_HD R weno5_bwd(R a, R b, R c, R d, R e, R hb, R &ab, R &bb, R &cb, R &db, R &eb) {
     const R q0 = (R(2) * a - R(7) * b + R(11) * c) * R(1.0 / 6.0);
     const R q1 = (-b + R(5) * c + R(2) * d) * R(1.0 / 6.0);
     const R q2 = (R(2) * c + R(5) * d - e) * R(1.0 / 6.0);
@@ -46,21 +46,24 @@ XF_HD void weno5_bwd(R a, R b, R c, R d, R e, R hb, R &ab, R &bb, R &cb, R &db, 
     cb += g0 * R(11.0 / 6.0) + g1 * R(5.0 / 6.0) + g2 * R(2.0 / 6.0) + A0 + R(3) * B0 - R(2) * A1 + A2 + R(3) * B2;
     db += g1 * R(2.0 / 6.0) + g2 * R(5.0 / 6.0) + A1 - B1 - R(2) * A2 - R(4) * B2;
     eb += g2 * R(-1.0 / 6.0) + A2 + B2;
+    return W;
 }
 
-// Backward of h = W(g+_{0..4}) + W(g-_{5..1}) with g+- = (wF +- al wU)/2:
-// returns the cotangents of wF and wU at the six stencil cells.
+// Forward and backward of h = W(g+_{0..4}) + W(g-_{5..1}) with
+// g+- = (wF +- al wU)/2: returns h and the cotangents of wF and wU at the six
+// stencil cells for the output cotangent hb.
 template <typename R>
-XF_HD void split_weno_bwd(const R *gp, const R *gm, R al, R hb, R *wFb, R *wUb) {
+XF_HD R split_weno_fb(const R *gp, const R *gm, R al, R hb, R *wFb, R *wUb) {
     R pb[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
     R mb[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-    weno5_bwd(gp[0], gp[1], gp[2], gp[3], gp[4], hb, pb[0], pb[1], pb[2], pb[3], pb[4]);
-    weno5_bwd(gm[5], gm[4], gm[3], gm[2], gm[1], hb, mb[5], mb[4], mb[3], mb[2], mb[1]);
+    const R h = weno5_bwd(gp[0], gp[1], gp[2], gp[3], gp[4], hb, pb[0], pb[1], pb[2], pb[3], pb[4]) +
+                weno5_bwd(gm[5], gm[4], gm[3], gm[2], gm[1], hb, mb[5], mb[4], mb[3], mb[2], mb[1]);
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
         wFb[m] = R(0.5) * (pb[m] + mb[m]);
         wUb[m] = R(0.5) * al * (pb[m] - mb[m]);
     }
+    return h;
 }
 
 template <typename R>
@@ -84,7 +87,7 @@ XF_HD void face_vjp(const Stencil &st, const ThermoK<R> &th, const R *Fb, const 
     constexpr int KN = Axes<DIR>::n, K1 = Axes<DIR>::t1, K2 = Axes<DIR>::t2;
     constexpr int IN = NS + KN, I1 = NS + K1, I2 = NS + K2;
 
-    // ================= forward recomputation =================
+    // ================= forward: Roe state and per-cell scalars =================
     R rL = R(0), rR = R(0);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -150,80 +153,26 @@ XF_HD void face_vjp(const Stencil &st, const ThermoK<R> &th, const R *Fb, const 
         a0 = rmax(a0, rabs(unm));
         aP = rmax(aP, rabs(unm + cm));
     }
-    // field values needed by the backward of the back-projection
-    R hm, hp, h1, h2;
-    R gMp[6], gMm[6], gPp[6], gPm[6], XU[6], XF[6];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-        const R mn = R(st.u(IN, m));
-        XU[m] = mn - utn * rh[m];
-        XF[m] = (mn * un[m] + R(st.p(1, m))) - utn * (rh[m] * un[m]);
-        const R wUm = R(0.5) * DU[m] - cih * XU[m], wFm = R(0.5) * DF[m] - cih * XF[m];
-        const R wUp = R(0.5) * DU[m] + cih * XU[m], wFp = R(0.5) * DF[m] + cih * XF[m];
-        gMp[m] = R(0.5) * (wFm + aM * wUm);
-        gMm[m] = R(0.5) * (wFm - aM * wUm);
-        gPp[m] = R(0.5) * (wFp + aP * wUp);
-        gPm[m] = R(0.5) * (wFp - aP * wUp);
-    }
-    hm = weno5(gMp[0], gMp[1], gMp[2], gMp[3], gMp[4]) + weno5(gMm[5], gMm[4], gMm[3], gMm[2], gMm[1]);
-    hp = weno5(gPp[0], gPp[1], gPp[2], gPp[3], gPp[4]) + weno5(gPm[5], gPm[4], gPm[3], gPm[2], gPm[1]);
-    {
-        R gp[6], gm[6];
-#pragma unroll
-        for (int m = 0; m < 6; ++m) {
-            const R wU = R(st.u(I1, m)) - ut1 * rh[m];
-            gp[m] = R(0.5) * (un[m] * wU + a0 * wU);
-            gm[m] = R(0.5) * (un[m] * wU - a0 * wU);
-        }
-        h1 = weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
-#pragma unroll
-        for (int m = 0; m < 6; ++m) {
-            const R wU = R(st.u(I2, m)) - ut2 * rh[m];
-            gp[m] = R(0.5) * (un[m] * wU + a0 * wU);
-            gm[m] = R(0.5) * (un[m] * wU - a0 * wU);
-        }
-        h2 = weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
-    }
-    R hs[NS];
-    R gsum = R(0);
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        R gp[6], gm[6];
-#pragma unroll
-        for (int m = 0; m < 6; ++m) {
-            const R r = R(st.u(s, m));
-            const R wU = r - Yt[s] * DU[m];
-            const R wF = r * un[m] - Yt[s] * DF[m];
-            gp[m] = R(0.5) * (wF + a0 * wU);
-            gm[m] = R(0.5) * (wF - a0 * wU);
-        }
-        hs[s] = weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
-        gsum += hs[s];
-    }
-    const R Asum = hm + hp, Dif = hp - hm;
 
-    // ================= backward =================
-    // back-projection: F_s = Y_s A + h_s; F_m = u (A + gsum) + c n D + t1 h1 + t2 h2;
-    // F_E = H A + u_n c D + u_t1 h1 + u_t2 h2 + sum_s (q2 - chi_s / Gam) h_s
+    // ================= back-projection cotangents known from Fb ============
+    // F_s = Y_s A + h_s; F_m = u (A + gsum) + c n D + t1 h1 + t2 h2;
+    // F_E = H A + u_n c D + u_t1 h1 + u_t2 h2 + sum_s (q2 - chi_s / Gam) h_s,
+    // A = h_- + h_+, D = h_+ - h_-, gsum = sum_s h_s.
     const R FbE = Fb[IE];
-    R Fbm[3] = {Fb[IM], Fb[IM + 1], Fb[IM + 2]};
-    R gsum_b = ut[0] * Fbm[0] + ut[1] * Fbm[1] + ut[2] * Fbm[2];
+    const R Fbm[3] = {Fb[IM], Fb[IM + 1], Fb[IM + 2]};
+    const R gsum_b = ut[0] * Fbm[0] + ut[1] * Fbm[1] + ut[2] * Fbm[2];
     R Asum_b = gsum_b + Ht * FbE;
 #pragma unroll
     for (int s = 0; s < NS; ++s) Asum_b += Yt[s] * Fb[s];
     const R Dif_b = ct * Fbm[KN] + utn * ct * FbE;
-    const R h1_b = Fbm[K1] + ut1 * FbE;
-    const R h2_b = Fbm[K2] + ut2 * FbE;
-    R ut_b[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) ut_b[k] = (Asum + gsum) * Fbm[k];
-    ut_b[KN] += ct * Dif * FbE;
-    ut_b[K1] += h1 * FbE;
-    ut_b[K2] += h2 * FbE;
-    R ct_b = Dif * Fbm[KN] + utn * Dif * FbE;
-    R Ht_b = Asum * FbE;
-    R q2_b = R(0), iGam_b = R(0);
+    R ut_b[3] = {R(0), R(0), R(0)};
+    R ct_b = R(0), Ht_b = R(0), q2_b = R(0), iGam_b = R(0), cih_b = R(0);
     R Yt_b[NS], chi_b[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        Yt_b[s] = R(0);
+        chi_b[s] = R(0);
+    }
     R un_b[6], DU_b[6], DF_b[6], rh_b[6], pm_b[6], Mn_b[6];
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
@@ -235,42 +184,55 @@ XF_HD void face_vjp(const Stencil &st, const ThermoK<R> &th, const R *Fb, const 
         Mn_b[m] = R(0);
     }
 
-    // species fields
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        Yt_b[s] = Asum * Fb[s];
-        const R hsb = Fb[s] + gsum_b + (q2 - chi[s] * iGam) * FbE;
-        q2_b += hs[s] * FbE;
-        chi_b[s] = -iGam * hs[s] * FbE;
-        iGam_b -= chi[s] * hs[s] * FbE;
-        R gp[6], gm[6], wFb[6], wUb[6];
+    // ================= acoustic pair: forward value and backward ===========
+    R Asum, Dif;
+    {
+        R gMp[6], gMm[6], gPp[6], gPm[6];
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
-            const R r = R(st.u(s, m));
-            const R wU = r - Yt[s] * DU[m];
-            const R wF = r * un[m] - Yt[s] * DF[m];
-            gp[m] = R(0.5) * (wF + a0 * wU);
-            gm[m] = R(0.5) * (wF - a0 * wU);
+            const R mn = R(st.u(IN, m));
+            const R XU = mn - utn * rh[m];
+            const R XF = (mn * un[m] + R(st.p(1, m))) - utn * (rh[m] * un[m]);
+            const R wUm = R(0.5) * DU[m] - cih * XU, wFm = R(0.5) * DF[m] - cih * XF;
+            const R wUp = R(0.5) * DU[m] + cih * XU, wFp = R(0.5) * DF[m] + cih * XF;
+            gMp[m] = R(0.5) * (wFm + aM * wUm);
+            gMm[m] = R(0.5) * (wFm - aM * wUm);
+            gPp[m] = R(0.5) * (wFp + aP * wUp);
+            gPm[m] = R(0.5) * (wFp - aP * wUp);
         }
-        split_weno_bwd(gp, gm, a0, hsb, wFb, wUb);
+        R wFmb[6], wUmb[6], wFpb[6], wUpb[6];
+        const R hm = split_weno_fb(gMp, gMm, aM, Asum_b - Dif_b, wFmb, wUmb);
+        const R hp = split_weno_fb(gPp, gPm, aP, Asum_b + Dif_b, wFpb, wUpb);
+        Asum = hm + hp;
+        Dif = hp - hm;
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
-            const R r = R(st.u(s, m));
-            out.u(s, m, double(wUb[m] + un[m] * wFb[m]));
-            un_b[m] += r * wFb[m];
-            Yt_b[s] -= DU[m] * wUb[m] + DF[m] * wFb[m];
-            DU_b[m] -= Yt[s] * wUb[m];
-            DF_b[m] -= Yt[s] * wFb[m];
+            const R mn = R(st.u(IN, m));
+            const R XU = mn - utn * rh[m];
+            const R XF = (mn * un[m] + R(st.p(1, m))) - utn * (rh[m] * un[m]);
+            DU_b[m] += R(0.5) * (wUmb[m] + wUpb[m]);
+            DF_b[m] += R(0.5) * (wFmb[m] + wFpb[m]);
+            const R XUb = cih * (wUpb[m] - wUmb[m]);
+            const R XFb = cih * (wFpb[m] - wFmb[m]);
+            cih_b += XU * (wUpb[m] - wUmb[m]) + XF * (wFpb[m] - wFmb[m]);
+            Mn_b[m] += XUb + un[m] * XFb;
+            ut_b[KN] -= rh[m] * XUb + rh[m] * un[m] * XFb;
+            rh_b[m] -= utn * XUb + utn * un[m] * XFb;
+            un_b[m] += (mn - utn * rh[m]) * XFb;
+            pm_b[m] += XFb;
         }
     }
+    ct_b += Dif * Fbm[KN] + utn * Dif * FbE;
+    ut_b[KN] += ct * Dif * FbE;
+    Ht_b += Asum * FbE;
 
-    // tangential fields
+    // ================= tangential pair =====================================
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
         const int I = a == 0 ? I1 : I2;
         const int K = a == 0 ? K1 : K2;
         const R uta = a == 0 ? ut1 : ut2;
-        const R hb = a == 0 ? h1_b : h2_b;
+        const R hb = Fbm[K] + uta * FbE;
         R gp[6], gm[6], wU[6], wFb[6], wUb[6];
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
@@ -278,7 +240,8 @@ XF_HD void face_vjp(const Stencil &st, const ThermoK<R> &th, const R *Fb, const 
             gp[m] = R(0.5) * (un[m] * wU[m] + a0 * wU[m]);
             gm[m] = R(0.5) * (un[m] * wU[m] - a0 * wU[m]);
         }
-        split_weno_bwd(gp, gm, a0, hb, wFb, wUb);
+        const R ha = split_weno_fb(gp, gm, a0, hb, wFb, wUb);
+        ut_b[K] += ha * FbE;
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
             un_b[m] += wU[m] * wFb[m];
@@ -289,30 +252,40 @@ XF_HD void face_vjp(const Stencil &st, const ThermoK<R> &th, const R *Fb, const 
         }
     }
 
-    // acoustic pair
-    R cih_b = R(0);
-    {
-        const R hm_b = Asum_b - Dif_b, hp_b = Asum_b + Dif_b;
-        R wFmb[6], wUmb[6], wFpb[6], wUpb[6];
-        split_weno_bwd(gMp, gMm, aM, hm_b, wFmb, wUmb);
-        split_weno_bwd(gPp, gPm, aP, hp_b, wFpb, wUpb);
+    // ================= species fields ======================================
+    R gsum = R(0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const R hsb = Fb[s] + gsum_b + (q2 - chi[s] * iGam) * FbE;
+        R gp[6], gm[6], wFb[6], wUb[6];
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
-            DU_b[m] += R(0.5) * (wUmb[m] + wUpb[m]);
-            DF_b[m] += R(0.5) * (wFmb[m] + wFpb[m]);
-            const R XUb = cih * (wUpb[m] - wUmb[m]);
-            const R XFb = cih * (wFpb[m] - wFmb[m]);
-            cih_b += XU[m] * (wUpb[m] - wUmb[m]) + XF[m] * (wFpb[m] - wFmb[m]);
-            const R mn = R(st.u(IN, m));
-            Mn_b[m] += XUb + un[m] * XFb;
-            ut_b[KN] -= rh[m] * XUb + rh[m] * un[m] * XFb;
-            rh_b[m] -= utn * XUb + utn * un[m] * XFb;
-            un_b[m] += (mn - utn * rh[m]) * XFb;
-            pm_b[m] += XFb;
+            const R r = R(st.u(s, m));
+            const R wU = r - Yt[s] * DU[m];
+            const R wF = r * un[m] - Yt[s] * DF[m];
+            gp[m] = R(0.5) * (wF + a0 * wU);
+            gm[m] = R(0.5) * (wF - a0 * wU);
+        }
+        const R hs = split_weno_fb(gp, gm, a0, hsb, wFb, wUb);
+        gsum += hs;
+        Yt_b[s] += Asum * Fb[s];
+        q2_b += hs * FbE;
+        chi_b[s] -= iGam * hs * FbE;
+        iGam_b -= chi[s] * hs * FbE;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            const R r = R(st.u(s, m));
+            out.u(s, m, double(wUb[m] + un[m] * wFb[m]));
+            un_b[m] += r * wFb[m];
+            Yt_b[s] -= DU[m] * wUb[m] + DF[m] * wFb[m];
+            DU_b[m] -= Yt[s] * wUb[m];
+            DF_b[m] -= Yt[s] * wFb[m];
         }
     }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ut_b[k] += (Asum + gsum) * Fbm[k];
 
-    // per-cell projections: DU = dpU / c^2, DF = dpF / c^2
+    // ================= per-cell projections: DU = dpU / c^2, DF = dpF / c^2
     R Gam_b = R(0), ic2_b = R(0);
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
@@ -355,7 +328,7 @@ XF_HD void face_vjp(const Stencil &st, const ThermoK<R> &th, const R *Fb, const 
         out.p(0, m, double(pm_bt));
     }
 
-    // Roe state: c^2, Gamma, chi_s, thermo at T~, averages
+    // ================= Roe state: c^2, Gamma, chi_s, thermo at T~, averages
     ct_b += R(0.5) * ic2 * cih_b;
     ic2_b += R(0.5) * ct * cih_b;
     const R c2_b = -ic2 * ic2 * ic2_b + ct_b / (R(2) * ct);

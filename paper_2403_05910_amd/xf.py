@@ -59,6 +59,7 @@ _fill_vjp = _sig("xf_fill_ghosts_vjp", _c_int, _vp, _vp, _vp)
 _rhs = _sig("xf_rhs", _c_int, _vp, _vp, _vp, _vp, _vp)
 _cfl = _sig("xf_cfl_dt", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
 _rk3 = _sig("xf_rk3_step", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
+_rk3_cfl = _sig("xf_rk3_step_cfl", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
 _rhs_vjp = _sig("xf_rhs_vjp", _c_int, _vp, _vp, _vp, _vp, _vp, _vp)
 _rk3_vjp = _sig("xf_rk3_step_vjp", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
 _status = _sig("xf_status", _c_int, _vp, _vp, ctypes.POINTER(ctypes.c_uint))
@@ -67,7 +68,7 @@ _timing_read = _sig("xf_timing_read", _c_int, _vp, _vp, _dp, ctypes.POINTER(ctyp
 _strerror = _sig("xf_strerror", ctypes.c_char_p, _c_int)
 
 EXPORTED = ["xf_create", "xf_destroy", "xf_state_elems", "xf_workspace_bytes", "xf_fill_ghosts",
-            "xf_fill_ghosts_vjp", "xf_rhs", "xf_cfl_dt", "xf_rk3_step", "xf_rhs_vjp", "xf_rk3_step_vjp",
+            "xf_fill_ghosts_vjp", "xf_rhs", "xf_cfl_dt", "xf_rk3_step", "xf_rk3_step_cfl", "xf_rhs_vjp", "xf_rk3_step_vjp",
             "xf_status", "xf_strerror", "xf_timing", "xf_timing_read"]
 KERNEL_CLASSES = ["prims", "sweep_x", "sweep_y", "sweep_z", "fill", "stage", "cfl", "zero",
                   "vjp_x", "vjp_y", "vjp_z", "prims_vjp", "fill_vjp"]
@@ -128,6 +129,10 @@ def xf_cfl_dt(ctx, U, cfl, dt_dev, ws, stream):
 
 def xf_rk3_step(ctx, U, dt, dt_dev, ws, stream):
     return _check(_rk3(ctx, U, dt, dt_dev, ws, stream), "xf_rk3_step")
+
+
+def xf_rk3_step_cfl(ctx, U, cfl, dt_dev, ws, stream):
+    return _check(_rk3_cfl(ctx, U, cfl, dt_dev, ws, stream), "xf_rk3_step_cfl")
 
 
 def xf_rhs_vjp(ctx, U, rhs_bar, U_bar, ws, stream):
@@ -271,6 +276,15 @@ class Context:
         else:
             xf_rk3_step(self.handle, self._ptr(U), float(dt), None, self.workspace(XF_OP_RK3), self._stream())
         return U
+
+    def rk3_step_cfl(self, U, cfl, dt_out=None):
+        """one RK3 step with dt = CFL limit of U^n computed on the device;
+        returns the one-element device tensor holding dt"""
+        torch = _torch()
+        dt_out = torch.empty(1, dtype=torch.float64, device=self.device) if dt_out is None else dt_out
+        xf_rk3_step_cfl(self.handle, self._ptr(U), float(cfl), dt_out.data_ptr(), self.workspace(XF_OP_RK3),
+                        self._stream())
+        return dt_out
 
     def rhs_vjp(self, U, rhs_bar, U_bar=None):
         U_bar = self.new_state() if U_bar is None else U_bar
