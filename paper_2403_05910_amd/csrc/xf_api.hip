@@ -1,6 +1,7 @@
 // xf_api.hip -- the C ABI of libxf.so (declared in include/xf.h): argument
 // checks on the host, then asynchronous launches on the caller's stream.
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -141,12 +142,14 @@ int sweeps_into(xf_ctx *c, const double *U, double *rhs, const double *P, const 
                 hipStream_t s) {
     const LaunchCtx &lc = c->lc;
     const int n[3] = {lc.g.nx, lc.g.ny, lc.g.nz};
+    // z, then y, then x: the x sweep (one face per thread, fully coalesced)
+    // is the last one and carries the fused stage
     int last = -1;
-    for (int d = 0; d < 3; ++d)
+    for (int d = 2; d >= 0; --d)
         if (n[d] > 1) last = d;
     xf::StageArgs off{};
     bool first = true;
-    for (int d = 0; d < 3; ++d) {
+    for (int d = 2; d >= 0; --d) {
         if (n[d] <= 1) continue;
         const int acc = first ? 0 : 1;
         const xf::StageArgs &sa = d == last ? stage : off;
@@ -278,6 +281,10 @@ int xf_create(const xf_grid *grid, const xf_thermo *thermo, int precision, xf_ct
     fill_thermo(c->lc.th64, thermo);
     fill_thermo(c->lc.th32, thermo);
     c->lc.precision = precision;
+    {
+        const char *v = getenv("XF_KERNEL_VARIANT");
+        c->lc.variant = v ? atoi(v) : 0;
+    }
     c->ns = thermo->ns;
     c->nv = thermo->ns + 4;
     c->ops = ops;

@@ -61,6 +61,7 @@ struct LaunchCtx {
     ThermoK<float> th32;
     unsigned *status;    // device status word (atomicOr of XF_FLAG_*)
     int precision;       // XF_PREC_*
+    int variant;         // kernel variant for measurements (environment XF_KERNEL_VARIANT), 0 = default
 };
 
 // Per species-count entry points (one translation unit per N).

@@ -36,6 +36,14 @@
 // Face code is compiled for the device and, for CPU checks of its arithmetic,
 // for the host as well.
 #define XF_HD __host__ __device__ __forceinline__
+// Compiler-only fence between phases of the face computation: keeps the
+// compiler from hoisting every stencil load to the top of the routine (which
+// holds ~100 loaded values in registers at once); emits no instruction.
+#ifdef __HIP_DEVICE_COMPILE__
+#define XF_FENCE() asm volatile("" ::: "memory")
+#else
+#define XF_FENCE() ((void)0)
+#endif
 
 namespace xf {
 
@@ -125,11 +133,12 @@ struct Axes {
     static constexpr int t2 = (DIR == 2) ? 1 : 2;
 };
 
-// Numerical flux at one face.  Fh[0..NS+3] receives F^ in conservative field
-// order.  flags collects XF_FLAG_C2 if the face c^2 is not positive.
-template <int NS, typename R, int DIR>
-XF_HD void face_flux(const Stencil &st, const ThermoK<R> &th, R *__restrict__ Fh,
-                                          unsigned &flags) {
+// Numerical flux at one face.  Each component of F^ is handed to out(q, v)
+// as soon as it is final (species first, then momentum and energy), so the
+// caller decides where it lives.  flags collects XF_FLAG_C2 if the face c^2
+// is not positive.  FENCE inserts compiler fences between the phases.
+template <int NS, typename R, int DIR, bool FENCE = false, class Out>
+XF_HD void face_flux_to(const Stencil &st, const ThermoK<R> &th, Out &&out, unsigned &flags) {
     constexpr int IM = NS;
     constexpr int IE = NS + 3;
     constexpr int IN = NS + Axes<DIR>::n;
@@ -175,6 +184,7 @@ XF_HD void face_flux(const Stencil &st, const ThermoK<R> &th, R *__restrict__ Fh
     const R cih = R(0.5) * ct * ic2;      // c / (2 c^2)
     const R utn = ut[Axes<DIR>::n], ut1 = ut[Axes<DIR>::t1], ut2 = ut[Axes<DIR>::t2];
 
+    if (FENCE) XF_FENCE();
     // ---- 2./3. per-cell scalars of the projections, LLF speeds ----------
     R un[6], DU[6], DF[6], rh[6];
     R aM = R(0), a0 = R(0), aP = R(0);
@@ -203,6 +213,7 @@ XF_HD void face_flux(const Stencil &st, const ThermoK<R> &th, R *__restrict__ Fh
         aP = rmax(aP, rabs(unm + cm));
     }
 
+    if (FENCE) XF_FENCE();
     // ---- acoustic pair ----------------------------------------------------
     R hm, hp;
     {
@@ -224,6 +235,7 @@ XF_HD void face_flux(const Stencil &st, const ThermoK<R> &th, R *__restrict__ Fh
     }
     const R Asum = hm + hp, Dif = hp - hm;
 
+    if (FENCE) XF_FENCE();
     // ---- tangential pair --------------------------------------------------
     R h1, h2;
     {
@@ -251,6 +263,7 @@ XF_HD void face_flux(const Stencil &st, const ThermoK<R> &th, R *__restrict__ Fh
     R gsum = R(0), gE = R(0);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
+        if (FENCE) XF_FENCE();
         R gp[6], gm[6];
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
@@ -261,7 +274,7 @@ XF_HD void face_flux(const Stencil &st, const ThermoK<R> &th, R *__restrict__ Fh
             gm[m] = R(0.5) * (wF - a0 * wU);
         }
         const R hs = weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
-        Fh[s] = Yt[s] * Asum + hs;
+        out(s, Yt[s] * Asum + hs);
         gsum += hs;
         gE += (q2 - chi[s] * iGam) * hs;
     }
@@ -273,10 +286,16 @@ XF_HD void face_flux(const Stencil &st, const ThermoK<R> &th, R *__restrict__ Fh
     Fm[Axes<DIR>::n] += ct * Dif;
     Fm[Axes<DIR>::t1] += h1;
     Fm[Axes<DIR>::t2] += h2;
-    Fh[IM + 0] = Fm[0];
-    Fh[IM + 1] = Fm[1];
-    Fh[IM + 2] = Fm[2];
-    Fh[IE] = Ht * Asum + utn * ct * Dif + ut1 * h1 + ut2 * h2 + gE;
+    out(IM + 0, Fm[0]);
+    out(IM + 1, Fm[1]);
+    out(IM + 2, Fm[2]);
+    out(IE, Ht * Asum + utn * ct * Dif + ut1 * h1 + ut2 * h2 + gE);
+}
+
+// Numerical flux at one face into Fh[0..NS+3] (conservative field order).
+template <int NS, typename R, int DIR>
+XF_HD void face_flux(const Stencil &st, const ThermoK<R> &th, R *__restrict__ Fh, unsigned &flags) {
+    face_flux_to<NS, R, DIR>(st, th, [&](int q, R v) { Fh[q] = v; }, flags);
 }
 
 }  // namespace xf

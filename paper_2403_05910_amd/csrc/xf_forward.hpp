@@ -123,17 +123,28 @@ __global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, dou
 }
 
 // ---------------------------------------------------------------------------
-// x sweep: faces linearised over interior rows (face i of row r = the face
-// between interior cells i-1 and i, i = 0..nx).  A block of 256 threads takes
-// 256 consecutive faces and blocks overlap by one face, so every cell whose
-// two faces lie in a block gets rhs = (F^_{i-1/2} - F^_{i+1/2}) / dx there
-// (the neighbour flux comes through LDS).  x is the first active sweep, so it
-// writes rhs rather than accumulating.
-// ---------------------------------------------------------------------------
-constexpr int kXBlock = 256;
+// Phase fences per kernel flavour: where they lower register pressure
+// without spilling (chosen from the compiler's resource report).
+#ifndef XF_FX64
+#define XF_FX64 false
+#endif
+#ifndef XF_FM64
+#define XF_FM64 false
+#endif
+template <typename R>
+struct SweepFence {
+    static constexpr bool x = false;
+    static constexpr bool march = true;
+};
+template <>
+struct SweepFence<double> {
+    static constexpr bool x = XF_FX64;
+    static constexpr bool march = XF_FM64;
+};
 
-// Write the finished residual d of one field at one cell: to rhs, or, when
-// the stage is fused, the stage combination to Uout.
+// Write the finished residual d of one field at one cell: to rhs (=, or +=
+// when accumulating), or, when the stage is fused, the stage combination
+// Uout = a U0 + b (Uin + h L) with L the complete residual.
 __device__ __forceinline__ void put_result(double *__restrict__ rhs, const StageArgs &sa, long long o, double d,
                                            double h, int accumulate) {
     const double L = accumulate ? rhs[o] + d : d;
@@ -145,9 +156,18 @@ __device__ __forceinline__ void put_result(double *__restrict__ rhs, const Stage
     sa.Uout[o] = sa.a == 0.0 ? sa.b * v : sa.a * sa.U0[o] + sa.b * v;
 }
 
+// ---------------------------------------------------------------------------
+// x sweep: faces linearised over interior rows (face i of row r = the face
+// between interior cells i-1 and i, i = 0..nx).  A block of 256 threads takes
+// 256 consecutive faces and blocks overlap by one face, so every cell whose
+// two faces lie in a block gets (F^_{i-1/2} - F^_{i+1/2}) / dx there; the
+// fluxes go straight to LDS as they are produced.
+// ---------------------------------------------------------------------------
+constexpr int kXBlock = 256;
+
 template <int NS, typename R>
 __global__ __launch_bounds__(kXBlock) void k_sweep_x(const double *__restrict__ U, const double *__restrict__ P,
-                                                     double *__restrict__ rhs, Geo g, ThermoK<R> th,
+                                                     double *__restrict__ rhs, Geo g, ThermoK<R> th, int accumulate,
                                                      StageArgs sa, unsigned *status) {
     constexpr int NV = NS + 4;
     __shared__ R sF[NV][kXBlock];
@@ -158,7 +178,6 @@ __global__ __launch_bounds__(kXBlock) void k_sweep_x(const double *__restrict__ 
     const bool valid = f < nfaces;
     long long row = 0;
     int i = 0;
-    R F[NV];
     unsigned flags = 0;
     long long rowbase = 0;
     if (valid) {
@@ -167,9 +186,7 @@ __global__ __launch_bounds__(kXBlock) void k_sweep_x(const double *__restrict__ 
         const int j = (int)(row % g.ny), k = (int)(row / g.ny);
         rowbase = (long long)(g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + g.gx;
         Stencil st{U, P, rowbase + i - 3, 1, g.cells};
-        face_flux<NS, R, 0>(st, th, F, flags);
-#pragma unroll
-        for (int q = 0; q < NV; ++q) sF[q][t] = F[q];
+        face_flux_to<NS, R, 0, SweepFence<R>::x>(st, th, [&](int q, R v) { sF[q][t] = v; }, flags);
     }
     __syncthreads();
     if (valid && t > 0 && i > 0) {
@@ -178,28 +195,52 @@ __global__ __launch_bounds__(kXBlock) void k_sweep_x(const double *__restrict__ 
         const double h = sa.on ? (sa.dt_dev ? *sa.dt_dev : sa.dt) : 0.0;
 #pragma unroll
         for (int q = 0; q < NV; ++q)
-            put_result(rhs, sa, q * g.cells + cell, double((sF[q][t - 1] - F[q]) * id), h, 0);
+            put_result(rhs, sa, q * g.cells + cell, double((sF[q][t - 1] - sF[q][t]) * id), h, accumulate);
     }
     if (flags) atomicOr(status, flags);
 }
 
 // ---------------------------------------------------------------------------
 // y/z sweeps: lanes run along x (coalesced), each thread marches one column
-// through a segment of the sweep axis, computing faces j-1/2 for
-// j = j0..j1 and updating cells j0..j1-1 with the previous face's flux held in
-// registers.  Segments are disjoint, so every cell is written by one thread.
+// through a segment of the sweep axis, computing faces j-1/2 for j = j0..j1
+// and finishing cell j-1 as soon as face j-1/2 is known; the previous face's
+// flux waits in a per-thread LDS slot.  Segments are disjoint, so every cell
+// is written by one thread.  Blocks are numbered so that the x-blocks that
+// share the same rows run on the same XCD (blocks are dealt to the 8 XCDs
+// round robin), which keeps the six-row reuse window in one L2.
 // ---------------------------------------------------------------------------
-template <int NS, typename R, int DIR>
+constexpr int kNumXcd = 8;
+
+__device__ __forceinline__ void xcd_block(unsigned &bx, unsigned &by, unsigned &bz) {
+    const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+    const unsigned n = gx * gy * gz;
+    const unsigned b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    // dispatch order b goes to XCD b % 8; give consecutive logical ids to the
+    // blocks one XCD receives (only when the count divides evenly)
+    unsigned l = b;
+    if (n % kNumXcd == 0) l = (b % kNumXcd) * (n / kNumXcd) + b / kNumXcd;
+    bx = l % gx;
+    by = (l / gx) % gy;
+    bz = l / (gx * gy);
+}
+
+// VAR 0: the previous face's flux waits in a per-thread LDS slot; VAR 1: in
+// registers (two NV-vectors live across the face computation).
+template <int NS, typename R, int DIR, int VAR>
 __global__ __launch_bounds__(256) void k_sweep_march(const double *__restrict__ U, const double *__restrict__ P,
                                                      double *__restrict__ rhs, Geo g, ThermoK<R> th,
                                                      int seglen, int accumulate, StageArgs sa, unsigned *status) {
     constexpr int NV = NS + 4;
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int tr = blockIdx.y * 4 + threadIdx.y;
+    __shared__ R sFp[VAR == 0 ? NV : 1][256];
+    unsigned bx, by, bz;
+    xcd_block(bx, by, bz);
+    const int x = bx * 64 + threadIdx.x;
+    const int tr = by * 4 + threadIdx.y;
+    const int tid = threadIdx.y * 64 + threadIdx.x;
     const int ntr = (DIR == 1) ? g.nz : g.ny;
     const int nsw = (DIR == 1) ? g.ny : g.nz;
     if (x >= g.nx || tr >= ntr) return;
-    const int j0 = blockIdx.z * seglen;
+    const int j0 = bz * seglen;
     if (j0 >= nsw) return;
     const int j1 = min(j0 + seglen, nsw);
     const long long step = (DIR == 1) ? g.sy : g.sz;
@@ -208,19 +249,35 @@ __global__ __launch_bounds__(256) void k_sweep_march(const double *__restrict__ 
                           ((DIR == 1) ? (long long)(g.gz + tr) * g.sz : (long long)(g.gy + tr) * g.sy);
     const R id = R((DIR == 1) ? g.idy : g.idz);
     const double h = sa.on ? (sa.dt_dev ? *sa.dt_dev : sa.dt) : 0.0;
-    R Fp[NV], F[NV];
     unsigned flags = 0;
-    for (int j = j0; j <= j1; ++j) {
-        Stencil st{U, P, col + (long long)(gs + j - 3) * step, step, g.cells};
-        face_flux<NS, R, DIR>(st, th, F, flags);
-        if (j > j0) {
+    if constexpr (VAR == 0) {
+        for (int j = j0; j <= j1; ++j) {
+            Stencil st{U, P, col + (long long)(gs + j - 3) * step, step, g.cells};
             const long long cell = col + (long long)(gs + j - 1) * step;
-#pragma unroll
-            for (int q = 0; q < NV; ++q)
-                put_result(rhs, sa, q * g.cells + cell, double((Fp[q] - F[q]) * id), h, accumulate);
+            const bool emit = j > j0;
+            face_flux_to<NS, R, DIR, SweepFence<R>::march>(
+                st, th,
+                [&](int q, R v) {
+                    if (emit)
+                        put_result(rhs, sa, q * g.cells + cell, double((sFp[q][tid] - v) * id), h, accumulate);
+                    sFp[q][tid] = v;
+                },
+                flags);
         }
+    } else {
+        R Fp[NV], F[NV];
+        for (int j = j0; j <= j1; ++j) {
+            Stencil st{U, P, col + (long long)(gs + j - 3) * step, step, g.cells};
+            face_flux_to<NS, R, DIR, SweepFence<R>::march>(st, th, [&](int q, R v) { F[q] = v; }, flags);
+            if (j > j0) {
+                const long long cell = col + (long long)(gs + j - 1) * step;
 #pragma unroll
-        for (int q = 0; q < NV; ++q) Fp[q] = F[q];
+                for (int q = 0; q < NV; ++q)
+                    put_result(rhs, sa, q * g.cells + cell, double((Fp[q] - F[q]) * id), h, accumulate);
+            }
+#pragma unroll
+            for (int q = 0; q < NV; ++q) Fp[q] = F[q];
+        }
     }
     if (flags) atomicOr(status, flags);
 }

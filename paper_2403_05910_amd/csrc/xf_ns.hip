@@ -28,19 +28,30 @@ hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumu
     if (dir == 0) {
         const long long nf = (long long)(g.nx + 1) * g.ny * g.nz;
         const unsigned nb = (unsigned)((nf - 1 + (kXBlock - 2)) / (kXBlock - 1));   // blocks overlap by one face
-        hipLaunchKernelGGL((k_sweep_x<NS, R>), dim3(nb), dim3(kXBlock), 0, s, U, P, rhs, g, th, sa, c.status);
+        hipLaunchKernelGGL((k_sweep_x<NS, R>), dim3(nb), dim3(kXBlock), 0, s, U, P, rhs, g, th, accumulate, sa,
+                           c.status);
         return hipGetLastError();
     }
     int nseg, seglen;
     march_shape(g, dir, &nseg, &seglen);
     const int ntr = dir == 1 ? g.nz : g.ny;
     dim3 grid((g.nx + 63) / 64, (ntr + 3) / 4, nseg), block(64, 4);
-    if (dir == 1)
-        hipLaunchKernelGGL((k_sweep_march<NS, R, 1>), grid, block, 0, s, U, P, rhs, g, th, seglen, accumulate,
-                           sa, c.status);
-    else
-        hipLaunchKernelGGL((k_sweep_march<NS, R, 2>), grid, block, 0, s, U, P, rhs, g, th, seglen, accumulate,
-                           sa, c.status);
+    const bool regs = c.variant == 1;
+    if (dir == 1) {
+        if (regs)
+            hipLaunchKernelGGL((k_sweep_march<NS, R, 1, 1>), grid, block, 0, s, U, P, rhs, g, th, seglen, accumulate,
+                               sa, c.status);
+        else
+            hipLaunchKernelGGL((k_sweep_march<NS, R, 1, 0>), grid, block, 0, s, U, P, rhs, g, th, seglen, accumulate,
+                               sa, c.status);
+    } else {
+        if (regs)
+            hipLaunchKernelGGL((k_sweep_march<NS, R, 2, 1>), grid, block, 0, s, U, P, rhs, g, th, seglen, accumulate,
+                               sa, c.status);
+        else
+            hipLaunchKernelGGL((k_sweep_march<NS, R, 2, 0>), grid, block, 0, s, U, P, rhs, g, th, seglen, accumulate,
+                               sa, c.status);
+    }
     return hipGetLastError();
 }
 

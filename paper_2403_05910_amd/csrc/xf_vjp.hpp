@@ -154,6 +154,7 @@ XF_HD void face_vjp(const Stencil &st, const ThermoK<R> &th, const R *Fb, const 
         aP = rmax(aP, rabs(unm + cm));
     }
 
+    XF_FENCE();
     // ================= back-projection cotangents known from Fb ============
     // F_s = Y_s A + h_s; F_m = u (A + gsum) + c n D + t1 h1 + t2 h2;
     // F_E = H A + u_n c D + u_t1 h1 + u_t2 h2 + sum_s (q2 - chi_s / Gam) h_s,
@@ -184,6 +185,7 @@ XF_HD void face_vjp(const Stencil &st, const ThermoK<R> &th, const R *Fb, const 
         Mn_b[m] = R(0);
     }
 
+    XF_FENCE();
     // ================= acoustic pair: forward value and backward ===========
     R Asum, Dif;
     {
@@ -229,6 +231,7 @@ XF_HD void face_vjp(const Stencil &st, const ThermoK<R> &th, const R *Fb, const 
     // ================= tangential pair =====================================
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
+        XF_FENCE();
         const int I = a == 0 ? I1 : I2;
         const int K = a == 0 ? K1 : K2;
         const R uta = a == 0 ? ut1 : ut2;
@@ -256,6 +259,7 @@ XF_HD void face_vjp(const Stencil &st, const ThermoK<R> &th, const R *Fb, const 
     R gsum = R(0);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
+        XF_FENCE();
         const R hsb = Fb[s] + gsum_b + (q2 - chi[s] * iGam) * FbE;
         R gp[6], gm[6], wFb[6], wUb[6];
 #pragma unroll
@@ -289,6 +293,7 @@ XF_HD void face_vjp(const Stencil &st, const ThermoK<R> &th, const R *Fb, const 
     R Gam_b = R(0), ic2_b = R(0);
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
+        XF_FENCE();
         R sc = R(0);
 #pragma unroll
         for (int s = 0; s < NS; ++s) sc += chi[s] * R(st.u(s, m));
@@ -328,6 +333,7 @@ XF_HD void face_vjp(const Stencil &st, const ThermoK<R> &th, const R *Fb, const 
         out.p(0, m, double(pm_bt));
     }
 
+    XF_FENCE();
     // ================= Roe state: c^2, Gamma, chi_s, thermo at T~, averages
     ct_b += R(0.5) * ic2 * cih_b;
     ic2_b += R(0.5) * ct * cih_b;
