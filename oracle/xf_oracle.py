@@ -558,10 +558,26 @@ def rhs(th, grid, U, alpha=None, return_aux=False):
         aux_flags |= FLAG_NAN
     aux["flags"] = aux_flags
     # per-field flux-divergence scale S_f = max |F^_f| / min_d dx_d (the scale
-    # against which round-off of this residual is judged)
+    # against which round-off of this residual is judged), and the same with
+    # a floor at the size of the LLF dissipation term, max_i (|u| + c)_i |U_f,i|
+    # (a field whose flux vanishes, e.g. a species at rest, still carries
+    # round-off of that size)
     dmin = min([grid.d[d] for d in grid.active()] or [1.0])
     aux["scale"] = aux["fmax"] / dmin
+    aux["scale_llf"] = np.maximum(aux["fmax"], dissipation_scale(th, grid, U, prim)) / dmin
     return (out, aux) if return_aux else out
+
+
+def dissipation_scale(th, grid, U, prim=None):
+    """per field, max over interior cells of (max_d |u_d| + c) |U_f|"""
+    iz, iy, ix = grid.interior()
+    if prim is None:
+        with np.errstate(all="ignore"):
+            prim = primitives(th, U)
+    lam = prim["c"].real.copy()
+    lam = lam + np.max(np.abs(prim["u"].real), axis=0)
+    v = lam[None] * np.abs(U.real)
+    return v[:, iz, iy, ix].reshape(U.shape[0], -1).max(axis=1)
 
 
 def rhs_at(th, grid, U, cells, return_fmax=False):
