@@ -54,7 +54,7 @@ size_t align_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace carve-up (byte offsets); every piece 256-byte aligned.
 struct Layout {
-    size_t P, Pbar, mx, L, U0, S2, V0, V1, V2, lam0, mu, total;
+    size_t P, Pbar, mx, L, U0, S2, Ly, Lz, V0, V1, V2, lam0, mu, total;
 };
 
 Layout layout(const xf_ctx *c, int op) {
@@ -78,6 +78,10 @@ Layout layout(const xf_ctx *c, int op) {
     }
     if (op == XF_OP_RK3) {
         l.S2 = o;
+        o += align_up(state);
+        l.Ly = o;
+        o += align_up(state);
+        l.Lz = o;
         o += align_up(state);
     }
     if (op == XF_OP_RK3_VJP) {
@@ -381,37 +385,48 @@ int xf_cfl_dt(xf_ctx *c, const double *U, double cfl, double *dt_dev, void *ws, 
     return XF_OK;
 }
 
-// One SSP-RK3 step with the stage combinations fused into the last sweep of
-// each right-hand side (ping-pong stage buffers S1, S2; stage 3 writes U in
-// place, each cell read and written by one thread).  With cfl > 0 the time
+// One SSP-RK3 step.  Every sweep writes its own residual buffer (stores
+// only: no read-modify-write inside the register-heavy sweep kernels), and a
+// light stage kernel sums them and applies the stage combination (ping-pong
+// stage buffers S1, S2; stage 3 writes U in place).  With cfl > 0 the time
 // step is reduced on the device from the stage-1 primitives of U^n and
-// written to *dt_dev before it is used.
+// written to *dt_out before it is used.
 int rk3_step(xf_ctx *c, double *U, double dt, const double *dt_in, double cfl, double *dt_out, void *ws,
              hipStream_t s) {
     const Layout l = layout(c, XF_OP_RK3);
-    double *P = at<double>(ws, l.P), *L = at<double>(ws, l.L);
+    const LaunchCtx &lc = c->lc;
+    const int n[3] = {lc.g.nx, lc.g.ny, lc.g.nz};
+    double *P = at<double>(ws, l.P);
     double *S1 = at<double>(ws, l.U0), *S2 = at<double>(ws, l.S2);
+    double *Ld[3] = {at<double>(ws, l.L), at<double>(ws, l.Ly), at<double>(ws, l.Lz)};
+    const double *Lsum[3] = {n[0] > 1 ? Ld[0] : nullptr, n[1] > 1 ? Ld[1] : nullptr, n[2] > 1 ? Ld[2] : nullptr};
     unsigned long long *mx = at<unsigned long long>(ws, l.mx);
     const double *h = dt_in;
     double *in[3] = {U, S1, S2};
     double *out[3] = {S1, S2, U};
     const double a[3] = {0.0, 0.75, 1.0 / 3.0};
     const double b[3] = {1.0, 0.25, 2.0 / 3.0};
+    const xf::StageArgs off{};
     for (int k = 0; k < 3; ++k) {
         XF_TRY(fill(c, in[k], s));
-        XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, in[k], P, s); }));
+        XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(lc, in[k], P, s); }));
         if (k == 0 && cfl > 0.0) {
             XF_TRY(timed(c, XF_K_CFL, s, [&] {
                 hipError_t e = xf::launch_cfl_reset(mx, s);
-                if (e == hipSuccess) e = c->ops->cfl(c->lc, U, P, mx, s);
+                if (e == hipSuccess) e = c->ops->cfl(lc, U, P, mx, s);
                 if (e == hipSuccess) e = xf::launch_cfl_finish(mx, cfl, dt_out, s);
                 return e;
             }));
             h = dt_out;
         }
-        const xf::StageArgs sa{U, in[k], out[k], a[k], b[k], dt, h, 1};
-        const int r = sweeps_into(c, in[k], L, P, sa, s);
-        if (r != XF_OK) return r;
+        for (int d = 2; d >= 0; --d) {
+            if (n[d] <= 1) continue;
+            XF_TRY(timed(c, XF_K_SWEEP_X + d, s,
+                         [&] { return c->ops->sweep(lc, d, 0, in[k], P, Ld[d], off, s); }));
+        }
+        XF_TRY(timed(c, XF_K_STAGE, s, [&] {
+            return xf::launch_rk3_stage_sum(lc, c->nv, out[k], U, in[k], Lsum, a[k], b[k], dt, h, s);
+        }));
     }
     XF_TRY(fill(c, U, s));
     return XF_OK;

@@ -92,6 +92,9 @@ hipError_t launch_rk3_stage(const LaunchCtx &, int nv, int stage, double *U, dou
                             const double *L, double dt, const double *dt_dev, hipStream_t);
 hipError_t launch_rk3_stage_vjp(const LaunchCtx &, int nv, int stage, double *lam, double *lam0,
                                 double *mu, const double *dt_dev, double dt, hipStream_t);
+hipError_t launch_rk3_stage_sum(const LaunchCtx &, int nv, double *Uout, const double *U0, const double *Uin,
+                                const double *const L[3], double a, double b, double dt, const double *dt_dev,
+                                hipStream_t);
 hipError_t launch_axpy_state(long long n, double a, const double *x, double b, double *y,
                              hipStream_t);
 hipError_t launch_cfl_reset(unsigned long long *mx, hipStream_t);

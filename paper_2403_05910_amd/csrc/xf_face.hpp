@@ -114,6 +114,24 @@ XF_HD float weno5(float a, float b, float c, float d, float e) {
     return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
 }
 
+// Blocks are dealt to the 8 XCDs of the chip round robin in dispatch order.
+// xcd_block renumbers them so that each XCD receives a contiguous range of
+// logical blocks (blocks that share stencil rows then share one L2).
+constexpr int kNumXcd = 8;
+
+__device__ __forceinline__ void xcd_block(unsigned &bx, unsigned &by, unsigned &bz) {
+    const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+    const unsigned n = gx * gy * gz;
+    const unsigned b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    // dispatch order b goes to XCD b % 8; give consecutive logical ids to the
+    // blocks one XCD receives (only when the count divides evenly)
+    unsigned l = b;
+    if (n % kNumXcd == 0) l = (b % kNumXcd) * (n / kNumXcd) + b / kNumXcd;
+    bx = l % gx;
+    by = (l / gx) % gy;
+    bz = l / (gx * gy);
+}
+
 // Read-only view of a 6-cell stencil along one axis.
 struct Stencil {
     const double *__restrict__ U;

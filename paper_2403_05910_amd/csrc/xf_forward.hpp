@@ -209,21 +209,6 @@ __global__ __launch_bounds__(kXBlock) void k_sweep_x(const double *__restrict__ 
 // share the same rows run on the same XCD (blocks are dealt to the 8 XCDs
 // round robin), which keeps the six-row reuse window in one L2.
 // ---------------------------------------------------------------------------
-constexpr int kNumXcd = 8;
-
-__device__ __forceinline__ void xcd_block(unsigned &bx, unsigned &by, unsigned &bz) {
-    const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
-    const unsigned n = gx * gy * gz;
-    const unsigned b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-    // dispatch order b goes to XCD b % 8; give consecutive logical ids to the
-    // blocks one XCD receives (only when the count divides evenly)
-    unsigned l = b;
-    if (n % kNumXcd == 0) l = (b % kNumXcd) * (n / kNumXcd) + b / kNumXcd;
-    bx = l % gx;
-    by = (l / gx) % gy;
-    bz = l / (gx * gy);
-}
-
 // VAR 0: the previous face's flux waits in a per-thread LDS slot; VAR 1: in
 // registers (two NV-vectors live across the face computation).
 template <int NS, typename R, int DIR, int VAR>

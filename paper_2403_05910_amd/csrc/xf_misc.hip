@@ -116,6 +116,30 @@ __global__ __launch_bounds__(256) void k_rk3_stage(double *U, double *U0, const 
     }
 }
 
+// Stage k of Eq. 16 from per-direction residuals, over the interior cells:
+// Uout = a U0 + b (Uin + h ((Lx + Ly) + Lz)) (a == 0 skips U0; a null L is an
+// inactive direction).  The residual is summed in the x, y, z order.  Uout
+// may alias U0 (each cell is read and written by one thread).
+__global__ __launch_bounds__(256) void k_rk3_stage_sum(double *Uout, const double *U0, const double *Uin,
+                                                       const double *Lx, const double *Ly, const double *Lz, Geo g,
+                                                       int nv, double a, double b, double dt, const double *dt_dev) {
+    const long long nint = (long long)g.nx * g.ny * g.nz;
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nint * nv) return;
+    const long long f = q / nint, r = q - f * nint;
+    const int i = (int)(r % g.nx);
+    const long long r2 = r / g.nx;
+    const int j = (int)(r2 % g.ny), k = (int)(r2 / g.ny);
+    const long long o = f * g.cells + (long long)(g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + (g.gx + i);
+    const double h = dt_dev ? *dt_dev : dt;
+    double L = 0.0;
+    if (Lx) L = Lx[o];
+    if (Ly) L = L + Ly[o];
+    if (Lz) L = L + Lz[o];
+    const double v = Uin[o] + h * L;
+    Uout[o] = a == 0.0 ? b * v : a * U0[o] + b * v;
+}
+
 // y = a x + b y (b == 0 ignores the old y, so y may hold anything)
 __global__ __launch_bounds__(256) void k_axpby(long long n, double a, const double *x, double b, double *y) {
     const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -206,6 +230,15 @@ hipError_t launch_rk3_stage_vjp(const LaunchCtx &c, int nv, int stage, double *l
     const long long n = c.g.cells * nv;
     hipLaunchKernelGGL(k_rk3_stage_vjp, dim3(blocks_for(n, 256)), dim3(256), 0, s, lam, lam0, mu, n, stage, dt,
                        dt_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk3_stage_sum(const LaunchCtx &c, int nv, double *Uout, const double *U0, const double *Uin,
+                                const double *const L[3], double a, double b, double dt, const double *dt_dev,
+                                hipStream_t s) {
+    const long long n = (long long)c.g.nx * c.g.ny * c.g.nz * nv;
+    hipLaunchKernelGGL(k_rk3_stage_sum, dim3(blocks_for(n, 256)), dim3(256), 0, s, Uout, U0, Uin, L[0], L[1], L[2],
+                       c.g, nv, a, b, dt, dt_dev);
     return hipGetLastError();
 }
 

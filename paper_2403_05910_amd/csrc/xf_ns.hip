@@ -36,7 +36,9 @@ hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumu
     march_shape(g, dir, &nseg, &seglen);
     const int ntr = dir == 1 ? g.nz : g.ny;
     dim3 grid((g.nx + 63) / 64, (ntr + 3) / 4, nseg), block(64, 4);
-    const bool regs = c.variant == 1;
+    // FP64: the previous face's flux in registers; FP32: in an LDS slot
+    // (measured faster for each precision); c.variant overrides for measurement
+    const bool regs = c.variant == 0 ? (sizeof(R) == 8) : (c.variant == 1);
     if (dir == 1) {
         if (regs)
             hipLaunchKernelGGL((k_sweep_march<NS, R, 1, 1>), grid, block, 0, s, U, P, rhs, g, th, seglen, accumulate,

@@ -415,10 +415,12 @@ __global__ __launch_bounds__(256) void k_sweep_vjp(const double *__restrict__ U,
                                                    double *__restrict__ Pbar, long long cells, MarchGeo mg,
                                                    ThermoK<R> th, double id, int seglen, int parity) {
     constexpr int NV = NS + 4;
-    const int l = blockIdx.x * 64 + threadIdx.x;
-    const int tr = blockIdx.y * 4 + threadIdx.y;
+    unsigned bx, by, bz;
+    xcd_block(bx, by, bz);
+    const int l = bx * 64 + threadIdx.x;
+    const int tr = by * 4 + threadIdx.y;
     if (l >= mg.nl || tr >= mg.nt) return;
-    const int seg = 2 * blockIdx.z + parity;
+    const int seg = 2 * bz + parity;
     const int j0 = seg * seglen;
     const int nfaces = mg.nsw + 1;
     if (j0 >= nfaces) return;
