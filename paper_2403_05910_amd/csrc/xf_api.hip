@@ -54,7 +54,7 @@ size_t align_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace carve-up (byte offsets); every piece 256-byte aligned.
 struct Layout {
-    size_t P, Pbar, mx, L, U0, S2, Ly, Lz, V0, V1, V2, lam0, mu, total;
+    size_t P, Pbar, mx, L, U0, S2, Ly, Lz, V0, V1, V2, lam0, mu, Uf, Pf, total;
 };
 
 Layout layout(const xf_ctx *c, int op) {
@@ -66,6 +66,12 @@ Layout layout(const xf_ctx *c, int op) {
     o += align_up(4 * cell);
     l.mx = o;
     o += kAlign;
+    if (c->lc.precision == XF_PREC_MIXED) {   // FP32 copies read by the mixed sweeps
+        l.Uf = o;
+        o += align_up((size_t)c->lc.g.cells * sizeof(float) * c->nv);
+        l.Pf = o;
+        o += align_up((size_t)c->lc.g.cells * sizeof(float) * 4);
+    }
     if (op == XF_OP_VJP || op == XF_OP_RK3_VJP) {
         l.Pbar = o;
         o += align_up(2 * cell);
@@ -142,7 +148,23 @@ hipError_t timed(xf_ctx *c, int cls, hipStream_t s, F &&launch) {
 // Primitives, then the active sweeps.  Without a fused stage the residual
 // goes to rhs (ghosts zeroed); with one, the last sweep writes the stage
 // combination and rhs only holds the partial sums of the earlier sweeps.
-int sweeps_into(xf_ctx *c, const double *U, double *rhs, const double *P, const xf::StageArgs &stage,
+// Primitive-variable buffers of one call: P (FP64), and for mixed-precision
+// contexts the FP32 copies Uf, Pf that the sweeps read.
+struct Prim {
+    double *P;
+    float *Uf, *Pf;
+};
+
+Prim prim_bufs(const xf_ctx *c, const Layout &l, void *ws) {
+    const bool mixed = c->lc.precision == XF_PREC_MIXED;
+    return {at<double>(ws, l.P), mixed ? at<float>(ws, l.Uf) : nullptr, mixed ? at<float>(ws, l.Pf) : nullptr};
+}
+
+hipError_t prims(xf_ctx *c, const double *U, const Prim &pb, hipStream_t s) {
+    return timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, pb.P, pb.Uf, pb.Pf, s); });
+}
+
+int sweeps_into(xf_ctx *c, const double *U, double *rhs, const Prim &pb, const xf::StageArgs &stage,
                 hipStream_t s) {
     const LaunchCtx &lc = c->lc;
     const int n[3] = {lc.g.nx, lc.g.ny, lc.g.nz};
@@ -157,17 +179,17 @@ int sweeps_into(xf_ctx *c, const double *U, double *rhs, const double *P, const 
         if (n[d] <= 1) continue;
         const int acc = first ? 0 : 1;
         const xf::StageArgs &sa = d == last ? stage : off;
-        XF_TRY(timed(c, XF_K_SWEEP_X + d, s, [&] { return c->ops->sweep(lc, d, acc, U, P, rhs, sa, s); }));
+        XF_TRY(timed(c, XF_K_SWEEP_X + d, s, [&] { return c->ops->sweep(lc, d, acc, U, pb.P, pb.Uf, pb.Pf, rhs, sa, s); }));
         first = false;
     }
     if (last < 0) return XF_EUNSUPPORTED;   // no active dimension (rejected by xf_create)
     return XF_OK;
 }
 
-int rhs_into(xf_ctx *c, const double *U, double *rhs, double *P, hipStream_t s) {
-    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, P, s); }));
+int rhs_into(xf_ctx *c, const double *U, double *rhs, const Prim &pb, hipStream_t s) {
+    XF_TRY(prims(c, U, pb, s));
     const xf::StageArgs off{};
-    const int r = sweeps_into(c, U, rhs, P, off, s);
+    const int r = sweeps_into(c, U, rhs, pb, off, s);
     if (r != XF_OK) return r;
     XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero_ghosts(c->lc, c->nv, rhs, s); }));
     return XF_OK;
@@ -177,7 +199,7 @@ int rhs_vjp_into(xf_ctx *c, const double *U, const double *rbar, double *Ubar, d
                  hipStream_t s) {
     const LaunchCtx &lc = c->lc;
     const int n[3] = {lc.g.nx, lc.g.ny, lc.g.nz};
-    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(lc, U, P, s); }));
+    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(lc, U, P, nullptr, nullptr, s); }));
     XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero(2 * lc.g.cells, Pbar, s); }));
     for (int d = 0; d < 3; ++d) {
         if (n[d] <= 1) continue;
@@ -366,7 +388,7 @@ int xf_rhs(xf_ctx *c, const double *U, double *rhs, void *ws, void *stream) {
     if (!c || !U || !rhs || !ws || U == rhs || !aligned8(U) || !aligned8(rhs) || !aligned8(ws))
         return XF_EINVAL;
     const Layout l = layout(c, XF_OP_RHS);
-    return rhs_into(c, U, rhs, at<double>(ws, l.P), (hipStream_t)stream);
+    return rhs_into(c, U, rhs, prim_bufs(c, l, ws), (hipStream_t)stream);
 }
 
 int xf_cfl_dt(xf_ctx *c, const double *U, double cfl, double *dt_dev, void *ws, void *stream) {
@@ -375,7 +397,7 @@ int xf_cfl_dt(xf_ctx *c, const double *U, double cfl, double *dt_dev, void *ws, 
     const hipStream_t s = (hipStream_t)stream;
     double *P = at<double>(ws, l.P);
     unsigned long long *mx = at<unsigned long long>(ws, l.mx);
-    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, P, s); }));
+    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, P, nullptr, nullptr, s); }));
     XF_TRY(timed(c, XF_K_CFL, s, [&] {
         hipError_t e = xf::launch_cfl_reset(mx, s);
         if (e == hipSuccess) e = c->ops->cfl(c->lc, U, P, mx, s);
@@ -396,7 +418,8 @@ int rk3_step(xf_ctx *c, double *U, double dt, const double *dt_in, double cfl, d
     const Layout l = layout(c, XF_OP_RK3);
     const LaunchCtx &lc = c->lc;
     const int n[3] = {lc.g.nx, lc.g.ny, lc.g.nz};
-    double *P = at<double>(ws, l.P);
+    const Prim pb = prim_bufs(c, l, ws);
+    double *P = pb.P;
     double *S1 = at<double>(ws, l.U0), *S2 = at<double>(ws, l.S2);
     double *Ld[3] = {at<double>(ws, l.L), at<double>(ws, l.Ly), at<double>(ws, l.Lz)};
     const double *Lsum[3] = {n[0] > 1 ? Ld[0] : nullptr, n[1] > 1 ? Ld[1] : nullptr, n[2] > 1 ? Ld[2] : nullptr};
@@ -409,7 +432,7 @@ int rk3_step(xf_ctx *c, double *U, double dt, const double *dt_in, double cfl, d
     const xf::StageArgs off{};
     for (int k = 0; k < 3; ++k) {
         XF_TRY(fill(c, in[k], s));
-        XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(lc, in[k], P, s); }));
+        XF_TRY(prims(c, in[k], pb, s));
         if (k == 0 && cfl > 0.0) {
             XF_TRY(timed(c, XF_K_CFL, s, [&] {
                 hipError_t e = xf::launch_cfl_reset(mx, s);
@@ -422,7 +445,7 @@ int rk3_step(xf_ctx *c, double *U, double dt, const double *dt_in, double cfl, d
         for (int d = 2; d >= 0; --d) {
             if (n[d] <= 1) continue;
             XF_TRY(timed(c, XF_K_SWEEP_X + d, s,
-                         [&] { return c->ops->sweep(lc, d, 0, in[k], P, Ld[d], off, s); }));
+                         [&] { return c->ops->sweep(lc, d, 0, in[k], P, pb.Uf, pb.Pf, Ld[d], off, s); }));
         }
         XF_TRY(timed(c, XF_K_STAGE, s, [&] {
             return xf::launch_rk3_stage_sum(lc, c->nv, out[k], U, in[k], Lsum, a[k], b[k], dt, h, s);
@@ -460,21 +483,22 @@ int xf_rk3_step_vjp(xf_ctx *c, const double *Un, double dt, double *Ubar, void *
     const hipStream_t s = (hipStream_t)stream;
     const LaunchCtx &lc = c->lc;
     const long long n = lc.g.cells * c->nv;
-    double *P = at<double>(ws, l.P), *Pbar = at<double>(ws, l.Pbar), *L = at<double>(ws, l.L);
+    const Prim pb = prim_bufs(c, l, ws);
+    double *P = pb.P, *Pbar = at<double>(ws, l.Pbar), *L = at<double>(ws, l.L);
     double *V0 = at<double>(ws, l.V0), *V1 = at<double>(ws, l.V1), *V2 = at<double>(ws, l.V2);
     double *lam0 = at<double>(ws, l.lam0), *mu = at<double>(ws, l.mu);
     int r;
     // forward stage states V0 = G(U_n), V1 = G(V0 + dt L(V0)), V2 = G(3/4 V0 + 1/4 (V1 + dt L(V1)))
     XF_TRY(timed(c, XF_K_STAGE, s, [&] { return xf::launch_copy(n, Un, V0, s); }));
     XF_TRY(fill(c, V0, s));
-    if ((r = rhs_into(c, V0, L, P, s)) != XF_OK) return r;
+    if ((r = rhs_into(c, V0, L, pb, s)) != XF_OK) return r;
     XF_TRY(timed(c, XF_K_STAGE, s, [&] {
         hipError_t e = xf::launch_copy(n, V0, V1, s);
         if (e == hipSuccess) e = xf::launch_axpy_state(n, dt, L, 1.0, V1, s);
         return e;
     }));
     XF_TRY(fill(c, V1, s));
-    if ((r = rhs_into(c, V1, L, P, s)) != XF_OK) return r;
+    if ((r = rhs_into(c, V1, L, pb, s)) != XF_OK) return r;
     XF_TRY(timed(c, XF_K_STAGE, s, [&] {
         hipError_t e = xf::launch_copy(n, V1, V2, s);
         if (e == hipSuccess) e = xf::launch_axpy_state(n, dt, L, 1.0, V2, s);

@@ -66,11 +66,13 @@ struct LaunchCtx {
 
 // Per species-count entry points (one translation unit per N).
 struct NsOps {
-    // primitive variables (T, p, c, 1/rho) of every cell a stencil reads
-    hipError_t (*prims)(const LaunchCtx &, const double *U, double *P, hipStream_t);
-    // one direction of the convective flux difference; accumulate: rhs += or rhs =
-    hipError_t (*sweep)(const LaunchCtx &, int dir, int accumulate, const double *U,
-                        const double *P, double *rhs, const StageArgs &stage, hipStream_t);
+    // primitive variables (T, p, c, 1/rho) of every cell a stencil reads;
+    // with Uf, Pf also FP32 copies of U and P for the mixed-precision sweeps
+    hipError_t (*prims)(const LaunchCtx &, const double *U, double *P, float *Uf, float *Pf, hipStream_t);
+    // one direction of the convective flux difference; accumulate: rhs += or
+    // rhs =.  FP64 sweeps read U, P; mixed-precision sweeps read Uf, Pf.
+    hipError_t (*sweep)(const LaunchCtx &, int dir, int accumulate, const double *U, const double *P,
+                        const float *Uf, const float *Pf, double *rhs, const StageArgs &stage, hipStream_t);
     // VJP of one direction: Ubar_direct += (dF/dU)^T ..., Pbar += (dF/d(p, T))^T ...
     hipError_t (*sweep_vjp)(const LaunchCtx &, int dir, const double *U, const double *P,
                             const double *rbar, double *Ubar, double *Pbar, hipStream_t);

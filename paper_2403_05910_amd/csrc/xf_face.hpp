@@ -132,16 +132,19 @@ __device__ __forceinline__ void xcd_block(unsigned &bx, unsigned &by, unsigned &
     bz = l / (gx * gy);
 }
 
-// Read-only view of a 6-cell stencil along one axis.
-struct Stencil {
-    const double *__restrict__ U;
-    const double *__restrict__ P;   // [4][cells]: T, p, c, 1/rho
+// Read-only view of a 6-cell stencil along one axis; S is the storage type
+// (FP64 state, or the FP32 copies the mixed path sweeps read).
+template <typename S>
+struct StencilT {
+    const S *__restrict__ U;
+    const S *__restrict__ P;        // [4][cells]: T, p, c, 1/rho
     long long base;                 // padded index of stencil cell 0 (= i-2)
     long long step;                 // index stride along the sweep axis
     long long cells;                // field stride
-    XF_HD double u(int f, int m) const { return U[f * cells + base + m * step]; }
-    XF_HD double p(int k, int m) const { return P[k * cells + base + m * step]; }
+    XF_HD S u(int f, int m) const { return U[f * cells + base + m * step]; }
+    XF_HD S p(int k, int m) const { return P[k * cells + base + m * step]; }
 };
+using Stencil = StencilT<double>;
 
 template <int DIR>
 struct Axes {
@@ -155,8 +158,8 @@ struct Axes {
 // as soon as it is final (species first, then momentum and energy), so the
 // caller decides where it lives.  flags collects XF_FLAG_C2 if the face c^2
 // is not positive.  FENCE inserts compiler fences between the phases.
-template <int NS, typename R, int DIR, bool FENCE = false, class Out>
-XF_HD void face_flux_to(const Stencil &st, const ThermoK<R> &th, Out &&out, unsigned &flags) {
+template <int NS, typename R, int DIR, bool FENCE = false, class St, class Out>
+XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned &flags) {
     constexpr int IM = NS;
     constexpr int IE = NS + 3;
     constexpr int IN = NS + Axes<DIR>::n;

@@ -64,9 +64,12 @@ XF_HD bool newton_T(const ThermoK<double> &th, const double *Y, double e, double
 
 // P[0..3][cell] = (T, p, c, 1/rho) for every cell with at most one
 // coordinate in a ghost layer (the cells axis-aligned stencils read).
+// Uf, Pf (optional): FP32 copies of U and of (T, p, c, 1/rho) for the
+// mixed-precision sweeps, written for the same cells.
 template <int NS>
 __global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, double *__restrict__ P, Geo g,
-                                               ThermoK<double> th, unsigned *status) {
+                                               ThermoK<double> th, unsigned *status, float *__restrict__ Uf,
+                                               float *__restrict__ Pf) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= g.cells) return;
     const int x = (int)(idx % g.px);
@@ -119,6 +122,14 @@ __global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, dou
     P[C + idx] = p;
     P[2 * C + idx] = c;
     P[3 * C + idx] = rinv;
+    if (Uf) {
+#pragma unroll
+        for (int f = 0; f < NS + 4; ++f) Uf[f * C + idx] = (float)U[f * C + idx];
+        Pf[idx] = (float)T;
+        Pf[C + idx] = (float)p;
+        Pf[2 * C + idx] = (float)c;
+        Pf[3 * C + idx] = (float)rinv;
+    }
     if (flags) atomicOr(status, flags);
 }
 
@@ -165,8 +176,8 @@ __device__ __forceinline__ void put_result(double *__restrict__ rhs, const Stage
 // ---------------------------------------------------------------------------
 constexpr int kXBlock = 256;
 
-template <int NS, typename R>
-__global__ __launch_bounds__(kXBlock) void k_sweep_x(const double *__restrict__ U, const double *__restrict__ P,
+template <int NS, typename R, typename S>
+__global__ __launch_bounds__(kXBlock) void k_sweep_x(const S *__restrict__ U, const S *__restrict__ P,
                                                      double *__restrict__ rhs, Geo g, ThermoK<R> th, int accumulate,
                                                      StageArgs sa, unsigned *status) {
     constexpr int NV = NS + 4;
@@ -185,7 +196,7 @@ __global__ __launch_bounds__(kXBlock) void k_sweep_x(const double *__restrict__ 
         i = (int)(f - row * nfx);
         const int j = (int)(row % g.ny), k = (int)(row / g.ny);
         rowbase = (long long)(g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + g.gx;
-        Stencil st{U, P, rowbase + i - 3, 1, g.cells};
+        StencilT<S> st{U, P, rowbase + i - 3, 1, g.cells};
         face_flux_to<NS, R, 0, SweepFence<R>::x>(st, th, [&](int q, R v) { sF[q][t] = v; }, flags);
     }
     __syncthreads();
@@ -211,8 +222,8 @@ __global__ __launch_bounds__(kXBlock) void k_sweep_x(const double *__restrict__ 
 // ---------------------------------------------------------------------------
 // VAR 0: the previous face's flux waits in a per-thread LDS slot; VAR 1: in
 // registers (two NV-vectors live across the face computation).
-template <int NS, typename R, int DIR, int VAR>
-__global__ __launch_bounds__(256) void k_sweep_march(const double *__restrict__ U, const double *__restrict__ P,
+template <int NS, typename R, int DIR, int VAR, typename S>
+__global__ __launch_bounds__(256) void k_sweep_march(const S *__restrict__ U, const S *__restrict__ P,
                                                      double *__restrict__ rhs, Geo g, ThermoK<R> th,
                                                      int seglen, int accumulate, StageArgs sa, unsigned *status) {
     constexpr int NV = NS + 4;
@@ -237,7 +248,7 @@ __global__ __launch_bounds__(256) void k_sweep_march(const double *__restrict__ 
     unsigned flags = 0;
     if constexpr (VAR == 0) {
         for (int j = j0; j <= j1; ++j) {
-            Stencil st{U, P, col + (long long)(gs + j - 3) * step, step, g.cells};
+            StencilT<S> st{U, P, col + (long long)(gs + j - 3) * step, step, g.cells};
             const long long cell = col + (long long)(gs + j - 1) * step;
             const bool emit = j > j0;
             face_flux_to<NS, R, DIR, SweepFence<R>::march>(
@@ -252,7 +263,7 @@ __global__ __launch_bounds__(256) void k_sweep_march(const double *__restrict__ 
     } else {
         R Fp[NV], F[NV];
         for (int j = j0; j <= j1; ++j) {
-            Stencil st{U, P, col + (long long)(gs + j - 3) * step, step, g.cells};
+            StencilT<S> st{U, P, col + (long long)(gs + j - 3) * step, step, g.cells};
             face_flux_to<NS, R, DIR, SweepFence<R>::march>(st, th, [&](int q, R v) { F[q] = v; }, flags);
             if (j > j0) {
                 const long long cell = col + (long long)(gs + j - 1) * step;

@@ -15,20 +15,20 @@ constexpr int NS = XF_NS;
 
 unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-hipError_t prims(const LaunchCtx &c, const double *U, double *P, hipStream_t s) {
+hipError_t prims(const LaunchCtx &c, const double *U, double *P, float *Uf, float *Pf, hipStream_t s) {
     hipLaunchKernelGGL(k_prims<NS>, dim3(blocks_for(c.g.cells, 256)), dim3(256), 0, s, U, P, c.g, c.th64,
-                       c.status);
+                       c.status, Uf, Pf);
     return hipGetLastError();
 }
 
-template <typename R>
-hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumulate, const double *U,
-                   const double *P, double *rhs, const StageArgs &sa, hipStream_t s) {
+template <typename R, typename S>
+hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumulate, const S *U, const S *P,
+                   double *rhs, const StageArgs &sa, hipStream_t s) {
     const Geo &g = c.g;
     if (dir == 0) {
         const long long nf = (long long)(g.nx + 1) * g.ny * g.nz;
         const unsigned nb = (unsigned)((nf - 1 + (kXBlock - 2)) / (kXBlock - 1));   // blocks overlap by one face
-        hipLaunchKernelGGL((k_sweep_x<NS, R>), dim3(nb), dim3(kXBlock), 0, s, U, P, rhs, g, th, accumulate, sa,
+        hipLaunchKernelGGL((k_sweep_x<NS, R, S>), dim3(nb), dim3(kXBlock), 0, s, U, P, rhs, g, th, accumulate, sa,
                            c.status);
         return hipGetLastError();
     }
@@ -41,26 +41,26 @@ hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumu
     const bool regs = c.variant == 0 ? (sizeof(R) == 8) : (c.variant == 1);
     if (dir == 1) {
         if (regs)
-            hipLaunchKernelGGL((k_sweep_march<NS, R, 1, 1>), grid, block, 0, s, U, P, rhs, g, th, seglen, accumulate,
-                               sa, c.status);
+            hipLaunchKernelGGL((k_sweep_march<NS, R, 1, 1, S>), grid, block, 0, s, U, P, rhs, g, th, seglen,
+                               accumulate, sa, c.status);
         else
-            hipLaunchKernelGGL((k_sweep_march<NS, R, 1, 0>), grid, block, 0, s, U, P, rhs, g, th, seglen, accumulate,
-                               sa, c.status);
+            hipLaunchKernelGGL((k_sweep_march<NS, R, 1, 0, S>), grid, block, 0, s, U, P, rhs, g, th, seglen,
+                               accumulate, sa, c.status);
     } else {
         if (regs)
-            hipLaunchKernelGGL((k_sweep_march<NS, R, 2, 1>), grid, block, 0, s, U, P, rhs, g, th, seglen, accumulate,
-                               sa, c.status);
+            hipLaunchKernelGGL((k_sweep_march<NS, R, 2, 1, S>), grid, block, 0, s, U, P, rhs, g, th, seglen,
+                               accumulate, sa, c.status);
         else
-            hipLaunchKernelGGL((k_sweep_march<NS, R, 2, 0>), grid, block, 0, s, U, P, rhs, g, th, seglen, accumulate,
-                               sa, c.status);
+            hipLaunchKernelGGL((k_sweep_march<NS, R, 2, 0, S>), grid, block, 0, s, U, P, rhs, g, th, seglen,
+                               accumulate, sa, c.status);
     }
     return hipGetLastError();
 }
 
-hipError_t sweep(const LaunchCtx &c, int dir, int accumulate, const double *U, const double *P, double *rhs,
-                 const StageArgs &sa, hipStream_t s) {
-    if (c.precision == XF_PREC_MIXED) return sweep_t<float>(c, c.th32, dir, accumulate, U, P, rhs, sa, s);
-    return sweep_t<double>(c, c.th64, dir, accumulate, U, P, rhs, sa, s);
+hipError_t sweep(const LaunchCtx &c, int dir, int accumulate, const double *U, const double *P, const float *Uf,
+                 const float *Pf, double *rhs, const StageArgs &sa, hipStream_t s) {
+    if (c.precision == XF_PREC_MIXED) return sweep_t<float, float>(c, c.th32, dir, accumulate, Uf, Pf, rhs, sa, s);
+    return sweep_t<double, double>(c, c.th64, dir, accumulate, U, P, rhs, sa, s);
 }
 
 MarchGeo march_geo(const Geo &g, int dir) {

@@ -231,3 +231,43 @@ def test_full_size_sampled_parity(which):
     err = field_err(rg, ro, scale)
     print(f"[parity] {which} sampled max err / S_f = {err.max():.3e}", flush=True)
     assert err.max() <= TOL, err
+
+
+# Mixed precision: FP32 arithmetic in the sweeps, FP64 primitives and
+# accumulation.  One FP32 face flux carries relative round-off of a few
+# hundred ulp (the characteristic projections sum O(N) terms, the WENO
+# weights divide by (eps + beta)^2), so the residual is held to 2e-5 S_f and
+# the state after a few RK3 steps to 1e-5 of each field's largest magnitude.
+MIXED_RHS_TOL = 2e-5
+MIXED_STATE_TOL = 1e-5
+
+
+@pytest.mark.parametrize("name", ["ragged3d_n3_outflow_x", "n9_3d_mixed_bc", "inert_sbi_32", "nine_sbi_32",
+                                  "plane2d_n3", "z_only_n3"])
+def test_rhs_mixed_within_fp32_bound(name):
+    case = CASES[name]
+    r_gpu, flags, _ = gpu_rhs(case, "mixed")
+    r_ora, aux, _ = oracle_rhs(case)
+    assert flags == 0
+    err = field_err(r_gpu, r_ora, aux["scale_llf"])
+    print(f"[parity] mixed {name} max err / S_f = {err.max():.3e}", flush=True)
+    assert err.max() <= MIXED_RHS_TOL, err
+
+
+@pytest.mark.parametrize("name,steps", [("inert_sbi_32", 5), ("n9_3d_mixed_bc", 3)])
+def test_rk3_mixed_within_fp32_bound(name, steps):
+    xf = _xf()
+    case = CASES[name]
+    th, g = oracle_objects(case)
+    Uo = O.fill_ghosts(g, case.U)
+    dt = 0.5 * O.cfl_dt(th, g, Uo, 0.5)
+    ctx = xf.Context.from_case(case, "mixed")
+    U = ctx.state_from_numpy(case.U)
+    for _ in range(steps):
+        Uo = O.rk3_step(th, g, Uo, dt)
+        ctx.rk3_step(U, dt)
+    assert ctx.status() == 0
+    scale = np.abs(Uo).reshape(Uo.shape[0], -1).max(axis=1)
+    err = field_err(U.cpu().numpy(), Uo, scale)
+    print(f"[parity] mixed rk3 {name} {steps} steps max err {err.max():.3e}", flush=True)
+    assert err.max() <= MIXED_STATE_TOL, err
