@@ -74,6 +74,58 @@ def roofline_of(kernels, case, precision):
             "flops_per_launch": flops}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+def rollout_ratio(torch, xf, n=64, steps=64, every=8):
+    """checkpointed RK3 rollout on the 5-species periodic mixture at n^3:
+    wall time of the plain forward (steps RK3 steps), of the checkpointed
+    forward and of its backward (segment recompute + RK3-step VJPs)"""
+    from paper_2403_05910_amd import workloads as W
+    case = W.periodic_mixture(n)
+    ctx = xf.Context.from_case(case)
+    U0 = ctx.state_from_numpy(case.U)
+    ctx.fill_ghosts(U0)
+    dt = 0.5 * ctx.cfl_dt(U0, 0.5).item()
+
+    def plain():
+        U = U0.clone()
+        for _ in range(steps):
+            ctx.rk3_step(U, dt)
+        return U
+
+    def clock(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    plain()
+    t_plain, _ = clock(plain)
+    g = torch.randn(ctx.shape, dtype=torch.float64, device=U0.device)
+    for rep in range(2):   # the first repetition warms up
+        X = U0.clone().requires_grad_(True)
+        t_fwd, Y = clock(lambda: xf.rollout(ctx, X, dt, steps, every))
+        torch.cuda.reset_peak_memory_stats()
+        t_bwd, _ = clock(lambda: Y.backward(g))
+        peak = torch.cuda.max_memory_allocated()
+        del X, Y
+    ctx.close()
+    return {"workload": f"periodic_mixture_{n}^3 (5 species)", "steps": steps, "ckpt_every": every,
+            "ms_forward_plain": t_plain * 1e3, "ms_forward_checkpointed": t_fwd * 1e3,
+            "ms_backward": t_bwd * 1e3, "backward_over_forward": t_bwd / t_plain,
+            "peak_bytes_during_backward": peak}
+
+
 def cpu_baseline(case, crop=56):
     """the oracle as it stands, on a crop^3 block of the same state (its
     halo taken from the neighbouring cells), straddling the shock and bubble"""
@@ -91,7 +143,7 @@ def cpu_baseline(case, crop=56):
     dt = time.perf_counter() - t0
     return {"value": crop ** 3 / dt, "unit": "cell-RHS evals/s", "cores": 1, "kind": "oracle",
             "sample": f"one FP64 RHS of a {crop}^3 crop (with its 3-cell halo) of the same state, "
-                      f"x0={x0}, y0={y0}, z0={z0}; numpy, single thread",
+                      f"x0={x0}, y0={y0}, z0={z0}; numpy, single thread, on {cpu_model()}",
             "seconds": dt}
 
 
@@ -178,10 +230,10 @@ def main():
         vm = 3 * cells * a.steps / secs_m
         log(f"[bench] mixed: {secs_m / a.steps * 1e3:.2f} ms/step, {vm:.3e} cell-RHS/s")
         # accuracy of the mixed path: both paths advance the same state by
-        # the same K steps at one fixed dt; per conservative field, the
-        # largest and the mean deviation relative to the field's largest
-        # magnitude (a residual compared directly is ill-posed where a flux
-        # vanishes, e.g. a species at rest)
+        # the same K steps at one fixed dt; then density, pressure (relative
+        # to their largest value) and mass fractions (absolute) of the two
+        # results, L_inf and mean over the interior.  (A residual compared
+        # directly is ill-posed where a flux vanishes, e.g. a species at rest.)
         V = U0.clone()
         ctx.fill_ghosts(V)
         dt_fix = ctx.cfl_dt(V, a.cfl).item()
@@ -189,20 +241,24 @@ def main():
         for _ in range(a.steps):
             ctx.rk3_step(Va, dt_fix)
             ctxm.rk3_step(Vb, dt_fix)
-        nv = ns + 4
-        ia, ib = Va[ctx.interior].reshape(nv, -1), Vb[ctx.interior].reshape(nv, -1)
-        d = (ib - ia).abs()
-        mag = ia.abs().amax(dim=1)
-        linf = (d.amax(dim=1) / mag).cpu().numpy()
-        l1 = (d.mean(dim=1) / mag).cpu().numpy()
-        del Va, Vb, ia, ib, d
+        inner = ctx.interior[1:]
+        pa, pb = ctx.primitives(Va)[(slice(None),) + inner], ctx.primitives(Vb)[(slice(None),) + inner]
+        ra, rb_ = 1.0 / pa[3], 1.0 / pb[3]
+        Ya, Yb = Va[ctx.interior][:ns] * pa[3], Vb[ctx.interior][:ns] * pb[3]
+
+        def errs(x, y, scale):
+            d = (x - y).abs()
+            return {"linf": float(d.max() / scale), "mean": float(d.mean() / scale)}
+
+        state_err = {"steps": a.steps, "dt": dt_fix, "vs": "FP64 path (itself within 1e-12 of the oracle)",
+                     "rho_rel": errs(rb_, ra, ra.abs().max()), "p_rel": errs(pb[1], pa[1], pa[1].abs().max()),
+                     "T_rel": errs(pb[0], pa[0], pa[0].abs().max()),
+                     "Y_abs": [errs(Yb[k], Ya[k], 1.0) for k in range(ns)]}
+        del Va, Vb, pa, pb, ra, rb_, Ya, Yb
         r64 = ctx.rhs(V)
         out["mixed"] = {"value": vm, "unit": "cell-RHS evals/s", "ms_per_step": secs_m / a.steps * 1e3,
                         "speedup_vs_fp64": vm / value,
-                        "state_err_after_steps": {
-                            "steps": a.steps, "dt": dt_fix,
-                            "linf_over_field_max": [float(x) for x in linf],
-                            "mean_over_field_max": [float(x) for x in l1]},
+                        "state_err_after_steps": state_err,
                         "roofline": roofline_of(kern_m, case, "mixed"),
                         "kernel_avg_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kern_m.items() if v[1]},
                         "flags": ctxm.status()}
@@ -247,6 +303,8 @@ def main():
             out["adjoint"]["rk3_adjoint_over_forward_step"] = t_rk3v / (secs / a.steps)
         except Exception as e:  # workspace too large for the device
             out["adjoint"]["rk3_step_vjp_error"] = str(e)
+        out["adjoint"]["rollout"] = rollout_ratio(torch, xf)
+        log(f"[bench] rollout backward/forward {out['adjoint']['rollout']['backward_over_forward']:.2f}")
     if not a.no_cpu:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(case)

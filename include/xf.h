@@ -128,6 +128,15 @@ int xf_fill_ghosts(xf_ctx *ctx, double *U, void *stream);
  * ws: xf_workspace_bytes(ctx, XF_OP_RHS) bytes. */
 int xf_rhs(xf_ctx *ctx, const double *U, double *rhs, void *ws, void *stream);
 
+/* Primitive variables of every cell (interior and ghosts): prim is
+ * [4][cells] FP64 (cells = xf_state_elems / Nv, the padded extent), holding
+ * T from the Newton iteration on the mixture internal energy (Eq. 21), p from
+ * the mixture equation of state (Eq. 7), the frozen sound speed c, and 1/rho.
+ * Non-physical cells set the status bits as in xf_rhs.  U's ghost layers
+ * must be valid for the ghost entries to be meaningful.  Caller-owned prim;
+ * no workspace.  Computed in FP64 in both precisions. */
+int xf_primitives(xf_ctx *ctx, const double *U, double *prim, void *stream);
+
 /* dt = cfl / max_i sum_{d active} (|u_d| + c)_i / dx_d over the interior
  * (Eq. 17 per direction, summed), written to the device double *dt_dev.
  * ws: xf_workspace_bytes(ctx, XF_OP_RHS) bytes. */

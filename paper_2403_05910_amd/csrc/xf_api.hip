@@ -391,6 +391,13 @@ int xf_rhs(xf_ctx *c, const double *U, double *rhs, void *ws, void *stream) {
     return rhs_into(c, U, rhs, prim_bufs(c, l, ws), (hipStream_t)stream);
 }
 
+int xf_primitives(xf_ctx *c, const double *U, double *prim, void *stream) {
+    if (!c || !U || !prim || !aligned8(U) || !aligned8(prim)) return XF_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, prim, nullptr, nullptr, s); }));
+    return XF_OK;
+}
+
 int xf_cfl_dt(xf_ctx *c, const double *U, double cfl, double *dt_dev, void *ws, void *stream) {
     if (!c || !U || !dt_dev || !ws || !(cfl > 0.0) || !aligned8(U) || !aligned8(ws)) return XF_EINVAL;
     const Layout l = layout(c, XF_OP_RHS);

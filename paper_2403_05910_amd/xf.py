@@ -57,6 +57,7 @@ _ws_bytes = _sig("xf_workspace_bytes", _c_size_t, _vp, _c_int)
 _fill = _sig("xf_fill_ghosts", _c_int, _vp, _vp, _vp)
 _fill_vjp = _sig("xf_fill_ghosts_vjp", _c_int, _vp, _vp, _vp)
 _rhs = _sig("xf_rhs", _c_int, _vp, _vp, _vp, _vp, _vp)
+_prims = _sig("xf_primitives", _c_int, _vp, _vp, _vp, _vp)
 _cfl = _sig("xf_cfl_dt", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
 _rk3 = _sig("xf_rk3_step", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
 _rk3_cfl = _sig("xf_rk3_step_cfl", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
@@ -68,7 +69,7 @@ _timing_read = _sig("xf_timing_read", _c_int, _vp, _vp, _dp, ctypes.POINTER(ctyp
 _strerror = _sig("xf_strerror", ctypes.c_char_p, _c_int)
 
 EXPORTED = ["xf_create", "xf_destroy", "xf_state_elems", "xf_workspace_bytes", "xf_fill_ghosts",
-            "xf_fill_ghosts_vjp", "xf_rhs", "xf_cfl_dt", "xf_rk3_step", "xf_rk3_step_cfl", "xf_rhs_vjp", "xf_rk3_step_vjp",
+            "xf_fill_ghosts_vjp", "xf_rhs", "xf_primitives", "xf_cfl_dt", "xf_rk3_step", "xf_rk3_step_cfl", "xf_rhs_vjp", "xf_rk3_step_vjp",
             "xf_status", "xf_strerror", "xf_timing", "xf_timing_read"]
 KERNEL_CLASSES = ["prims", "sweep_x", "sweep_y", "sweep_z", "fill", "stage", "cfl", "zero",
                   "vjp_x", "vjp_y", "vjp_z", "prims_vjp", "fill_vjp"]
@@ -121,6 +122,10 @@ def xf_fill_ghosts_vjp(ctx, Ubar, stream):
 
 def xf_rhs(ctx, U, rhs, ws, stream):
     return _check(_rhs(ctx, U, rhs, ws, stream), "xf_rhs")
+
+
+def xf_primitives(ctx, U, prim, stream):
+    return _check(_prims(ctx, U, prim, stream), "xf_primitives")
 
 
 def xf_cfl_dt(ctx, U, cfl, dt_dev, ws, stream):
@@ -238,10 +243,11 @@ class Context:
         assert tuple(U.shape) == self.shape, (U.shape, self.shape)
         return torch.from_numpy(np.ascontiguousarray(U, dtype=np.float64)).to(self.device)
 
-    def _ptr(self, t):
+    def _ptr(self, t, shape=None):
         torch = _torch()
-        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == self.shape):
-            raise ValueError(f"expected a contiguous float64 device tensor of shape {self.shape}")
+        shape = self.shape if shape is None else shape
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == shape):
+            raise ValueError(f"expected a contiguous float64 device tensor of shape {shape}")
         return t.data_ptr()
 
     @staticmethod
@@ -260,6 +266,13 @@ class Context:
     def rhs(self, U, out=None):
         out = self.new_state() if out is None else out
         xf_rhs(self.handle, self._ptr(U), self._ptr(out), self.workspace(XF_OP_RHS), self._stream())
+        return out
+
+    def primitives(self, U, out=None):
+        """(T, p, c, 1/rho) of every padded cell, shape (4,) + the padded grid"""
+        torch = _torch()
+        out = torch.empty((4,) + self.shape[1:], dtype=torch.float64, device=self.device) if out is None else out
+        xf_primitives(self.handle, self._ptr(U), self._ptr(out, (4,) + self.shape[1:]), self._stream())
         return out
 
     def cfl_dt(self, U, cfl, out=None):

@@ -271,3 +271,23 @@ def test_rk3_mixed_within_fp32_bound(name, steps):
     err = field_err(U.cpu().numpy(), Uo, scale)
     print(f"[parity] mixed rk3 {name} {steps} steps max err {err.max():.3e}", flush=True)
     assert err.max() <= MIXED_STATE_TOL, err
+
+
+@pytest.mark.parametrize("name", ["n9_3d_mixed_bc", "sod_400", "inert_sbi_32"])
+def test_primitives_match_oracle(name):
+    xf = _xf()
+    case = CASES[name]
+    ctx = xf.Context.from_case(case)
+    U = ctx.state_from_numpy(case.U)
+    ctx.fill_ghosts(U)
+    P = ctx.primitives(U).cpu().numpy()
+    assert ctx.status() == 0
+    th, g = oracle_objects(case)
+    Uo = O.fill_ghosts(g, case.U)
+    Po = O.primitives(th, Uo.reshape(Uo.shape[0], -1))
+    for k, key in enumerate(["T", "p", "c"]):
+        ref = Po[key].reshape(P.shape[1:])
+        err = np.max(np.abs(P[k] - ref) / np.abs(ref))
+        assert err <= 1e-13, (key, err)
+    rho = Uo[:case.thermo.ns].sum(axis=0)
+    assert np.max(np.abs(P[3] * rho - 1.0)) <= 1e-15
