@@ -161,7 +161,7 @@ Prim prim_bufs(const xf_ctx *c, const Layout &l, void *ws) {
 }
 
 hipError_t prims(xf_ctx *c, const double *U, const Prim &pb, hipStream_t s) {
-    return timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, pb.P, pb.Uf, pb.Pf, s); });
+    return timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, pb.P, pb.Uf, pb.Pf, 0, s); });
 }
 
 int sweeps_into(xf_ctx *c, const double *U, double *rhs, const Prim &pb, const xf::StageArgs &stage,
@@ -199,7 +199,7 @@ int rhs_vjp_into(xf_ctx *c, const double *U, const double *rbar, double *Ubar, d
                  hipStream_t s) {
     const LaunchCtx &lc = c->lc;
     const int n[3] = {lc.g.nx, lc.g.ny, lc.g.nz};
-    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(lc, U, P, nullptr, nullptr, s); }));
+    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(lc, U, P, nullptr, nullptr, 0, s); }));
     XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero(2 * lc.g.cells, Pbar, s); }));
     for (int d = 0; d < 3; ++d) {
         if (n[d] <= 1) continue;
@@ -394,7 +394,7 @@ int xf_rhs(xf_ctx *c, const double *U, double *rhs, void *ws, void *stream) {
 int xf_primitives(xf_ctx *c, const double *U, double *prim, void *stream) {
     if (!c || !U || !prim || !aligned8(U) || !aligned8(prim)) return XF_EINVAL;
     const hipStream_t s = (hipStream_t)stream;
-    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, prim, nullptr, nullptr, s); }));
+    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, prim, nullptr, nullptr, 1, s); }));
     return XF_OK;
 }
 
@@ -404,7 +404,7 @@ int xf_cfl_dt(xf_ctx *c, const double *U, double cfl, double *dt_dev, void *ws, 
     const hipStream_t s = (hipStream_t)stream;
     double *P = at<double>(ws, l.P);
     unsigned long long *mx = at<unsigned long long>(ws, l.mx);
-    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, P, nullptr, nullptr, s); }));
+    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, P, nullptr, nullptr, 0, s); }));
     XF_TRY(timed(c, XF_K_CFL, s, [&] {
         hipError_t e = xf::launch_cfl_reset(mx, s);
         if (e == hipSuccess) e = c->ops->cfl(c->lc, U, P, mx, s);

@@ -66,9 +66,11 @@ struct LaunchCtx {
 
 // Per species-count entry points (one translation unit per N).
 struct NsOps {
-    // primitive variables (T, p, c, 1/rho) of every cell a stencil reads;
-    // with Uf, Pf also FP32 copies of U and P for the mixed-precision sweeps
-    hipError_t (*prims)(const LaunchCtx &, const double *U, double *P, float *Uf, float *Pf, hipStream_t);
+    // primitive variables (T, p, c, 1/rho) of every cell a stencil reads (of
+    // every padded cell with all_cells); with Uf, Pf also FP32 copies of U
+    // and P for the mixed-precision sweeps
+    hipError_t (*prims)(const LaunchCtx &, const double *U, double *P, float *Uf, float *Pf, int all_cells,
+                        hipStream_t);
     // one direction of the convective flux difference; accumulate: rhs += or
     // rhs =.  FP64 sweeps read U, P; mixed-precision sweeps read Uf, Pf.
     hipError_t (*sweep)(const LaunchCtx &, int dir, int accumulate, const double *U, const double *P,

@@ -69,7 +69,7 @@ XF_HD bool newton_T(const ThermoK<double> &th, const double *Y, double e, double
 template <int NS>
 __global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, double *__restrict__ P, Geo g,
                                                ThermoK<double> th, unsigned *status, float *__restrict__ Uf,
-                                               float *__restrict__ Pf) {
+                                               float *__restrict__ Pf, int all_cells) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= g.cells) return;
     const int x = (int)(idx % g.px);
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, dou
     const int z = (int)(r / g.py);
     const int ng = (x < g.gx || x >= g.gx + g.nx) + (y < g.gy || y >= g.gy + g.ny) +
                    (z < g.gz || z >= g.gz + g.nz);
-    if (ng > 1) return;
+    if (ng > 1 && !all_cells) return;   // edge and corner ghosts: outside every stencil
     const long long C = g.cells;
     double Y[NS];
     double rho = 0.0;
@@ -134,23 +134,22 @@ __global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, dou
 }
 
 // ---------------------------------------------------------------------------
-// Phase fences per kernel flavour: where they lower register pressure
-// without spilling (chosen from the compiler's resource report).
-#ifndef XF_FX64
-#define XF_FX64 false
-#endif
-#ifndef XF_FM64
-#define XF_FM64 false
-#endif
+// Phase fences and occupancy per kernel flavour, chosen from the compiler's
+// resource report and timings: the FP64 face-per-thread sweeps keep below 256
+// registers (two waves per SIMD) when the face's phases are fenced; the FP64
+// marching sweep runs best unfenced at one wave per SIMD (forcing two spills
+// inside its face loop); the FP32 sweeps fit three waves unforced.
 template <typename R>
-struct SweepFence {
-    static constexpr bool x = false;
-    static constexpr bool march = true;
+struct SweepTune {
+    static constexpr bool fence_face = false;   // face-per-thread sweeps (x, tiled y/z)
+    static constexpr bool fence_march = true;
+    static constexpr int waves = 1;             // minimum waves per SIMD asked of the compiler
 };
 template <>
-struct SweepFence<double> {
-    static constexpr bool x = XF_FX64;
-    static constexpr bool march = XF_FM64;
+struct SweepTune<double> {
+    static constexpr bool fence_face = true;
+    static constexpr bool fence_march = false;
+    static constexpr int waves = 2;
 };
 
 // Write the finished residual d of one field at one cell: to rhs (=, or +=
@@ -177,9 +176,9 @@ __device__ __forceinline__ void put_result(double *__restrict__ rhs, const Stage
 constexpr int kXBlock = 256;
 
 template <int NS, typename R, typename S>
-__global__ __launch_bounds__(kXBlock) void k_sweep_x(const S *__restrict__ U, const S *__restrict__ P,
-                                                     double *__restrict__ rhs, Geo g, ThermoK<R> th, int accumulate,
-                                                     StageArgs sa, unsigned *status) {
+__global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(SweepTune<R>::waves))) void k_sweep_x(
+    const S *__restrict__ U, const S *__restrict__ P, double *__restrict__ rhs, Geo g, ThermoK<R> th, int accumulate,
+    StageArgs sa, unsigned *status) {
     constexpr int NV = NS + 4;
     __shared__ R sF[NV][kXBlock];
     const int t = threadIdx.x;
@@ -197,7 +196,7 @@ __global__ __launch_bounds__(kXBlock) void k_sweep_x(const S *__restrict__ U, co
         const int j = (int)(row % g.ny), k = (int)(row / g.ny);
         rowbase = (long long)(g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + g.gx;
         StencilT<S> st{U, P, rowbase + i - 3, 1, g.cells};
-        face_flux_to<NS, R, 0, SweepFence<R>::x>(st, th, [&](int q, R v) { sF[q][t] = v; }, flags);
+        face_flux_to<NS, R, 0, SweepTune<R>::fence_face>(st, th, [&](int q, R v) { sF[q][t] = v; }, flags);
     }
     __syncthreads();
     if (valid && t > 0 && i > 0) {
@@ -207,6 +206,53 @@ __global__ __launch_bounds__(kXBlock) void k_sweep_x(const S *__restrict__ U, co
 #pragma unroll
         for (int q = 0; q < NV; ++q)
             put_result(rhs, sa, q * g.cells + cell, double((sF[q][t - 1] - sF[q][t]) * id), h, accumulate);
+    }
+    if (flags) atomicOr(status, flags);
+}
+
+// ---------------------------------------------------------------------------
+// Tiled y/z sweep: one face per thread, like the x sweep.  A block is a tile
+// of kTileX x-columns by kTileS consecutive faces along the sweep axis (in one
+// plane of the third axis); tiles overlap by one face along the sweep axis,
+// so each finishes kTileS - 1 cells per column.  Lanes run along x, so every
+// stencil load of a wave reads whole rows (16 doubles = one 128-byte line).
+// Tiles that are neighbours along the sweep axis share six stencil rows and
+// are numbered to run on the same XCD.
+// ---------------------------------------------------------------------------
+constexpr int kTileX = 16, kTileS = 16;
+
+template <int NS, typename R, int DIR, typename S>
+__global__ __launch_bounds__(kTileX *kTileS) __attribute__((amdgpu_waves_per_eu(SweepTune<R>::waves))) void
+k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, double *__restrict__ rhs, Geo g, ThermoK<R> th,
+             int accumulate, StageArgs sa, unsigned *status) {
+    constexpr int NV = NS + 4;
+    __shared__ R sF[NV][kTileS][kTileX];
+    unsigned bx, by, bz;
+    xcd_block(bx, by, bz);
+    const int tx = threadIdx.x, ts = threadIdx.y;
+    const int x = bx * kTileX + tx;
+    const int j = by * (kTileS - 1) + ts;            // face j: between cells j-1 and j of the sweep axis
+    const int nsw = (DIR == 1) ? g.ny : g.nz;
+    const bool valid = x < g.nx && j <= nsw;
+    const long long step = (DIR == 1) ? g.sy : g.sz;
+    const int gs = (DIR == 1) ? g.gy : g.gz;
+    const long long col = (long long)(g.gx + x) +
+                          ((DIR == 1) ? (long long)(g.gz + bz) * g.sz : (long long)(g.gy + bz) * g.sy);
+    unsigned flags = 0;
+    if (valid) {
+        StencilT<S> st{U, P, col + (long long)(gs + j - 3) * step, step, g.cells};
+        face_flux_to<NS, R, DIR, SweepTune<R>::fence_face>(st, th, [&](int q, R v) { sF[q][ts][tx] = v; },
+                                                          flags);
+    }
+    __syncthreads();
+    if (valid && ts > 0) {
+        const R id = R((DIR == 1) ? g.idy : g.idz);
+        const long long cell = col + (long long)(gs + j - 1) * step;
+        const double h = sa.on ? (sa.dt_dev ? *sa.dt_dev : sa.dt) : 0.0;
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            put_result(rhs, sa, q * g.cells + cell, double((sF[q][ts - 1][tx] - sF[q][ts][tx]) * id), h,
+                       accumulate);
     }
     if (flags) atomicOr(status, flags);
 }
@@ -251,7 +297,7 @@ __global__ __launch_bounds__(256) void k_sweep_march(const S *__restrict__ U, co
             StencilT<S> st{U, P, col + (long long)(gs + j - 3) * step, step, g.cells};
             const long long cell = col + (long long)(gs + j - 1) * step;
             const bool emit = j > j0;
-            face_flux_to<NS, R, DIR, SweepFence<R>::march>(
+            face_flux_to<NS, R, DIR, SweepTune<R>::fence_march>(
                 st, th,
                 [&](int q, R v) {
                     if (emit)
@@ -264,7 +310,7 @@ __global__ __launch_bounds__(256) void k_sweep_march(const S *__restrict__ U, co
         R Fp[NV], F[NV];
         for (int j = j0; j <= j1; ++j) {
             StencilT<S> st{U, P, col + (long long)(gs + j - 3) * step, step, g.cells};
-            face_flux_to<NS, R, DIR, SweepFence<R>::march>(st, th, [&](int q, R v) { F[q] = v; }, flags);
+            face_flux_to<NS, R, DIR, SweepTune<R>::fence_march>(st, th, [&](int q, R v) { F[q] = v; }, flags);
             if (j > j0) {
                 const long long cell = col + (long long)(gs + j - 1) * step;
 #pragma unroll

@@ -15,9 +15,10 @@ constexpr int NS = XF_NS;
 
 unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-hipError_t prims(const LaunchCtx &c, const double *U, double *P, float *Uf, float *Pf, hipStream_t s) {
+hipError_t prims(const LaunchCtx &c, const double *U, double *P, float *Uf, float *Pf, int all_cells,
+                 hipStream_t s) {
     hipLaunchKernelGGL(k_prims<NS>, dim3(blocks_for(c.g.cells, 256)), dim3(256), 0, s, U, P, c.g, c.th64,
-                       c.status, Uf, Pf);
+                       c.status, Uf, Pf, all_cells);
     return hipGetLastError();
 }
 
@@ -32,13 +33,25 @@ hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumu
                            c.status);
         return hipGetLastError();
     }
+    const int ntr = dir == 1 ? g.nz : g.ny;
+    const int nsw = dir == 1 ? g.ny : g.nz;
+    const unsigned tiles = (unsigned)((nsw + kTileS - 2) / (kTileS - 1));
+    // c.variant (measurement only): 0 default = tiled, 1 = marching with the
+    // previous flux in registers, 2 = marching with it in LDS
+    if (c.variant == 0 && ntr <= 65535 && tiles <= 65535u) {
+        dim3 grid((g.nx + kTileX - 1) / kTileX, tiles, ntr), block(kTileX, kTileS);
+        if (dir == 1)
+            hipLaunchKernelGGL((k_sweep_tile<NS, R, 1, S>), grid, block, 0, s, U, P, rhs, g, th, accumulate, sa,
+                               c.status);
+        else
+            hipLaunchKernelGGL((k_sweep_tile<NS, R, 2, S>), grid, block, 0, s, U, P, rhs, g, th, accumulate, sa,
+                               c.status);
+        return hipGetLastError();
+    }
     int nseg, seglen;
     march_shape(g, dir, &nseg, &seglen);
-    const int ntr = dir == 1 ? g.nz : g.ny;
     dim3 grid((g.nx + 63) / 64, (ntr + 3) / 4, nseg), block(64, 4);
-    // FP64: the previous face's flux in registers; FP32: in an LDS slot
-    // (measured faster for each precision); c.variant overrides for measurement
-    const bool regs = c.variant == 0 ? (sizeof(R) == 8) : (c.variant == 1);
+    const bool regs = c.variant != 2;
     if (dir == 1) {
         if (regs)
             hipLaunchKernelGGL((k_sweep_march<NS, R, 1, 1, S>), grid, block, 0, s, U, P, rhs, g, th, seglen,
