@@ -78,8 +78,9 @@ enum {
 
 #define XF_MAX_SPECIES 9
 
-/* Uniform Cartesian grid (Sec. III.A, Fig. 3).  n_d >= 1; a dimension with
- * n_d > 1 needs n_d >= 3.  bc order: -x, +x, -y, +y, -z, +z; XF_BC_PERIODIC
+/* Uniform Cartesian grid (Sec. III.A, Fig. 3).  1 <= n_d <= 65535 (the
+ * launch grids put single axes on the y and z grid dimensions); a dimension
+ * with n_d > 1 needs n_d >= 3.  bc order: -x, +x, -y, +y, -z, +z; XF_BC_PERIODIC
  * wraps, XF_BC_OUTFLOW copies the nearest interior cell (zero gradient).
  * Periodic sides must come in pairs. */
 typedef struct {

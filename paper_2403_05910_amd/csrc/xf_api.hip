@@ -54,7 +54,7 @@ size_t align_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace carve-up (byte offsets); every piece 256-byte aligned.
 struct Layout {
-    size_t P, Pbar, mx, L, U0, S2, Ly, Lz, V0, V1, V2, lam0, mu, Uf, Pf, total;
+    size_t P, Pbar, rec, mx, L, U0, S2, Ly, Lz, V0, V1, V2, lam0, mu, Uf, Pf, total;
 };
 
 Layout layout(const xf_ctx *c, int op) {
@@ -75,6 +75,8 @@ Layout layout(const xf_ctx *c, int op) {
     if (op == XF_OP_VJP || op == XF_OP_RK3_VJP) {
         l.Pbar = o;
         o += align_up(2 * cell);
+        l.rec = o;   // record between the two halves of the face VJP
+        o += align_up((size_t)xf::vjp_record_fields(c->ns) * (size_t)xf::vjp_record_rows(c->lc.g) * sizeof(double));
     }
     if (op == XF_OP_RK3 || op == XF_OP_RK3_VJP) {
         l.L = o;
@@ -196,7 +198,7 @@ int rhs_into(xf_ctx *c, const double *U, double *rhs, const Prim &pb, hipStream_
 }
 
 int rhs_vjp_into(xf_ctx *c, const double *U, const double *rbar, double *Ubar, double *P, double *Pbar,
-                 hipStream_t s) {
+                 double *rec, hipStream_t s) {
     const LaunchCtx &lc = c->lc;
     const int n[3] = {lc.g.nx, lc.g.ny, lc.g.nz};
     XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(lc, U, P, nullptr, nullptr, 0, s); }));
@@ -204,7 +206,7 @@ int rhs_vjp_into(xf_ctx *c, const double *U, const double *rbar, double *Ubar, d
     for (int d = 0; d < 3; ++d) {
         if (n[d] <= 1) continue;
         XF_TRY(timed(c, XF_K_VJP_X + d, s,
-                     [&] { return c->ops->sweep_vjp(lc, d, U, P, rbar, Ubar, Pbar, s); }));
+                     [&] { return c->ops->sweep_vjp(lc, d, U, P, rbar, Ubar, Pbar, rec, xf::vjp_record_rows(lc.g), s); }));
     }
     XF_TRY(timed(c, XF_K_PRIMS_VJP, s, [&] { return c->ops->prims_vjp(lc, U, P, Pbar, Ubar, s); }));
     return XF_OK;
@@ -222,7 +224,7 @@ bool grid_ok(const xf_grid *g) {
     const int n[3] = {g->nx, g->ny, g->nz};
     const double d[3] = {g->dx, g->dy, g->dz};
     for (int k = 0; k < 3; ++k) {
-        if (n[k] < 1) return false;
+        if (n[k] < 1 || n[k] > 65535) return false;
         if (n[k] > 1) {
             if (n[k] < 3) return false;
             if (!(d[k] > 0.0)) return false;
@@ -479,7 +481,8 @@ int xf_rhs_vjp(xf_ctx *c, const double *U, const double *rbar, double *Ubar, voi
         !aligned8(Ubar) || !aligned8(ws))
         return XF_EINVAL;
     const Layout l = layout(c, XF_OP_VJP);
-    return rhs_vjp_into(c, U, rbar, Ubar, at<double>(ws, l.P), at<double>(ws, l.Pbar), (hipStream_t)stream);
+    return rhs_vjp_into(c, U, rbar, Ubar, at<double>(ws, l.P), at<double>(ws, l.Pbar), at<double>(ws, l.rec),
+                        (hipStream_t)stream);
 }
 
 int xf_rk3_step_vjp(xf_ctx *c, const double *Un, double dt, double *Ubar, void *ws, void *stream) {
@@ -518,7 +521,7 @@ int xf_rk3_step_vjp(xf_ctx *c, const double *Un, double dt, double *Ubar, void *
     XF_TRY(fill_vjp(c, Ubar, s));
     for (int stage = 3; stage >= 1; --stage) {
         XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero(n, mu, s); }));
-        if ((r = rhs_vjp_into(c, Vs[stage - 1], Ubar, mu, P, Pbar, s)) != XF_OK) return r;
+        if ((r = rhs_vjp_into(c, Vs[stage - 1], Ubar, mu, P, Pbar, at<double>(ws, l.rec), s)) != XF_OK) return r;
         XF_TRY(timed(c, XF_K_STAGE, s,
                      [&] { return xf::launch_rk3_stage_vjp(lc, c->nv, stage, Ubar, lam0, mu, nullptr, dt, s); }));
         if (stage > 1) XF_TRY(fill_vjp(c, Ubar, s));

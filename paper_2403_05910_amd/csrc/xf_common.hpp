@@ -76,8 +76,11 @@ struct NsOps {
     hipError_t (*sweep)(const LaunchCtx &, int dir, int accumulate, const double *U, const double *P,
                         const float *Uf, const float *Pf, double *rhs, const StageArgs &stage, hipStream_t);
     // VJP of one direction: Ubar_direct += (dF/dU)^T ..., Pbar += (dF/d(p, T))^T ...
+    // rec: vjp_record_fields(ns) x nrec doubles of scratch between the two
+    // halves of the face VJP (nrec >= vjp_record_rows(g))
     hipError_t (*sweep_vjp)(const LaunchCtx &, int dir, const double *U, const double *P,
-                            const double *rbar, double *Ubar, double *Pbar, hipStream_t);
+                            const double *rbar, double *Ubar, double *Pbar, double *rec, long long nrec,
+                            hipStream_t);
     // VJP of the primitive map: Ubar += (d(p, T)/dU)^T Pbar
     hipError_t (*prims_vjp)(const LaunchCtx &, const double *U, const double *P,
                             const double *Pbar, double *Ubar, hipStream_t);
@@ -87,6 +90,31 @@ struct NsOps {
 };
 
 const NsOps *ops_for_ns(int ns);
+
+// Launch geometry of the face VJP (shared by the launchers and the workspace
+// layout).  x: waves of 64 consecutive faces in one z-plane, launch groups of
+// every sixth wave, blocks of up to 4 waves; y/z: blocks of 64 x 4 threads
+// over (x, faces of one class along the sweep axis), one block row per plane.
+constexpr int kVjpGroups = 6;
+inline int vjp_record_fields(int ns) { return 44 + 2 * ns; }
+inline long long vjp_x_waves_per_plane(const Geo &g) { return ((long long)(g.nx + 1) * g.ny + 63) / 64; }
+inline long long vjp_yz_threads(const Geo &g, int dir) {
+    const int nsw = dir == 1 ? g.ny : g.nz, ntr = dir == 1 ? g.nz : g.ny;
+    const long long per_class = nsw / 6 + 1;
+    return (long long)((g.nx + 63) / 64) * 64 * ((per_class + 3) / 4) * 4 * ntr;
+}
+// record rows one launch of any direction can use
+inline long long vjp_record_rows(const Geo &g) {
+    long long n = 0;
+    if (g.nx > 1) {
+        const long long waves = (vjp_x_waves_per_plane(g) + kVjpGroups - 1) / kVjpGroups;
+        const long long rows = (waves + 3) / 4 * 4 * 64 * g.nz;   // blocks of 4 waves (an upper bound for 1)
+        n = rows > n ? rows : n;
+    }
+    if (g.ny > 1) n = vjp_yz_threads(g, 1) > n ? vjp_yz_threads(g, 1) : n;
+    if (g.nz > 1) n = vjp_yz_threads(g, 2) > n ? vjp_yz_threads(g, 2) : n;
+    return n;
+}
 
 // Species-independent launches (xf_misc.hip).
 hipError_t launch_fill_ghosts(const LaunchCtx &, int nv, double *U, hipStream_t);

@@ -76,64 +76,55 @@ hipError_t sweep(const LaunchCtx &c, int dir, int accumulate, const double *U, c
     return sweep_t<double, double>(c, c.th64, dir, accumulate, U, P, rhs, sa, s);
 }
 
-MarchGeo march_geo(const Geo &g, int dir) {
-    MarchGeo m;
-    m.origin = (long long)g.gz * g.sz + (long long)g.gy * g.sy + g.gx;
+template <typename R, int HALF>
+hipError_t launch_vjp_group(const LaunchCtx &c, const ThermoK<R> &th, int dir, int grp, const double *U,
+                            const double *P, const double *rbar, double *Ubar, double *Pbar, double *rec,
+                            long long nrec, hipStream_t s) {
+    const Geo &g = c.g;
     if (dir == 0) {
-        m.sl = g.sy; m.nl = g.ny;
-        m.st = g.sz; m.nt = g.nz;
-        m.ss = 1;    m.nsw = g.nx;
-    } else if (dir == 1) {
-        m.sl = 1;    m.nl = g.nx;
-        m.st = g.sz; m.nt = g.nz;
-        m.ss = g.sy; m.nsw = g.ny;
+        // consecutive faces per wave with a private LDS window of W cells
+        const int rowf = g.nx + 1;
+        const int bounds = (63 + rowf - 1) / rowf;               // row boundaries 64 faces can cross
+        const int W = 69 + 5 * bounds;
+        const size_t per_wave = (size_t)(NS + 6) * W * sizeof(double);
+        const int wpb = per_wave * 4 <= 65536 ? 4 : 1;
+        const long long waves = (vjp_x_waves_per_plane(g) - grp + kVjpGroups - 1) / kVjpGroups;
+        dim3 grid((unsigned)((waves + wpb - 1) / wpb), g.nz), block(64 * wpb);
+        hipLaunchKernelGGL((k_face_vjp_x<NS, R, HALF>), grid, block, per_wave * wpb, s, U, P, rbar, Ubar, Pbar, rec,
+                           nrec, g, th, W, grp);
     } else {
-        m.sl = 1;    m.nl = g.nx;
-        m.st = g.sy; m.nt = g.ny;
-        m.ss = g.sz; m.nsw = g.nz;
+        const int nsw = dir == 1 ? g.ny : g.nz;
+        dim3 grid((g.nx + 63) / 64, (nsw / 6 + 1 + 3) / 4, dir == 1 ? g.nz : g.ny), block(64, 4);
+        if (dir == 1)
+            hipLaunchKernelGGL((k_face_vjp<NS, R, 1, HALF>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec, g,
+                               th, grp);
+        else
+            hipLaunchKernelGGL((k_face_vjp<NS, R, 2, HALF>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec, g,
+                               th, grp);
     }
-    return m;
+    return hipGetLastError();
 }
 
+// Six launch groups per direction (x: waves w = grp mod 6; y/z: faces
+// j = grp mod 6), each as the two halves of the face VJP.
 template <typename R>
 hipError_t sweep_vjp_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, const double *U, const double *P,
-                       const double *rbar, double *Ubar, double *Pbar, hipStream_t s) {
+                       const double *rbar, double *Ubar, double *Pbar, double *rec, long long nrec, hipStream_t s) {
     const Geo &g = c.g;
-    const MarchGeo mg = march_geo(g, dir);
-    const double id = dir == 0 ? g.idx : (dir == 1 ? g.idy : g.idz);
-    // segments of at least 8 faces (two segments a column apart never touch
-    // the same cell); enough of them to fill the chip
-    const long long cols = (long long)mg.nl * mg.nt;
-    const int nfaces = mg.nsw + 1;
-    int seglen = nfaces;
-    const long long want = 16384;   // threads in flight per launch
-    if (cols < want) {
-        const long long segs = (want + cols - 1) / cols;
-        seglen = (int)((nfaces + segs - 1) / segs);
-        if (seglen < 8) seglen = 8;
-    }
-    const int nseg = (nfaces + seglen - 1) / seglen;
-    dim3 grid((mg.nl + 63) / 64, (mg.nt + 3) / 4, (nseg + 1) / 2), block(64, 4);
-    for (int parity = 0; parity < 2; ++parity) {
-        if (dir == 0)
-            hipLaunchKernelGGL((k_sweep_vjp<NS, R, 0>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, g.cells, mg,
-                               th, id, seglen, parity);
-        else if (dir == 1)
-            hipLaunchKernelGGL((k_sweep_vjp<NS, R, 1>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, g.cells, mg,
-                               th, id, seglen, parity);
-        else
-            hipLaunchKernelGGL((k_sweep_vjp<NS, R, 2>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, g.cells, mg,
-                               th, id, seglen, parity);
-        const hipError_t e = hipGetLastError();
+    const long long ngrp = dir == 0 ? vjp_x_waves_per_plane(g) : (long long)(dir == 1 ? g.ny : g.nz) + 1;
+    for (int grp = 0; grp < kVjpGroups && grp < ngrp; ++grp) {
+        hipError_t e = launch_vjp_group<R, 0>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, rec, nrec, s);
+        if (e == hipSuccess) e = launch_vjp_group<R, 1>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, rec, nrec, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
 hipError_t sweep_vjp(const LaunchCtx &c, int dir, const double *U, const double *P, const double *rbar,
-                     double *Ubar, double *Pbar, hipStream_t s) {
-    if (c.precision == XF_PREC_MIXED) return sweep_vjp_t<float>(c, c.th32, dir, U, P, rbar, Ubar, Pbar, s);
-    return sweep_vjp_t<double>(c, c.th64, dir, U, P, rbar, Ubar, Pbar, s);
+                     double *Ubar, double *Pbar, double *rec, long long nrec, hipStream_t s) {
+    if (c.precision == XF_PREC_MIXED)
+        return sweep_vjp_t<float>(c, c.th32, dir, U, P, rbar, Ubar, Pbar, rec, nrec, s);
+    return sweep_vjp_t<double>(c, c.th64, dir, U, P, rbar, Ubar, Pbar, rec, nrec, s);
 }
 
 hipError_t prims_vjp(const LaunchCtx &c, const double *U, const double *P, const double *Pbar, double *Ubar,

@@ -80,52 +80,107 @@ struct Sink {
     XF_HD void p(int k, int m, double v) const { Pb[k * cells + base + m * step] += v; }
 };
 
-template <int NS, typename R, int DIR>
-XF_HD void face_vjp(const Stencil &st, const ThermoK<R> &th, const R *Fb, const Sink &out) {
+// Where the cotangents of one stencil go, variant 2: a wave's private LDS
+// window of the padded cells its faces touch ([NV + 2][W], field-major;
+// stencil cell 0 of this thread's face at window index off).  Lanes of a wave
+// share window cells through different (field, cell) calls, so the
+// read-modify-writes must stay in program order even where one thread's
+// addresses differ: the accesses are volatile (LDS executes a wave's
+// instructions in order).
+struct SinkLds {
+    volatile double *w;
+    int W, off, mstep, pofs;   // window length, offset of stencil cell 0, cell stride, start of the P rows
+    XF_HD void u(int f, int m, double v) const { w[f * W + off + m * mstep] += v; }
+    XF_HD void p(int k, int m, double v) const { w[pofs + k * W + off + m * mstep] += v; }
+};
+
+// Forward Roe state of one face (shared by both halves of the face VJP).
+template <int NS, typename R>
+struct RoeFwd {
+    R sL, sR, Ssum, wL, wR, r2, r3, aL, aR, ut[3], Ht, Tt, Yt[NS], chi[NS], cvb, Gam, q2, c2, ct, ic2, cih, iGam;
+    XF_HD RoeFwd(const Stencil &st, const ThermoK<R> &th) {
+        constexpr int IM = NS;
+        constexpr int IE = NS + 3;
+        R rL = R(0), rR = R(0);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            rL += R(st.u(s, 2));
+            rR += R(st.u(s, 3));
+        }
+        sL = xsqrt(rL);
+        sR = xsqrt(rR);
+        Ssum = sL + sR;
+        wL = sL / Ssum;
+        wR = R(1) - wL;
+        r2 = R(st.p(3, 2));
+        r3 = R(st.p(3, 3));
+        aL = wL * r2;
+        aR = wR * r3;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ut[k] = aL * R(st.u(IM + k, 2)) + aR * R(st.u(IM + k, 3));
+        Ht = aL * (R(st.u(IE, 2)) + R(st.p(1, 2))) + aR * (R(st.u(IE, 3)) + R(st.p(1, 3)));
+        Tt = wL * R(st.p(0, 2)) + wR * R(st.p(0, 3));
+        R Rb = R(0);
+        cvb = R(0);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            Yt[s] = aL * R(st.u(s, 2)) + aR * R(st.u(s, 3));
+            Rb += Yt[s] * th.Rs[s];
+            cvb += Yt[s] * cv_species(th, s, Tt);
+            chi[s] = e_species(th, s, Tt);
+        }
+        Gam = Rb / cvb;
+        q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+        c2 = Gam * (Ht - q2);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            chi[s] = Gam * (R(0.5) * q2 - chi[s]) + th.Rs[s] * Tt;
+            c2 += Yt[s] * chi[s];
+        }
+        ct = xsqrt(c2);
+        ic2 = R(1) / c2;
+        cih = R(0.5) * ct * ic2;
+        iGam = R(1) / Gam;
+    }
+};
+
+// Record passed from the first half of the face VJP to the second: the
+// per-cell cotangents of DU, DF, u_n, rho, p, m_n (6 each), those of the Roe
+// Y_s and chi_s, of u~ and of c~, H~, q~^2, 1/Gamma, c~/(2 c~^2).
+template <int NS>
+struct VjpRec {
+    static constexpr int N = 44 + 2 * NS;
+    static constexpr int DUb = 0, DFb = 6, unb = 12, rhb = 18, pmb = 24, Mnb = 30, Ytb = 36, chib = 36 + NS,
+                         utb = 36 + 2 * NS, ctb = utb + 3, Htb = ctb + 1, q2b = ctb + 2, iGamb = ctb + 3,
+                         cihb = ctb + 4;
+    double *__restrict__ r;
+    long long stride, idx;
+    XF_HD void put(int k, double v) const { r[k * stride + idx] = v; }
+    XF_HD double get(int k) const { return r[k * stride + idx]; }
+};
+
+#define XF_ROE_UNPACK(rf)                                                                                   \
+    const R sL = rf.sL, sR = rf.sR, Ssum = rf.Ssum, wL = rf.wL, wR = rf.wR, r2 = rf.r2, r3 = rf.r3,        \
+            aL = rf.aL, aR = rf.aR, Ht = rf.Ht, Tt = rf.Tt, cvb = rf.cvb, Gam = rf.Gam, q2 = rf.q2,        \
+            c2 = rf.c2, ct = rf.ct, ic2 = rf.ic2, cih = rf.cih, iGam = rf.iGam;                            \
+    const R *ut = rf.ut, *Yt = rf.Yt, *chi = rf.chi;                                                       \
+    (void)sL; (void)sR; (void)Ssum; (void)wL; (void)wR; (void)r2; (void)r3; (void)aL; (void)aR; (void)Ht; \
+    (void)Tt; (void)cvb; (void)c2; (void)ct; (void)cih; (void)iGam
+
+// First half: forward recompute, then the backward through the back-projection,
+// the WENO5 reconstructions and the characteristic projections' dependence on
+// each cell's own values; writes the direct cell cotangents to `out` and the
+// accumulated ones to `rec`.
+template <int NS, typename R, int DIR, class Out>
+XF_HD void face_vjp_a(const Stencil &st, const ThermoK<R> &th, const R *Fb, const Out &out, const VjpRec<NS> &rec) {
     constexpr int IM = NS;
     constexpr int IE = NS + 3;
     constexpr int KN = Axes<DIR>::n, K1 = Axes<DIR>::t1, K2 = Axes<DIR>::t2;
     constexpr int IN = NS + KN, I1 = NS + K1, I2 = NS + K2;
 
     // ================= forward: Roe state and per-cell scalars =================
-    R rL = R(0), rR = R(0);
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        rL += R(st.u(s, 2));
-        rR += R(st.u(s, 3));
-    }
-    const R sL = xsqrt(rL), sR = xsqrt(rR);
-    const R Ssum = sL + sR;
-    const R wL = sL / Ssum;
-    const R wR = R(1) - wL;
-    const R r2 = R(st.p(3, 2)), r3 = R(st.p(3, 3));
-    const R aL = wL * r2, aR = wR * r3;
-    R ut[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) ut[k] = aL * R(st.u(IM + k, 2)) + aR * R(st.u(IM + k, 3));
-    const R Ht = aL * (R(st.u(IE, 2)) + R(st.p(1, 2))) + aR * (R(st.u(IE, 3)) + R(st.p(1, 3)));
-    const R Tt = wL * R(st.p(0, 2)) + wR * R(st.p(0, 3));
-    R Yt[NS], chi[NS];
-    R Rb = R(0), cvb = R(0);
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        Yt[s] = aL * R(st.u(s, 2)) + aR * R(st.u(s, 3));
-        Rb += Yt[s] * th.Rs[s];
-        cvb += Yt[s] * cv_species(th, s, Tt);
-        chi[s] = e_species(th, s, Tt);
-    }
-    const R Gam = Rb / cvb;
-    const R q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
-    R c2 = Gam * (Ht - q2);
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        chi[s] = Gam * (R(0.5) * q2 - chi[s]) + th.Rs[s] * Tt;
-        c2 += Yt[s] * chi[s];
-    }
-    const R ct = xsqrt(c2);
-    const R ic2 = R(1) / c2;
-    const R cih = R(0.5) * ct * ic2;
-    const R iGam = R(1) / Gam;
+    const RoeFwd<NS, R> rf(st, th);
+    XF_ROE_UNPACK(rf);
     const R utn = ut[KN], ut1 = ut[K1], ut2 = ut[K2];
 
     R un[6], DU[6], DF[6], rh[6];
@@ -289,6 +344,54 @@ XF_HD void face_vjp(const Stencil &st, const ThermoK<R> &th, const R *Fb, const 
 #pragma unroll
     for (int k = 0; k < 3; ++k) ut_b[k] += (Asum + gsum) * Fbm[k];
 
+    using Rc = VjpRec<NS>;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        rec.put(Rc::DUb + m, double(DU_b[m]));
+        rec.put(Rc::DFb + m, double(DF_b[m]));
+        rec.put(Rc::unb + m, double(un_b[m]));
+        rec.put(Rc::rhb + m, double(rh_b[m]));
+        rec.put(Rc::pmb + m, double(pm_b[m]));
+        rec.put(Rc::Mnb + m, double(Mn_b[m]));
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        rec.put(Rc::Ytb + s, double(Yt_b[s]));
+        rec.put(Rc::chib + s, double(chi_b[s]));
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rec.put(Rc::utb + k, double(ut_b[k]));
+    rec.put(Rc::ctb, double(ct_b));
+    rec.put(Rc::Htb, double(Ht_b));
+    rec.put(Rc::q2b, double(q2_b));
+    rec.put(Rc::iGamb, double(iGam_b));
+    rec.put(Rc::cihb, double(cih_b));
+}
+
+// Second half: forward Roe state again, the record, then the backward through
+// the per-cell projection scalars DU, DF, the Roe state (c~^2, Gamma~, chi_s
+// and the species thermo at T~), the sqrt(rho) averages and their weights.
+template <int NS, typename R, int DIR, class Out>
+XF_HD void face_vjp_b(const Stencil &st, const ThermoK<R> &th, const Out &out, const VjpRec<NS> &rec) {
+    constexpr int IM = NS;
+    constexpr int IE = NS + 3;
+    constexpr int KN = Axes<DIR>::n;
+    constexpr int IN = NS + KN;
+    using Rc = VjpRec<NS>;
+    const RoeFwd<NS, R> rf(st, th);
+    XF_ROE_UNPACK(rf);
+    const R utn = ut[KN];
+    R ut_b[3], Yt_b[NS], chi_b[NS];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ut_b[k] = R(rec.get(Rc::utb + k));
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        Yt_b[s] = R(rec.get(Rc::Ytb + s));
+        chi_b[s] = R(rec.get(Rc::chib + s));
+    }
+    R ct_b = R(rec.get(Rc::ctb)), Ht_b = R(rec.get(Rc::Htb)), q2_b = R(rec.get(Rc::q2b));
+    const R iGam_b = R(rec.get(Rc::iGamb)), cih_b = R(rec.get(Rc::cihb));
+
     // ================= per-cell projections: DU = dpU / c^2, DF = dpF / c^2
     R Gam_b = R(0), ic2_b = R(0);
 #pragma unroll
@@ -301,17 +404,19 @@ XF_HD void face_vjp(const Stencil &st, const ThermoK<R> &th, const R *Fb, const 
         const R E = R(st.u(IE, m));
         const R M0 = R(st.u(IM, m)), M1 = R(st.u(IM + 1, m)), M2 = R(st.u(IM + 2, m));
         const R mn = R(st.u(IN, m));
+        const R unm = mn * rinv;
+        const R DUb = R(rec.get(Rc::DUb + m)), DFb = R(rec.get(Rc::DFb + m));
         const R um = ut[0] * M0 + ut[1] * M1 + ut[2] * M2;
         const R dpU = sc - Gam * um + Gam * E;
-        const R dpF = un[m] * sc - Gam * (un[m] * um + pm * utn) + Gam * ((E + pm) * un[m]);
-        const R dpU_b = ic2 * DU_b[m], dpF_b = ic2 * DF_b[m];
-        ic2_b += dpU * DU_b[m] + dpF * DF_b[m];
-        const R sc_b = dpU_b + un[m] * dpF_b;
-        const R um_b = -Gam * (dpU_b + un[m] * dpF_b);
-        const R E_b = Gam * (dpU_b + un[m] * dpF_b);
-        Gam_b += (E - um) * dpU_b + ((E + pm) * un[m] - un[m] * um - pm * utn) * dpF_b;
-        const R un_bt = un_b[m] + (sc - Gam * um + Gam * (E + pm)) * dpF_b;
-        const R pm_bt = pm_b[m] + Gam * (un[m] - utn) * dpF_b;
+        const R dpF = unm * sc - Gam * (unm * um + pm * utn) + Gam * ((E + pm) * unm);
+        const R dpU_b = ic2 * DUb, dpF_b = ic2 * DFb;
+        ic2_b += dpU * DUb + dpF * DFb;
+        const R sc_b = dpU_b + unm * dpF_b;
+        const R um_b = -Gam * (dpU_b + unm * dpF_b);
+        const R E_b = Gam * (dpU_b + unm * dpF_b);
+        Gam_b += (E - um) * dpU_b + ((E + pm) * unm - unm * um - pm * utn) * dpF_b;
+        const R un_bt = R(rec.get(Rc::unb + m)) + (sc - Gam * um + Gam * (E + pm)) * dpF_b;
+        const R pm_bt = R(rec.get(Rc::pmb + m)) + Gam * (unm - utn) * dpF_b;
         ut_b[KN] -= Gam * pm * dpF_b;
         ut_b[0] += M0 * um_b;
         ut_b[1] += M1 * um_b;
@@ -320,10 +425,10 @@ XF_HD void face_vjp(const Stencil &st, const ThermoK<R> &th, const R *Fb, const 
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             R v = ut[k] * um_b;
-            if (k == KN) v += Mn_b[m] + rinv * un_bt;
+            if (k == KN) v += R(rec.get(Rc::Mnb + m)) + rinv * un_bt;
             out.u(IM + k, m, double(v));
         }
-        const R sp = rh_b[m] - rinv * rinv * rinv_b;
+        const R sp = R(rec.get(Rc::rhb + m)) - rinv * rinv * rinv_b;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             chi_b[s] += R(st.u(s, m)) * sc_b;
@@ -396,53 +501,127 @@ XF_HD void face_vjp(const Stencil &st, const ThermoK<R> &th, const R *Fb, const 
 }
 
 // ---------------------------------------------------------------------------
-// Marching VJP sweep.  Memory axes are given by strides, so the same kernel
-// serves x (lanes along y), y and z (lanes along x).  A thread owns one column
-// and one segment of its faces; faces j-1/2 scatter into cells j-3..j+2 of
-// their own column, so two segments of a column are in flight together only if
-// they are at least one segment apart: launch 0 takes the even segments,
-// launch 1 the odd ones.  No atomics; the summation order is fixed.
+// The face VJP runs as two kernels per group of faces (HALF 0: face_vjp_a,
+// HALF 1: face_vjp_b) so that neither keeps the other's live state; the
+// record between them is indexed by the thread's linear index in the launch
+// (both halves use the same grid), with stride nrec.
+//
+// x direction: lanes take consecutive x faces, linearised over the rows of
+// one z-plane (face f of the plane: row f / (nx + 1), face f % (nx + 1)).
+// The padded rows of a plane are contiguous, so the cells the 64 faces of a
+// wave touch form one run of at most W = 69 + 5 b padded cells (b = row
+// boundaries the wave crosses; face k of the wave has its stencil at offset
+// k + 5 b_k).  Each wave accumulates its cotangents in a private LDS window
+// over that run: within one instruction the 64 lanes address 64 distinct
+// cells, and the window accesses keep program order, so no atomics are
+// needed.  The window is then added to Ubar / Pbar with coalesced
+// read-modify-writes.  Runs of waves w and w + 1 can share up to five cells,
+// those of w and w + 2 cannot; launch `grp` takes the waves w = grp mod 6.
 // ---------------------------------------------------------------------------
-struct MarchGeo {
-    long long origin;         // padded index of interior cell (0, 0, 0)
-    long long sl, st, ss;     // strides of the lane, transverse and sweep axes
-    int nl, nt, nsw;          // interior extents of those axes
-};
-
-template <int NS, typename R, int DIR>
-__global__ __launch_bounds__(256) void k_sweep_vjp(const double *__restrict__ U, const double *__restrict__ P,
-                                                   const double *__restrict__ rbar, double *__restrict__ Ubar,
-                                                   double *__restrict__ Pbar, long long cells, MarchGeo mg,
-                                                   ThermoK<R> th, double id, int seglen, int parity) {
+template <int NS, typename R, int HALF>
+__global__ __launch_bounds__(256) void k_face_vjp_x(const double *__restrict__ U, const double *__restrict__ P,
+                                                    const double *__restrict__ rbar, double *__restrict__ Ubar,
+                                                    double *__restrict__ Pbar, double *__restrict__ rec,
+                                                    long long nrec, Geo g, ThermoK<R> th, int W, int grp) {
     constexpr int NV = NS + 4;
-    unsigned bx, by, bz;
-    xcd_block(bx, by, bz);
-    const int l = bx * 64 + threadIdx.x;
-    const int tr = by * 4 + threadIdx.y;
-    if (l >= mg.nl || tr >= mg.nt) return;
-    const int seg = 2 * bz + parity;
-    const int j0 = seg * seglen;
-    const int nfaces = mg.nsw + 1;
-    if (j0 >= nfaces) return;
-    const int j1 = min(j0 + seglen, nfaces);
-    const long long col = mg.origin + l * mg.sl + tr * mg.st;
-    for (int j = j0; j < j1; ++j) {
-        // face j-1/2 between interior cells j-1 and j: dF = (rbar_j - rbar_{j-1}) / dx
+    extern __shared__ double xf_win[];
+    const int wpb = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long rowf = (long long)g.nx + 1;          // faces per row
+    const long long nfp = rowf * g.ny;                   // faces per plane
+    const long long wpp = (nfp + 63) / 64;               // waves per plane
+    const long long wid = 6 * ((long long)blockIdx.x * wpb + wv) + grp;
+    const long long C = g.cells;
+    const long long zb = (long long)(g.gz + blockIdx.y) * g.sz + (long long)g.gy * g.sy;   // plane's first row
+    double *w = xf_win + (size_t)wv * (NV + 2) * W;
+    for (int i = lane; i < (NV + 2) * W; i += 64) w[i] = 0.0;
+    __syncthreads();
+    const long long f0 = wid * 64, f = f0 + lane;
+    const long long r0 = f0 / rowf;
+    const long long base0 = zb + r0 * g.sy + (f0 - r0 * rowf);   // stencil cell 0 of the wave's first face
+    if (wid < wpp && f < nfp) {
+        const long long r = f / rowf;
+        const int i = (int)(f - r * rowf);
+        const long long row = zb + r * g.sy + g.gx;             // interior cell 0 of the row
         R Fb[NV];
         bool any = false;
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
-            const double rr = (j < mg.nsw) ? rbar[q * cells + col + (long long)j * mg.ss] : 0.0;
-            const double rl = (j > 0) ? rbar[q * cells + col + (long long)(j - 1) * mg.ss] : 0.0;
-            Fb[q] = R((rr - rl) * id);
+            const double rr = i < g.nx ? rbar[q * C + row + i] : 0.0;
+            const double rl = i > 0 ? rbar[q * C + row + i - 1] : 0.0;
+            Fb[q] = R((rr - rl) * g.idx);
             any = any || (Fb[q] != R(0));
         }
-        if (!any) continue;
-        const long long base = col + (long long)(j - 3) * mg.ss;
-        Stencil st{U, P, base, mg.ss, cells};
-        Sink sk{Ubar, Pbar, base, mg.ss, cells};
-        face_vjp<NS, R, DIR>(st, th, Fb, sk);
+        if (any) {
+            const long long base = row + i - 3;
+            Stencil st{U, P, base, 1, C};
+            SinkLds sk{w, W, (int)(base - base0), 1, NV * W};
+            const VjpRec<NS> rc{rec, nrec, ((long long)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x};
+            if constexpr (HALF == 0)
+                face_vjp_a<NS, R, 0>(st, th, Fb, sk, rc);
+            else
+                face_vjp_b<NS, R, 0>(st, th, sk, rc);
+        }
     }
+    __syncthreads();
+    if (wid < wpp) {
+        const long long fl = min(f0 + 63, nfp - 1);
+        const long long rl = fl / rowf;
+        const int span = (int)(zb + rl * g.sy + (fl - rl * rowf) - base0) + 6;
+        for (int c = lane; c < span; c += 64) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) Ubar[q * C + base0 + c] += w[q * W + c];
+            Pbar[base0 + c] += w[NV * W + c];
+            Pbar[C + base0 + c] += w[(NV + 1) * W + c];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// y and z directions: one thread per face, lanes along x (coalesced),
+// threadIdx.y / blockIdx.y over the faces of a class, blockIdx.z over the
+// third axis.  Launch p (p = 0..5) takes the faces j = p, p + 6, ... of every
+// line along the sweep axis (face j lies between cells j-1 and j); their
+// six-cell windows j-3..j+2 are disjoint, so each read-modify-write of a
+// cotangent is the only one in flight for its cell and every cell receives
+// its contributions in a fixed order.
+// ---------------------------------------------------------------------------
+template <int NS, typename R, int DIR, int HALF>
+__global__ __launch_bounds__(256) void k_face_vjp(const double *__restrict__ U, const double *__restrict__ P,
+                                                  const double *__restrict__ rbar, double *__restrict__ Ubar,
+                                                  double *__restrict__ Pbar, double *__restrict__ rec, long long nrec,
+                                                  Geo g, ThermoK<R> th, int p) {
+    constexpr int NV = NS + 4;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = p + 6 * (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    const int nsw = DIR == 1 ? g.ny : g.nz;
+    if (x >= g.nx || j > nsw) return;
+    const long long ss = DIR == 1 ? g.sy : g.sz;
+    const double id = DIR == 1 ? g.idy : g.idz;
+    const long long col = (long long)(g.gx + x) + (DIR == 1 ? (long long)(g.gz + blockIdx.z) * g.sz + (long long)g.gy * g.sy
+                                                            : (long long)(g.gy + blockIdx.z) * g.sy + (long long)g.gz * g.sz);
+    const long long C = g.cells;
+    // rhs_{j-1} = (F_{j-1/2} - F_{j+1/2}) / dx and rhs_j = (F_{j+1/2} - ...):
+    // the cotangent of this face's flux is (rbar_j - rbar_{j-1}) / dx
+    R Fb[NV];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const double rr = j < nsw ? rbar[q * C + col + (long long)j * ss] : 0.0;
+        const double rl = j > 0 ? rbar[q * C + col + (long long)(j - 1) * ss] : 0.0;
+        Fb[q] = R((rr - rl) * id);
+        any = any || (Fb[q] != R(0));
+    }
+    if (!any) return;
+    const long long base = col + (long long)(j - 3) * ss;
+    Stencil st{U, P, base, ss, C};
+    Sink sk{Ubar, Pbar, base, ss, C};
+    const long long tid = ((long long)(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) *
+                              (blockDim.x * blockDim.y) + threadIdx.y * blockDim.x + threadIdx.x;
+    const VjpRec<NS> rc{rec, nrec, tid};
+    if constexpr (HALF == 0)
+        face_vjp_a<NS, R, DIR>(st, th, Fb, sk, rc);
+    else
+        face_vjp_b<NS, R, DIR>(st, th, sk, rc);
 }
 
 // Per-cell backward of (p, T)(U): p = T sum_s rho_s R_s, and T from

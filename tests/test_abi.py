@@ -52,6 +52,7 @@ def test_strerror_and_argument_errors_without_device():
         xf.xf_grid(8, 1, 1, 0.1, 1, 1, (ctypes.c_int * 6)(0, 1, 0, 0, 0, 0)),    # unpaired periodic side
         xf.xf_grid(8, 1, 1, 0.1, 1, 1, (ctypes.c_int * 6)(7, 7, 0, 0, 0, 0)),    # unknown bc
         xf.xf_grid(0, 1, 1, 0.1, 1, 1, (ctypes.c_int * 6)(0, 0, 0, 0, 0, 0)),    # n < 1
+        xf.xf_grid(8, 70000, 1, 0.1, 0.1, 1, (ctypes.c_int * 6)(0, 0, 0, 0, 0, 0)),  # n > 65535
     ]
     for g in bad_grids:
         assert xf._create(ctypes.byref(g), ctypes.byref(th), 0, ctypes.byref(h)) == xf.XF_EINVAL

@@ -86,6 +86,11 @@ VJP_CASES = {
     "wave1d": lambda: W.wave_1d(40),
     "plane2d_n2": lambda: W.random_smooth_state(W.sampled_table([4.0, 30.0], 2), (17, 9, 1), seed=24, jump=True),
     "inert_sbi_16": lambda: W.inert_sbi(16),
+    # x VJP: 64 consecutive faces cross up to 16 rows when nx = 3 (widest LDS
+    # window, one wave per block); with nx = 70 waves straddle row ends
+    "n9_thin_x": lambda: W.random_smooth_state(W.sampled_table(W.W9, 0), (3, 7, 5), seed=25, jump=True,
+                                               bc=(1, 1, 0, 0, 0, 0)),
+    "n2_long_x": lambda: W.random_smooth_state(W.sampled_table([4.0, 30.0], 2), (70, 5, 3), seed=26, jump=True),
 }
 
 
