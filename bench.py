@@ -57,6 +57,40 @@ def timed_steps(torch, ctx, U, dt_dev, steps, cfl):
     return t1 - t0, ctx.timing_read()
 
 
+PROFILE = os.path.join(ROOT, "profiles", "sweeps_nine_species_sbi_256.md")
+
+
+def kernel_source_hash():
+    """hash of the kernel sources and the ABI header (what the counters were taken on)"""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2403_05910_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(ROOT, "include", "xf.h"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_class, precision):
+    """HBM bytes per launch of a kernel class from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated against a device copy);
+    None when the summary is missing or the kernels changed since"""
+    try:
+        with open(PROFILE) as f:
+            text = f.read()
+        blob = text.split("```json", 1)[1].split("```", 1)[0]
+        data = json.loads(blob)
+    except (OSError, IndexError, ValueError):
+        return None
+    if data.get("source_hash") != kernel_source_hash():
+        return None
+    row = data.get("traffic_bytes_per_launch", {}).get(precision, {}).get(kernel_class)
+    return None if row is None else row["fetch"] + row["write"]
+
+
 def roofline_of(kernels, case, precision):
     """dominant kernel class by total time; flops per launch from the
     algorithmic count; achieved = flops per launch / average launch time"""
@@ -70,8 +104,8 @@ def roofline_of(kernels, case, precision):
     achieved = flops / avg_s / 1e12
     peak = pm.PEAK["fp32_vector_TFLOPs" if precision == "mixed" else "fp64_vector_TFLOPs"]
     return {"kernel": name, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None, "avg_launch_ms": ms / launches, "launches": launches,
-            "flops_per_launch": flops}
+            "frac": achieved / peak, "traffic": measured_traffic(name, precision), "traffic_unit": "bytes/launch",
+            "avg_launch_ms": ms / launches, "launches": launches, "flops_per_launch": flops}
 
 
 def cpu_model():
@@ -126,7 +160,7 @@ def rollout_ratio(torch, xf, n=64, steps=64, every=8):
             "peak_bytes_during_backward": peak}
 
 
-def cpu_baseline(case, crop=56):
+def cpu_baseline(case, crop=96):
     """the oracle as it stands, on a crop^3 block of the same state (its
     halo taken from the neighbouring cells), straddling the shock and bubble"""
     import oracle as O
