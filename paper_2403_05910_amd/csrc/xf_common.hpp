@@ -100,8 +100,13 @@ inline int vjp_record_fields(int ns) { return 44 + 2 * ns; }
 inline long long vjp_x_waves_per_plane(const Geo &g) { return ((long long)(g.nx + 1) * g.ny + 63) / 64; }
 inline long long vjp_yz_threads(const Geo &g, int dir) {
     const int nsw = dir == 1 ? g.ny : g.nz, ntr = dir == 1 ? g.nz : g.ny;
+    // blocked form: 16 x 16 faces per block, every sixth face block per launch
+    const long long nfb = (nsw + 1 + 15) / 16;
+    const long long blocked = (long long)((g.nx + 15) / 16) * ((nfb + kVjpGroups - 1) / kVjpGroups) * ntr * 256;
+    // face-class form: faces j = p (mod 6), 64 x 4 threads per block
     const long long per_class = nsw / 6 + 1;
-    return (long long)((g.nx + 63) / 64) * 64 * ((per_class + 3) / 4) * 4 * ntr;
+    const long long classes = (long long)((g.nx + 63) / 64) * 64 * ((per_class + 3) / 4) * 4 * ntr;
+    return blocked > classes ? blocked : classes;
 }
 // record rows one launch of any direction can use
 inline long long vjp_record_rows(const Geo &g) {

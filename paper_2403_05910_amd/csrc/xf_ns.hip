@@ -92,6 +92,18 @@ hipError_t launch_vjp_group(const LaunchCtx &c, const ThermoK<R> &th, int dir, i
         dim3 grid((unsigned)((waves + wpb - 1) / wpb), g.nz), block(64 * wpb);
         hipLaunchKernelGGL((k_face_vjp_x<NS, R, HALF>), grid, block, per_wave * wpb, s, U, P, rbar, Ubar, Pbar, rec,
                            nrec, g, th, W, grp);
+    } else if (c.variant != 4) {
+        const int nsw = dir == 1 ? g.ny : g.nz;
+        const int xt = (g.nx + kVjpTX - 1) / kVjpTX;
+        const int nfb = (nsw + 1 + kVjpFB - 1) / kVjpFB;
+        const int nb = (nfb - grp + kVjpGroups - 1) / kVjpGroups;
+        dim3 grid((unsigned)(xt * nb), dir == 1 ? g.nz : g.ny), block(256);
+        if (dir == 1)
+            hipLaunchKernelGGL((k_face_vjp_yz<NS, R, 1, HALF>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec,
+                               g, th, grp);
+        else
+            hipLaunchKernelGGL((k_face_vjp_yz<NS, R, 2, HALF>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec,
+                               g, th, grp);
     } else {
         const int nsw = dir == 1 ? g.ny : g.nz;
         dim3 grid((g.nx + 63) / 64, (nsw / 6 + 1 + 3) / 4, dir == 1 ? g.nz : g.ny), block(64, 4);
@@ -111,7 +123,9 @@ template <typename R>
 hipError_t sweep_vjp_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, const double *U, const double *P,
                        const double *rbar, double *Ubar, double *Pbar, double *rec, long long nrec, hipStream_t s) {
     const Geo &g = c.g;
-    const long long ngrp = dir == 0 ? vjp_x_waves_per_plane(g) : (long long)(dir == 1 ? g.ny : g.nz) + 1;
+    const int nsw = dir == 1 ? g.ny : g.nz;
+    const long long ngrp = dir == 0 ? vjp_x_waves_per_plane(g)
+                                    : (c.variant == 4 ? nsw + 1 : (nsw + 1 + kVjpFB - 1) / kVjpFB);
     for (int grp = 0; grp < kVjpGroups && grp < ngrp; ++grp) {
         hipError_t e = launch_vjp_group<R, 0>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, rec, nrec, s);
         if (e == hipSuccess) e = launch_vjp_group<R, 1>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, rec, nrec, s);

@@ -624,6 +624,93 @@ __global__ __launch_bounds__(256) void k_face_vjp(const double *__restrict__ U, 
         face_vjp_b<NS, R, DIR>(st, th, sk, rc);
 }
 
+// ---------------------------------------------------------------------------
+// y and z directions, blocked: a block takes 16 x-columns by 16 consecutive
+// faces j0..j0+15 of the sweep axis (j0 = 16 b) in one plane of the third
+// axis; wave w of the block takes faces j0+4w..j0+4w+3 (lane = 16 ts + tx),
+// so each stencil load of a wave reads four whole 128-byte rows.  Wave w
+// accumulates in a private LDS window of sweep rows j0+4w-3..j0+4w+5 (within
+// one instruction its lanes address distinct cells); the block then adds,
+// for each of its 21 x 16 cells, the windows that cover it in wave order to
+// Ubar / Pbar (one coalesced read-modify-write per cell and field).  Blocks
+// b and b + 1 share six rows, blocks b and b + 6 none: launch `phase` takes
+// the blocks b = phase mod 6.
+// ---------------------------------------------------------------------------
+constexpr int kVjpTX = 16, kVjpFB = 16, kVjpWin = kVjpTX * 9;
+
+template <int NS, typename R, int DIR, int HALF>
+__global__ __launch_bounds__(256) void k_face_vjp_yz(const double *__restrict__ U, const double *__restrict__ P,
+                                                     const double *__restrict__ rbar, double *__restrict__ Ubar,
+                                                     double *__restrict__ Pbar, double *__restrict__ rec,
+                                                     long long nrec, Geo g, ThermoK<R> th, int phase) {
+    constexpr int NV = NS + 4;
+    __shared__ double xf_wyz[4][(NV + 2) * kVjpWin];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tx = lane & (kVjpTX - 1), ts = lane / kVjpTX;
+    const int nsw = DIR == 1 ? g.ny : g.nz;
+    const long long ss = DIR == 1 ? g.sy : g.sz;
+    const int gs = DIR == 1 ? g.gy : g.gz;
+    const int xt = (g.nx + kVjpTX - 1) / kVjpTX;                   // x tiles
+    const int nfb = (nsw + 1 + kVjpFB - 1) / kVjpFB;               // face blocks along the sweep axis
+    const int nb = (nfb - phase + kVjpGroups - 1) / kVjpGroups;    // face blocks of this phase
+    const int xi = blockIdx.x % xt;
+    const int b = phase + kVjpGroups * (int)(blockIdx.x / xt);     // this block's face block (< nfb)
+    const int tr = blockIdx.y;                                     // plane of the third axis
+    const int j0 = b * kVjpFB;
+    const int x = xi * kVjpTX + tx;
+    const int j = j0 + 4 * wv + ts;
+    const long long C = g.cells;
+    // padded index of the cell at x = x0 + tx, interior sweep index 0, in this plane
+    const long long col0 = (long long)g.gx + (DIR == 1 ? (long long)(g.gz + tr) * g.sz : (long long)(g.gy + tr) * g.sy) +
+                           (long long)gs * ss;
+    volatile double *w = xf_wyz[wv];
+    for (int i = lane; i < (NV + 2) * kVjpWin; i += 64) w[i] = 0.0;
+    __syncthreads();
+    (void)nb;
+    if (x < g.nx && j <= nsw) {
+        const long long col = col0 + x;
+        const double id = DIR == 1 ? g.idy : g.idz;
+        R Fb[NV];
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const double rr = j < nsw ? rbar[q * C + col + (long long)j * ss] : 0.0;
+            const double rl = j > 0 ? rbar[q * C + col + (long long)(j - 1) * ss] : 0.0;
+            Fb[q] = R((rr - rl) * id);
+            any = any || (Fb[q] != R(0));
+        }
+        if (any) {
+            const long long base = col + (long long)(j - 3) * ss;
+            Stencil st{U, P, base, ss, C};
+            // window row r of wave w = sweep row j0 + 4w - 3 + r; stencil cell m is row ts + m
+            SinkLds sk{w, kVjpWin, ts * kVjpTX + tx, kVjpTX, NV * kVjpWin};
+            const VjpRec<NS> rc{rec, nrec, (long long)(blockIdx.y * gridDim.x + blockIdx.x) * 256 + threadIdx.x};
+            if constexpr (HALF == 0)
+                face_vjp_a<NS, R, DIR>(st, th, Fb, sk, rc);
+            else
+                face_vjp_b<NS, R, DIR>(st, th, sk, rc);
+        }
+    }
+    __syncthreads();
+    // block rows r = 0..20 (sweep rows j0-3 .. j0+17); wave w covers r in [4w, 4w+9)
+    for (int c = threadIdx.x; c < kVjpTX * (kVjpFB + 5); c += 256) {
+        const int r = c / kVjpTX, cx = xi * kVjpTX + (c % kVjpTX);
+        const int row = j0 - 3 + r;                       // interior index along the sweep axis
+        if (cx >= g.nx || row > nsw + 2) continue;
+        const int wlo = r >= 8 ? (r - 8 + 3) / 4 : 0, whi = min(3, r / 4);
+        const long long cell = col0 + cx + (long long)row * ss;
+#pragma unroll
+        for (int q = 0; q < NV + 2; ++q) {
+            double v = 0.0;
+            for (int ww = wlo; ww <= whi; ++ww) v += xf_wyz[ww][q * kVjpWin + (r - 4 * ww) * kVjpTX + (c % kVjpTX)];
+            if (q < NV)
+                Ubar[q * C + cell] += v;
+            else
+                Pbar[(q - NV) * C + cell] += v;
+        }
+    }
+}
+
 // Per-cell backward of (p, T)(U): p = T sum_s rho_s R_s, and T from
 // rho e(T) = E - |m|^2 / (2 rho) by the implicit-function rule
 //   dT = (dE - u.dm + |u|^2/2 sum_s drho_s - sum_s e_s(T) drho_s) / (rho C_v).
