@@ -15,6 +15,8 @@ What it computes, in the paper's order and notation (Sec. II.C):
   * conservative flux difference (F^_{i+1/2} - F^_{i-1/2}) / dx    (Eq. 13)
   * SSP-RK3 time march                                          (Eq. 16)
   * CFL time step lambda = dt/dx = CFL / Lambda                 (Eq. 17)
+  * positivity-preserving blend of the face flux with the
+    Lax-Friedrichs flux, for rho and the partial densities      (Sec. II.C.2, Eq. 17-20)
 
 The arithmetic is deliberately plain: dense L and R matrices per face, dense
 matrix-vector products, the three-division WENO form, no fusion or reordering.
@@ -36,6 +38,8 @@ Readings of points the paper leaves open (each is stated where it is used):
     constant-volume one (C_v = sum Y_s C_p,s - Rbar, as the same equation says).
   * Eq. 17 writes U^{n+1} = U^n + lambda (F_{i+1/2} - F_{i-1/2}); the residual
     of Eq. 13 carries the opposite sign, which is the one used here.
+  * Positivity preserving (Eq. 17-20; the limiting factor follows the cited
+    method, which the paper does not restate): see positivity_limit.
 """
 from __future__ import annotations
 
@@ -479,6 +483,67 @@ def face_flux(th, d, Ust, Pst, alpha=None):
     return Fhat, alpha, roe["c2"]
 
 
+# ---------------------------------------------------------------------------
+# Positivity-preserving flux blend (Sec. II.C.2, Eq. 17-20)
+# ---------------------------------------------------------------------------
+PP_RHO_FLOOR = 1e-13   # total density floor, relative to min(rho_L, rho_R)
+PP_Y_FLOOR = 1e-12     # partial densities may reach -1e-12 rho of their own cell
+
+
+def lax_friedrichs_flux(th, d, Ust, Pst, lf):
+    """Eq. 19 at faces i+1/2: 1/2 [F(U_i) + F(U_i+1) + lf (U_i - U_i+1)],
+    U_i, U_i+1 the stencil slots 2 and 3; lf (F,) the dissipation coefficient."""
+    Fm = physical_flux(th, Ust, Pst, d)
+    return 0.5 * (Fm[:, 2] + Fm[:, 3] + lf * (Ust[:, 2] - Ust[:, 3]))
+
+
+def positivity_limit(th, d, Ust, Pst, Fhat, alpha, lam):
+    """Blend F* = F^LF + theta (F^ - F^LF) of Eq. 20 at faces i+1/2.
+
+    Eq. 18 writes the Euler update of cell i as the mean of the half-step
+    states U_i - 2 lam F_{i+1/2} and U_i + 2 lam F_{i-1/2}.  Readings (the
+    paper defers the limiting factor to the method it cites):
+      * the components kept positive are the total density and every partial
+        density rho_s (the paper extends the density limiter to the mass
+        fractions): floors 1e-13 min(rho_i, rho_i+1) for rho and
+        -1e-12 rho of the half-state's own cell for rho_s (a vanishing species
+        tolerates round-off of that size, which leaves Y_s >= -1e-12);
+      * the Lax-Friedrichs coefficient of Eq. 19 is the face's largest LLF
+        wave speed, i.e. the larger acoustic one;
+      * in D active dimensions the update is the mean of D one-dimensional
+        updates with lam = D dt / dx_d each (lam is passed in);
+      * per face and component, theta is the largest value in [0, 1] for which
+        the half-states of both neighbouring cells stay at or above the floor;
+        the face's theta is the minimum over components and both cells, and
+        theta = 1 leaves F^ untouched.
+    Ust (Nv, 6, F), Pst as in face_flux; Fhat (Nv, F); alpha (Nv, F) the
+    face's LLF speeds (rows u-c, ..., u+c); lam a scalar.
+    Returns (Fstar (Nv, F), theta (F,))."""
+    ns = th.ns
+    lf = np.maximum(alpha[0].real, alpha[-1].real)
+    FLF = lax_friedrichs_flux(th, d, Ust, Pst, lf)
+
+    def comps(V):                      # rows: rho, rho_1 .. rho_ns
+        return np.concatenate([V[:ns].sum(axis=0, keepdims=True), V[:ns]], axis=0)
+
+    qL, qR = comps(Ust[:, 2]), comps(Ust[:, 3])
+    qH, qLF = comps(Fhat), comps(FLF)
+    rhoL, rhoR = qL[0].real, qR[0].real
+    floor_rho = PP_RHO_FLOOR * np.minimum(rhoL, rhoR)
+    epsL = np.concatenate([floor_rho[None], np.broadcast_to(-PP_Y_FLOOR * rhoL, (ns,) + rhoL.shape)], axis=0)
+    epsR = np.concatenate([floor_rho[None], np.broadcast_to(-PP_Y_FLOOR * rhoR, (ns,) + rhoR.shape)], axis=0)
+    theta = np.ones(Fhat.shape[1])
+    for q0, sgn, eps in ((qL, -1.0, epsL), (qR, 1.0, epsR)):
+        w_hi = (q0 + sgn * 2.0 * lam * qH).real          # half-state with the high-order flux
+        w_lo = (q0 + sgn * 2.0 * lam * qLF).real         # ... with the Lax-Friedrichs flux
+        gap = w_lo - w_hi
+        with np.errstate(all="ignore"):
+            t = np.where(w_hi >= eps, 1.0, np.where(gap > 0, (w_lo - eps) / gap, 0.0))
+        theta = np.minimum(theta, np.clip(t, 0.0, 1.0).min(axis=0))
+    Fstar = np.where(theta == 1.0, Fhat, FLF + theta * (Fhat - FLF))
+    return Fstar, theta
+
+
 def _stencils(Q, axis, g, n):
     """the six stencil slices along `axis` for faces k = 0..n (face k lies
     between padded cells g+k-1 and g+k)"""
@@ -486,11 +551,14 @@ def _stencils(Q, axis, g, n):
                     axis=0)
 
 
-def rhs(th, grid, U, alpha=None, return_aux=False):
+def rhs(th, grid, U, alpha=None, return_aux=False, pp_dt=None):
     """Convective residual L(U) = -sum_d (F^_{i+1/2} - F^_{i-1/2}) / dx_d
     (Eq. 13) on the interior of the padded state U (Nv, Z, Y, X); ghost cells
     of U must already hold their boundary values; ghost cells of the result are
-    zero.  alpha, if given, is a dict d -> frozen LLF speeds (Nv, faces)."""
+    zero.  alpha, if given, is a dict d -> frozen LLF speeds (Nv, faces).
+    pp_dt, if given, is the time step of the Euler stage the residual is used
+    in: the face fluxes are then blended by positivity_limit with
+    lam = D pp_dt / dx_d (D active dimensions)."""
     nv = th.ns + 4
     assert U.shape == (nv,) + grid.padded, (U.shape, grid.padded)
     with np.errstate(all="ignore"):
@@ -548,6 +616,11 @@ def rhs(th, grid, U, alpha=None, return_aux=False):
         with np.errstate(all="ignore"):
             Fh, al, c2 = face_flux(th, d, Ust, Pst, a_in)
         aux["alpha"][d] = al
+        if pp_dt is not None:
+            lam = len(grid.active()) * pp_dt / grid.d[d]
+            with np.errstate(all="ignore"):
+                Fh, theta = positivity_limit(th, d, Ust, Pst, Fh, al, lam)
+            aux.setdefault("theta", {})[d] = theta
         aux["fmax"] = np.maximum(aux["fmax"], np.max(np.abs(Fh.real), axis=1))
         if np.any(c2.real <= 0):
             aux_flags |= FLAG_C2
@@ -664,16 +737,18 @@ def ssp_rk3(L, U, dt):
     return U / 3.0 + 2.0 / 3.0 * (U2 + dt * L(U2))
 
 
-def rk3_step(th, grid, U, dt, alpha=None):
+def rk3_step(th, grid, U, dt, alpha=None, pp=False):
     """One SSP-RK3 step of the convective system with ghosts refilled before
     every stage.  alpha: optional list of three frozen-speed dicts, one per
-    stage (in stage order)."""
+    stage (in stage order).  pp: blend every stage's face fluxes for
+    positivity (each SSP-RK3 stage is a convex combination of Euler steps of
+    size dt)."""
     a = list(alpha) if alpha is not None else [None, None, None]
     stage = [0]
 
     def L(V):
         V = fill_ghosts(grid, V)
-        r = rhs(th, grid, V, a[stage[0]])
+        r = rhs(th, grid, V, a[stage[0]], pp_dt=dt if pp else None)
         stage[0] += 1
         return r
 

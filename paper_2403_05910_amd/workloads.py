@@ -428,6 +428,46 @@ def sod(nx=400, gamma=1.4):
     return Case("sod", (nx, 1, 1), (1.0 / nx, 1.0, 1.0), (1, 1, 1, 1, 1, 1), tab, U)
 
 
+def species_interface_1d(nx=200):
+    """Sharp two-gas slab advected through a periodic box: gas A
+    (gamma, W) = (1.4, 28.96) on [0.25, 0.75), gas B (1.667, 4.003) elsewhere,
+    u = 1, p = 1, T = 1e-3 (about 7x denser A); the mass fractions jump from 0
+    to 1 in one cell, where WENO reconstruction undershoots."""
+    tab = perfect_gas_table([1.4, 1.667], [28.96, 4.003])
+    x = (np.arange(nx) + 0.5) / nx
+    inside = (x >= 0.25) & (x < 0.75)
+    Y = np.stack([np.where(inside, 1.0, 0.0), np.where(inside, 0.0, 1.0)])
+    T = np.full(nx, 1e-3)
+    Rm = mixture_R(tab, Y)
+    rho = 1.0 / (Rm * T)
+    vel = np.zeros((3, nx))
+    vel[0] = 1.0
+    interior = assemble(tab, rho, vel, T, Y).reshape(6, 1, 1, nx)
+    U, g = _padded((nx, 1, 1), 6)
+    _place(U, g, interior)
+    return Case("species_interface_1d", (nx, 1, 1), (1.0 / nx, 1.0, 1.0), (0,) * 6, tab, U)
+
+
+def double_rarefaction_1d(nx=200, u0=3.0):
+    """Two gases pulled apart: (rho, u, p) = (1, -u0, 0.4) with gas A
+    (gamma 1.4, W 28.96) for x < 0.5 and (1, +u0, 0.4) with gas B (1.667,
+    4.003) beyond; outflow at both ends.  Two strong rarefactions leave a
+    near-vacuum between them (u0 = 2 is the classic '123' case)."""
+    tab = perfect_gas_table([1.4, 1.667], [28.96, 4.003])
+    x = (np.arange(nx) + 0.5) / nx
+    left = x < 0.5
+    Y = np.stack([np.where(left, 1.0, 0.0), np.where(left, 0.0, 1.0)])
+    rho = np.ones(nx)
+    p = np.full(nx, 0.4)
+    T = p / (rho * mixture_R(tab, Y))
+    vel = np.zeros((3, nx))
+    vel[0] = np.where(left, -u0, u0)
+    interior = assemble(tab, rho, vel, T, Y).reshape(6, 1, 1, nx)
+    U, g = _padded((nx, 1, 1), 6)
+    _place(U, g, interior)
+    return Case("double_rarefaction_1d", (nx, 1, 1), (1.0 / nx, 1.0, 1.0), (1,) * 6, tab, U)
+
+
 def random_smooth_state(tab, n, seed, amp=0.05, u_scale=50.0, T0=300.0, p0=1e5, bc=(0,) * 6,
                         jump=False):
     """A generic random state on a small grid for parity tests: smooth Fourier

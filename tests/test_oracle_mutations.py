@@ -149,3 +149,47 @@ def test_newton_with_cp_denominator_still_converges_but_energy_with_cp_caught(mo
     changes the EOS and the textbook comparison fails."""
     _patch(monkeypatch, "mixture_e", lambda th, Y, T: np.sum(Y * th.R * X.h_over_R(th, T), axis=-1))
     assert _fails(P.test_single_gas_matches_textbook_solver, rng)
+
+
+# -- positivity-preserving blend (pins in test_oracle_positivity.py) --------
+import test_oracle_positivity as PP  # noqa: E402
+
+
+def test_positivity_half_step_factor_caught(monkeypatch):
+    orig = X.positivity_limit
+    # half-states U -+ lam F instead of U -+ 2 lam F (Eq. 18)
+    _patch(monkeypatch, "positivity_limit", lambda th, d, Ust, Pst, Fh, al, lam: orig(th, d, Ust, Pst, Fh, al, 0.5 * lam))
+    assert _fails(PP.test_half_states_respect_floors_with_largest_theta, 2)
+
+
+def test_positivity_side_sign_caught(monkeypatch):
+    def bad(th, d, Ust, Pst, Fhat, alpha, lam):
+        ns = th.ns
+        lf = np.maximum(alpha[0].real, alpha[-1].real)
+        FLF = X.lax_friedrichs_flux(th, d, Ust, Pst, lf)
+        comps = lambda V: np.concatenate([V[:ns].sum(axis=0, keepdims=True), V[:ns]], axis=0)
+        qL, qR = comps(Ust[:, 2]), comps(Ust[:, 3])
+        qH, qLF = comps(Fhat), comps(FLF)
+        rhoL, rhoR = qL[0].real, qR[0].real
+        fr = X.PP_RHO_FLOOR * np.minimum(rhoL, rhoR)
+        epsL = np.concatenate([fr[None], np.broadcast_to(-X.PP_Y_FLOOR * rhoL, (ns,) + rhoL.shape)])
+        epsR = np.concatenate([fr[None], np.broadcast_to(-X.PP_Y_FLOOR * rhoR, (ns,) + rhoR.shape)])
+        theta = np.ones(Fhat.shape[1])
+        for q0, sgn, eps in ((qL, 1.0, epsL), (qR, -1.0, epsR)):      # planted: sides swapped
+            w_hi = q0 + sgn * 2.0 * lam * qH
+            w_lo = q0 + sgn * 2.0 * lam * qLF
+            gap = w_lo - w_hi
+            with np.errstate(all="ignore"):
+                t = np.where(w_hi >= eps, 1.0, np.where(gap > 0, (w_lo - eps) / gap, 0.0))
+            theta = np.minimum(theta, np.clip(t, 0.0, 1.0).min(axis=0))
+        return np.where(theta == 1.0, Fhat, FLF + theta * (Fhat - FLF)), theta
+    _patch(monkeypatch, "positivity_limit", bad)
+    assert _fails(PP.test_half_states_respect_floors_with_largest_theta, 3)
+    assert _fails(PP.test_mass_fractions_stay_above_floor_over_a_run)
+
+
+def test_positivity_not_applied_caught(monkeypatch):
+    _patch(monkeypatch, "positivity_limit",
+           lambda th, d, Ust, Pst, Fh, al, lam: (Fh, np.ones(Fh.shape[1])))
+    assert _fails(PP.test_mass_fractions_stay_above_floor_over_a_run)
+    assert _fails(PP.test_half_states_respect_floors_with_largest_theta, 4)
