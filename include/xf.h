@@ -150,6 +150,19 @@ int xf_cfl_dt(xf_ctx *ctx, const double *U, double cfl, double *dt_dev, void *ws
  * ws: xf_workspace_bytes(ctx, XF_OP_RK3) bytes. */
 int xf_rk3_step(xf_ctx *ctx, double *U, double dt, const double *dt_dev, void *ws, void *stream);
 
+/* Positivity-preserving flux blend (Sec. II.C.2, Eq. 17-20) in the SSP-RK3
+ * steps of this context (xf_rk3_step, xf_rk3_step_cfl), off by default.
+ * Each face flux becomes F_LF + theta (F^ - F_LF), F_LF the Lax-Friedrichs
+ * flux of Eq. 19 (coefficient: the face's larger acoustic LLF speed) and
+ * theta in [0, 1] the largest value keeping the Euler half-states
+ * U_i -+ 2 lam F of Eq. 18 (lam = D dt / dx_d, D active dimensions) at or
+ * above 1e-13 min(rho_i, rho_i+1) in total density and -1e-13 rho of the
+ * cell in every partial density (-1e-6 rho in XF_PREC_MIXED, above FP32
+ * round-off).  Stages use the step's dt.  xf_rhs and
+ * xf_rhs_vjp are unaffected (the blend needs a time step); xf_rk3_step_vjp
+ * returns XF_EUNSUPPORTED while the blend is on.  enable: 0 or 1. */
+int xf_set_positivity(xf_ctx *ctx, int enable);
+
 /* xf_rk3_step with the time step of Eq. 17 computed on the device from U^n
  * (the same reduction as xf_cfl_dt, reusing the first stage's primitives)
  * and written to the device double *dt_dev before the stages use it.  This

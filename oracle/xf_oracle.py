@@ -487,7 +487,7 @@ def face_flux(th, d, Ust, Pst, alpha=None):
 # Positivity-preserving flux blend (Sec. II.C.2, Eq. 17-20)
 # ---------------------------------------------------------------------------
 PP_RHO_FLOOR = 1e-13   # total density floor, relative to min(rho_L, rho_R)
-PP_Y_FLOOR = 1e-12     # partial densities may reach -1e-12 rho of their own cell
+PP_Y_FLOOR = 1e-13     # partial densities may reach -1e-13 rho of their own cell
 
 
 def lax_friedrichs_flux(th, d, Ust, Pst, lf):
@@ -506,8 +506,9 @@ def positivity_limit(th, d, Ust, Pst, Fhat, alpha, lam):
       * the components kept positive are the total density and every partial
         density rho_s (the paper extends the density limiter to the mass
         fractions): floors 1e-13 min(rho_i, rho_i+1) for rho and
-        -1e-12 rho of the half-state's own cell for rho_s (a vanishing species
-        tolerates round-off of that size, which leaves Y_s >= -1e-12);
+        -1e-13 rho of the half-state's own cell for rho_s (a vanishing species
+        tolerates round-off of that size; the new state, a mean of half-states,
+        then keeps Y_s above -1e-12);
       * the Lax-Friedrichs coefficient of Eq. 19 is the face's largest LLF
         wave speed, i.e. the larger acoustic one;
       * in D active dimensions the update is the mean of D one-dimensional

@@ -36,6 +36,7 @@ struct xf_ctx {
     int device;
     // per-kernel timing (off unless xf_timing enabled it)
     bool timing;
+    int pp;   // positivity-preserving flux blend in the RK3 step
     struct Rec {
         int cls;
         hipEvent_t a, b;
@@ -286,6 +287,7 @@ int xf_create(const xf_grid *grid, const xf_thermo *thermo, int precision, xf_ct
     xf_ctx *c = new (std::nothrow) xf_ctx();
     if (!c) return XF_ENOMEM;
     c->timing = false;
+    c->pp = 0;
     xf::Geo &g = c->lc.g;
     g.nx = grid->nx;
     g.ny = grid->ny;
@@ -438,7 +440,6 @@ int rk3_step(xf_ctx *c, double *U, double dt, const double *dt_in, double cfl, d
     double *out[3] = {S1, S2, U};
     const double a[3] = {0.0, 0.75, 1.0 / 3.0};
     const double b[3] = {1.0, 0.25, 2.0 / 3.0};
-    const xf::StageArgs off{};
     for (int k = 0; k < 3; ++k) {
         XF_TRY(fill(c, in[k], s));
         XF_TRY(prims(c, in[k], pb, s));
@@ -451,16 +452,24 @@ int rk3_step(xf_ctx *c, double *U, double dt, const double *dt_in, double cfl, d
             }));
             h = dt_out;
         }
+        // no fused stage; the step size only for the positivity blend
+        const xf::StageArgs sw{nullptr, nullptr, nullptr, 0.0, 0.0, dt, h, 0, c->pp};
         for (int d = 2; d >= 0; --d) {
             if (n[d] <= 1) continue;
             XF_TRY(timed(c, XF_K_SWEEP_X + d, s,
-                         [&] { return c->ops->sweep(lc, d, 0, in[k], P, pb.Uf, pb.Pf, Ld[d], off, s); }));
+                         [&] { return c->ops->sweep(lc, d, 0, in[k], P, pb.Uf, pb.Pf, Ld[d], sw, s); }));
         }
         XF_TRY(timed(c, XF_K_STAGE, s, [&] {
             return xf::launch_rk3_stage_sum(lc, c->nv, out[k], U, in[k], Lsum, a[k], b[k], dt, h, s);
         }));
     }
     XF_TRY(fill(c, U, s));
+    return XF_OK;
+}
+
+int xf_set_positivity(xf_ctx *c, int enable) {
+    if (!c) return XF_EINVAL;
+    c->pp = enable != 0;
     return XF_OK;
 }
 
@@ -489,6 +498,7 @@ int xf_rk3_step_vjp(xf_ctx *c, const double *Un, double dt, double *Ubar, void *
     if (!c || !Un || !Ubar || !ws || Un == Ubar || !aligned8(Un) || !aligned8(Ubar) || !aligned8(ws) ||
         !(dt >= 0.0))
         return XF_EINVAL;
+    if (c->pp) return XF_EUNSUPPORTED;   // the adjoint is of the unblended step
     const Layout l = layout(c, XF_OP_RK3_VJP);
     const hipStream_t s = (hipStream_t)stream;
     const LaunchCtx &lc = c->lc;

@@ -51,7 +51,8 @@ struct StageArgs {
     double *Uout;
     double a, b, dt;
     const double *dt_dev;
-    int on;
+    int on;   // write the stage combination instead of the residual
+    int pp;   // blend the face fluxes for positivity with the step dt (or *dt_dev)
 };
 
 // Everything a launch needs besides buffers.

@@ -52,6 +52,8 @@ XF_HD float xsqrt(float a) { return sqrtf(a); }
 
 template <typename R>
 XF_HD R rmax(R a, R b) { return a > b ? a : b; }
+template <typename R>
+XF_HD R rmin(R a, R b) { return a < b ? a : b; }
 
 template <typename R>
 XF_HD R rabs(R a) { return a < R(0) ? -a : a; }
@@ -317,6 +319,95 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
 template <int NS, typename R, int DIR>
 XF_HD void face_flux(const Stencil &st, const ThermoK<R> &th, R *__restrict__ Fh, unsigned &flags) {
     face_flux_to<NS, R, DIR>(st, th, [&](int q, R v) { Fh[q] = v; }, flags);
+}
+
+// ---------------------------------------------------------------------------
+// Positivity-preserving blend of one face flux (Sec. II.C.2, Eq. 17-20):
+// F* = F_LF + theta (F^ - F_LF), F_LF the Lax-Friedrichs flux of Eq. 19 with
+// the face's larger acoustic LLF speed as its coefficient, theta the largest
+// value in [0, 1] that keeps the Euler half-states U_i - 2 lam F* and
+// U_i+1 + 2 lam F* of Eq. 18 at or above the floors: total density
+// 1e-13 min(rho_i, rho_i+1), each partial density -1e-13 rho of its own cell
+// in FP64 (-1e-6 rho in FP32, above that precision's round-off of a
+// vanishing species' flux); the minimum over the components and both cells;
+// theta = 1 leaves F^ untouched.  lam = D dt / dx for D active dimensions (the multi-dimensional
+// Euler step is the mean of D one-dimensional ones).  F holds F^ on entry and
+// F* on return.
+// ---------------------------------------------------------------------------
+constexpr double kPpRhoFloor = 1e-13;
+template <typename R>
+struct PpFloor {
+    static constexpr double y = 1e-6;
+};
+template <>
+struct PpFloor<double> {
+    static constexpr double y = 1e-13;
+};
+
+template <int NS, typename R, int DIR, class St>
+XF_HD void pp_limit(const St &st, R lam, R *F) {
+    constexpr int NV = NS + 4, IE = NS + 3, IN = NS + Axes<DIR>::n;
+    R aM = R(0), aP = R(0);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        const R rinv = R(st.p(3, m)), cm = R(st.p(2, m));
+        const R unm = R(st.u(IN, m)) * rinv;
+        aM = rmax(aM, rabs(unm - cm));
+        aP = rmax(aP, rabs(unm + cm));
+    }
+    const R lf = rmax(aM, aP);
+    const R pL = R(st.p(1, 2)), pR = R(st.p(1, 3));
+    const R unL = R(st.u(IN, 2)) * R(st.p(3, 2)), unR = R(st.u(IN, 3)) * R(st.p(3, 3));
+    R FLF[NV];
+#pragma unroll
+    for (int f = 0; f < NV; ++f) {
+        const R uL = R(st.u(f, 2)), uR = R(st.u(f, 3));
+        R fL, fR;
+        if (f == IE) {
+            fL = (uL + pL) * unL;
+            fR = (uR + pR) * unR;
+        } else if (f == IN) {
+            fL = uL * unL + pL;
+            fR = uR * unR + pR;
+        } else {
+            fL = uL * unL;
+            fR = uR * unR;
+        }
+        FLF[f] = R(0.5) * ((fL + fR) + lf * (uL - uR));
+    }
+    // components kept positive: rho (row 0), rho_1 .. rho_NS
+    R rhoL = R(0), rhoR = R(0), qH = R(0), qLF = R(0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        rhoL += R(st.u(s, 2));
+        rhoR += R(st.u(s, 3));
+        qH += F[s];
+        qLF += FLF[s];
+    }
+    const R two_lam = R(2) * lam;
+    const R floor_rho = R(kPpRhoFloor) * rmin(rhoL, rhoR);
+    R theta = R(1);
+    auto bound = [&](R q0, R sgn, R h, R lo, R eps) {
+        const R w_hi = q0 + sgn * two_lam * h;       // half-state with the high-order flux
+        const R w_lo = q0 + sgn * two_lam * lo;      // ... with the Lax-Friedrichs flux
+        const R gap = w_lo - w_hi;
+        R t = R(1);
+        if (!(w_hi >= eps)) t = gap > R(0) ? (w_lo - eps) / gap : R(0);
+        t = rmin(rmax(t, R(0)), R(1));
+        theta = rmin(theta, t);
+    };
+    bound(rhoL, R(-1), qH, qLF, floor_rho);
+    bound(rhoR, R(1), qH, qLF, floor_rho);
+    const R epsL = -R(PpFloor<R>::y) * rhoL, epsR = -R(PpFloor<R>::y) * rhoR;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        bound(R(st.u(s, 2)), R(-1), F[s], FLF[s], epsL);
+        bound(R(st.u(s, 3)), R(1), F[s], FLF[s], epsR);
+    }
+    if (theta < R(1)) {
+#pragma unroll
+        for (int f = 0; f < NV; ++f) F[f] = FLF[f] + theta * (F[f] - FLF[f]);
+    }
 }
 
 }  // namespace xf

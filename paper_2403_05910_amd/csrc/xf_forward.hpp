@@ -152,6 +152,14 @@ struct SweepTune<double> {
     static constexpr int waves = 2;
 };
 
+// lam = D dt / dx_d of the positivity blend (D active dimensions).
+template <typename R>
+__device__ __forceinline__ R pp_lambda(const Geo &g, const StageArgs &sa, double idx) {
+    const double h = sa.dt_dev ? *sa.dt_dev : sa.dt;
+    const int D = (g.nx > 1) + (g.ny > 1) + (g.nz > 1);
+    return R(D * h * idx);
+}
+
 // Write the finished residual d of one field at one cell: to rhs (=, or +=
 // when accumulating), or, when the stage is fused, the stage combination
 // Uout = a U0 + b (Uin + h L) with L the complete residual.
@@ -175,7 +183,7 @@ __device__ __forceinline__ void put_result(double *__restrict__ rhs, const Stage
 // ---------------------------------------------------------------------------
 constexpr int kXBlock = 256;
 
-template <int NS, typename R, typename S>
+template <int NS, typename R, typename S, bool PP>
 __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(SweepTune<R>::waves))) void k_sweep_x(
     const S *__restrict__ U, const S *__restrict__ P, double *__restrict__ rhs, Geo g, ThermoK<R> th, int accumulate,
     StageArgs sa, unsigned *status) {
@@ -197,6 +205,14 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(SweepTu
         rowbase = (long long)(g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + g.gx;
         StencilT<S> st{U, P, rowbase + i - 3, 1, g.cells};
         face_flux_to<NS, R, 0, SweepTune<R>::fence_face>(st, th, [&](int q, R v) { sF[q][t] = v; }, flags);
+        if constexpr (PP) {
+            R Fq[NV];
+#pragma unroll
+            for (int q = 0; q < NV; ++q) Fq[q] = sF[q][t];
+            pp_limit<NS, R, 0>(st, pp_lambda<R>(g, sa, g.idx), Fq);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) sF[q][t] = Fq[q];
+        }
     }
     __syncthreads();
     if (valid && t > 0 && i > 0) {
@@ -221,7 +237,7 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(SweepTu
 // ---------------------------------------------------------------------------
 constexpr int kTileX = 16, kTileS = 16;
 
-template <int NS, typename R, int DIR, typename S>
+template <int NS, typename R, int DIR, typename S, bool PP>
 __global__ __launch_bounds__(kTileX *kTileS) __attribute__((amdgpu_waves_per_eu(SweepTune<R>::waves))) void
 k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, double *__restrict__ rhs, Geo g, ThermoK<R> th,
              int accumulate, StageArgs sa, unsigned *status) {
@@ -243,6 +259,14 @@ k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, double *__restric
         StencilT<S> st{U, P, col + (long long)(gs + j - 3) * step, step, g.cells};
         face_flux_to<NS, R, DIR, SweepTune<R>::fence_face>(st, th, [&](int q, R v) { sF[q][ts][tx] = v; },
                                                           flags);
+        if constexpr (PP) {
+            R Fq[NV];
+#pragma unroll
+            for (int q = 0; q < NV; ++q) Fq[q] = sF[q][ts][tx];
+            pp_limit<NS, R, DIR>(st, pp_lambda<R>(g, sa, DIR == 1 ? g.idy : g.idz), Fq);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) sF[q][ts][tx] = Fq[q];
+        }
     }
     __syncthreads();
     if (valid && ts > 0) {

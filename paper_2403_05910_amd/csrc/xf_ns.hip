@@ -29,8 +29,12 @@ hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumu
     if (dir == 0) {
         const long long nf = (long long)(g.nx + 1) * g.ny * g.nz;
         const unsigned nb = (unsigned)((nf - 1 + (kXBlock - 2)) / (kXBlock - 1));   // blocks overlap by one face
-        hipLaunchKernelGGL((k_sweep_x<NS, R, S>), dim3(nb), dim3(kXBlock), 0, s, U, P, rhs, g, th, accumulate, sa,
-                           c.status);
+        if (sa.pp)
+            hipLaunchKernelGGL((k_sweep_x<NS, R, S, true>), dim3(nb), dim3(kXBlock), 0, s, U, P, rhs, g, th,
+                               accumulate, sa, c.status);
+        else
+            hipLaunchKernelGGL((k_sweep_x<NS, R, S, false>), dim3(nb), dim3(kXBlock), 0, s, U, P, rhs, g, th,
+                               accumulate, sa, c.status);
         return hipGetLastError();
     }
     const int ntr = dir == 1 ? g.nz : g.ny;
@@ -38,14 +42,20 @@ hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumu
     const unsigned tiles = (unsigned)((nsw + kTileS - 2) / (kTileS - 1));
     // c.variant (measurement only): 0 default = tiled, 1 = marching with the
     // previous flux in registers, 2 = marching with it in LDS
-    if (c.variant == 0 && ntr <= 65535 && tiles <= 65535u) {
+    if ((c.variant == 0 || sa.pp) && ntr <= 65535 && tiles <= 65535u) {   // the positivity blend lives here
         dim3 grid((g.nx + kTileX - 1) / kTileX, tiles, ntr), block(kTileX, kTileS);
-        if (dir == 1)
-            hipLaunchKernelGGL((k_sweep_tile<NS, R, 1, S>), grid, block, 0, s, U, P, rhs, g, th, accumulate, sa,
-                               c.status);
+        if (dir == 1 && sa.pp)
+            hipLaunchKernelGGL((k_sweep_tile<NS, R, 1, S, true>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
+                               sa, c.status);
+        else if (dir == 1)
+            hipLaunchKernelGGL((k_sweep_tile<NS, R, 1, S, false>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
+                               sa, c.status);
+        else if (sa.pp)
+            hipLaunchKernelGGL((k_sweep_tile<NS, R, 2, S, true>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
+                               sa, c.status);
         else
-            hipLaunchKernelGGL((k_sweep_tile<NS, R, 2, S>), grid, block, 0, s, U, P, rhs, g, th, accumulate, sa,
-                               c.status);
+            hipLaunchKernelGGL((k_sweep_tile<NS, R, 2, S, false>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
+                               sa, c.status);
         return hipGetLastError();
     }
     int nseg, seglen;

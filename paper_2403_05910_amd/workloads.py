@@ -448,6 +448,30 @@ def species_interface_1d(nx=200):
     return Case("species_interface_1d", (nx, 1, 1), (1.0 / nx, 1.0, 1.0), (0,) * 6, tab, U)
 
 
+def species_slab(n=(48, 40, 1)):
+    """Multi-dimensional sharp interface: gas A (1.4, 28.96) in the slab
+    |x - 0.5 - 0.1 sin(2 pi y) - 0.05 sin(2 pi z)| < 0.25 of the periodic unit
+    box, gas B (1.667, 4.003) elsewhere, u = (1, 0.5, 0.25) (components on
+    inactive axes dropped), p = 1, T = 1e-3."""
+    nn = tuple(n)
+    tab = perfect_gas_table([1.4, 1.667], [28.96, 4.003])
+    xs = [(np.arange(k) + 0.5) / k for k in nn]
+    X, Yc, Z = np.meshgrid(xs[0], xs[1], xs[2], indexing="ij")
+    X, Yc, Z = (np.transpose(a, (2, 1, 0)) for a in (X, Yc, Z))          # (z, y, x)
+    inside = np.abs(X - 0.5 - 0.1 * np.sin(2 * np.pi * Yc) - 0.05 * np.sin(2 * np.pi * Z)) < 0.25
+    Y = np.stack([np.where(inside, 1.0, 0.0), np.where(inside, 0.0, 1.0)])
+    T = np.full(inside.shape, 1e-3)
+    rho = 1.0 / (mixture_R(tab, Y) * T)
+    vel = np.zeros((3,) + inside.shape)
+    for k, v in enumerate((1.0, 0.5, 0.25)):
+        if nn[k] > 1:
+            vel[k] = v
+    interior = assemble(tab, rho, vel, T, Y)
+    U, g = _padded(nn, 6)
+    _place(U, g, interior)
+    return Case("species_slab", nn, tuple(1.0 / k for k in nn), (0,) * 6, tab, U)
+
+
 def double_rarefaction_1d(nx=200, u0=3.0):
     """Two gases pulled apart: (rho, u, p) = (1, -u0, 0.4) with gas A
     (gamma 1.4, W 28.96) for x < 0.5 and (1, +u0, 0.4) with gas B (1.667,

@@ -60,6 +60,7 @@ _rhs = _sig("xf_rhs", _c_int, _vp, _vp, _vp, _vp, _vp)
 _prims = _sig("xf_primitives", _c_int, _vp, _vp, _vp, _vp)
 _cfl = _sig("xf_cfl_dt", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
 _rk3 = _sig("xf_rk3_step", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
+_set_pp = _sig("xf_set_positivity", _c_int, _vp, _c_int)
 _rk3_cfl = _sig("xf_rk3_step_cfl", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
 _rhs_vjp = _sig("xf_rhs_vjp", _c_int, _vp, _vp, _vp, _vp, _vp, _vp)
 _rk3_vjp = _sig("xf_rk3_step_vjp", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
@@ -69,8 +70,9 @@ _timing_read = _sig("xf_timing_read", _c_int, _vp, _vp, _dp, ctypes.POINTER(ctyp
 _strerror = _sig("xf_strerror", ctypes.c_char_p, _c_int)
 
 EXPORTED = ["xf_create", "xf_destroy", "xf_state_elems", "xf_workspace_bytes", "xf_fill_ghosts",
-            "xf_fill_ghosts_vjp", "xf_rhs", "xf_primitives", "xf_cfl_dt", "xf_rk3_step", "xf_rk3_step_cfl", "xf_rhs_vjp", "xf_rk3_step_vjp",
-            "xf_status", "xf_strerror", "xf_timing", "xf_timing_read"]
+            "xf_fill_ghosts_vjp", "xf_rhs", "xf_primitives", "xf_cfl_dt", "xf_rk3_step", "xf_rk3_step_cfl",
+            "xf_set_positivity", "xf_rhs_vjp", "xf_rk3_step_vjp", "xf_status", "xf_strerror", "xf_timing",
+            "xf_timing_read"]
 KERNEL_CLASSES = ["prims", "sweep_x", "sweep_y", "sweep_z", "fill", "stage", "cfl", "zero",
                   "vjp_x", "vjp_y", "vjp_z", "prims_vjp", "fill_vjp"]
 
@@ -136,6 +138,10 @@ def xf_rk3_step(ctx, U, dt, dt_dev, ws, stream):
     return _check(_rk3(ctx, U, dt, dt_dev, ws, stream), "xf_rk3_step")
 
 
+def xf_set_positivity(ctx, enable):
+    return _check(_set_pp(ctx, int(bool(enable))), "xf_set_positivity")
+
+
 def xf_rk3_step_cfl(ctx, U, cfl, dt_dev, ws, stream):
     return _check(_rk3_cfl(ctx, U, cfl, dt_dev, ws, stream), "xf_rk3_step_cfl")
 
@@ -198,6 +204,7 @@ class Context:
         self.ns = len(self.W)
         self.nv = self.ns + 4
         self.precision = precision
+        self.positivity = False
         g = [3 if k > 1 else 0 for k in self.n]
         self.shape = (self.nv, self.n[2] + 2 * g[2], self.n[1] + 2 * g[1], self.n[0] + 2 * g[0])
         self.interior = (slice(None), slice(g[2], g[2] + self.n[2]), slice(g[1], g[1] + self.n[1]),
@@ -280,6 +287,12 @@ class Context:
         out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
         xf_cfl_dt(self.handle, self._ptr(U), float(cfl), out.data_ptr(), self.workspace(XF_OP_RHS), self._stream())
         return out
+
+    def set_positivity(self, enable=True):
+        """positivity-preserving flux blend in rk3_step / rk3_step_cfl"""
+        xf_set_positivity(self.handle, enable)
+        self.positivity = bool(enable)
+        return self
 
     def rk3_step(self, U, dt):
         """dt: a float, or a one-element float64 device tensor (no host round trip)"""

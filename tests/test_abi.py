@@ -70,5 +70,6 @@ def test_strerror_and_argument_errors_without_device():
     assert xf._rhs_vjp(None, None, None, None, None, None) == xf.XF_EINVAL
     assert xf._rk3_vjp(None, None, 0.1, None, None, None) == xf.XF_EINVAL
     assert xf._fill(None, None, None) == xf.XF_EINVAL
+    assert xf._set_pp(None, 1) == xf.XF_EINVAL
     assert xf._state_elems(None) == 0
     assert xf._ws_bytes(None, 0) == 0
