@@ -6,8 +6,9 @@ A step is one pass of the whole hot path over the state: the CFL time step
 primitives with the Newton temperature, the x/y/z Roe-characteristic
 WENO5-LLF flux differences and the stage update.  The metric is interior
 cell-RHS evaluations per second (3 per cell per step), FP64.  Beside it the
-same line reports the FP32-mixed path (throughput and its per-field error
-against FP64), the adjoint (VJP) throughput and adjoint/forward time ratios,
+same line reports the FP32-mixed path (throughput and its state error
+against FP64), the step with the positivity-preserving flux blend, the
+adjoint (VJP) throughput and adjoint/forward time ratios,
 the roofline of the dominant kernel (timed live with HIP events on the stream
 it runs on) and the CPU oracle on a bounded crop of the same state.
 
@@ -298,6 +299,21 @@ def main():
                         "flags": ctxm.status()}
         ctxm.close()
         del Um
+        # positivity-preserving blend (Sec. II.C.2): the same FP64 step with the
+        # blend on; its cost and the status word it leaves
+        ctxp = xf.Context.from_case(case, "fp64").set_positivity(True)
+        Up = U0.clone()
+        ctxp.fill_ghosts(Up)
+        run_steps(ctxp, Up, dt_dev, a.warmup, a.cfl)
+        torch.cuda.synchronize()
+        secs_p, kern_p = timed_steps(torch, ctxp, Up, dt_dev, a.steps, a.cfl)
+        out["positivity"] = {"value": 3 * cells * a.steps / secs_p, "unit": "cell-RHS evals/s",
+                             "ms_per_step": secs_p / a.steps * 1e3, "overhead_vs_fp64": secs_p / secs - 1.0,
+                             "status_flags": ctxp.status(), "status_flags_without": flags,
+                             "kernel_avg_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kern_p.items() if v[1]}}
+        log(f"[bench] positivity: {secs_p / a.steps * 1e3:.2f} ms/step, flags {out['positivity']['status_flags']}")
+        ctxp.close()
+        del Up
         # adjoint: one RHS VJP per evaluation, against one forward RHS
         rb = torch.randn_like(r64)
         Ub = torch.zeros_like(r64)
