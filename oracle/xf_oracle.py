@@ -28,7 +28,9 @@ Readings of points the paper leaves open (each is stated where it is used):
   * Roe average: sqrt(rho) weights on u, H, Y_s and T; the face sound speed is
     defined by the pressure-derivative identity so that L R = I exactly.
   * LLF: component-wise wave speed, the max over the 6 stencil cells of the
-    cell eigenvalue |u_n - c|, |u_n| or |u_n + c| of that characteristic field.
+    cell eigenvalue |u_n - c|, |u_n| or |u_n + c| of that characteristic field;
+    ROE: |u~_n - c~|, |u~_n|, |u~_n + c~| of the face's Roe state; GLF: the
+    largest LLF speed of the field over all faces of the direction.
   * Eigenbasis of the repeated eigenvalue u_n: partial-density waves
     d(rho_s) - Y_s dp / c^2 and the two tangential momentum waves.
   * Finite-difference point values (Shu-Osher flux splitting), cell centres at
@@ -448,13 +450,19 @@ def _take(prim, idx):
     return out
 
 
-def face_flux(th, d, Ust, Pst, alpha=None):
+VISC_TYPES = ("LLF", "ROE", "GLF")
+
+
+def face_flux(th, d, Ust, Pst, alpha=None, visc="LLF"):
     """Numerical flux at faces i+1/2 from the 6-cell stencils m = i-2..i+3.
 
     Ust: (Nv, 6, F) conservative values of the stencil cells (slot 2 = cell i,
     slot 3 = cell i+1); Pst: primitives of the same cells (values (6, F); u
-    (3, 6, F); Y (6, F, ns)).  alpha, if given, is the (Nv, F) array of LLF
-    wave speeds to use instead of computing them (a frozen dissipation).
+    (3, 6, F); Y (6, F, ns)).  alpha, if given, is the (Nv, F) array of
+    wave speeds to use instead of computing them (a frozen dissipation; the
+    global GLF speeds arrive this way).  visc: the artificial viscosity of
+    Eq. 14 (Table I): "LLF" as below, or "ROE", |lambda_n| of the face's Roe
+    state (u~_n - c~, u~_n, u~_n + c~), no entropy fix.
     Returns (Fhat (Nv, F), alpha (Nv, F), c2 of the Roe state (F,)).
 
     Steps: Roe state of cells i, i+1; dense L, R; component-wise LLF speed
@@ -467,7 +475,10 @@ def face_flux(th, d, Ust, Pst, alpha=None):
     roe = roe_state(th, pL, pR)
     L = eigen_L(th, roe, d)          # (F, nv, nv)
     R = eigen_R(th, roe, d)
-    if alpha is None:
+    if alpha is None and visc == "ROE":
+        un, c = roe["u"][d], roe["c"]
+        alpha = np.abs(np.stack([un - c] + [un] * (nv - 2) + [un + c], axis=0).real)
+    elif alpha is None:
         lam = eigenvalues(th, Pst, d)            # (nv, 6, F)
         alpha = np.max(np.abs(lam.real), axis=1)  # (nv, F)
     Fm = physical_flux(th, Ust, Pst, d)          # (nv, 6, F)
@@ -552,14 +563,18 @@ def _stencils(Q, axis, g, n):
                     axis=0)
 
 
-def rhs(th, grid, U, alpha=None, return_aux=False, pp_dt=None):
+def rhs(th, grid, U, alpha=None, return_aux=False, pp_dt=None, visc="LLF"):
     """Convective residual L(U) = -sum_d (F^_{i+1/2} - F^_{i-1/2}) / dx_d
     (Eq. 13) on the interior of the padded state U (Nv, Z, Y, X); ghost cells
     of U must already hold their boundary values; ghost cells of the result are
     zero.  alpha, if given, is a dict d -> frozen LLF speeds (Nv, faces).
     pp_dt, if given, is the time step of the Euler stage the residual is used
     in: the face fluxes are then blended by positivity_limit with
-    lam = D pp_dt / dx_d (D active dimensions)."""
+    lam = D pp_dt / dx_d (D active dimensions).  visc: "LLF", "ROE" or "GLF"
+    (Table I).  Reading of GLF: per direction and characteristic field, the
+    largest LLF speed over all faces of that direction (the device-wide
+    maximum the paper reduces across processes)."""
+    assert visc in VISC_TYPES, visc
     nv = th.ns + 4
     assert U.shape == (nv,) + grid.padded, (U.shape, grid.padded)
     with np.errstate(all="ignore"):
@@ -614,8 +629,12 @@ def rhs(th, grid, U, alpha=None, return_aux=False, pp_dt=None):
                 s = _stencils(v, ax, g, n)
                 Pst[k] = s.reshape(6, nf)
         a_in = None if alpha is None else alpha[d]
+        if a_in is None and visc == "GLF":
+            lam_c = eigenvalues(th, Pst, d)                           # (nv, 6, F)
+            glf = np.max(np.abs(lam_c.real), axis=(1, 2))             # (nv,)
+            a_in = np.broadcast_to(glf[:, None], (nv, nf)).copy()
         with np.errstate(all="ignore"):
-            Fh, al, c2 = face_flux(th, d, Ust, Pst, a_in)
+            Fh, al, c2 = face_flux(th, d, Ust, Pst, a_in, visc)
         aux["alpha"][d] = al
         if pp_dt is not None:
             lam = len(grid.active()) * pp_dt / grid.d[d]
@@ -738,7 +757,7 @@ def ssp_rk3(L, U, dt):
     return U / 3.0 + 2.0 / 3.0 * (U2 + dt * L(U2))
 
 
-def rk3_step(th, grid, U, dt, alpha=None, pp=False):
+def rk3_step(th, grid, U, dt, alpha=None, pp=False, visc="LLF"):
     """One SSP-RK3 step of the convective system with ghosts refilled before
     every stage.  alpha: optional list of three frozen-speed dicts, one per
     stage (in stage order).  pp: blend every stage's face fluxes for
@@ -749,7 +768,7 @@ def rk3_step(th, grid, U, dt, alpha=None, pp=False):
 
     def L(V):
         V = fill_ghosts(grid, V)
-        r = rhs(th, grid, V, a[stage[0]], pp_dt=dt if pp else None)
+        r = rhs(th, grid, V, a[stage[0]], pp_dt=dt if pp else None, visc=visc)
         stage[0] += 1
         return r
 

@@ -55,7 +55,7 @@ def test_weight_power_one_caught(monkeypatch):
 
 def test_dropped_RT_in_species_energy_caught(monkeypatch, rng):
     _patch(monkeypatch, "species_e", lambda th, T: th.R * X.h_over_R(th, T))
-    assert _fails(P.test_single_gas_matches_textbook_solver, rng)
+    assert _fails(P.test_single_gas_matches_textbook_solver, rng, "LLF")
 
 
 def test_swapped_roe_weights_caught(monkeypatch, rng):
@@ -70,7 +70,7 @@ def test_swapped_roe_weights_caught(monkeypatch, rng):
         fakeR["rho"] = pL["rho"]
         return orig(th, fake, fakeR)
     _patch(monkeypatch, "roe_state", bad)
-    assert _fails(P.test_single_gas_matches_textbook_solver, rng)
+    assert _fails(P.test_single_gas_matches_textbook_solver, rng, "LLF")
 
 
 def test_tangential_row_sign_caught(monkeypatch, rng):
@@ -120,7 +120,7 @@ def test_wrong_acoustic_eigenvalue_caught(monkeypatch, rng):
         lam = orig(th, prim, d)
         return np.concatenate([lam[-1:], lam[1:]], axis=0)   # u+c used for the u-c field
     _patch(monkeypatch, "eigenvalues", bad)
-    assert _fails(P.test_single_gas_matches_textbook_solver, rng)
+    assert _fails(P.test_single_gas_matches_textbook_solver, rng, "LLF")
 
 
 def test_wrong_rk3_stage_weight_caught(monkeypatch):
@@ -148,7 +148,7 @@ def test_newton_with_cp_denominator_still_converges_but_energy_with_cp_caught(mo
     the round trip cannot see it), but an energy map that uses h instead of e
     changes the EOS and the textbook comparison fails."""
     _patch(monkeypatch, "mixture_e", lambda th, Y, T: np.sum(Y * th.R * X.h_over_R(th, T), axis=-1))
-    assert _fails(P.test_single_gas_matches_textbook_solver, rng)
+    assert _fails(P.test_single_gas_matches_textbook_solver, rng, "LLF")
 
 
 # -- positivity-preserving blend (pins in test_oracle_positivity.py) --------
@@ -193,3 +193,24 @@ def test_positivity_not_applied_caught(monkeypatch):
            lambda th, d, Ust, Pst, Fh, al, lam: (Fh, np.ones(Fh.shape[1])))
     assert _fails(PP.test_mass_fractions_stay_above_floor_over_a_run)
     assert _fails(PP.test_half_states_respect_floors_with_largest_theta, 4)
+
+
+def test_roe_speed_without_abs_caught(monkeypatch, rng):
+    orig = X.face_flux
+
+    def bad(th, d, Ust, Pst, alpha=None, visc="LLF"):
+        if alpha is None and visc == "ROE":
+            roe = X.roe_state(th, X._take(Pst, 2), X._take(Pst, 3))
+            un, c = roe["u"][d], roe["c"]
+            nv = th.ns + 4
+            alpha = np.stack([un - c] + [un] * (nv - 2) + [un + c], axis=0).real   # planted: no |.|
+        return orig(th, d, Ust, Pst, alpha, "LLF" if alpha is not None else visc)
+    _patch(monkeypatch, "face_flux", bad)
+    assert _fails(P.test_single_gas_matches_textbook_solver, rng, "ROE")
+
+
+def test_scaled_wave_speed_caught_for_glf(monkeypatch, rng):
+    orig_eig = X.eigenvalues
+    # planted: cell wave speeds scaled by 0.9 (the global maximum too small)
+    _patch(monkeypatch, "eigenvalues", lambda th, prim, d: orig_eig(th, prim, d).real * 0.9)
+    assert _fails(P.test_single_gas_matches_textbook_solver, rng, "GLF")

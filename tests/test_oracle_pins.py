@@ -248,9 +248,11 @@ def _weno_textbook(v):
     return sum(wk * qk for wk, qk in zip(w, q)) / sum(w)
 
 
-def textbook_rhs_1d(gamma, U, n, dx):
+def textbook_rhs_1d(gamma, U, n, dx, visc="LLF"):
     """Characteristic WENO5 + component-wise LLF x-flux difference for one
     ideal gas with state (rho, rho u, rho v, rho w, E); U padded with 3 ghosts.
+    visc "ROE": speeds |u~ - c~|, |u~|, |u~ + c~| of the face's Roe average;
+    "GLF": each field's largest LLF speed over all faces.
     Right eigenvectors from the classical ideal-gas form (Toro, Ch. 3):
     K1 = (1, u-c, v, w, H-uc), K2 = (1, u, v, w, q^2/2), K3 = (0,0,1,0,v),
     K4 = (0,0,0,1,w), K5 = (1, u+c, v, w, H+uc); left ones by matrix inverse."""
@@ -262,6 +264,9 @@ def textbook_rhs_1d(gamma, U, n, dx):
     H = (E + p) / rho
     F = np.stack([rho * u, rho * u * u + p, rho * u * v, rho * u * w, (E + p) * u])
     flux = np.zeros((5, n + 1))
+    llf = [np.array([[abs(u[m] - c[m]), abs(u[m]), abs(u[m]), abs(u[m]), abs(u[m] + c[m])]
+                     for m in range(k, k + 6)]).max(axis=0) for k in range(n + 1)]
+    glf = np.max(llf, axis=0)
     for k in range(n + 1):
         i = k + 2
         sL, sR = np.sqrt(rho[i]), np.sqrt(rho[i + 1])
@@ -276,8 +281,13 @@ def textbook_rhs_1d(gamma, U, n, dx):
                       [Ht - ut * ct, 0.5 * q2, vt, wt, Ht + ut * ct]])
         Kinv = np.linalg.inv(K)
         cells = range(i - 2, i + 4)
-        lam = np.array([[abs(u[m] - c[m]), abs(u[m]), abs(u[m]), abs(u[m]), abs(u[m] + c[m])] for m in cells])
-        al = lam.max(axis=0)
+        if visc == "ROE":
+            al = np.array([abs(ut - ct), abs(ut), abs(ut), abs(ut), abs(ut + ct)])
+        elif visc == "GLF":
+            al = glf
+        else:
+            lam = np.array([[abs(u[m] - c[m]), abs(u[m]), abs(u[m]), abs(u[m]), abs(u[m] + c[m])] for m in cells])
+            al = lam.max(axis=0)
         fc = np.array([Kinv @ F[:, m] for m in cells])
         uc = np.array([Kinv @ U[:, m] for m in cells])
         gp = 0.5 * (fc + al * uc)
@@ -301,12 +311,44 @@ def _single_gas_case(rng, n=40, gamma=1.4, jump=True):
     return th, g, O.fill_ghosts(g, U)
 
 
-def test_single_gas_matches_textbook_solver(rng):
+@pytest.mark.parametrize("visc", ["LLF", "ROE", "GLF"])
+def test_single_gas_matches_textbook_solver(rng, visc):
     th, g, U = _single_gas_case(rng)
-    r, aux = O.rhs(th, g, U, return_aux=True)
-    ref = textbook_rhs_1d(1.4, U[:, 0, 0, :], g.nx, g.dx)
+    r, aux = O.rhs(th, g, U, return_aux=True, visc=visc)
+    ref = textbook_rhs_1d(1.4, U[:, 0, 0, :], g.nx, g.dx, visc)
     err = rel_field_err(r[:, 0, 0, 3:-3], ref, aux["scale"])
     assert err.max() <= 1e-13, err
+
+
+@pytest.mark.parametrize("visc", ["ROE", "GLF"])
+def test_dissipation_variants_keep_freestream_and_conservation(rng, visc):
+    """a uniform state stays exactly uniform; on a periodic box the residual
+    sums to zero field by field (the flux difference telescopes)"""
+    th = thermal_table(3)
+    g = O.Grid(10, 8, 6, 0.1, 0.125, 1 / 6, (0,) * 6)
+    rho, u, T, Y = random_mixture_prims(th, rng, (1,))
+    U = np.broadcast_to(O.conservative(th, rho, u, T, Y).reshape(-1, 1, 1, 1), (th.ns + 4,) + g.padded).copy()
+    assert np.all(O.rhs(th, g, U, visc=visc) == 0.0)
+    rho, u, T, Y = random_mixture_prims(th, rng, (6, 8, 10))
+    V = np.zeros((th.ns + 4,) + g.padded)
+    iz, iy, ix = g.interior()
+    V[:, iz, iy, ix] = O.conservative(th, rho, u, T, Y)
+    V = O.fill_ghosts(g, V)
+    r = O.rhs(th, g, V, visc=visc)
+    tot = r.reshape(th.ns + 4, -1).sum(axis=1)
+    assert np.all(np.abs(tot) <= 1e-12 * np.abs(r).reshape(th.ns + 4, -1).sum(axis=1) + 1e-300)
+
+
+def test_dissipation_speeds_ordering(rng):
+    """GLF speeds bound the LLF ones face by face; the Roe speeds never exceed
+    them for a single perfect gas (|u~ -+ c~| lies between the two cells')"""
+    th, g, U = _single_gas_case(rng, jump=False)
+    _, a_l = O.rhs(th, g, U, return_aux=True, visc="LLF")
+    _, a_g = O.rhs(th, g, U, return_aux=True, visc="GLF")
+    _, a_r = O.rhs(th, g, U, return_aux=True, visc="ROE")
+    al, ag, ar = a_l["alpha"][0], a_g["alpha"][0], a_r["alpha"][0]
+    assert np.all(ag >= al) and np.allclose(ag.max(axis=1), al.max(axis=1), rtol=0, atol=0)
+    assert np.all(ar <= al * (1 + 1e-12))
 
 
 def test_two_species_with_absent_second_reduces_to_single(rng):
