@@ -150,6 +150,18 @@ int xf_cfl_dt(xf_ctx *ctx, const double *U, double cfl, double *dt_dev, void *ws
  * ws: xf_workspace_bytes(ctx, XF_OP_RK3) bytes. */
 int xf_rk3_step(xf_ctx *ctx, double *U, double dt, const double *dt_dev, void *ws, void *stream);
 
+/* Artificial viscosity of the flux splitting of Eq. 14 (the options of
+ * Table I): XF_VISC_LLF (default), per face and characteristic field the
+ * largest |lambda| of the field over the six stencil cells; XF_VISC_ROE,
+ * |lambda| of the face's Roe state (u~_n - c~, u~_n, u~_n + c~), no entropy
+ * fix; XF_VISC_GLF, per direction and field the largest LLF speed over all
+ * faces of the direction, reduced on the device after every primitive pass.
+ * Applies to every later call on the context; the VJPs hold the chosen speeds
+ * fixed.  The positivity blend keeps the LLF speeds as its Lax-Friedrichs
+ * coefficient.  Returns XF_EINVAL for another type. */
+enum { XF_VISC_LLF = 0, XF_VISC_ROE = 1, XF_VISC_GLF = 2 };
+int xf_set_dissipation(xf_ctx *ctx, int type);
+
 /* Positivity-preserving flux blend (Sec. II.C.2, Eq. 17-20) in the SSP-RK3
  * steps of this context (xf_rk3_step, xf_rk3_step_cfl), off by default.
  * Each face flux becomes F_LF + theta (F^ - F_LF), F_LF the Lax-Friedrichs

@@ -638,8 +638,12 @@ def rhs(th, grid, U, alpha=None, return_aux=False, pp_dt=None, visc="LLF"):
         aux["alpha"][d] = al
         if pp_dt is not None:
             lam = len(grid.active()) * pp_dt / grid.d[d]
+            # the Lax-Friedrichs coefficient stays the LLF speed whatever the
+            # splitting's viscosity (Eq. 19 is positive only with a bound on
+            # the neighbouring cells' wave speeds)
+            al_lf = al if (visc == "LLF" and a_in is None) else np.max(np.abs(eigenvalues(th, Pst, d).real), axis=1)
             with np.errstate(all="ignore"):
-                Fh, theta = positivity_limit(th, d, Ust, Pst, Fh, al, lam)
+                Fh, theta = positivity_limit(th, d, Ust, Pst, Fh, al_lf, lam)
             aux.setdefault("theta", {})[d] = theta
         aux["fmax"] = np.maximum(aux["fmax"], np.max(np.abs(Fh.real), axis=1))
         if np.any(c2.real <= 0):

@@ -156,15 +156,36 @@ hipError_t timed(xf_ctx *c, int cls, hipStream_t s, F &&launch) {
 struct Prim {
     double *P;
     float *Uf, *Pf;
+    unsigned long long *mx;   // [0]: CFL maximum; [1 + 3 d .. 3 + 3 d]: GLF speeds of direction d
 };
 
 Prim prim_bufs(const xf_ctx *c, const Layout &l, void *ws) {
     const bool mixed = c->lc.precision == XF_PREC_MIXED;
-    return {at<double>(ws, l.P), mixed ? at<float>(ws, l.Uf) : nullptr, mixed ? at<float>(ws, l.Pf) : nullptr};
+    return {at<double>(ws, l.P), mixed ? at<float>(ws, l.Uf) : nullptr, mixed ? at<float>(ws, l.Pf) : nullptr,
+            at<unsigned long long>(ws, l.mx)};
+}
+
+// GLF speeds of the active directions from the primitives just computed; a
+// no-op for the other artificial viscosities.
+hipError_t glf_speeds(xf_ctx *c, const double *U, const double *P, unsigned long long *mx, hipStream_t s) {
+    if (c->lc.visc != XF_VISC_GLF) return hipSuccess;
+    const int n[3] = {c->lc.g.nx, c->lc.g.ny, c->lc.g.nz};
+    return timed(c, XF_K_CFL, s, [&] {
+        hipError_t e = xf::launch_reset_u64(mx + 1, 9, s);
+        for (int d = 0; d < 3 && e == hipSuccess; ++d)
+            if (n[d] > 1) e = c->ops->glf(c->lc, d, U, P, mx + 1 + 3 * d, s);
+        return e;
+    });
+}
+
+const double *glf_of(const xf_ctx *c, const unsigned long long *mx, int d) {
+    return c->lc.visc == XF_VISC_GLF ? reinterpret_cast<const double *>(mx + 1 + 3 * d) : nullptr;
 }
 
 hipError_t prims(xf_ctx *c, const double *U, const Prim &pb, hipStream_t s) {
-    return timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, pb.P, pb.Uf, pb.Pf, 0, s); });
+    hipError_t e = timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, pb.P, pb.Uf, pb.Pf, 0, s); });
+    if (e == hipSuccess) e = glf_speeds(c, U, pb.P, pb.mx, s);
+    return e;
 }
 
 int sweeps_into(xf_ctx *c, const double *U, double *rhs, const Prim &pb, const xf::StageArgs &stage,
@@ -182,7 +203,7 @@ int sweeps_into(xf_ctx *c, const double *U, double *rhs, const Prim &pb, const x
         if (n[d] <= 1) continue;
         const int acc = first ? 0 : 1;
         const xf::StageArgs &sa = d == last ? stage : off;
-        XF_TRY(timed(c, XF_K_SWEEP_X + d, s, [&] { return c->ops->sweep(lc, d, acc, U, pb.P, pb.Uf, pb.Pf, rhs, sa, s); }));
+        XF_TRY(timed(c, XF_K_SWEEP_X + d, s, [&] { return c->ops->sweep(lc, d, acc, U, pb.P, pb.Uf, pb.Pf, rhs, sa, glf_of(c, pb.mx, d), s); }));
         first = false;
     }
     if (last < 0) return XF_EUNSUPPORTED;   // no active dimension (rejected by xf_create)
@@ -199,15 +220,19 @@ int rhs_into(xf_ctx *c, const double *U, double *rhs, const Prim &pb, hipStream_
 }
 
 int rhs_vjp_into(xf_ctx *c, const double *U, const double *rbar, double *Ubar, double *P, double *Pbar,
-                 double *rec, hipStream_t s) {
+                 double *rec, unsigned long long *mx, hipStream_t s) {
     const LaunchCtx &lc = c->lc;
     const int n[3] = {lc.g.nx, lc.g.ny, lc.g.nz};
     XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(lc, U, P, nullptr, nullptr, 0, s); }));
+    XF_TRY(glf_speeds(c, U, P, mx, s));
     XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero(2 * lc.g.cells, Pbar, s); }));
     for (int d = 0; d < 3; ++d) {
         if (n[d] <= 1) continue;
         XF_TRY(timed(c, XF_K_VJP_X + d, s,
-                     [&] { return c->ops->sweep_vjp(lc, d, U, P, rbar, Ubar, Pbar, rec, xf::vjp_record_rows(lc.g), s); }));
+                     [&] {
+                         return c->ops->sweep_vjp(lc, d, U, P, rbar, Ubar, Pbar, rec, xf::vjp_record_rows(lc.g),
+                                                  glf_of(c, mx, d), s);
+                     }));
     }
     XF_TRY(timed(c, XF_K_PRIMS_VJP, s, [&] { return c->ops->prims_vjp(lc, U, P, Pbar, Ubar, s); }));
     return XF_OK;
@@ -311,6 +336,7 @@ int xf_create(const xf_grid *grid, const xf_thermo *thermo, int precision, xf_ct
     fill_thermo(c->lc.th64, thermo);
     fill_thermo(c->lc.th32, thermo);
     c->lc.precision = precision;
+    c->lc.visc = XF_VISC_LLF;
     {
         const char *v = getenv("XF_KERNEL_VARIANT");
         c->lc.variant = v ? atoi(v) : 0;
@@ -457,13 +483,20 @@ int rk3_step(xf_ctx *c, double *U, double dt, const double *dt_in, double cfl, d
         for (int d = 2; d >= 0; --d) {
             if (n[d] <= 1) continue;
             XF_TRY(timed(c, XF_K_SWEEP_X + d, s,
-                         [&] { return c->ops->sweep(lc, d, 0, in[k], P, pb.Uf, pb.Pf, Ld[d], sw, s); }));
+                         [&] { return c->ops->sweep(lc, d, 0, in[k], P, pb.Uf, pb.Pf, Ld[d], sw, glf_of(c, pb.mx, d), s); }));
         }
         XF_TRY(timed(c, XF_K_STAGE, s, [&] {
             return xf::launch_rk3_stage_sum(lc, c->nv, out[k], U, in[k], Lsum, a[k], b[k], dt, h, s);
         }));
     }
     XF_TRY(fill(c, U, s));
+    return XF_OK;
+}
+
+int xf_set_dissipation(xf_ctx *c, int type) {
+    if (!c) return XF_EINVAL;
+    if (type != XF_VISC_LLF && type != XF_VISC_ROE && type != XF_VISC_GLF) return XF_EINVAL;
+    c->lc.visc = type;
     return XF_OK;
 }
 
@@ -491,7 +524,7 @@ int xf_rhs_vjp(xf_ctx *c, const double *U, const double *rbar, double *Ubar, voi
         return XF_EINVAL;
     const Layout l = layout(c, XF_OP_VJP);
     return rhs_vjp_into(c, U, rbar, Ubar, at<double>(ws, l.P), at<double>(ws, l.Pbar), at<double>(ws, l.rec),
-                        (hipStream_t)stream);
+                        at<unsigned long long>(ws, l.mx), (hipStream_t)stream);
 }
 
 int xf_rk3_step_vjp(xf_ctx *c, const double *Un, double dt, double *Ubar, void *ws, void *stream) {
@@ -531,7 +564,9 @@ int xf_rk3_step_vjp(xf_ctx *c, const double *Un, double dt, double *Ubar, void *
     XF_TRY(fill_vjp(c, Ubar, s));
     for (int stage = 3; stage >= 1; --stage) {
         XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero(n, mu, s); }));
-        if ((r = rhs_vjp_into(c, Vs[stage - 1], Ubar, mu, P, Pbar, at<double>(ws, l.rec), s)) != XF_OK) return r;
+        if ((r = rhs_vjp_into(c, Vs[stage - 1], Ubar, mu, P, Pbar, at<double>(ws, l.rec),
+                              at<unsigned long long>(ws, l.mx), s)) != XF_OK)
+            return r;
         XF_TRY(timed(c, XF_K_STAGE, s,
                      [&] { return xf::launch_rk3_stage_vjp(lc, c->nv, stage, Ubar, lam0, mu, nullptr, dt, s); }));
         if (stage > 1) XF_TRY(fill_vjp(c, Ubar, s));

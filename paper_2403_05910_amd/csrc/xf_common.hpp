@@ -62,6 +62,7 @@ struct LaunchCtx {
     ThermoK<float> th32;
     unsigned *status;    // device status word (atomicOr of XF_FLAG_*)
     int precision;       // XF_PREC_*
+    int visc;            // artificial viscosity: kViscLlf, kViscRoe or kViscGlf
     int variant;         // kernel variant for measurements (environment XF_KERNEL_VARIANT), 0 = default
 };
 
@@ -74,14 +75,20 @@ struct NsOps {
                         hipStream_t);
     // one direction of the convective flux difference; accumulate: rhs += or
     // rhs =.  FP64 sweeps read U, P; mixed-precision sweeps read Uf, Pf.
+    // glf: the direction's three GLF speeds (device) when lc.visc is GLF
     hipError_t (*sweep)(const LaunchCtx &, int dir, int accumulate, const double *U, const double *P,
-                        const float *Uf, const float *Pf, double *rhs, const StageArgs &stage, hipStream_t);
+                        const float *Uf, const float *Pf, double *rhs, const StageArgs &stage, const double *glf,
+                        hipStream_t);
     // VJP of one direction: Ubar_direct += (dF/dU)^T ..., Pbar += (dF/d(p, T))^T ...
     // rec: vjp_record_fields(ns) x nrec doubles of scratch between the two
     // halves of the face VJP (nrec >= vjp_record_rows(g))
     hipError_t (*sweep_vjp)(const LaunchCtx &, int dir, const double *U, const double *P,
                             const double *rbar, double *Ubar, double *Pbar, double *rec, long long nrec,
-                            hipStream_t);
+                            const double *glf, hipStream_t);
+    // GLF speeds of one direction: atomicMax of |u_d - c|, |u_d|, |u_d + c|
+    // (uint64 bits of positive doubles) into mx[0..2], which must start at 0
+    hipError_t (*glf)(const LaunchCtx &, int dir, const double *U, const double *P, unsigned long long *mx,
+                      hipStream_t);
     // VJP of the primitive map: Ubar += (d(p, T)/dU)^T Pbar
     hipError_t (*prims_vjp)(const LaunchCtx &, const double *U, const double *P,
                             const double *Pbar, double *Ubar, hipStream_t);
@@ -136,6 +143,7 @@ hipError_t launch_rk3_stage_sum(const LaunchCtx &, int nv, double *Uout, const d
 hipError_t launch_axpy_state(long long n, double a, const double *x, double b, double *y,
                              hipStream_t);
 hipError_t launch_cfl_reset(unsigned long long *mx, hipStream_t);
+hipError_t launch_reset_u64(unsigned long long *p, int n, hipStream_t);
 hipError_t launch_cfl_finish(const unsigned long long *mx, double cfl, double *dt_dev,
                              hipStream_t);
 hipError_t launch_copy(long long n, const double *src, double *dst, hipStream_t);

@@ -160,8 +160,21 @@ struct Axes {
 // as soon as it is final (species first, then momentum and energy), so the
 // caller decides where it lives.  flags collects XF_FLAG_C2 if the face c^2
 // is not positive.  FENCE inserts compiler fences between the phases.
-template <int NS, typename R, int DIR, bool FENCE = false, class St, class Out>
-XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned &flags) {
+// Artificial viscosity of the flux splitting (Eq. 14; Table I): LLF, the
+// max over the six stencil cells of each field's |lambda|; ROE, |lambda| of
+// the face's Roe state (u~_n - c~, u~_n, u~_n + c~); GLF, each field's
+// largest LLF speed over all faces of the direction (glf: the three speeds
+// u_n - c, u_n, u_n + c, reduced beforehand).
+constexpr int kViscLlf = 0, kViscRoe = 1, kViscGlf = 2;
+struct Dissip {
+    int type;
+    const double *glf;
+};
+
+// VISC = false compiles the LLF speeds only (ds is ignored); VISC = true
+// follows ds.type at run time.
+template <int NS, typename R, int DIR, bool FENCE = false, bool VISC = false, class St, class Out>
+XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned &flags, const Dissip &ds) {
     constexpr int IM = NS;
     constexpr int IE = NS + 3;
     constexpr int IN = NS + Axes<DIR>::n;
@@ -234,6 +247,17 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
         aM = rmax(aM, rabs(unm - cm));
         a0 = rmax(a0, rabs(unm));
         aP = rmax(aP, rabs(unm + cm));
+    }
+    if constexpr (VISC) {
+        if (ds.type == kViscRoe) {
+            aM = rabs(utn - ct);
+            a0 = rabs(utn);
+            aP = rabs(utn + ct);
+        } else if (ds.type == kViscGlf) {
+            aM = R(ds.glf[0]);
+            a0 = R(ds.glf[1]);
+            aP = R(ds.glf[2]);
+        }
     }
 
     if (FENCE) XF_FENCE();
@@ -318,7 +342,7 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
 // Numerical flux at one face into Fh[0..NS+3] (conservative field order).
 template <int NS, typename R, int DIR>
 XF_HD void face_flux(const Stencil &st, const ThermoK<R> &th, R *__restrict__ Fh, unsigned &flags) {
-    face_flux_to<NS, R, DIR>(st, th, [&](int q, R v) { Fh[q] = v; }, flags);
+    face_flux_to<NS, R, DIR>(st, th, [&](int q, R v) { Fh[q] = v; }, flags, Dissip{kViscLlf, nullptr});
 }
 
 // ---------------------------------------------------------------------------

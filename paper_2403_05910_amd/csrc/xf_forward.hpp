@@ -183,10 +183,10 @@ __device__ __forceinline__ void put_result(double *__restrict__ rhs, const Stage
 // ---------------------------------------------------------------------------
 constexpr int kXBlock = 256;
 
-template <int NS, typename R, typename S, bool PP>
+template <int NS, typename R, typename S, bool PP, bool VISC>
 __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(SweepTune<R>::waves))) void k_sweep_x(
     const S *__restrict__ U, const S *__restrict__ P, double *__restrict__ rhs, Geo g, ThermoK<R> th, int accumulate,
-    StageArgs sa, unsigned *status) {
+    StageArgs sa, unsigned *status, Dissip ds) {
     constexpr int NV = NS + 4;
     __shared__ R sF[NV][kXBlock];
     const int t = threadIdx.x;
@@ -204,7 +204,8 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(SweepTu
         const int j = (int)(row % g.ny), k = (int)(row / g.ny);
         rowbase = (long long)(g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + g.gx;
         StencilT<S> st{U, P, rowbase + i - 3, 1, g.cells};
-        face_flux_to<NS, R, 0, SweepTune<R>::fence_face>(st, th, [&](int q, R v) { sF[q][t] = v; }, flags);
+        face_flux_to<NS, R, 0, SweepTune<R>::fence_face, VISC>(st, th, [&](int q, R v) { sF[q][t] = v; }, flags,
+                                                               ds);
         if constexpr (PP) {
             R Fq[NV];
 #pragma unroll
@@ -237,10 +238,10 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(SweepTu
 // ---------------------------------------------------------------------------
 constexpr int kTileX = 16, kTileS = 16;
 
-template <int NS, typename R, int DIR, typename S, bool PP>
+template <int NS, typename R, int DIR, typename S, bool PP, bool VISC>
 __global__ __launch_bounds__(kTileX *kTileS) __attribute__((amdgpu_waves_per_eu(SweepTune<R>::waves))) void
 k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, double *__restrict__ rhs, Geo g, ThermoK<R> th,
-             int accumulate, StageArgs sa, unsigned *status) {
+             int accumulate, StageArgs sa, unsigned *status, Dissip ds) {
     constexpr int NV = NS + 4;
     __shared__ R sF[NV][kTileS][kTileX];
     unsigned bx, by, bz;
@@ -257,8 +258,8 @@ k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, double *__restric
     unsigned flags = 0;
     if (valid) {
         StencilT<S> st{U, P, col + (long long)(gs + j - 3) * step, step, g.cells};
-        face_flux_to<NS, R, DIR, SweepTune<R>::fence_face>(st, th, [&](int q, R v) { sF[q][ts][tx] = v; },
-                                                          flags);
+        face_flux_to<NS, R, DIR, SweepTune<R>::fence_face, VISC>(st, th, [&](int q, R v) { sF[q][ts][tx] = v; },
+                                                                 flags, ds);
         if constexpr (PP) {
             R Fq[NV];
 #pragma unroll
@@ -328,13 +329,14 @@ __global__ __launch_bounds__(256) void k_sweep_march(const S *__restrict__ U, co
                         put_result(rhs, sa, q * g.cells + cell, double((sFp[q][tid] - v) * id), h, accumulate);
                     sFp[q][tid] = v;
                 },
-                flags);
+                flags, Dissip{kViscLlf, nullptr});
         }
     } else {
         R Fp[NV], F[NV];
         for (int j = j0; j <= j1; ++j) {
             StencilT<S> st{U, P, col + (long long)(gs + j - 3) * step, step, g.cells};
-            face_flux_to<NS, R, DIR, SweepTune<R>::fence_march>(st, th, [&](int q, R v) { F[q] = v; }, flags);
+            face_flux_to<NS, R, DIR, SweepTune<R>::fence_march>(st, th, [&](int q, R v) { F[q] = v; }, flags,
+                                                               Dissip{kViscLlf, nullptr});
             if (j > j0) {
                 const long long cell = col + (long long)(gs + j - 1) * step;
 #pragma unroll
@@ -378,6 +380,51 @@ __global__ __launch_bounds__(256) void k_cfl(const double *__restrict__ U, const
     if (threadIdx.x == 0) {
         const double m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
         atomicMax(mx, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// GLF speeds of direction d: max of |u_d - c|, |u_d|, |u_d + c| over every
+// cell the direction's stencils read (interior in the other axes, the full
+// padded extent along d), three 64-bit atomicMax per block into mx[0..2]
+// (positive doubles order like their bit patterns).
+// ---------------------------------------------------------------------------
+template <int NS>
+__global__ __launch_bounds__(256) void k_glf(const double *__restrict__ U, const double *__restrict__ P, Geo g,
+                                             int dir, unsigned long long *mx) {
+    const int ex = dir == 0 ? g.px : g.nx, ey = dir == 1 ? g.py : g.ny, ez = dir == 2 ? g.pz : g.nz;
+    const int ox = dir == 0 ? 0 : g.gx, oy = dir == 1 ? 0 : g.gy, oz = dir == 2 ? 0 : g.gz;
+    const long long n = (long long)ex * ey * ez;
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(q % ex);
+        const long long r = q / ex;
+        const int j = (int)(r % ey), k = (int)(r / ey);
+        const long long idx = (long long)(oz + k) * g.sz + (long long)(oy + j) * g.sy + (ox + i);
+        const double rinv = P[3 * g.cells + idx], c = P[2 * g.cells + idx];
+        const double un = U[(NS + dir) * g.cells + idx] * rinv;
+        m0 = fmax(m0, fabs(un - c));
+        m1 = fmax(m1, fabs(un));
+        m2 = fmax(m2, fabs(un + c));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        m0 = fmax(m0, __shfl_xor(m0, off, 64));
+        m1 = fmax(m1, __shfl_xor(m1, off, 64));
+        m2 = fmax(m2, __shfl_xor(m2, off, 64));
+    }
+    __shared__ double wmax[3][4];
+    if ((threadIdx.x & 63) == 0) {
+        wmax[0][threadIdx.x >> 6] = m0;
+        wmax[1][threadIdx.x >> 6] = m1;
+        wmax[2][threadIdx.x >> 6] = m2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const double *w = wmax[threadIdx.x];
+        const double m = fmax(fmax(w[0], w[1]), fmax(w[2], w[3]));
+        atomicMax(mx + threadIdx.x, (unsigned long long)__double_as_longlong(m));
     }
 }
 

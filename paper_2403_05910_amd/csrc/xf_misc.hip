@@ -171,6 +171,10 @@ __global__ __launch_bounds__(256) void k_rk3_stage_vjp(double *lam, double *lam0
 
 __global__ void k_cfl_reset(unsigned long long *mx) { *mx = 0ull; }
 
+__global__ void k_reset_u64(unsigned long long *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
 __global__ void k_cfl_finish(const unsigned long long *mx, double cfl, double *dt) {
     *dt = cfl / __longlong_as_double((long long)*mx);
 }
@@ -249,6 +253,12 @@ hipError_t launch_axpy_state(long long n, double a, const double *x, double b, d
 
 hipError_t launch_cfl_reset(unsigned long long *mx, hipStream_t s) {
     hipLaunchKernelGGL(k_cfl_reset, dim3(1), dim3(1), 0, s, mx);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_u64(unsigned long long *p, int n, hipStream_t s) {
+    if (n < 1 || n > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reset_u64, dim3(1), dim3(64), 0, s, p, n);
     return hipGetLastError();
 }
 

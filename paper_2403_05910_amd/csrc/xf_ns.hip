@@ -22,42 +22,45 @@ hipError_t prims(const LaunchCtx &c, const double *U, double *P, float *Uf, floa
     return hipGetLastError();
 }
 
-template <typename R, typename S>
-hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumulate, const S *U, const S *P,
-                   double *rhs, const StageArgs &sa, hipStream_t s) {
+template <typename R, typename S, bool PP, bool VISC>
+hipError_t launch_face_sweep(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumulate, const S *U,
+                             const S *P, double *rhs, const StageArgs &sa, const Dissip &ds, hipStream_t s) {
     const Geo &g = c.g;
     if (dir == 0) {
         const long long nf = (long long)(g.nx + 1) * g.ny * g.nz;
         const unsigned nb = (unsigned)((nf - 1 + (kXBlock - 2)) / (kXBlock - 1));   // blocks overlap by one face
-        if (sa.pp)
-            hipLaunchKernelGGL((k_sweep_x<NS, R, S, true>), dim3(nb), dim3(kXBlock), 0, s, U, P, rhs, g, th,
-                               accumulate, sa, c.status);
-        else
-            hipLaunchKernelGGL((k_sweep_x<NS, R, S, false>), dim3(nb), dim3(kXBlock), 0, s, U, P, rhs, g, th,
-                               accumulate, sa, c.status);
+        hipLaunchKernelGGL((k_sweep_x<NS, R, S, PP, VISC>), dim3(nb), dim3(kXBlock), 0, s, U, P, rhs, g, th,
+                           accumulate, sa, c.status, ds);
         return hipGetLastError();
     }
     const int ntr = dir == 1 ? g.nz : g.ny;
     const int nsw = dir == 1 ? g.ny : g.nz;
     const unsigned tiles = (unsigned)((nsw + kTileS - 2) / (kTileS - 1));
-    // c.variant (measurement only): 0 default = tiled, 1 = marching with the
-    // previous flux in registers, 2 = marching with it in LDS
-    if ((c.variant == 0 || sa.pp) && ntr <= 65535 && tiles <= 65535u) {   // the positivity blend lives here
-        dim3 grid((g.nx + kTileX - 1) / kTileX, tiles, ntr), block(kTileX, kTileS);
-        if (dir == 1 && sa.pp)
-            hipLaunchKernelGGL((k_sweep_tile<NS, R, 1, S, true>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
-                               sa, c.status);
-        else if (dir == 1)
-            hipLaunchKernelGGL((k_sweep_tile<NS, R, 1, S, false>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
-                               sa, c.status);
-        else if (sa.pp)
-            hipLaunchKernelGGL((k_sweep_tile<NS, R, 2, S, true>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
-                               sa, c.status);
-        else
-            hipLaunchKernelGGL((k_sweep_tile<NS, R, 2, S, false>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
-                               sa, c.status);
-        return hipGetLastError();
+    dim3 grid((g.nx + kTileX - 1) / kTileX, tiles, ntr), block(kTileX, kTileS);
+    if (dir == 1)
+        hipLaunchKernelGGL((k_sweep_tile<NS, R, 1, S, PP, VISC>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
+                           sa, c.status, ds);
+    else
+        hipLaunchKernelGGL((k_sweep_tile<NS, R, 2, S, PP, VISC>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
+                           sa, c.status, ds);
+    return hipGetLastError();
+}
+
+template <typename R, typename S>
+hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumulate, const S *U, const S *P,
+                   double *rhs, const StageArgs &sa, const Dissip &ds, hipStream_t s) {
+    const Geo &g = c.g;
+    // c.variant (measurement only) 1 or 2 runs the y/z column march (LLF, no
+    // positivity blend) instead of the tiled kernel
+    if (dir == 0 || c.variant == 0 || sa.pp || ds.type != kViscLlf) {
+        const bool v = ds.type != kViscLlf;
+        if (sa.pp)
+            return v ? launch_face_sweep<R, S, true, true>(c, th, dir, accumulate, U, P, rhs, sa, ds, s)
+                     : launch_face_sweep<R, S, true, false>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
+        return v ? launch_face_sweep<R, S, false, true>(c, th, dir, accumulate, U, P, rhs, sa, ds, s)
+                 : launch_face_sweep<R, S, false, false>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
     }
+    const int ntr = dir == 1 ? g.nz : g.ny;
     int nseg, seglen;
     march_shape(g, dir, &nseg, &seglen);
     dim3 grid((g.nx + 63) / 64, (ntr + 3) / 4, nseg), block(64, 4);
@@ -81,15 +84,18 @@ hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumu
 }
 
 hipError_t sweep(const LaunchCtx &c, int dir, int accumulate, const double *U, const double *P, const float *Uf,
-                 const float *Pf, double *rhs, const StageArgs &sa, hipStream_t s) {
-    if (c.precision == XF_PREC_MIXED) return sweep_t<float, float>(c, c.th32, dir, accumulate, Uf, Pf, rhs, sa, s);
-    return sweep_t<double, double>(c, c.th64, dir, accumulate, U, P, rhs, sa, s);
+                 const float *Pf, double *rhs, const StageArgs &sa, const double *glf, hipStream_t s) {
+    const Dissip ds{c.visc, glf};
+    if (c.visc == kViscGlf && !glf) return hipErrorInvalidValue;
+    if (c.precision == XF_PREC_MIXED)
+        return sweep_t<float, float>(c, c.th32, dir, accumulate, Uf, Pf, rhs, sa, ds, s);
+    return sweep_t<double, double>(c, c.th64, dir, accumulate, U, P, rhs, sa, ds, s);
 }
 
 template <typename R, int HALF>
 hipError_t launch_vjp_group(const LaunchCtx &c, const ThermoK<R> &th, int dir, int grp, const double *U,
                             const double *P, const double *rbar, double *Ubar, double *Pbar, double *rec,
-                            long long nrec, hipStream_t s) {
+                            long long nrec, const Dissip &ds, hipStream_t s) {
     const Geo &g = c.g;
     if (dir == 0) {
         // consecutive faces per wave with a private LDS window of W cells
@@ -101,7 +107,7 @@ hipError_t launch_vjp_group(const LaunchCtx &c, const ThermoK<R> &th, int dir, i
         const long long waves = (vjp_x_waves_per_plane(g) - grp + kVjpGroups - 1) / kVjpGroups;
         dim3 grid((unsigned)((waves + wpb - 1) / wpb), g.nz), block(64 * wpb);
         hipLaunchKernelGGL((k_face_vjp_x<NS, R, HALF>), grid, block, per_wave * wpb, s, U, P, rbar, Ubar, Pbar, rec,
-                           nrec, g, th, W, grp);
+                           nrec, g, th, W, grp, ds);
     } else if (c.variant != 4) {
         const int nsw = dir == 1 ? g.ny : g.nz;
         const int xt = (g.nx + kVjpTX - 1) / kVjpTX;
@@ -110,19 +116,19 @@ hipError_t launch_vjp_group(const LaunchCtx &c, const ThermoK<R> &th, int dir, i
         dim3 grid((unsigned)(xt * nb), dir == 1 ? g.nz : g.ny), block(256);
         if (dir == 1)
             hipLaunchKernelGGL((k_face_vjp_yz<NS, R, 1, HALF>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec,
-                               g, th, grp);
+                               g, th, grp, ds);
         else
             hipLaunchKernelGGL((k_face_vjp_yz<NS, R, 2, HALF>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec,
-                               g, th, grp);
+                               g, th, grp, ds);
     } else {
         const int nsw = dir == 1 ? g.ny : g.nz;
         dim3 grid((g.nx + 63) / 64, (nsw / 6 + 1 + 3) / 4, dir == 1 ? g.nz : g.ny), block(64, 4);
         if (dir == 1)
             hipLaunchKernelGGL((k_face_vjp<NS, R, 1, HALF>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec, g,
-                               th, grp);
+                               th, grp, ds);
         else
             hipLaunchKernelGGL((k_face_vjp<NS, R, 2, HALF>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec, g,
-                               th, grp);
+                               th, grp, ds);
     }
     return hipGetLastError();
 }
@@ -131,24 +137,37 @@ hipError_t launch_vjp_group(const LaunchCtx &c, const ThermoK<R> &th, int dir, i
 // j = grp mod 6), each as the two halves of the face VJP.
 template <typename R>
 hipError_t sweep_vjp_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, const double *U, const double *P,
-                       const double *rbar, double *Ubar, double *Pbar, double *rec, long long nrec, hipStream_t s) {
+                       const double *rbar, double *Ubar, double *Pbar, double *rec, long long nrec, const Dissip &ds,
+                       hipStream_t s) {
     const Geo &g = c.g;
     const int nsw = dir == 1 ? g.ny : g.nz;
     const long long ngrp = dir == 0 ? vjp_x_waves_per_plane(g)
                                     : (c.variant == 4 ? nsw + 1 : (nsw + 1 + kVjpFB - 1) / kVjpFB);
     for (int grp = 0; grp < kVjpGroups && grp < ngrp; ++grp) {
-        hipError_t e = launch_vjp_group<R, 0>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, rec, nrec, s);
-        if (e == hipSuccess) e = launch_vjp_group<R, 1>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, rec, nrec, s);
+        hipError_t e = launch_vjp_group<R, 0>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, rec, nrec, ds, s);
+        if (e == hipSuccess) e = launch_vjp_group<R, 1>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, rec, nrec, ds, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
 hipError_t sweep_vjp(const LaunchCtx &c, int dir, const double *U, const double *P, const double *rbar,
-                     double *Ubar, double *Pbar, double *rec, long long nrec, hipStream_t s) {
+                     double *Ubar, double *Pbar, double *rec, long long nrec, const double *glf, hipStream_t s) {
+    const Dissip ds{c.visc, glf};
+    if (c.visc == kViscGlf && !glf) return hipErrorInvalidValue;
     if (c.precision == XF_PREC_MIXED)
-        return sweep_vjp_t<float>(c, c.th32, dir, U, P, rbar, Ubar, Pbar, rec, nrec, s);
-    return sweep_vjp_t<double>(c, c.th64, dir, U, P, rbar, Ubar, Pbar, rec, nrec, s);
+        return sweep_vjp_t<float>(c, c.th32, dir, U, P, rbar, Ubar, Pbar, rec, nrec, ds, s);
+    return sweep_vjp_t<double>(c, c.th64, dir, U, P, rbar, Ubar, Pbar, rec, nrec, ds, s);
+}
+
+hipError_t glf(const LaunchCtx &c, int dir, const double *U, const double *P, unsigned long long *mx,
+               hipStream_t s) {
+    const Geo &g = c.g;
+    const long long n = (long long)(dir == 0 ? g.px : g.nx) * (dir == 1 ? g.py : g.ny) * (dir == 2 ? g.pz : g.nz);
+    long long nb = blocks_for(n, 256);
+    if (nb > 2048) nb = 2048;   // grid-stride: three atomics per block
+    hipLaunchKernelGGL(k_glf<NS>, dim3((unsigned)nb), dim3(256), 0, s, U, P, g, dir, mx);
+    return hipGetLastError();
 }
 
 hipError_t prims_vjp(const LaunchCtx &c, const double *U, const double *P, const double *Pbar, double *Ubar,
@@ -166,7 +185,7 @@ hipError_t cfl(const LaunchCtx &c, const double *U, const double *P, unsigned lo
     return hipGetLastError();
 }
 
-const NsOps kOps = {prims, sweep, sweep_vjp, prims_vjp, cfl};
+const NsOps kOps = {prims, sweep, sweep_vjp, glf, prims_vjp, cfl};
 
 }  // namespace
 

@@ -172,7 +172,8 @@ struct VjpRec {
 // each cell's own values; writes the direct cell cotangents to `out` and the
 // accumulated ones to `rec`.
 template <int NS, typename R, int DIR, class Out>
-XF_HD void face_vjp_a(const Stencil &st, const ThermoK<R> &th, const R *Fb, const Out &out, const VjpRec<NS> &rec) {
+XF_HD void face_vjp_a(const Stencil &st, const ThermoK<R> &th, const R *Fb, const Out &out, const VjpRec<NS> &rec,
+                      const Dissip &ds) {
     constexpr int IM = NS;
     constexpr int IE = NS + 3;
     constexpr int KN = Axes<DIR>::n, K1 = Axes<DIR>::t1, K2 = Axes<DIR>::t2;
@@ -207,6 +208,15 @@ XF_HD void face_vjp_a(const Stencil &st, const ThermoK<R> &th, const R *Fb, cons
         aM = rmax(aM, rabs(unm - cm));
         a0 = rmax(a0, rabs(unm));
         aP = rmax(aP, rabs(unm + cm));
+    }
+    if (ds.type == kViscRoe) {   // speeds of the Roe state, held fixed like the LLF ones
+        aM = rabs(utn - ct);
+        a0 = rabs(utn);
+        aP = rabs(utn + ct);
+    } else if (ds.type == kViscGlf) {
+        aM = R(ds.glf[0]);
+        a0 = R(ds.glf[1]);
+        aP = R(ds.glf[2]);
     }
 
     XF_FENCE();
@@ -522,7 +532,8 @@ template <int NS, typename R, int HALF>
 __global__ __launch_bounds__(256) void k_face_vjp_x(const double *__restrict__ U, const double *__restrict__ P,
                                                     const double *__restrict__ rbar, double *__restrict__ Ubar,
                                                     double *__restrict__ Pbar, double *__restrict__ rec,
-                                                    long long nrec, Geo g, ThermoK<R> th, int W, int grp) {
+                                                    long long nrec, Geo g, ThermoK<R> th, int W, int grp,
+                                                    Dissip ds) {
     constexpr int NV = NS + 4;
     extern __shared__ double xf_win[];
     const int wpb = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -557,7 +568,7 @@ __global__ __launch_bounds__(256) void k_face_vjp_x(const double *__restrict__ U
             SinkLds sk{w, W, (int)(base - base0), 1, NV * W};
             const VjpRec<NS> rc{rec, nrec, ((long long)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x};
             if constexpr (HALF == 0)
-                face_vjp_a<NS, R, 0>(st, th, Fb, sk, rc);
+                face_vjp_a<NS, R, 0>(st, th, Fb, sk, rc, ds);
             else
                 face_vjp_b<NS, R, 0>(st, th, sk, rc);
         }
@@ -589,7 +600,7 @@ template <int NS, typename R, int DIR, int HALF>
 __global__ __launch_bounds__(256) void k_face_vjp(const double *__restrict__ U, const double *__restrict__ P,
                                                   const double *__restrict__ rbar, double *__restrict__ Ubar,
                                                   double *__restrict__ Pbar, double *__restrict__ rec, long long nrec,
-                                                  Geo g, ThermoK<R> th, int p) {
+                                                  Geo g, ThermoK<R> th, int p, Dissip ds) {
     constexpr int NV = NS + 4;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = p + 6 * (int)(blockIdx.y * blockDim.y + threadIdx.y);
@@ -619,7 +630,7 @@ __global__ __launch_bounds__(256) void k_face_vjp(const double *__restrict__ U, 
                               (blockDim.x * blockDim.y) + threadIdx.y * blockDim.x + threadIdx.x;
     const VjpRec<NS> rc{rec, nrec, tid};
     if constexpr (HALF == 0)
-        face_vjp_a<NS, R, DIR>(st, th, Fb, sk, rc);
+        face_vjp_a<NS, R, DIR>(st, th, Fb, sk, rc, ds);
     else
         face_vjp_b<NS, R, DIR>(st, th, sk, rc);
 }
@@ -642,7 +653,7 @@ template <int NS, typename R, int DIR, int HALF>
 __global__ __launch_bounds__(256) void k_face_vjp_yz(const double *__restrict__ U, const double *__restrict__ P,
                                                      const double *__restrict__ rbar, double *__restrict__ Ubar,
                                                      double *__restrict__ Pbar, double *__restrict__ rec,
-                                                     long long nrec, Geo g, ThermoK<R> th, int phase) {
+                                                     long long nrec, Geo g, ThermoK<R> th, int phase, Dissip ds) {
     constexpr int NV = NS + 4;
     __shared__ double xf_wyz[4][(NV + 2) * kVjpWin];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -686,7 +697,7 @@ __global__ __launch_bounds__(256) void k_face_vjp_yz(const double *__restrict__ 
             SinkLds sk{w, kVjpWin, ts * kVjpTX + tx, kVjpTX, NV * kVjpWin};
             const VjpRec<NS> rc{rec, nrec, (long long)(blockIdx.y * gridDim.x + blockIdx.x) * 256 + threadIdx.x};
             if constexpr (HALF == 0)
-                face_vjp_a<NS, R, DIR>(st, th, Fb, sk, rc);
+                face_vjp_a<NS, R, DIR>(st, th, Fb, sk, rc, ds);
             else
                 face_vjp_b<NS, R, DIR>(st, th, sk, rc);
         }

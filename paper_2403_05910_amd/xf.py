@@ -22,6 +22,8 @@ XF_OK, XF_EINVAL, XF_EDEVICE, XF_ENOMEM, XF_ENONPHYS, XF_EUNSUPPORTED = 0, -1, -
 XF_BC_PERIODIC, XF_BC_OUTFLOW = 0, 1
 XF_PREC_FP64, XF_PREC_MIXED = 0, 1
 XF_OP_RHS, XF_OP_RK3, XF_OP_VJP, XF_OP_RK3_VJP = 0, 1, 2, 3
+XF_VISC_LLF, XF_VISC_ROE, XF_VISC_GLF = 0, 1, 2
+VISC = {"LLF": XF_VISC_LLF, "ROE": XF_VISC_ROE, "GLF": XF_VISC_GLF}
 FLAGS = {1: "rho<=0", 2: "Y<0", 4: "p<=0 or T<=0", 8: "T out of range", 16: "Newton not converged",
          32: "Roe c^2<=0", 64: "NaN/Inf"}
 
@@ -61,6 +63,7 @@ _prims = _sig("xf_primitives", _c_int, _vp, _vp, _vp, _vp)
 _cfl = _sig("xf_cfl_dt", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
 _rk3 = _sig("xf_rk3_step", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
 _set_pp = _sig("xf_set_positivity", _c_int, _vp, _c_int)
+_set_visc = _sig("xf_set_dissipation", _c_int, _vp, _c_int)
 _rk3_cfl = _sig("xf_rk3_step_cfl", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
 _rhs_vjp = _sig("xf_rhs_vjp", _c_int, _vp, _vp, _vp, _vp, _vp, _vp)
 _rk3_vjp = _sig("xf_rk3_step_vjp", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
@@ -71,7 +74,7 @@ _strerror = _sig("xf_strerror", ctypes.c_char_p, _c_int)
 
 EXPORTED = ["xf_create", "xf_destroy", "xf_state_elems", "xf_workspace_bytes", "xf_fill_ghosts",
             "xf_fill_ghosts_vjp", "xf_rhs", "xf_primitives", "xf_cfl_dt", "xf_rk3_step", "xf_rk3_step_cfl",
-            "xf_set_positivity", "xf_rhs_vjp", "xf_rk3_step_vjp", "xf_status", "xf_strerror", "xf_timing",
+            "xf_set_dissipation", "xf_set_positivity", "xf_rhs_vjp", "xf_rk3_step_vjp", "xf_status", "xf_strerror", "xf_timing",
             "xf_timing_read"]
 KERNEL_CLASSES = ["prims", "sweep_x", "sweep_y", "sweep_z", "fill", "stage", "cfl", "zero",
                   "vjp_x", "vjp_y", "vjp_z", "prims_vjp", "fill_vjp"]
@@ -136,6 +139,10 @@ def xf_cfl_dt(ctx, U, cfl, dt_dev, ws, stream):
 
 def xf_rk3_step(ctx, U, dt, dt_dev, ws, stream):
     return _check(_rk3(ctx, U, dt, dt_dev, ws, stream), "xf_rk3_step")
+
+
+def xf_set_dissipation(ctx, visc):
+    return _check(_set_visc(ctx, int(visc)), "xf_set_dissipation")
 
 
 def xf_set_positivity(ctx, enable):
@@ -205,6 +212,7 @@ class Context:
         self.nv = self.ns + 4
         self.precision = precision
         self.positivity = False
+        self.visc = "LLF"
         g = [3 if k > 1 else 0 for k in self.n]
         self.shape = (self.nv, self.n[2] + 2 * g[2], self.n[1] + 2 * g[1], self.n[0] + 2 * g[0])
         self.interior = (slice(None), slice(g[2], g[2] + self.n[2]), slice(g[1], g[1] + self.n[1]),
@@ -287,6 +295,12 @@ class Context:
         out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
         xf_cfl_dt(self.handle, self._ptr(U), float(cfl), out.data_ptr(), self.workspace(XF_OP_RHS), self._stream())
         return out
+
+    def set_dissipation(self, visc="LLF"):
+        """artificial viscosity of the flux splitting: "LLF", "ROE" or "GLF" """
+        xf_set_dissipation(self.handle, VISC[visc])
+        self.visc = visc
+        return self
 
     def set_positivity(self, enable=True):
         """positivity-preserving flux blend in rk3_step / rk3_step_cfl"""

@@ -27,9 +27,9 @@ def _xf():
     return xf
 
 
-def gpu_rhs(case, precision="fp64"):
+def gpu_rhs(case, precision="fp64", visc="LLF"):
     xf = _xf()
-    ctx = xf.Context.from_case(case, precision)
+    ctx = xf.Context.from_case(case, precision).set_dissipation(visc)
     U = ctx.state_from_numpy(case.U)
     ctx.fill_ghosts(U)
     r = ctx.rhs(U)
@@ -39,10 +39,10 @@ def gpu_rhs(case, precision="fp64"):
     return out
 
 
-def oracle_rhs(case):
+def oracle_rhs(case, visc="LLF"):
     th, g = oracle_objects(case)
     U = O.fill_ghosts(g, case.U)
-    r, aux = O.rhs(th, g, U, return_aux=True)
+    r, aux = O.rhs(th, g, U, return_aux=True, visc=visc)
     return r, aux, U
 
 
@@ -291,3 +291,45 @@ def test_primitives_match_oracle(name):
         assert err <= 1e-13, (key, err)
     rho = Uo[:case.thermo.ns].sum(axis=0)
     assert np.max(np.abs(P[3] * rho - 1.0)) <= 1e-15
+
+
+
+@pytest.mark.parametrize("visc", ["ROE", "GLF"])
+@pytest.mark.parametrize("name", ["ragged3d_n3_outflow_x", "n9_3d_mixed_bc", "inert_sbi_32", "plane2d_n3",
+                                  "y_only_n3", "wave1d_600"])
+def test_rhs_dissipation_variants_match_oracle(name, visc):
+    case = CASES[name]
+    r_gpu, flags, _ = gpu_rhs(case, visc=visc)
+    r_ora, aux, _ = oracle_rhs(case, visc)
+    assert flags == 0
+    err = field_err(r_gpu, r_ora, aux["scale_llf"])
+    print(f"[parity] {visc} {name} max err / S_f = {err.max():.3e}", flush=True)
+    assert err.max() <= TOL, err
+
+
+@pytest.mark.parametrize("visc", ["ROE", "GLF"])
+def test_rk3_dissipation_variants_match_oracle(visc):
+    xf = _xf()
+    case = CASES["inert_sbi_32"]
+    th, g = oracle_objects(case)
+    Uo = O.fill_ghosts(g, case.U)
+    dt = 0.5 * O.cfl_dt(th, g, Uo, 0.5)
+    ctx = xf.Context.from_case(case).set_dissipation(visc)
+    U = ctx.state_from_numpy(case.U)
+    for _ in range(3):
+        Uo = O.rk3_step(th, g, Uo, dt, visc=visc)
+        ctx.rk3_step(U, dt)
+    assert ctx.status() == 0
+    scale = np.abs(Uo).reshape(Uo.shape[0], -1).max(axis=1)
+    err = field_err(U.cpu().numpy(), Uo, scale)
+    print(f"[parity] rk3 {visc} inert_sbi_32 max err {err.max():.3e}", flush=True)
+    assert err.max() <= 1e-12, err
+
+
+def test_rhs_glf_mixed_within_fp32_bound():
+    case = CASES["n9_3d_mixed_bc"]
+    r_gpu, flags, _ = gpu_rhs(case, "mixed", visc="GLF")
+    r_ora, aux, _ = oracle_rhs(case, "GLF")
+    err = field_err(r_gpu, r_ora, aux["scale_llf"])
+    print(f"[parity] mixed GLF max err / S_f = {err.max():.3e}", flush=True)
+    assert err.max() <= MIXED_RHS_TOL, err

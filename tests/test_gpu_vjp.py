@@ -39,7 +39,7 @@ def _field_scale(U, grid):
     return np.abs(U[:, iz, iy, ix]).reshape(U.shape[0], -1).max(axis=1)
 
 
-def vjp_dot_check(case, precision, seed, fold=True):
+def vjp_dot_check(case, precision, seed, fold=True, visc="LLF"):
     """GPU <J^T rbar, w> versus oracle <rbar, J w> by complex step.
     fold=True: J of L(G(U)) w.r.t. interior U; fold=False: J of L(U) with
     ghost values as independent inputs (U's ghosts already hold values)."""
@@ -47,7 +47,7 @@ def vjp_dot_check(case, precision, seed, fold=True):
     th, g = oracle_objects(case)
     rng = np.random.default_rng(seed)
     Ubase = O.fill_ghosts(g, case.U) if fold else case.U
-    r0, aux = O.rhs(th, g, Ubase, return_aux=True)
+    r0, aux = O.rhs(th, g, Ubase, return_aux=True, visc=visc)
     sc = np.where(aux["scale"] > 0, aux["scale"], 1.0)
     rbar = interior_random(case.U.shape, g, rng, 1.0 / sc)
     fs = _field_scale(Ubase, g)
@@ -59,12 +59,12 @@ def vjp_dot_check(case, precision, seed, fold=True):
         w[:, mask] = rng.standard_normal((case.U.shape[0], mask.sum())) * fs[:, None]
     h = 1e-30
     Uc = Ubase + 1j * h * w
-    rc = O.rhs(th, g, O.fill_ghosts(g, Uc) if fold else Uc)
+    rc = O.rhs(th, g, O.fill_ghosts(g, Uc) if fold else Uc, visc=visc)
     terms = rbar * rc.imag / h
     ref = np.sum(terms)
     mag = np.sum(np.abs(terms))
 
-    ctx = xf.Context.from_case(case, precision)
+    ctx = xf.Context.from_case(case, precision).set_dissipation(visc)
     U = ctx.state_from_numpy(Ubase)
     if fold:
         ctx.fill_ghosts(U)
@@ -293,3 +293,13 @@ def test_vjp_is_deterministic():
     a = ctx.rhs_vjp(U, rb)
     b = ctx.rhs_vjp(U, rb)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("visc", ["ROE", "GLF"])
+@pytest.mark.parametrize("name", ["n3_outflow_x", "n9_periodic", "plane2d_n2"])
+def test_vjp_dissipation_variants_match_complex_step(name, visc):
+    """the VJP with the ROE or GLF speeds held fixed (the oracle's complex
+    step holds them fixed too: both are computed from real parts)"""
+    got, ref, mag = vjp_dot_check(VJP_CASES[name](), "fp64", 61, visc=visc)
+    print(f"[vjp] {name} {visc} rel err {abs(got - ref) / mag:.3e}", flush=True)
+    assert abs(got - ref) <= 1e-12 * mag
