@@ -35,7 +35,8 @@ Readings of points the paper leaves open (each is stated where it is used):
     d(rho_s) - Y_s dp / c^2 and the two tangential momentum waves.
   * Finite-difference point values (Shu-Osher flux splitting), cell centres at
     (i + 1/2) dx.
-  * WENO5-JS with d = (1/10, 6/10, 3/10), p = 2, absolute eps = 1e-6.
+  * WENO5-JS with d = (1/10, 6/10, 3/10), p = 2, absolute eps = 1e-6;
+    WENO-CU6 (the paper's other six-cell option) as stated at weno_cu6.
   * Eq. 21 calls C_v the constant-pressure heat capacity; it is the
     constant-volume one (C_v = sum Y_s C_p,s - Rbar, as the same equation says).
   * Eq. 17 writes U^{n+1} = U^n + lambda (F_{i+1/2} - F_{i-1/2}); the residual
@@ -437,6 +438,65 @@ def weno5(a, b, c, d, e):
 
 
 # ---------------------------------------------------------------------------
+# WENO-CU6: the central-upwind sixth-order WENO the paper offers as REC in
+# Eq. 15 (its reference [34]; the paper restates none of its formulas)
+# ---------------------------------------------------------------------------
+CU6_D = (1.0 / 20.0, 9.0 / 20.0, 9.0 / 20.0, 1.0 / 20.0)
+CU6_C = 20.0
+CU6_EPS = 1e-6
+
+
+def smoothness_form(offsets):
+    """Quadratic form B of the Jiang-Shu smoothness indicator
+    beta = sum_{l >= 1} dx^(2l-1) int_{cell i} (p^(l))^2 dx of the polynomial p
+    whose averages over the cells at `offsets` (relative to cell i, dx = 1)
+    are the data f: beta = f^T B f.  Built in floating point from the
+    cell-average moment matrix and exact monomial integrals."""
+    n = len(offsets)
+    A = np.array([[((c + 0.5) ** (k + 1) - (c - 0.5) ** (k + 1)) / (k + 1) for k in range(n)] for c in offsets])
+    C = np.linalg.solve(A, np.eye(n))          # polynomial coefficients = C @ f
+    B = np.zeros((n, n))
+    D = C.copy()
+    for _ in range(1, n):
+        D = np.array([k * D[k] for k in range(1, D.shape[0])])     # coefficients of the next derivative
+        m = D.shape[0]
+        G = np.array([[(0.5 ** (i + j + 1) - (-0.5) ** (i + j + 1)) / (i + j + 1) for j in range(m)]
+                      for i in range(m)])
+        B += D.T @ G @ D
+    return B
+
+
+CU6_B6 = smoothness_form(range(-2, 4))
+
+
+def weno_cu6(a, b, c, d, e, f):
+    """Sixth-order central-upwind WENO value at the right edge of the cell
+    holding c, from the six point values a..f (cells i-2..i+3).  Reading of
+    the cited scheme: the three WENO5 candidates plus the downwind candidate
+    of (d, e, f); linear weights (1, 9, 9, 1)/20, which give the sixth-order
+    central value; smoothness beta_0..2 of the three upwind sub-stencils and
+    beta_6 of the whole stencil for the downwind one;
+    tau_6 = beta_6 - (beta_0 + 4 beta_1 + beta_2)/6;
+    alpha_k = d_k (C + tau_6 / (beta_k + eps)), C = 20, eps = 1e-6 absolute
+    (as in the WENO5 reading: with a vanishing eps a sub-stencil that is flat
+    to round-off takes all the weight, which drops the scheme to third order
+    on a smooth entropy wave, and 1e-40 also underflows in FP32);
+    result sum_k alpha_k q_k / sum_k alpha_k."""
+    q0, q1, q2 = weno5_candidates(a, b, c, d, e)
+    q3 = (11.0 * d - 7.0 * e + 2.0 * f) / 6.0
+    b0, b1, b2 = weno5_smoothness(a, b, c, d, e)
+    v = np.stack(np.broadcast_arrays(a, b, c, d, e, f), axis=0)
+    b6 = np.einsum("i...,ij,j...->...", v, CU6_B6, v)
+    tau = b6 - (b0 + 4.0 * b1 + b2) / 6.0
+    al = [CU6_D[k] * (CU6_C + tau / (bk + CU6_EPS)) for k, bk in enumerate((b0, b1, b2, b6))]
+    s = al[0] + al[1] + al[2] + al[3]
+    return (al[0] / s) * q0 + (al[1] / s) * q1 + (al[2] / s) * q2 + (al[3] / s) * q3
+
+
+RECON_TYPES = ("WENO5", "CU6")
+
+
+# ---------------------------------------------------------------------------
 # face flux (Eq. 14-15) and right-hand side (Eq. 13)
 # ---------------------------------------------------------------------------
 def _take(prim, idx):
@@ -453,7 +513,7 @@ def _take(prim, idx):
 VISC_TYPES = ("LLF", "ROE", "GLF")
 
 
-def face_flux(th, d, Ust, Pst, alpha=None, visc="LLF"):
+def face_flux(th, d, Ust, Pst, alpha=None, visc="LLF", recon="WENO5"):
     """Numerical flux at faces i+1/2 from the 6-cell stencils m = i-2..i+3.
 
     Ust: (Nv, 6, F) conservative values of the stencil cells (slot 2 = cell i,
@@ -488,8 +548,12 @@ def face_flux(th, d, Ust, Pst, alpha=None, visc="LLF"):
     al = alpha.T                                 # (F, nv)
     gp = 0.5 * (f + al * v)
     gm = 0.5 * (f - al * v)
-    hp = weno5(gp[0], gp[1], gp[2], gp[3], gp[4])
-    hm = weno5(gm[5], gm[4], gm[3], gm[2], gm[1])
+    if recon == "CU6":
+        hp = weno_cu6(gp[0], gp[1], gp[2], gp[3], gp[4], gp[5])
+        hm = weno_cu6(gm[5], gm[4], gm[3], gm[2], gm[1], gm[0])
+    else:
+        hp = weno5(gp[0], gp[1], gp[2], gp[3], gp[4])
+        hm = weno5(gm[5], gm[4], gm[3], gm[2], gm[1])
     Fhat = np.einsum("Fjn,Fn->jF", R, hp + hm)
     return Fhat, alpha, roe["c2"]
 
@@ -563,7 +627,7 @@ def _stencils(Q, axis, g, n):
                     axis=0)
 
 
-def rhs(th, grid, U, alpha=None, return_aux=False, pp_dt=None, visc="LLF"):
+def rhs(th, grid, U, alpha=None, return_aux=False, pp_dt=None, visc="LLF", recon="WENO5"):
     """Convective residual L(U) = -sum_d (F^_{i+1/2} - F^_{i-1/2}) / dx_d
     (Eq. 13) on the interior of the padded state U (Nv, Z, Y, X); ghost cells
     of U must already hold their boundary values; ghost cells of the result are
@@ -573,8 +637,10 @@ def rhs(th, grid, U, alpha=None, return_aux=False, pp_dt=None, visc="LLF"):
     lam = D pp_dt / dx_d (D active dimensions).  visc: "LLF", "ROE" or "GLF"
     (Table I).  Reading of GLF: per direction and characteristic field, the
     largest LLF speed over all faces of that direction (the device-wide
-    maximum the paper reduces across processes)."""
+    maximum the paper reduces across processes).  recon: "WENO5" (WENO5-JS
+    on the five cells of each side) or "CU6" (WENO-CU6 on all six)."""
     assert visc in VISC_TYPES, visc
+    assert recon in RECON_TYPES, recon
     nv = th.ns + 4
     assert U.shape == (nv,) + grid.padded, (U.shape, grid.padded)
     with np.errstate(all="ignore"):
@@ -634,7 +700,7 @@ def rhs(th, grid, U, alpha=None, return_aux=False, pp_dt=None, visc="LLF"):
             glf = np.max(np.abs(lam_c.real), axis=(1, 2))             # (nv,)
             a_in = np.broadcast_to(glf[:, None], (nv, nf)).copy()
         with np.errstate(all="ignore"):
-            Fh, al, c2 = face_flux(th, d, Ust, Pst, a_in, visc)
+            Fh, al, c2 = face_flux(th, d, Ust, Pst, a_in, visc, recon)
         aux["alpha"][d] = al
         if pp_dt is not None:
             lam = len(grid.active()) * pp_dt / grid.d[d]
@@ -761,7 +827,7 @@ def ssp_rk3(L, U, dt):
     return U / 3.0 + 2.0 / 3.0 * (U2 + dt * L(U2))
 
 
-def rk3_step(th, grid, U, dt, alpha=None, pp=False, visc="LLF"):
+def rk3_step(th, grid, U, dt, alpha=None, pp=False, visc="LLF", recon="WENO5"):
     """One SSP-RK3 step of the convective system with ghosts refilled before
     every stage.  alpha: optional list of three frozen-speed dicts, one per
     stage (in stage order).  pp: blend every stage's face fluxes for
@@ -772,7 +838,7 @@ def rk3_step(th, grid, U, dt, alpha=None, pp=False, visc="LLF"):
 
     def L(V):
         V = fill_ghosts(grid, V)
-        r = rhs(th, grid, V, a[stage[0]], pp_dt=dt if pp else None, visc=visc)
+        r = rhs(th, grid, V, a[stage[0]], pp_dt=dt if pp else None, visc=visc, recon=recon)
         stage[0] += 1
         return r
 

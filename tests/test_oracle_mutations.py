@@ -198,13 +198,13 @@ def test_positivity_not_applied_caught(monkeypatch):
 def test_roe_speed_without_abs_caught(monkeypatch, rng):
     orig = X.face_flux
 
-    def bad(th, d, Ust, Pst, alpha=None, visc="LLF"):
+    def bad(th, d, Ust, Pst, alpha=None, visc="LLF", recon="WENO5"):
         if alpha is None and visc == "ROE":
             roe = X.roe_state(th, X._take(Pst, 2), X._take(Pst, 3))
             un, c = roe["u"][d], roe["c"]
             nv = th.ns + 4
             alpha = np.stack([un - c] + [un] * (nv - 2) + [un + c], axis=0).real   # planted: no |.|
-        return orig(th, d, Ust, Pst, alpha, "LLF" if alpha is not None else visc)
+        return orig(th, d, Ust, Pst, alpha, "LLF" if alpha is not None else visc, recon)
     _patch(monkeypatch, "face_flux", bad)
     assert _fails(P.test_single_gas_matches_textbook_solver, rng, "ROE")
 
@@ -214,3 +214,28 @@ def test_scaled_wave_speed_caught_for_glf(monkeypatch, rng):
     # planted: cell wave speeds scaled by 0.9 (the global maximum too small)
     _patch(monkeypatch, "eigenvalues", lambda th, prim, d: orig_eig(th, prim, d).real * 0.9)
     assert _fails(P.test_single_gas_matches_textbook_solver, rng, "GLF")
+
+
+# -- WENO-CU6 (pins in test_oracle_cu6.py) ------------------------------------
+import test_oracle_cu6 as CU  # noqa: E402
+
+
+def test_cu6_wrong_linear_weights_caught(monkeypatch, rng):
+    _patch(monkeypatch, "CU6_D", (9.0 / 20.0, 1.0 / 20.0, 1.0 / 20.0, 9.0 / 20.0))
+    assert _fails(CU.test_sixth_order_on_smooth_data)
+
+
+def test_cu6_downwind_candidate_sign_caught(monkeypatch):
+    def bad(a, b, c, d, e, f):
+        q0, q1, q2 = X.weno5_candidates(a, b, c, d, e)
+        q3 = (11.0 * d + 7.0 * e - 2.0 * f) / 6.0          # planted: signs of e and f flipped
+        b0, b1, b2 = X.weno5_smoothness(a, b, c, d, e)
+        v = np.stack(np.broadcast_arrays(a, b, c, d, e, f), axis=0)
+        b6 = np.einsum("i...,ij,j...->...", v, X.CU6_B6, v)
+        tau = b6 - (b0 + 4.0 * b1 + b2) / 6.0
+        al = [X.CU6_D[k] * (X.CU6_C + tau / (bk + X.CU6_EPS)) for k, bk in enumerate((b0, b1, b2, b6))]
+        s_ = al[0] + al[1] + al[2] + al[3]
+        return (al[0] * q0 + al[1] * q1 + al[2] * q2 + al[3] * q3) / s_
+    _patch(monkeypatch, "weno_cu6", bad)
+    assert _fails(CU.test_sixth_order_on_smooth_data)
+    assert _fails(CU.test_cu6_advected_wave_converges)
