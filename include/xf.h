@@ -162,6 +162,18 @@ int xf_rk3_step(xf_ctx *ctx, double *U, double dt, const double *dt_dev, void *w
 enum { XF_VISC_LLF = 0, XF_VISC_ROE = 1, XF_VISC_GLF = 2 };
 int xf_set_dissipation(xf_ctx *ctx, int type);
 
+/* Reconstruction REC of Eq. 15: XF_RECON_WENO5 (default; WENO5-JS, linear
+ * weights (1, 6, 3)/10, eps = 1e-6), or XF_RECON_CU6, the sixth-order
+ * central-upwind WENO the paper also offers (four candidates on the six
+ * stencil cells, the downwind one (11 f_i+1 - 7 f_i+2 + 2 f_i+3)/6, linear
+ * weights (1, 9, 9, 1)/20, alpha_k = d_k (20 + tau6 / (beta_k + 1e-6)),
+ * beta_3 = beta6 the Jiang-Shu smoothness of the six-cell quintic,
+ * tau6 = beta6 - (beta_0 + 4 beta_1 + beta_2)/6).  Applies to every later
+ * forward call; xf_rhs_vjp and xf_rk3_step_vjp return XF_EUNSUPPORTED while
+ * CU6 is selected.  Returns XF_EINVAL for another type. */
+enum { XF_RECON_WENO5 = 0, XF_RECON_CU6 = 1 };
+int xf_set_reconstruction(xf_ctx *ctx, int type);
+
 /* Positivity-preserving flux blend (Sec. II.C.2, Eq. 17-20) in the SSP-RK3
  * steps of this context (xf_rk3_step, xf_rk3_step_cfl), off by default.
  * Each face flux becomes F_LF + theta (F^ - F_LF), F_LF the Lax-Friedrichs

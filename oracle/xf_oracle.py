@@ -446,27 +446,46 @@ CU6_C = 20.0
 CU6_EPS = 1e-6
 
 
-def smoothness_form(offsets):
-    """Quadratic form B of the Jiang-Shu smoothness indicator
+def smoothness_parts(offsets):
+    """Pieces of the Jiang-Shu smoothness indicator
     beta = sum_{l >= 1} dx^(2l-1) int_{cell i} (p^(l))^2 dx of the polynomial p
     whose averages over the cells at `offsets` (relative to cell i, dx = 1)
-    are the data f: beta = f^T B f.  Built in floating point from the
+    are the data f: for l = 1..n-1 the matrix D_l giving the coefficients of
+    p^(l) from f and the Gram matrix G_l of the monomials on [-1/2, 1/2], so
+    beta = sum_l (D_l f)^T G_l (D_l f).  Built in floating point from the
     cell-average moment matrix and exact monomial integrals."""
     n = len(offsets)
     A = np.array([[((c + 0.5) ** (k + 1) - (c - 0.5) ** (k + 1)) / (k + 1) for k in range(n)] for c in offsets])
-    C = np.linalg.solve(A, np.eye(n))          # polynomial coefficients = C @ f
-    B = np.zeros((n, n))
-    D = C.copy()
+    D = np.linalg.solve(A, np.eye(n))          # polynomial coefficients = D @ f
+    parts = []
     for _ in range(1, n):
         D = np.array([k * D[k] for k in range(1, D.shape[0])])     # coefficients of the next derivative
         m = D.shape[0]
         G = np.array([[(0.5 ** (i + j + 1) - (-0.5) ** (i + j + 1)) / (i + j + 1) for j in range(m)]
                       for i in range(m)])
-        B += D.T @ G @ D
-    return B
+        parts.append((D, G))
+    return parts
 
 
+def smoothness_form(offsets):
+    """the same indicator as one quadratic form: beta = f^T B f"""
+    return sum(D.T @ G @ D for D, G in smoothness_parts(offsets))
+
+
+CU6_PARTS = smoothness_parts(range(-2, 4))
 CU6_B6 = smoothness_form(range(-2, 4))
+
+
+def smoothness6(v):
+    """beta of the six-cell quintic for values v (6, ...): the data are first
+    shifted by the centre value (beta ignores constants), then the positive
+    Gram forms of the derivatives are summed, so no large terms cancel"""
+    w = v - v[2]
+    out = 0.0
+    for D, G in CU6_PARTS:
+        Dw = np.einsum("kj,j...->k...", D, w)
+        out = out + np.einsum("k...,kj,j...->...", Dw, G, Dw)
+    return out
 
 
 def weno_cu6(a, b, c, d, e, f):
@@ -485,8 +504,7 @@ def weno_cu6(a, b, c, d, e, f):
     q0, q1, q2 = weno5_candidates(a, b, c, d, e)
     q3 = (11.0 * d - 7.0 * e + 2.0 * f) / 6.0
     b0, b1, b2 = weno5_smoothness(a, b, c, d, e)
-    v = np.stack(np.broadcast_arrays(a, b, c, d, e, f), axis=0)
-    b6 = np.einsum("i...,ij,j...->...", v, CU6_B6, v)
+    b6 = smoothness6(np.stack(np.broadcast_arrays(a, b, c, d, e, f), axis=0))
     tau = b6 - (b0 + 4.0 * b1 + b2) / 6.0
     al = [CU6_D[k] * (CU6_C + tau / (bk + CU6_EPS)) for k, bk in enumerate((b0, b1, b2, b6))]
     s = al[0] + al[1] + al[2] + al[3]

@@ -337,6 +337,7 @@ int xf_create(const xf_grid *grid, const xf_thermo *thermo, int precision, xf_ct
     fill_thermo(c->lc.th32, thermo);
     c->lc.precision = precision;
     c->lc.visc = XF_VISC_LLF;
+    c->lc.recon = XF_RECON_WENO5;
     {
         const char *v = getenv("XF_KERNEL_VARIANT");
         c->lc.variant = v ? atoi(v) : 0;
@@ -500,6 +501,13 @@ int xf_set_dissipation(xf_ctx *c, int type) {
     return XF_OK;
 }
 
+int xf_set_reconstruction(xf_ctx *c, int type) {
+    if (!c) return XF_EINVAL;
+    if (type != XF_RECON_WENO5 && type != XF_RECON_CU6) return XF_EINVAL;
+    c->lc.recon = type;
+    return XF_OK;
+}
+
 int xf_set_positivity(xf_ctx *c, int enable) {
     if (!c) return XF_EINVAL;
     c->pp = enable != 0;
@@ -522,6 +530,7 @@ int xf_rhs_vjp(xf_ctx *c, const double *U, const double *rbar, double *Ubar, voi
     if (!c || !U || !rbar || !Ubar || !ws || Ubar == U || Ubar == rbar || !aligned8(U) || !aligned8(rbar) ||
         !aligned8(Ubar) || !aligned8(ws))
         return XF_EINVAL;
+    if (c->lc.recon != XF_RECON_WENO5) return XF_EUNSUPPORTED;   // the adjoint is of WENO5
     const Layout l = layout(c, XF_OP_VJP);
     return rhs_vjp_into(c, U, rbar, Ubar, at<double>(ws, l.P), at<double>(ws, l.Pbar), at<double>(ws, l.rec),
                         at<unsigned long long>(ws, l.mx), (hipStream_t)stream);
@@ -532,6 +541,7 @@ int xf_rk3_step_vjp(xf_ctx *c, const double *Un, double dt, double *Ubar, void *
         !(dt >= 0.0))
         return XF_EINVAL;
     if (c->pp) return XF_EUNSUPPORTED;   // the adjoint is of the unblended step
+    if (c->lc.recon != XF_RECON_WENO5) return XF_EUNSUPPORTED;
     const Layout l = layout(c, XF_OP_RK3_VJP);
     const hipStream_t s = (hipStream_t)stream;
     const LaunchCtx &lc = c->lc;

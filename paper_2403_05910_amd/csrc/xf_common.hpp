@@ -63,6 +63,7 @@ struct LaunchCtx {
     unsigned *status;    // device status word (atomicOr of XF_FLAG_*)
     int precision;       // XF_PREC_*
     int visc;            // artificial viscosity: kViscLlf, kViscRoe or kViscGlf
+    int recon;           // reconstruction: kReconWeno5 or kReconCu6
     int variant;         // kernel variant for measurements (environment XF_KERNEL_VARIANT), 0 = default
 };
 

@@ -116,6 +116,83 @@ XF_HD float weno5(float a, float b, float c, float d, float e) {
     return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
 }
 
+// WENO-CU6 value at the right edge of the cell holding c, from the six
+// point values a..f (cells i-2..i+3): the three WENO5 candidates plus the
+// downwind one (11 d - 7 e + 2 f)/6, linear weights (1, 9, 9, 1)/20,
+// alpha_k = d_k (20 + tau6 / (beta_k + 1e-6)) with beta_3 = beta6, the
+// smoothness of the whole six-cell stencil, and tau6 = beta6 -
+// (beta_0 + 4 beta_1 + beta_2)/6.  beta6 is the Jiang-Shu integral of the
+// stencil's quintic over cell i, a quadratic form that vanishes on
+// constants; it is evaluated as sum_k D_k z_k^2 over the first differences
+// (z_k = sum_{i >= k} L_ik (f_{i+1} - f_i), the exact LDL^T factors of the
+// form rounded to double), which has no cancellation.  One division: all
+// alpha_k are multiplied by prod_j (beta_j + eps).
+template <typename R>
+XF_HD R cu6_beta6(R a, R b, R c, R d, R e, R f) {
+    const R d0 = b - a, d1 = c - b, d2 = d - c, d3 = e - d, d4 = f - e;
+    const R z0 = d0 + R(-3.3800293620919937) * d1 + R(4.137755308541131) * d2 + R(-2.2318538224071762) * d3 +
+                 R(0.4518745009732172) * d4;
+    const R z1 = d1 + R(-1.8788632502196132) * d2 + R(1.2398246217680282) * d3 + R(-0.2835945203123665) * d4;
+    const R z2 = d2 + R(-0.8641384480158466) * d3 + R(0.22441845180562248) * d4;
+    const R z3 = d3 + R(-0.3841978250666033) * d4;
+    return R(2.2468501984126985) * z0 * z0 + R(3.6320275079835525) * z1 * z1 + R(4.213886137822353) * z2 * z2 +
+           R(1.0316113515772065) * z3 * z3 + R(0.03897812227306876) * d4 * d4;
+}
+
+XF_HD double weno_cu6(double a, double b, double c, double d, double e, double f) {
+    const double q0 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
+    const double q1 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
+    const double q2 = (2.0 * c + 5.0 * d - e) * (1.0 / 6.0);
+    const double q3 = (11.0 * d - 7.0 * e + 2.0 * f) * (1.0 / 6.0);
+    const double t0 = a - 2.0 * b + c, u0 = a - 4.0 * b + 3.0 * c;
+    const double t1 = b - 2.0 * c + d, u1 = b - d;
+    const double t2 = c - 2.0 * d + e, u2 = 3.0 * c - 4.0 * d + e;
+    const double b0 = (13.0 / 12.0) * t0 * t0 + 0.25 * u0 * u0;
+    const double b1 = (13.0 / 12.0) * t1 * t1 + 0.25 * u1 * u1;
+    const double b2 = (13.0 / 12.0) * t2 * t2 + 0.25 * u2 * u2;
+    const double b6 = cu6_beta6(a, b, c, d, e, f);
+    const double tau = b6 - (b0 + 4.0 * b1 + b2) * (1.0 / 6.0);
+    const double e0 = b0 + 1e-6, e1 = b1 + 1e-6, e2 = b2 + 1e-6, e3 = b6 + 1e-6;
+    const double p01 = e0 * e1, p23 = e2 * e3;
+    const double w0 = (1.0 / 20.0) * (20.0 * e0 + tau) * (e1 * p23);
+    const double w1 = (9.0 / 20.0) * (20.0 * e1 + tau) * (e0 * p23);
+    const double w2 = (9.0 / 20.0) * (20.0 * e2 + tau) * (p01 * e3);
+    const double w3 = (1.0 / 20.0) * (20.0 * e3 + tau) * (p01 * e2);
+    return (w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3) / (w0 + w1 + w2 + w3);
+}
+
+// FP32 form: beta_k + eps and tau are scaled by one power of two (exact),
+// which leaves the weights unchanged and keeps the fourth-degree products in
+// range.
+XF_HD float weno_cu6(float a, float b, float c, float d, float e, float f) {
+    const float q0 = (2.0f * a - 7.0f * b + 11.0f * c) * (1.0f / 6.0f);
+    const float q1 = (-b + 5.0f * c + 2.0f * d) * (1.0f / 6.0f);
+    const float q2 = (2.0f * c + 5.0f * d - e) * (1.0f / 6.0f);
+    const float q3 = (11.0f * d - 7.0f * e + 2.0f * f) * (1.0f / 6.0f);
+    const float t0 = a - 2.0f * b + c, u0 = a - 4.0f * b + 3.0f * c;
+    const float t1 = b - 2.0f * c + d, u1 = b - d;
+    const float t2 = c - 2.0f * d + e, u2 = 3.0f * c - 4.0f * d + e;
+    const float b0 = (13.0f / 12.0f) * t0 * t0 + 0.25f * u0 * u0;
+    const float b1 = (13.0f / 12.0f) * t1 * t1 + 0.25f * u1 * u1;
+    const float b2 = (13.0f / 12.0f) * t2 * t2 + 0.25f * u2 * u2;
+    const float b6 = cu6_beta6(a, b, c, d, e, f);
+    float tau = b6 - (b0 + 4.0f * b1 + b2) * (1.0f / 6.0f);
+    float e0 = b0 + 1e-6f, e1 = b1 + 1e-6f, e2 = b2 + 1e-6f, e3 = b6 + 1e-6f;
+    int ex;
+    frexpf(fmaxf(fmaxf(e0, e1), fmaxf(e2, e3)), &ex);
+    e0 = ldexpf(e0, -ex);
+    e1 = ldexpf(e1, -ex);
+    e2 = ldexpf(e2, -ex);
+    e3 = ldexpf(e3, -ex);
+    tau = ldexpf(tau, -ex);
+    const float p01 = e0 * e1, p23 = e2 * e3;
+    const float w0 = (1.0f / 20.0f) * (20.0f * e0 + tau) * (e1 * p23);
+    const float w1 = (9.0f / 20.0f) * (20.0f * e1 + tau) * (e0 * p23);
+    const float w2 = (9.0f / 20.0f) * (20.0f * e2 + tau) * (p01 * e3);
+    const float w3 = (1.0f / 20.0f) * (20.0f * e3 + tau) * (p01 * e2);
+    return (w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3) / (w0 + w1 + w2 + w3);
+}
+
 // Blocks are dealt to the 8 XCDs of the chip round robin in dispatch order.
 // xcd_block renumbers them so that each XCD receives a contiguous range of
 // logical blocks (blocks that share stencil rows then share one L2).
@@ -166,13 +243,28 @@ struct Axes {
 // largest LLF speed over all faces of the direction (glf: the three speeds
 // u_n - c, u_n, u_n + c, reduced beforehand).
 constexpr int kViscLlf = 0, kViscRoe = 1, kViscGlf = 2;
+constexpr int kReconWeno5 = 0, kReconCu6 = 1;
 struct Dissip {
     int type;
     const double *glf;
+    int recon;   // kReconWeno5 or kReconCu6
 };
 
-// VISC = false compiles the LLF speeds only (ds is ignored); VISC = true
-// follows ds.type at run time.
+// Reconstruction of one characteristic field at the face from the split
+// values of the six cells: WENO5-JS of g+ on cells i-2..i+2 plus g- mirrored
+// on i+3..i-1, or WENO-CU6 of both on all six cells.
+template <bool OPTS, typename R>
+XF_HD R recon_pair(const R *gp, const R *gm, int recon) {
+    if constexpr (OPTS) {
+        if (recon == kReconCu6)
+            return weno_cu6(gp[0], gp[1], gp[2], gp[3], gp[4], gp[5]) +
+                   weno_cu6(gm[5], gm[4], gm[3], gm[2], gm[1], gm[0]);
+    }
+    return weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
+}
+
+// VISC = false compiles the default scheme only (LLF speeds, WENO5; ds is
+// ignored); VISC = true follows ds.type and ds.recon at run time.
 template <int NS, typename R, int DIR, bool FENCE = false, bool VISC = false, class St, class Out>
 XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned &flags, const Dissip &ds) {
     constexpr int IM = NS;
@@ -277,8 +369,8 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
             gPp[m] = R(0.5) * (wFp + aP * wUp);
             gPm[m] = R(0.5) * (wFp - aP * wUp);
         }
-        hm = weno5(gMp[0], gMp[1], gMp[2], gMp[3], gMp[4]) + weno5(gMm[5], gMm[4], gMm[3], gMm[2], gMm[1]);
-        hp = weno5(gPp[0], gPp[1], gPp[2], gPp[3], gPp[4]) + weno5(gPm[5], gPm[4], gPm[3], gPm[2], gPm[1]);
+        hm = recon_pair<VISC>(gMp, gMm, ds.recon);
+        hp = recon_pair<VISC>(gPp, gPm, ds.recon);
     }
     const R Asum = hm + hp, Dif = hp - hm;
 
@@ -294,7 +386,7 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
             gp[m] = R(0.5) * (wF + a0 * wU);
             gm[m] = R(0.5) * (wF - a0 * wU);
         }
-        h1 = weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
+        h1 = recon_pair<VISC>(gp, gm, ds.recon);
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
             const R wU = R(st.u(I2, m)) - ut2 * rh[m];
@@ -302,7 +394,7 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
             gp[m] = R(0.5) * (wF + a0 * wU);
             gm[m] = R(0.5) * (wF - a0 * wU);
         }
-        h2 = weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
+        h2 = recon_pair<VISC>(gp, gm, ds.recon);
     }
 
     // ---- species fields, back-projected as they come ----------------------
@@ -320,7 +412,7 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
             gp[m] = R(0.5) * (wF + a0 * wU);
             gm[m] = R(0.5) * (wF - a0 * wU);
         }
-        const R hs = weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
+        const R hs = recon_pair<VISC>(gp, gm, ds.recon);
         out(s, Yt[s] * Asum + hs);
         gsum += hs;
         gE += (q2 - chi[s] * iGam) * hs;

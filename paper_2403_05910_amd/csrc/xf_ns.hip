@@ -52,8 +52,8 @@ hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumu
     const Geo &g = c.g;
     // c.variant (measurement only) 1 or 2 runs the y/z column march (LLF, no
     // positivity blend) instead of the tiled kernel
-    if (dir == 0 || c.variant == 0 || sa.pp || ds.type != kViscLlf) {
-        const bool v = ds.type != kViscLlf;
+    if (dir == 0 || c.variant == 0 || sa.pp || ds.type != kViscLlf || ds.recon != kReconWeno5) {
+        const bool v = ds.type != kViscLlf || ds.recon != kReconWeno5;
         if (sa.pp)
             return v ? launch_face_sweep<R, S, true, true>(c, th, dir, accumulate, U, P, rhs, sa, ds, s)
                      : launch_face_sweep<R, S, true, false>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
@@ -85,7 +85,7 @@ hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumu
 
 hipError_t sweep(const LaunchCtx &c, int dir, int accumulate, const double *U, const double *P, const float *Uf,
                  const float *Pf, double *rhs, const StageArgs &sa, const double *glf, hipStream_t s) {
-    const Dissip ds{c.visc, glf};
+    const Dissip ds{c.visc, glf, c.recon};
     if (c.visc == kViscGlf && !glf) return hipErrorInvalidValue;
     if (c.precision == XF_PREC_MIXED)
         return sweep_t<float, float>(c, c.th32, dir, accumulate, Uf, Pf, rhs, sa, ds, s);
@@ -153,7 +153,7 @@ hipError_t sweep_vjp_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, const 
 
 hipError_t sweep_vjp(const LaunchCtx &c, int dir, const double *U, const double *P, const double *rbar,
                      double *Ubar, double *Pbar, double *rec, long long nrec, const double *glf, hipStream_t s) {
-    const Dissip ds{c.visc, glf};
+    const Dissip ds{c.visc, glf, c.recon};
     if (c.visc == kViscGlf && !glf) return hipErrorInvalidValue;
     if (c.precision == XF_PREC_MIXED)
         return sweep_vjp_t<float>(c, c.th32, dir, U, P, rbar, Ubar, Pbar, rec, nrec, ds, s);

@@ -24,6 +24,8 @@ XF_PREC_FP64, XF_PREC_MIXED = 0, 1
 XF_OP_RHS, XF_OP_RK3, XF_OP_VJP, XF_OP_RK3_VJP = 0, 1, 2, 3
 XF_VISC_LLF, XF_VISC_ROE, XF_VISC_GLF = 0, 1, 2
 VISC = {"LLF": XF_VISC_LLF, "ROE": XF_VISC_ROE, "GLF": XF_VISC_GLF}
+XF_RECON_WENO5, XF_RECON_CU6 = 0, 1
+RECON = {"WENO5": XF_RECON_WENO5, "CU6": XF_RECON_CU6}
 FLAGS = {1: "rho<=0", 2: "Y<0", 4: "p<=0 or T<=0", 8: "T out of range", 16: "Newton not converged",
          32: "Roe c^2<=0", 64: "NaN/Inf"}
 
@@ -64,6 +66,7 @@ _cfl = _sig("xf_cfl_dt", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
 _rk3 = _sig("xf_rk3_step", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
 _set_pp = _sig("xf_set_positivity", _c_int, _vp, _c_int)
 _set_visc = _sig("xf_set_dissipation", _c_int, _vp, _c_int)
+_set_recon = _sig("xf_set_reconstruction", _c_int, _vp, _c_int)
 _rk3_cfl = _sig("xf_rk3_step_cfl", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
 _rhs_vjp = _sig("xf_rhs_vjp", _c_int, _vp, _vp, _vp, _vp, _vp, _vp)
 _rk3_vjp = _sig("xf_rk3_step_vjp", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
@@ -74,8 +77,8 @@ _strerror = _sig("xf_strerror", ctypes.c_char_p, _c_int)
 
 EXPORTED = ["xf_create", "xf_destroy", "xf_state_elems", "xf_workspace_bytes", "xf_fill_ghosts",
             "xf_fill_ghosts_vjp", "xf_rhs", "xf_primitives", "xf_cfl_dt", "xf_rk3_step", "xf_rk3_step_cfl",
-            "xf_set_dissipation", "xf_set_positivity", "xf_rhs_vjp", "xf_rk3_step_vjp", "xf_status", "xf_strerror", "xf_timing",
-            "xf_timing_read"]
+            "xf_set_dissipation", "xf_set_reconstruction", "xf_set_positivity", "xf_rhs_vjp", "xf_rk3_step_vjp",
+            "xf_status", "xf_strerror", "xf_timing", "xf_timing_read"]
 KERNEL_CLASSES = ["prims", "sweep_x", "sweep_y", "sweep_z", "fill", "stage", "cfl", "zero",
                   "vjp_x", "vjp_y", "vjp_z", "prims_vjp", "fill_vjp"]
 
@@ -143,6 +146,10 @@ def xf_rk3_step(ctx, U, dt, dt_dev, ws, stream):
 
 def xf_set_dissipation(ctx, visc):
     return _check(_set_visc(ctx, int(visc)), "xf_set_dissipation")
+
+
+def xf_set_reconstruction(ctx, recon):
+    return _check(_set_recon(ctx, int(recon)), "xf_set_reconstruction")
 
 
 def xf_set_positivity(ctx, enable):
@@ -213,6 +220,7 @@ class Context:
         self.precision = precision
         self.positivity = False
         self.visc = "LLF"
+        self.recon = "WENO5"
         g = [3 if k > 1 else 0 for k in self.n]
         self.shape = (self.nv, self.n[2] + 2 * g[2], self.n[1] + 2 * g[1], self.n[0] + 2 * g[0])
         self.interior = (slice(None), slice(g[2], g[2] + self.n[2]), slice(g[1], g[1] + self.n[1]),
@@ -300,6 +308,12 @@ class Context:
         """artificial viscosity of the flux splitting: "LLF", "ROE" or "GLF" """
         xf_set_dissipation(self.handle, VISC[visc])
         self.visc = visc
+        return self
+
+    def set_reconstruction(self, recon="WENO5"):
+        """reconstruction of the characteristic fluxes: "WENO5" or "CU6" """
+        xf_set_reconstruction(self.handle, RECON[recon])
+        self.recon = recon
         return self
 
     def set_positivity(self, enable=True):

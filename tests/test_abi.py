@@ -71,5 +71,7 @@ def test_strerror_and_argument_errors_without_device():
     assert xf._rk3_vjp(None, None, 0.1, None, None, None) == xf.XF_EINVAL
     assert xf._fill(None, None, None) == xf.XF_EINVAL
     assert xf._set_pp(None, 1) == xf.XF_EINVAL
+    assert xf._set_visc(None, 1) == xf.XF_EINVAL
+    assert xf._set_recon(None, 1) == xf.XF_EINVAL
     assert xf._state_elems(None) == 0
     assert xf._ws_bytes(None, 0) == 0

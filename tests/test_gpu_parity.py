@@ -27,9 +27,9 @@ def _xf():
     return xf
 
 
-def gpu_rhs(case, precision="fp64", visc="LLF"):
+def gpu_rhs(case, precision="fp64", visc="LLF", recon="WENO5"):
     xf = _xf()
-    ctx = xf.Context.from_case(case, precision).set_dissipation(visc)
+    ctx = xf.Context.from_case(case, precision).set_dissipation(visc).set_reconstruction(recon)
     U = ctx.state_from_numpy(case.U)
     ctx.fill_ghosts(U)
     r = ctx.rhs(U)
@@ -39,10 +39,10 @@ def gpu_rhs(case, precision="fp64", visc="LLF"):
     return out
 
 
-def oracle_rhs(case, visc="LLF"):
+def oracle_rhs(case, visc="LLF", recon="WENO5"):
     th, g = oracle_objects(case)
     U = O.fill_ghosts(g, case.U)
-    r, aux = O.rhs(th, g, U, return_aux=True, visc=visc)
+    r, aux = O.rhs(th, g, U, return_aux=True, visc=visc, recon=recon)
     return r, aux, U
 
 
@@ -333,3 +333,54 @@ def test_rhs_glf_mixed_within_fp32_bound():
     err = field_err(r_gpu, r_ora, aux["scale_llf"])
     print(f"[parity] mixed GLF max err / S_f = {err.max():.3e}", flush=True)
     assert err.max() <= MIXED_RHS_TOL, err
+
+
+
+@pytest.mark.parametrize("name", ["ragged3d_n3_outflow_x", "n9_3d_mixed_bc", "inert_sbi_32", "plane2d_n3",
+                                  "z_only_n3", "wave1d_600", "sod_400"])
+def test_rhs_cu6_matches_oracle(name):
+    case = CASES[name]
+    r_gpu, flags, _ = gpu_rhs(case, recon="CU6")
+    r_ora, aux, _ = oracle_rhs(case, recon="CU6")
+    assert flags == 0
+    err = field_err(r_gpu, r_ora, aux["scale_llf"])
+    print(f"[parity] CU6 {name} max err / S_f = {err.max():.3e}", flush=True)
+    assert err.max() <= TOL, err
+
+
+@pytest.mark.parametrize("visc,pp", [("LLF", False), ("GLF", True)])
+def test_rk3_cu6_matches_oracle(visc, pp):
+    xf = _xf()
+    case = CASES["inert_sbi_32"]
+    th, g = oracle_objects(case)
+    Uo = O.fill_ghosts(g, case.U)
+    dt = 0.5 * O.cfl_dt(th, g, Uo, 0.5)
+    ctx = xf.Context.from_case(case).set_reconstruction("CU6").set_dissipation(visc).set_positivity(pp)
+    U = ctx.state_from_numpy(case.U)
+    for _ in range(3):
+        Uo = O.rk3_step(th, g, Uo, dt, visc=visc, recon="CU6", pp=pp)
+        ctx.rk3_step(U, dt)
+    assert ctx.status() == 0
+    scale = np.abs(Uo).reshape(Uo.shape[0], -1).max(axis=1)
+    err = field_err(U.cpu().numpy(), Uo, scale)
+    print(f"[parity] rk3 CU6 {visc} pp={pp} inert_sbi_32 max err {err.max():.3e}", flush=True)
+    assert err.max() <= 1e-12, err
+
+
+def test_rhs_cu6_mixed_within_fp32_bound():
+    case = CASES["n9_3d_mixed_bc"]
+    r_gpu, flags, _ = gpu_rhs(case, "mixed", recon="CU6")
+    r_ora, aux, _ = oracle_rhs(case, recon="CU6")
+    err = field_err(r_gpu, r_ora, aux["scale_llf"])
+    print(f"[parity] mixed CU6 max err / S_f = {err.max():.3e}", flush=True)
+    assert err.max() <= MIXED_RHS_TOL, err
+
+
+def test_vjp_refuses_cu6():
+    xf = _xf()
+    case = CASES["n1_thermal_3d"]
+    ctx = xf.Context.from_case(case).set_reconstruction("CU6")
+    U = ctx.state_from_numpy(case.U)
+    with pytest.raises(xf.XfError) as e:
+        ctx.rhs_vjp(U, torch.zeros_like(U))
+    assert e.value.code == xf.XF_EUNSUPPORTED

@@ -230,8 +230,7 @@ def test_cu6_downwind_candidate_sign_caught(monkeypatch):
         q0, q1, q2 = X.weno5_candidates(a, b, c, d, e)
         q3 = (11.0 * d + 7.0 * e - 2.0 * f) / 6.0          # planted: signs of e and f flipped
         b0, b1, b2 = X.weno5_smoothness(a, b, c, d, e)
-        v = np.stack(np.broadcast_arrays(a, b, c, d, e, f), axis=0)
-        b6 = np.einsum("i...,ij,j...->...", v, X.CU6_B6, v)
+        b6 = X.smoothness6(np.stack(np.broadcast_arrays(a, b, c, d, e, f), axis=0))
         tau = b6 - (b0 + 4.0 * b1 + b2) / 6.0
         al = [X.CU6_D[k] * (X.CU6_C + tau / (bk + X.CU6_EPS)) for k, bk in enumerate((b0, b1, b2, b6))]
         s_ = al[0] + al[1] + al[2] + al[3]
