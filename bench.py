@@ -7,7 +7,8 @@ primitives with the Newton temperature, the x/y/z Roe-characteristic
 WENO5-LLF flux differences and the stage update.  The metric is interior
 cell-RHS evaluations per second (3 per cell per step), FP64.  Beside it the
 same line reports the FP32-mixed path (throughput and its state error
-against FP64), the step with the positivity-preserving flux blend, the
+against FP64), the step with the positivity-preserving flux blend, the steps
+with the ROE or GLF viscosity and with WENO-CU6, the
 adjoint (VJP) throughput and adjoint/forward time ratios,
 the roofline of the dominant kernel (timed live with HIP events on the stream
 it runs on) and the CPU oracle on a bounded crop of the same state.
@@ -150,15 +151,18 @@ def rollout_ratio(torch, xf, n=64, steps=64, every=8):
     for rep in range(2):   # the first repetition warms up
         X = U0.clone().requires_grad_(True)
         t_fwd, Y = clock(lambda: xf.rollout(ctx, X, dt, steps, every))
+        base = torch.cuda.memory_allocated()
         torch.cuda.reset_peak_memory_stats()
         t_bwd, _ = clock(lambda: Y.backward(g))
-        peak = torch.cuda.max_memory_allocated()
+        peak = torch.cuda.max_memory_allocated() - base
         del X, Y
+    formula = xf.rollout_memory_bytes(ctx, steps, every)
     ctx.close()
     return {"workload": f"periodic_mixture_{n}^3 (5 species)", "steps": steps, "ckpt_every": every,
             "ms_forward_plain": t_plain * 1e3, "ms_forward_checkpointed": t_fwd * 1e3,
             "ms_backward": t_bwd * 1e3, "backward_over_forward": t_bwd / t_plain,
-            "peak_bytes_during_backward": peak}
+            "extra_peak_bytes_during_backward": peak,
+            "formula_bytes": formula}
 
 
 def cpu_baseline(case, crop=96):
@@ -314,6 +318,23 @@ def main():
         log(f"[bench] positivity: {secs_p / a.steps * 1e3:.2f} ms/step, flags {out['positivity']['status_flags']}")
         ctxp.close()
         del Up
+        # the paper's other scheme options on the same FP64 step: ROE and GLF
+        # artificial viscosity, WENO-CU6 reconstruction
+        out["scheme_options"] = {}
+        for label, visc, recon in (("ROE", "ROE", "WENO5"), ("GLF", "GLF", "WENO5"), ("CU6", "LLF", "CU6")):
+            ctxo = xf.Context.from_case(case, "fp64").set_dissipation(visc).set_reconstruction(recon)
+            Uo = U0.clone()
+            ctxo.fill_ghosts(Uo)
+            run_steps(ctxo, Uo, dt_dev, 1, a.cfl)
+            torch.cuda.synchronize()
+            secs_o, kern_o = timed_steps(torch, ctxo, Uo, dt_dev, max(2, a.steps // 2), a.cfl)
+            n_o = max(2, a.steps // 2)
+            out["scheme_options"][label] = {
+                "ms_per_step": secs_o / n_o * 1e3, "value": 3 * cells * n_o / secs_o, "status_flags": ctxo.status(),
+                "kernel_avg_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kern_o.items() if v[1]}}
+            log(f"[bench] {label}: {secs_o / n_o * 1e3:.2f} ms/step")
+            ctxo.close()
+            del Uo
         # adjoint: one RHS VJP per evaluation, against one forward RHS
         rb = torch.randn_like(r64)
         Ub = torch.zeros_like(r64)
