@@ -71,38 +71,42 @@ XF_HD R e_species(const ThermoK<R> &th, int s, R T) {
 
 // WENO5-JS value at the right edge of the cell holding c (linear weights
 // 1/10, 6/10, 3/10; absolute eps = 1e-6; weights (eps + beta)^-2).  Written
-// with one division: alpha_k / sum alpha = d_k prod_{j!=k} s_j / sum(...),
-// s_k = (eps + beta_k)^2.
+// with one division and with the constant factors gathered where they cost
+// least, none of which changes the weights in exact arithmetic: the
+// smoothness indicators are taken times 12 (13 t^2 + 3 u^2, eps 12e-6), the
+// linear weights times 10 (1, 6, 3), and the candidates times 6, their 1/6
+// applied once to the denominator;
+// alpha_k / sum alpha = d_k prod_{j!=k} s_j / sum(...), s_k = (eps + beta_k)^2.
 XF_HD double weno5(double a, double b, double c, double d, double e) {
-    const double q0 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
-    const double q1 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
-    const double q2 = (2.0 * c + 5.0 * d - e) * (1.0 / 6.0);
+    const double q0 = 2.0 * a - 7.0 * b + 11.0 * c;
+    const double q1 = -b + 5.0 * c + 2.0 * d;
+    const double q2 = 2.0 * c + 5.0 * d - e;
     const double t0 = a - 2.0 * b + c, u0 = a - 4.0 * b + 3.0 * c;
     const double t1 = b - 2.0 * c + d, u1 = b - d;
     const double t2 = c - 2.0 * d + e, u2 = 3.0 * c - 4.0 * d + e;
-    double s0 = 1e-6 + ((13.0 / 12.0) * t0 * t0 + 0.25 * u0 * u0);
-    double s1 = 1e-6 + ((13.0 / 12.0) * t1 * t1 + 0.25 * u1 * u1);
-    double s2 = 1e-6 + ((13.0 / 12.0) * t2 * t2 + 0.25 * u2 * u2);
+    double s0 = (13.0 * t0) * t0 + ((3.0 * u0) * u0 + 12e-6);
+    double s1 = (13.0 * t1) * t1 + ((3.0 * u1) * u1 + 12e-6);
+    double s2 = (13.0 * t2) * t2 + ((3.0 * u2) * u2 + 12e-6);
     s0 *= s0;
     s1 *= s1;
     s2 *= s2;
-    const double w0 = 0.1 * (s1 * s2), w1 = 0.6 * (s0 * s2), w2 = 0.3 * (s0 * s1);
-    return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+    const double w0 = s1 * s2, w1 = 6.0 * (s0 * s2), w2 = 3.0 * (s0 * s1);
+    return (w0 * q0 + w1 * q1 + w2 * q2) / (6.0 * (w0 + w1 + w2));
 }
 
 // FP32 form.  The (eps + beta)^2 products can overflow FP32, so the three
 // (eps + beta) are first scaled by the same power of two (exact, no rounding),
 // which leaves the weights unchanged.
 XF_HD float weno5(float a, float b, float c, float d, float e) {
-    const float q0 = (2.0f * a - 7.0f * b + 11.0f * c) * (1.0f / 6.0f);
-    const float q1 = (-b + 5.0f * c + 2.0f * d) * (1.0f / 6.0f);
-    const float q2 = (2.0f * c + 5.0f * d - e) * (1.0f / 6.0f);
+    const float q0 = 2.0f * a - 7.0f * b + 11.0f * c;
+    const float q1 = -b + 5.0f * c + 2.0f * d;
+    const float q2 = 2.0f * c + 5.0f * d - e;
     const float t0 = a - 2.0f * b + c, u0 = a - 4.0f * b + 3.0f * c;
     const float t1 = b - 2.0f * c + d, u1 = b - d;
     const float t2 = c - 2.0f * d + e, u2 = 3.0f * c - 4.0f * d + e;
-    float s0 = 1e-6f + ((13.0f / 12.0f) * t0 * t0 + 0.25f * u0 * u0);
-    float s1 = 1e-6f + ((13.0f / 12.0f) * t1 * t1 + 0.25f * u1 * u1);
-    float s2 = 1e-6f + ((13.0f / 12.0f) * t2 * t2 + 0.25f * u2 * u2);
+    float s0 = (13.0f * t0) * t0 + ((3.0f * u0) * u0 + 12e-6f);
+    float s1 = (13.0f * t1) * t1 + ((3.0f * u1) * u1 + 12e-6f);
+    float s2 = (13.0f * t2) * t2 + ((3.0f * u2) * u2 + 12e-6f);
     const float smax = fmaxf(s0, fmaxf(s1, s2));
     int ex;
     frexpf(smax, &ex);
@@ -112,8 +116,8 @@ XF_HD float weno5(float a, float b, float c, float d, float e) {
     s0 *= s0;
     s1 *= s1;
     s2 *= s2;
-    const float w0 = 0.1f * (s1 * s2), w1 = 0.6f * (s0 * s2), w2 = 0.3f * (s0 * s1);
-    return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+    const float w0 = s1 * s2, w1 = 6.0f * (s0 * s2), w2 = 3.0f * (s0 * s1);
+    return (w0 * q0 + w1 * q1 + w2 * q2) / (6.0f * (w0 + w1 + w2));
 }
 
 // WENO-CU6 value at the right edge of the cell holding c, from the six
