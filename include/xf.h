@@ -169,8 +169,8 @@ int xf_set_dissipation(xf_ctx *ctx, int type);
  * weights (1, 9, 9, 1)/20, alpha_k = d_k (20 + tau6 / (beta_k + 1e-6)),
  * beta_3 = beta6 the Jiang-Shu smoothness of the six-cell quintic,
  * tau6 = beta6 - (beta_0 + 4 beta_1 + beta_2)/6).  Applies to every later
- * forward call; xf_rhs_vjp and xf_rk3_step_vjp return XF_EUNSUPPORTED while
- * CU6 is selected.  Returns XF_EINVAL for another type. */
+ * call, the VJPs included (they differentiate the chosen reconstruction with
+ * the dissipation speeds held fixed).  Returns XF_EINVAL for another type. */
 enum { XF_RECON_WENO5 = 0, XF_RECON_CU6 = 1 };
 int xf_set_reconstruction(xf_ctx *ctx, int type);
 

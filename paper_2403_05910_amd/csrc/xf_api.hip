@@ -530,7 +530,6 @@ int xf_rhs_vjp(xf_ctx *c, const double *U, const double *rbar, double *Ubar, voi
     if (!c || !U || !rbar || !Ubar || !ws || Ubar == U || Ubar == rbar || !aligned8(U) || !aligned8(rbar) ||
         !aligned8(Ubar) || !aligned8(ws))
         return XF_EINVAL;
-    if (c->lc.recon != XF_RECON_WENO5) return XF_EUNSUPPORTED;   // the adjoint is of WENO5
     const Layout l = layout(c, XF_OP_VJP);
     return rhs_vjp_into(c, U, rbar, Ubar, at<double>(ws, l.P), at<double>(ws, l.Pbar), at<double>(ws, l.rec),
                         at<unsigned long long>(ws, l.mx), (hipStream_t)stream);
@@ -541,7 +540,6 @@ int xf_rk3_step_vjp(xf_ctx *c, const double *Un, double dt, double *Ubar, void *
         !(dt >= 0.0))
         return XF_EINVAL;
     if (c->pp) return XF_EUNSUPPORTED;   // the adjoint is of the unblended step
-    if (c->lc.recon != XF_RECON_WENO5) return XF_EUNSUPPORTED;
     const Layout l = layout(c, XF_OP_RK3_VJP);
     const hipStream_t s = (hipStream_t)stream;
     const LaunchCtx &lc = c->lc;

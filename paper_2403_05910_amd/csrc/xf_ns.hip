@@ -92,7 +92,7 @@ hipError_t sweep(const LaunchCtx &c, int dir, int accumulate, const double *U, c
     return sweep_t<double, double>(c, c.th64, dir, accumulate, U, P, rhs, sa, ds, s);
 }
 
-template <typename R, int HALF>
+template <typename R, int HALF, bool CU6>
 hipError_t launch_vjp_group(const LaunchCtx &c, const ThermoK<R> &th, int dir, int grp, const double *U,
                             const double *P, const double *rbar, double *Ubar, double *Pbar, double *rec,
                             long long nrec, const Dissip &ds, hipStream_t s) {
@@ -106,7 +106,7 @@ hipError_t launch_vjp_group(const LaunchCtx &c, const ThermoK<R> &th, int dir, i
         const int wpb = per_wave * 4 <= 65536 ? 4 : 1;
         const long long waves = (vjp_x_waves_per_plane(g) - grp + kVjpGroups - 1) / kVjpGroups;
         dim3 grid((unsigned)((waves + wpb - 1) / wpb), g.nz), block(64 * wpb);
-        hipLaunchKernelGGL((k_face_vjp_x<NS, R, HALF>), grid, block, per_wave * wpb, s, U, P, rbar, Ubar, Pbar, rec,
+        hipLaunchKernelGGL((k_face_vjp_x<NS, R, HALF, CU6>), grid, block, per_wave * wpb, s, U, P, rbar, Ubar, Pbar, rec,
                            nrec, g, th, W, grp, ds);
     } else if (c.variant != 4) {
         const int nsw = dir == 1 ? g.ny : g.nz;
@@ -115,19 +115,19 @@ hipError_t launch_vjp_group(const LaunchCtx &c, const ThermoK<R> &th, int dir, i
         const int nb = (nfb - grp + kVjpGroups - 1) / kVjpGroups;
         dim3 grid((unsigned)(xt * nb), dir == 1 ? g.nz : g.ny), block(256);
         if (dir == 1)
-            hipLaunchKernelGGL((k_face_vjp_yz<NS, R, 1, HALF>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec,
+            hipLaunchKernelGGL((k_face_vjp_yz<NS, R, 1, HALF, CU6>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec,
                                g, th, grp, ds);
         else
-            hipLaunchKernelGGL((k_face_vjp_yz<NS, R, 2, HALF>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec,
+            hipLaunchKernelGGL((k_face_vjp_yz<NS, R, 2, HALF, CU6>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec,
                                g, th, grp, ds);
     } else {
         const int nsw = dir == 1 ? g.ny : g.nz;
         dim3 grid((g.nx + 63) / 64, (nsw / 6 + 1 + 3) / 4, dir == 1 ? g.nz : g.ny), block(64, 4);
         if (dir == 1)
-            hipLaunchKernelGGL((k_face_vjp<NS, R, 1, HALF>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec, g,
+            hipLaunchKernelGGL((k_face_vjp<NS, R, 1, HALF, CU6>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec, g,
                                th, grp, ds);
         else
-            hipLaunchKernelGGL((k_face_vjp<NS, R, 2, HALF>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec, g,
+            hipLaunchKernelGGL((k_face_vjp<NS, R, 2, HALF, CU6>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec, g,
                                th, grp, ds);
     }
     return hipGetLastError();
@@ -144,8 +144,12 @@ hipError_t sweep_vjp_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, const 
     const long long ngrp = dir == 0 ? vjp_x_waves_per_plane(g)
                                     : (c.variant == 4 ? nsw + 1 : (nsw + 1 + kVjpFB - 1) / kVjpFB);
     for (int grp = 0; grp < kVjpGroups && grp < ngrp; ++grp) {
-        hipError_t e = launch_vjp_group<R, 0>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, rec, nrec, ds, s);
-        if (e == hipSuccess) e = launch_vjp_group<R, 1>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, rec, nrec, ds, s);
+        // the second half does not depend on the reconstruction
+        hipError_t e = ds.recon == kReconCu6
+                           ? launch_vjp_group<R, 0, true>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, rec, nrec, ds, s)
+                           : launch_vjp_group<R, 0, false>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, rec, nrec, ds, s);
+        if (e == hipSuccess)
+            e = launch_vjp_group<R, 1, false>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, rec, nrec, ds, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -52,6 +52,100 @@ XF_HD R weno5_bwd(R a, R b, R c, R d, R e, R hb, R &ab, R &bb, R &cb, R &db, R &
 // Forward and backward of h = W(g+_{0..4}) + W(g-_{5..1}) with
 // g+- = (wF +- al wU)/2: returns h and the cotangents of wF and wU at the six
 // stencil cells for the output cotangent hb.
+// WENO-CU6 backward (forms as in weno_cu6 of the face code).  Adds
+// hb * dW/d(a..f) to (ab..fb), W the value of weno_cu6(a..f):
+// W = sum_k w_k q_k, w_k = alpha_k / S, alpha_k = d_k (C + tau / e_k),
+// e_k = beta_k + eps (beta_3 = beta6), so
+// dW = sum_k w_k dq_k + sum_k (q_k - W) / S * d_k / e_k (dtau - tau dbeta_k / e_k).
+template <typename R>
+XF_HD R cu6_bwd(R a, R b, R c, R d, R e, R f, R hb, R &ab, R &bb, R &cb, R &db, R &eb, R &fb) {
+    const R q0 = (R(2) * a - R(7) * b + R(11) * c) * R(1.0 / 6.0);
+    const R q1 = (-b + R(5) * c + R(2) * d) * R(1.0 / 6.0);
+    const R q2 = (R(2) * c + R(5) * d - e) * R(1.0 / 6.0);
+    const R q3 = (R(11) * d - R(7) * e + R(2) * f) * R(1.0 / 6.0);
+    const R t0 = a - R(2) * b + c, u0 = a - R(4) * b + R(3) * c;
+    const R t1 = b - R(2) * c + d, u1 = b - d;
+    const R t2 = c - R(2) * d + e, u2 = R(3) * c - R(4) * d + e;
+    const R b0 = R(13.0 / 12.0) * t0 * t0 + R(0.25) * u0 * u0;
+    const R b1 = R(13.0 / 12.0) * t1 * t1 + R(0.25) * u1 * u1;
+    const R b2 = R(13.0 / 12.0) * t2 * t2 + R(0.25) * u2 * u2;
+    // beta6 = sum_k D_k z_k^2 over first differences (constants of cu6_beta6)
+    const R d0 = b - a, d1 = c - b, d2 = d - c, d3 = e - d, d4 = f - e;
+    const R L10 = R(-3.3800293620919937), L20 = R(4.137755308541131), L30 = R(-2.2318538224071762),
+            L40 = R(0.4518745009732172), L21 = R(-1.8788632502196132), L31 = R(1.2398246217680282),
+            L41 = R(-0.2835945203123665), L32 = R(-0.8641384480158466), L42 = R(0.22441845180562248),
+            L43 = R(-0.3841978250666033);
+    const R D0 = R(2.2468501984126985), D1 = R(3.6320275079835525), D2 = R(4.213886137822353),
+            D3 = R(1.0316113515772065), D4 = R(0.03897812227306876);
+    const R z0 = d0 + L10 * d1 + L20 * d2 + L30 * d3 + L40 * d4;
+    const R z1 = d1 + L21 * d2 + L31 * d3 + L41 * d4;
+    const R z2 = d2 + L32 * d3 + L42 * d4;
+    const R z3 = d3 + L43 * d4;
+    const R b6 = D0 * z0 * z0 + D1 * z1 * z1 + D2 * z2 * z2 + D3 * z3 * z3 + D4 * d4 * d4;
+    const R tau = b6 - (b0 + R(4) * b1 + b2) * R(1.0 / 6.0);
+    const R ie0 = R(1) / (b0 + R(1e-6)), ie1 = R(1) / (b1 + R(1e-6)), ie2 = R(1) / (b2 + R(1e-6)),
+            ie3 = R(1) / (b6 + R(1e-6));
+    const R al0 = R(1.0 / 20.0) * (R(20) + tau * ie0), al1 = R(9.0 / 20.0) * (R(20) + tau * ie1);
+    const R al2 = R(9.0 / 20.0) * (R(20) + tau * ie2), al3 = R(1.0 / 20.0) * (R(20) + tau * ie3);
+    const R iS = R(1) / (al0 + al1 + al2 + al3);
+    const R W = (al0 * q0 + al1 * q1 + al2 * q2 + al3 * q3) * iS;
+    // cotangents of the candidates, of tau and of the betas
+    const R g0 = hb * (q0 - W) * iS * R(1.0 / 20.0) * ie0, g1 = hb * (q1 - W) * iS * R(9.0 / 20.0) * ie1;
+    const R g2 = hb * (q2 - W) * iS * R(9.0 / 20.0) * ie2, g3 = hb * (q3 - W) * iS * R(1.0 / 20.0) * ie3;
+    const R tau_b = g0 + g1 + g2 + g3;
+    const R b0_b = -g0 * tau * ie0 - tau_b * R(1.0 / 6.0);
+    const R b1_b = -g1 * tau * ie1 - tau_b * R(4.0 / 6.0);
+    const R b2_b = -g2 * tau * ie2 - tau_b * R(1.0 / 6.0);
+    const R b6_b = -g3 * tau * ie3 + tau_b;
+    const R w0 = hb * al0 * iS, w1 = hb * al1 * iS, w2 = hb * al2 * iS, w3 = hb * al3 * iS;
+    // candidates
+    ab += w0 * R(2.0 / 6.0);
+    bb += w0 * R(-7.0 / 6.0) - w1 * R(1.0 / 6.0);
+    cb += w0 * R(11.0 / 6.0) + w1 * R(5.0 / 6.0) + w2 * R(2.0 / 6.0);
+    db += w1 * R(2.0 / 6.0) + w2 * R(5.0 / 6.0) + w3 * R(11.0 / 6.0);
+    eb += -w2 * R(1.0 / 6.0) - w3 * R(7.0 / 6.0);
+    fb += w3 * R(2.0 / 6.0);
+    // Jiang-Shu indicators of the three upwind sub-stencils
+    const R A0 = R(13.0 / 6.0) * t0 * b0_b, B0 = R(0.5) * u0 * b0_b;
+    const R A1 = R(13.0 / 6.0) * t1 * b1_b, B1 = R(0.5) * u1 * b1_b;
+    const R A2 = R(13.0 / 6.0) * t2 * b2_b, B2 = R(0.5) * u2 * b2_b;
+    ab += A0 + B0;
+    bb += -R(2) * A0 - R(4) * B0 + A1 + B1;
+    cb += A0 + R(3) * B0 - R(2) * A1 + A2 + R(3) * B2;
+    db += A1 - B1 - R(2) * A2 - R(4) * B2;
+    eb += A2 + B2;
+    // beta6 through its squares and the first differences
+    const R y0 = R(2) * D0 * z0 * b6_b, y1 = R(2) * D1 * z1 * b6_b, y2 = R(2) * D2 * z2 * b6_b,
+            y3 = R(2) * D3 * z3 * b6_b, y4 = R(2) * D4 * d4 * b6_b;
+    const R d0b = y0;
+    const R d1b = L10 * y0 + y1;
+    const R d2b = L20 * y0 + L21 * y1 + y2;
+    const R d3b = L30 * y0 + L31 * y1 + L32 * y2 + y3;
+    const R d4b = L40 * y0 + L41 * y1 + L42 * y2 + L43 * y3 + y4;
+    ab -= d0b;
+    bb += d0b - d1b;
+    cb += d1b - d2b;
+    db += d2b - d3b;
+    eb += d3b - d4b;
+    fb += d4b;
+    return W;
+}
+
+// split_weno_fb for WENO-CU6: h = CU6(g+_{0..5}) + CU6(g-_{5..0}).
+template <typename R>
+XF_HD R split_cu6_fb(const R *gp, const R *gm, R al, R hb, R *wFb, R *wUb) {
+    R pb[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    R mb[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    const R h = cu6_bwd(gp[0], gp[1], gp[2], gp[3], gp[4], gp[5], hb, pb[0], pb[1], pb[2], pb[3], pb[4], pb[5]) +
+                cu6_bwd(gm[5], gm[4], gm[3], gm[2], gm[1], gm[0], hb, mb[5], mb[4], mb[3], mb[2], mb[1], mb[0]);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        wFb[m] = R(0.5) * (pb[m] + mb[m]);
+        wUb[m] = R(0.5) * al * (pb[m] - mb[m]);
+    }
+    return h;
+}
+
 template <typename R>
 XF_HD R split_weno_fb(const R *gp, const R *gm, R al, R hb, R *wFb, R *wUb) {
     R pb[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
@@ -86,9 +180,11 @@ struct Sink {
 // share window cells through different (field, cell) calls, so the
 // read-modify-writes must stay in program order even where one thread's
 // addresses differ: the accesses are volatile (LDS executes a wave's
-// instructions in order).
+// instructions in order).  The pointer carries the LDS address space, so no
+// generic-address checks are generated.
+typedef __attribute__((address_space(3))) double lds_double;   // a pointer known to be LDS
 struct SinkLds {
-    volatile double *w;
+    volatile lds_double *w;
     int W, off, mstep, pofs;   // window length, offset of stencil cell 0, cell stride, start of the P rows
     XF_HD void u(int f, int m, double v) const { w[f * W + off + m * mstep] += v; }
     XF_HD void p(int k, int m, double v) const { w[pofs + k * W + off + m * mstep] += v; }
@@ -171,7 +267,7 @@ struct VjpRec {
 // the WENO5 reconstructions and the characteristic projections' dependence on
 // each cell's own values; writes the direct cell cotangents to `out` and the
 // accumulated ones to `rec`.
-template <int NS, typename R, int DIR, class Out>
+template <int NS, typename R, int DIR, bool CU6 = false, class Out>
 XF_HD void face_vjp_a(const Stencil &st, const ThermoK<R> &th, const R *Fb, const Out &out, const VjpRec<NS> &rec,
                       const Dissip &ds) {
     constexpr int IM = NS;
@@ -180,6 +276,7 @@ XF_HD void face_vjp_a(const Stencil &st, const ThermoK<R> &th, const R *Fb, cons
     constexpr int IN = NS + KN, I1 = NS + K1, I2 = NS + K2;
 
     // ================= forward: Roe state and per-cell scalars =================
+    constexpr bool cu6 = CU6;   // WENO-CU6 reconstruction (else WENO5)
     const RoeFwd<NS, R> rf(st, th);
     XF_ROE_UNPACK(rf);
     const R utn = ut[KN], ut1 = ut[K1], ut2 = ut[K2];
@@ -268,8 +365,10 @@ XF_HD void face_vjp_a(const Stencil &st, const ThermoK<R> &th, const R *Fb, cons
             gPm[m] = R(0.5) * (wFp - aP * wUp);
         }
         R wFmb[6], wUmb[6], wFpb[6], wUpb[6];
-        const R hm = split_weno_fb(gMp, gMm, aM, Asum_b - Dif_b, wFmb, wUmb);
-        const R hp = split_weno_fb(gPp, gPm, aP, Asum_b + Dif_b, wFpb, wUpb);
+        const R hm = cu6 ? split_cu6_fb(gMp, gMm, aM, Asum_b - Dif_b, wFmb, wUmb)
+                         : split_weno_fb(gMp, gMm, aM, Asum_b - Dif_b, wFmb, wUmb);
+        const R hp = cu6 ? split_cu6_fb(gPp, gPm, aP, Asum_b + Dif_b, wFpb, wUpb)
+                         : split_weno_fb(gPp, gPm, aP, Asum_b + Dif_b, wFpb, wUpb);
         Asum = hm + hp;
         Dif = hp - hm;
 #pragma unroll
@@ -308,7 +407,7 @@ XF_HD void face_vjp_a(const Stencil &st, const ThermoK<R> &th, const R *Fb, cons
             gp[m] = R(0.5) * (un[m] * wU[m] + a0 * wU[m]);
             gm[m] = R(0.5) * (un[m] * wU[m] - a0 * wU[m]);
         }
-        const R ha = split_weno_fb(gp, gm, a0, hb, wFb, wUb);
+        const R ha = cu6 ? split_cu6_fb(gp, gm, a0, hb, wFb, wUb) : split_weno_fb(gp, gm, a0, hb, wFb, wUb);
         ut_b[K] += ha * FbE;
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
@@ -335,7 +434,7 @@ XF_HD void face_vjp_a(const Stencil &st, const ThermoK<R> &th, const R *Fb, cons
             gp[m] = R(0.5) * (wF + a0 * wU);
             gm[m] = R(0.5) * (wF - a0 * wU);
         }
-        const R hs = split_weno_fb(gp, gm, a0, hsb, wFb, wUb);
+        const R hs = cu6 ? split_cu6_fb(gp, gm, a0, hsb, wFb, wUb) : split_weno_fb(gp, gm, a0, hsb, wFb, wUb);
         gsum += hs;
         Yt_b[s] += Asum * Fb[s];
         q2_b += hs * FbE;
@@ -528,7 +627,7 @@ XF_HD void face_vjp_b(const Stencil &st, const ThermoK<R> &th, const Out &out, c
 // read-modify-writes.  Runs of waves w and w + 1 can share up to five cells,
 // those of w and w + 2 cannot; launch `grp` takes the waves w = grp mod 6.
 // ---------------------------------------------------------------------------
-template <int NS, typename R, int HALF>
+template <int NS, typename R, int HALF, bool CU6>
 __global__ __launch_bounds__(256) void k_face_vjp_x(const double *__restrict__ U, const double *__restrict__ P,
                                                     const double *__restrict__ rbar, double *__restrict__ Ubar,
                                                     double *__restrict__ Pbar, double *__restrict__ rec,
@@ -565,10 +664,10 @@ __global__ __launch_bounds__(256) void k_face_vjp_x(const double *__restrict__ U
         if (any) {
             const long long base = row + i - 3;
             Stencil st{U, P, base, 1, C};
-            SinkLds sk{w, W, (int)(base - base0), 1, NV * W};
+            SinkLds sk{(volatile lds_double *)w, W, (int)(base - base0), 1, NV * W};
             const VjpRec<NS> rc{rec, nrec, ((long long)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x};
             if constexpr (HALF == 0)
-                face_vjp_a<NS, R, 0>(st, th, Fb, sk, rc, ds);
+                face_vjp_a<NS, R, 0, CU6>(st, th, Fb, sk, rc, ds);
             else
                 face_vjp_b<NS, R, 0>(st, th, sk, rc);
         }
@@ -596,7 +695,7 @@ __global__ __launch_bounds__(256) void k_face_vjp_x(const double *__restrict__ U
 // cotangent is the only one in flight for its cell and every cell receives
 // its contributions in a fixed order.
 // ---------------------------------------------------------------------------
-template <int NS, typename R, int DIR, int HALF>
+template <int NS, typename R, int DIR, int HALF, bool CU6>
 __global__ __launch_bounds__(256) void k_face_vjp(const double *__restrict__ U, const double *__restrict__ P,
                                                   const double *__restrict__ rbar, double *__restrict__ Ubar,
                                                   double *__restrict__ Pbar, double *__restrict__ rec, long long nrec,
@@ -630,7 +729,7 @@ __global__ __launch_bounds__(256) void k_face_vjp(const double *__restrict__ U, 
                               (blockDim.x * blockDim.y) + threadIdx.y * blockDim.x + threadIdx.x;
     const VjpRec<NS> rc{rec, nrec, tid};
     if constexpr (HALF == 0)
-        face_vjp_a<NS, R, DIR>(st, th, Fb, sk, rc, ds);
+        face_vjp_a<NS, R, DIR, CU6>(st, th, Fb, sk, rc, ds);
     else
         face_vjp_b<NS, R, DIR>(st, th, sk, rc);
 }
@@ -649,7 +748,7 @@ __global__ __launch_bounds__(256) void k_face_vjp(const double *__restrict__ U, 
 // ---------------------------------------------------------------------------
 constexpr int kVjpTX = 16, kVjpFB = 16, kVjpWin = kVjpTX * 9;
 
-template <int NS, typename R, int DIR, int HALF>
+template <int NS, typename R, int DIR, int HALF, bool CU6>
 __global__ __launch_bounds__(256) void k_face_vjp_yz(const double *__restrict__ U, const double *__restrict__ P,
                                                      const double *__restrict__ rbar, double *__restrict__ Ubar,
                                                      double *__restrict__ Pbar, double *__restrict__ rec,
@@ -694,10 +793,10 @@ __global__ __launch_bounds__(256) void k_face_vjp_yz(const double *__restrict__ 
             const long long base = col + (long long)(j - 3) * ss;
             Stencil st{U, P, base, ss, C};
             // window row r of wave w = sweep row j0 + 4w - 3 + r; stencil cell m is row ts + m
-            SinkLds sk{w, kVjpWin, ts * kVjpTX + tx, kVjpTX, NV * kVjpWin};
+            SinkLds sk{(volatile lds_double *)xf_wyz[wv], kVjpWin, ts * kVjpTX + tx, kVjpTX, NV * kVjpWin};
             const VjpRec<NS> rc{rec, nrec, (long long)(blockIdx.y * gridDim.x + blockIdx.x) * 256 + threadIdx.x};
             if constexpr (HALF == 0)
-                face_vjp_a<NS, R, DIR>(st, th, Fb, sk, rc, ds);
+                face_vjp_a<NS, R, DIR, CU6>(st, th, Fb, sk, rc, ds);
             else
                 face_vjp_b<NS, R, DIR>(st, th, sk, rc);
         }

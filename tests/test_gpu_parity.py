@@ -374,13 +374,3 @@ def test_rhs_cu6_mixed_within_fp32_bound():
     err = field_err(r_gpu, r_ora, aux["scale_llf"])
     print(f"[parity] mixed CU6 max err / S_f = {err.max():.3e}", flush=True)
     assert err.max() <= MIXED_RHS_TOL, err
-
-
-def test_vjp_refuses_cu6():
-    xf = _xf()
-    case = CASES["n1_thermal_3d"]
-    ctx = xf.Context.from_case(case).set_reconstruction("CU6")
-    U = ctx.state_from_numpy(case.U)
-    with pytest.raises(xf.XfError) as e:
-        ctx.rhs_vjp(U, torch.zeros_like(U))
-    assert e.value.code == xf.XF_EUNSUPPORTED

@@ -39,7 +39,7 @@ def _field_scale(U, grid):
     return np.abs(U[:, iz, iy, ix]).reshape(U.shape[0], -1).max(axis=1)
 
 
-def vjp_dot_check(case, precision, seed, fold=True, visc="LLF"):
+def vjp_dot_check(case, precision, seed, fold=True, visc="LLF", recon="WENO5"):
     """GPU <J^T rbar, w> versus oracle <rbar, J w> by complex step.
     fold=True: J of L(G(U)) w.r.t. interior U; fold=False: J of L(U) with
     ghost values as independent inputs (U's ghosts already hold values)."""
@@ -47,7 +47,7 @@ def vjp_dot_check(case, precision, seed, fold=True, visc="LLF"):
     th, g = oracle_objects(case)
     rng = np.random.default_rng(seed)
     Ubase = O.fill_ghosts(g, case.U) if fold else case.U
-    r0, aux = O.rhs(th, g, Ubase, return_aux=True, visc=visc)
+    r0, aux = O.rhs(th, g, Ubase, return_aux=True, visc=visc, recon=recon)
     sc = np.where(aux["scale"] > 0, aux["scale"], 1.0)
     rbar = interior_random(case.U.shape, g, rng, 1.0 / sc)
     fs = _field_scale(Ubase, g)
@@ -59,12 +59,12 @@ def vjp_dot_check(case, precision, seed, fold=True, visc="LLF"):
         w[:, mask] = rng.standard_normal((case.U.shape[0], mask.sum())) * fs[:, None]
     h = 1e-30
     Uc = Ubase + 1j * h * w
-    rc = O.rhs(th, g, O.fill_ghosts(g, Uc) if fold else Uc, visc=visc)
+    rc = O.rhs(th, g, O.fill_ghosts(g, Uc) if fold else Uc, visc=visc, recon=recon)
     terms = rbar * rc.imag / h
     ref = np.sum(terms)
     mag = np.sum(np.abs(terms))
 
-    ctx = xf.Context.from_case(case, precision).set_dissipation(visc)
+    ctx = xf.Context.from_case(case, precision).set_dissipation(visc).set_reconstruction(recon)
     U = ctx.state_from_numpy(Ubase)
     if fold:
         ctx.fill_ghosts(U)
@@ -302,4 +302,37 @@ def test_vjp_dissipation_variants_match_complex_step(name, visc):
     step holds them fixed too: both are computed from real parts)"""
     got, ref, mag = vjp_dot_check(VJP_CASES[name](), "fp64", 61, visc=visc)
     print(f"[vjp] {name} {visc} rel err {abs(got - ref) / mag:.3e}", flush=True)
+    assert abs(got - ref) <= 1e-12 * mag
+
+
+@pytest.mark.parametrize("name", ["n3_outflow_x", "n9_periodic", "plane2d_n2"])
+def test_vjp_cu6_matches_complex_step(name):
+    """the WENO-CU6 adjoint (its weights differentiated through beta6 and
+    tau6) against the oracle's complex step"""
+    got, ref, mag = vjp_dot_check(VJP_CASES[name](), "fp64", 71, recon="CU6")
+    print(f"[vjp] {name} CU6 rel err {abs(got - ref) / mag:.3e}", flush=True)
+    assert abs(got - ref) <= 1e-12 * mag
+
+
+def test_rk3_step_vjp_cu6_glf():
+    """one RK3-step adjoint with WENO-CU6 and GLF speeds against the oracle's
+    complex step through the same step"""
+    xf = _xf()
+    case = VJP_CASES["n3_outflow_x"]()
+    th, g = oracle_objects(case)
+    rng = np.random.default_rng(81)
+    U0 = O.fill_ghosts(g, case.U)
+    dt = 0.4 * O.cfl_dt(th, g, U0, 0.5)
+    lam = interior_random(case.U.shape, g, rng, 1.0 / _field_scale(U0, g))
+    w = interior_random(case.U.shape, g, rng, _field_scale(U0, g))
+    h = 1e-30
+    Uc = O.rk3_step(th, g, U0 + 1j * h * w, dt, visc="GLF", recon="CU6")
+    terms = lam * Uc.imag / h
+    ref, mag = np.sum(terms), np.sum(np.abs(terms))
+    ctx = xf.Context.from_case(case).set_dissipation("GLF").set_reconstruction("CU6")
+    Ut = ctx.state_from_numpy(U0)
+    lt = ctx.state_from_numpy(lam)
+    ctx.rk3_step_vjp(Ut, dt, lt)
+    got = float(np.sum(lt.cpu().numpy() * w))
+    print(f"[vjp] rk3 step CU6+GLF rel err {abs(got - ref) / mag:.3e}", flush=True)
     assert abs(got - ref) <= 1e-12 * mag
