@@ -12,6 +12,7 @@ What it computes, in the paper's order and notation (Sec. II.C):
   * per-face Roe-averaged eigensystem Lambda = L A R           (Sec. II.C.1, text of Eq. 13-15)
   * characteristic flux splitting F_m^pm = 1/2 L (F_m +- Lam U_m)  (Eq. 14)
   * WENO5-JS reconstruction and back-projection F^ = R (F+ + F-)   (Eq. 15)
+    (or the scheme's other REC options: WENO-CU6, WENO7-JS)
   * conservative flux difference (F^_{i+1/2} - F^_{i-1/2}) / dx    (Eq. 13)
   * SSP-RK3 time march                                          (Eq. 16)
   * CFL time step lambda = dt/dx = CFL / Lambda                 (Eq. 17)
@@ -27,7 +28,8 @@ complex-step derivative automatically holds the LLF wave speeds fixed.
 Readings of points the paper leaves open (each is stated where it is used):
   * Roe average: sqrt(rho) weights on u, H, Y_s and T; the face sound speed is
     defined by the pressure-derivative identity so that L R = I exactly.
-  * LLF: component-wise wave speed, the max over the 6 stencil cells of the
+  * LLF: component-wise wave speed, the max over the stencil cells (six, or
+    eight for WENO7) of the
     cell eigenvalue |u_n - c|, |u_n| or |u_n + c| of that characteristic field;
     ROE: |u~_n - c~|, |u~_n|, |u~_n + c~| of the face's Roe state; GLF: the
     largest LLF speed of the field over all faces of the direction.
@@ -36,7 +38,8 @@ Readings of points the paper leaves open (each is stated where it is used):
   * Finite-difference point values (Shu-Osher flux splitting), cell centres at
     (i + 1/2) dx.
   * WENO5-JS with d = (1/10, 6/10, 3/10), p = 2, absolute eps = 1e-6;
-    WENO-CU6 (the paper's other six-cell option) as stated at weno_cu6.
+    WENO-CU6 (the paper's other six-cell option) as stated at weno_cu6;
+    WENO7-JS (eight-cell stencils, 4 ghost layers) as stated at weno7.
   * Eq. 21 calls C_v the constant-pressure heat capacity; it is the
     constant-volume one (C_v = sum Y_s C_p,s - Rbar, as the same equation says).
   * Eq. 17 writes U^{n+1} = U^n + lambda (F_{i+1/2} - F_{i-1/2}); the residual
@@ -73,8 +76,10 @@ BC_OUTFLOW = 1
 # ---------------------------------------------------------------------------
 @dataclass
 class Grid:
-    """Uniform Cartesian grid with 3 ghost layers in every active dimension
-    (the block/halo layout of Sec. III.A, Fig. 3).  bc = (-x,+x,-y,+y,-z,+z)."""
+    """Uniform Cartesian grid with ng ghost layers in every active dimension
+    (the block/halo layout of Sec. III.A, Fig. 3): 3 for the six-cell
+    stencils of WENO5 and WENO-CU6, 4 for the eight-cell stencils of WENO7.
+    bc = (-x,+x,-y,+y,-z,+z)."""
     nx: int
     ny: int
     nz: int
@@ -82,6 +87,7 @@ class Grid:
     dy: float
     dz: float
     bc: tuple = (0, 0, 0, 0, 0, 0)
+    ng: int = 3
 
     @property
     def n(self):
@@ -93,7 +99,7 @@ class Grid:
 
     def g(self, axis):
         """ghost width of spatial axis 0=x,1=y,2=z"""
-        return 3 if self.n[axis] > 1 else 0
+        return self.ng if self.n[axis] > 1 else 0
 
     def active(self):
         return [a for a in range(3) if self.n[a] > 1]
@@ -476,16 +482,21 @@ CU6_PARTS = smoothness_parts(range(-2, 4))
 CU6_B6 = smoothness_form(range(-2, 4))
 
 
+def smoothness_gram(parts, w):
+    """sum over the parts (D_l, G_l) of (D_l w)^T G_l (D_l w) for values w
+    (n, ...): the indicator as a sum of positive Gram forms"""
+    out = 0.0
+    for D, G in parts:
+        Dw = np.einsum("kj,j...->k...", D, w)
+        out = out + np.einsum("k...,kj,j...->...", Dw, G, Dw)
+    return out
+
+
 def smoothness6(v):
     """beta of the six-cell quintic for values v (6, ...): the data are first
     shifted by the centre value (beta ignores constants), then the positive
     Gram forms of the derivatives are summed, so no large terms cancel"""
-    w = v - v[2]
-    out = 0.0
-    for D, G in CU6_PARTS:
-        Dw = np.einsum("kj,j...->k...", D, w)
-        out = out + np.einsum("k...,kj,j...->...", Dw, G, Dw)
-    return out
+    return smoothness_gram(CU6_PARTS, v - v[2])
 
 
 def weno_cu6(a, b, c, d, e, f):
@@ -511,7 +522,56 @@ def weno_cu6(a, b, c, d, e, f):
     return (al[0] / s) * q0 + (al[1] / s) * q1 + (al[2] / s) * q2 + (al[3] / s) * q3
 
 
-RECON_TYPES = ("WENO5", "CU6")
+# ---------------------------------------------------------------------------
+# WENO7: the seventh-order WENO-JS the paper also offers as REC in Eq. 15
+# (Balsara and Shu's extension of the Jiang-Shu weights to four cubic
+# sub-stencils; the paper restates none of its formulas)
+# ---------------------------------------------------------------------------
+WENO7_D = (1.0 / 35.0, 12.0 / 35.0, 18.0 / 35.0, 4.0 / 35.0)
+WENO7_PARTS = [smoothness_parts(range(k - 3, k + 1)) for k in range(4)]
+
+
+def weno7_candidates(a, b, c, d, e, f, g):
+    """The four fourth-order candidate values at the right edge of the cell
+    holding d (cell i), from the sub-stencils of cells i-3..i, i-2..i+1,
+    i-1..i+2 and i..i+3: the value at x_{i+1/2} of the cubic whose cell
+    averages are the data."""
+    q0 = (-3.0 * a + 13.0 * b - 23.0 * c + 25.0 * d) / 12.0
+    q1 = (b - 5.0 * c + 13.0 * d + 3.0 * e) / 12.0
+    q2 = (-c + 7.0 * d + 7.0 * e - f) / 12.0
+    q3 = (3.0 * d + 13.0 * e - 5.0 * f + g) / 12.0
+    return q0, q1, q2, q3
+
+
+def weno7_smoothness(a, b, c, d, e, f, g):
+    """Jiang-Shu indicators of the four cubic sub-stencils (the integral
+    definition, as positive Gram forms of data shifted by the value of cell i,
+    which lies in every sub-stencil)"""
+    v = np.stack(np.broadcast_arrays(a, b, c, d, e, f, g), axis=0)
+    w = v - v[3]
+    return tuple(smoothness_gram(WENO7_PARTS[k], w[k:k + 4]) for k in range(4))
+
+
+def weno7(a, b, c, d, e, f, g):
+    """Seventh-order WENO-JS value at the right edge of the cell holding d,
+    from the seven point values a..g (cells i-3..i+3): alpha_k = d_k /
+    (eps + beta_k)^2 with linear weights (1, 12, 18, 4)/35, which combine the
+    four candidates into the seven-cell value, and absolute eps = 1e-6 as in
+    the WENO5 reading; result sum_k alpha_k q_k / sum_k alpha_k."""
+    q = weno7_candidates(a, b, c, d, e, f, g)
+    beta = weno7_smoothness(a, b, c, d, e, f, g)
+    al = [WENO7_D[k] / (WENO_EPS + beta[k]) ** 2 for k in range(4)]
+    s = al[0] + al[1] + al[2] + al[3]
+    return (al[0] / s) * q[0] + (al[1] / s) * q[1] + (al[2] / s) * q[2] + (al[3] / s) * q[3]
+
+
+RECON_TYPES = ("WENO5", "CU6", "WENO7")
+
+
+def stencil_radius(recon):
+    """half width of the stencil of one face: 3 (six cells i-2..i+3) for
+    WENO5 and WENO-CU6, 4 (eight cells i-3..i+4) for WENO7"""
+    return 4 if recon == "WENO7" else 3
 
 
 # ---------------------------------------------------------------------------
@@ -532,11 +592,13 @@ VISC_TYPES = ("LLF", "ROE", "GLF")
 
 
 def face_flux(th, d, Ust, Pst, alpha=None, visc="LLF", recon="WENO5"):
-    """Numerical flux at faces i+1/2 from the 6-cell stencils m = i-2..i+3.
+    """Numerical flux at faces i+1/2 from the stencils of 2r cells
+    m = i-r+1..i+r (r = stencil_radius(recon): six cells i-2..i+3 for WENO5
+    and CU6, eight cells i-3..i+4 for WENO7).
 
-    Ust: (Nv, 6, F) conservative values of the stencil cells (slot 2 = cell i,
-    slot 3 = cell i+1); Pst: primitives of the same cells (values (6, F); u
-    (3, 6, F); Y (6, F, ns)).  alpha, if given, is the (Nv, F) array of
+    Ust: (Nv, 2r, F) conservative values of the stencil cells (slot r-1 =
+    cell i, slot r = cell i+1); Pst: primitives of the same cells (values
+    (2r, F); u (3, 2r, F); Y (2r, F, ns)).  alpha, if given, is the (Nv, F) array of
     wave speeds to use instead of computing them (a frozen dissipation; the
     global GLF speeds arrive this way).  visc: the artificial viscosity of
     Eq. 14 (Table I): "LLF" as below, or "ROE", |lambda_n| of the face's Roe
@@ -544,12 +606,14 @@ def face_flux(th, d, Ust, Pst, alpha=None, visc="LLF", recon="WENO5"):
     Returns (Fhat (Nv, F), alpha (Nv, F), c2 of the Roe state (F,)).
 
     Steps: Roe state of cells i, i+1; dense L, R; component-wise LLF speed
-    alpha_n = max_m |lambda_n(U_m)| over the 6 cells; F_m^pm = 1/2 L (F_m +-
-    alpha U_m) (Eq. 14); plus side from m = i-2..i+2, minus side mirrored from
-    m = i+3..i-1; Fhat = R (F^+ + F^-) (Eq. 15)."""
+    alpha_n = max_m |lambda_n(U_m)| over the stencil's cells; F_m^pm = 1/2 L
+    (F_m +- alpha U_m) (Eq. 14); plus side from the 2r - 1 cells m <= i+r-1,
+    minus side mirrored from m = i+r..i-r+2; Fhat = R (F^+ + F^-) (Eq. 15)."""
     nv = th.ns + 4
-    pL = _take(Pst, 2)
-    pR = _take(Pst, 3)
+    r = stencil_radius(recon)
+    assert Ust.shape[1] == 2 * r, (Ust.shape, recon)
+    pL = _take(Pst, r - 1)
+    pR = _take(Pst, r)
     roe = roe_state(th, pL, pR)
     L = eigen_L(th, roe, d)          # (F, nv, nv)
     R = eigen_R(th, roe, d)
@@ -557,9 +621,9 @@ def face_flux(th, d, Ust, Pst, alpha=None, visc="LLF", recon="WENO5"):
         un, c = roe["u"][d], roe["c"]
         alpha = np.abs(np.stack([un - c] + [un] * (nv - 2) + [un + c], axis=0).real)
     elif alpha is None:
-        lam = eigenvalues(th, Pst, d)            # (nv, 6, F)
+        lam = eigenvalues(th, Pst, d)            # (nv, 2r, F)
         alpha = np.max(np.abs(lam.real), axis=1)  # (nv, F)
-    Fm = physical_flux(th, Ust, Pst, d)          # (nv, 6, F)
+    Fm = physical_flux(th, Ust, Pst, d)          # (nv, 2r, F)
     # characteristic projections, dense: f[m, F, n] = sum_j L[F, n, j] Fm[j, m, F]
     f = np.einsum("Fnj,jmF->mFn", L, Fm)
     v = np.einsum("Fnj,jmF->mFn", L, Ust)
@@ -569,6 +633,9 @@ def face_flux(th, d, Ust, Pst, alpha=None, visc="LLF", recon="WENO5"):
     if recon == "CU6":
         hp = weno_cu6(gp[0], gp[1], gp[2], gp[3], gp[4], gp[5])
         hm = weno_cu6(gm[5], gm[4], gm[3], gm[2], gm[1], gm[0])
+    elif recon == "WENO7":
+        hp = weno7(gp[0], gp[1], gp[2], gp[3], gp[4], gp[5], gp[6])
+        hm = weno7(gm[7], gm[6], gm[5], gm[4], gm[3], gm[2], gm[1])
     else:
         hp = weno5(gp[0], gp[1], gp[2], gp[3], gp[4])
         hm = weno5(gm[5], gm[4], gm[3], gm[2], gm[1])
@@ -585,9 +652,11 @@ PP_Y_FLOOR = 1e-13     # partial densities may reach -1e-13 rho of their own cel
 
 def lax_friedrichs_flux(th, d, Ust, Pst, lf):
     """Eq. 19 at faces i+1/2: 1/2 [F(U_i) + F(U_i+1) + lf (U_i - U_i+1)],
-    U_i, U_i+1 the stencil slots 2 and 3; lf (F,) the dissipation coefficient."""
+    U_i, U_i+1 the stencil's two middle slots; lf (F,) the dissipation
+    coefficient."""
     Fm = physical_flux(th, Ust, Pst, d)
-    return 0.5 * (Fm[:, 2] + Fm[:, 3] + lf * (Ust[:, 2] - Ust[:, 3]))
+    r = Ust.shape[1] // 2
+    return 0.5 * (Fm[:, r - 1] + Fm[:, r] + lf * (Ust[:, r - 1] - Ust[:, r]))
 
 
 def positivity_limit(th, d, Ust, Pst, Fhat, alpha, lam):
@@ -610,7 +679,7 @@ def positivity_limit(th, d, Ust, Pst, Fhat, alpha, lam):
         the half-states of both neighbouring cells stay at or above the floor;
         the face's theta is the minimum over components and both cells, and
         theta = 1 leaves F^ untouched.
-    Ust (Nv, 6, F), Pst as in face_flux; Fhat (Nv, F); alpha (Nv, F) the
+    Ust (Nv, 2r, F), Pst as in face_flux; Fhat (Nv, F); alpha (Nv, F) the
     face's LLF speeds (rows u-c, ..., u+c); lam a scalar.
     Returns (Fstar (Nv, F), theta (F,))."""
     ns = th.ns
@@ -620,7 +689,8 @@ def positivity_limit(th, d, Ust, Pst, Fhat, alpha, lam):
     def comps(V):                      # rows: rho, rho_1 .. rho_ns
         return np.concatenate([V[:ns].sum(axis=0, keepdims=True), V[:ns]], axis=0)
 
-    qL, qR = comps(Ust[:, 2]), comps(Ust[:, 3])
+    r = Ust.shape[1] // 2
+    qL, qR = comps(Ust[:, r - 1]), comps(Ust[:, r])
     qH, qLF = comps(Fhat), comps(FLF)
     rhoL, rhoR = qL[0].real, qR[0].real
     floor_rho = PP_RHO_FLOOR * np.minimum(rhoL, rhoR)
@@ -638,10 +708,10 @@ def positivity_limit(th, d, Ust, Pst, Fhat, alpha, lam):
     return Fstar, theta
 
 
-def _stencils(Q, axis, g, n):
-    """the six stencil slices along `axis` for faces k = 0..n (face k lies
-    between padded cells g+k-1 and g+k)"""
-    return np.stack([np.take(Q, np.arange(g - 3 + m, g - 2 + m + n), axis=axis) for m in range(6)],
+def _stencils(Q, axis, g, n, r=3):
+    """the 2r stencil slices along `axis` for faces k = 0..n (face k lies
+    between padded cells g+k-1 and g+k; slot m holds cell g+k-r+m)"""
+    return np.stack([np.take(Q, np.arange(g - r + m, g - r + m + n + 1), axis=axis) for m in range(2 * r)],
                     axis=0)
 
 
@@ -656,9 +726,12 @@ def rhs(th, grid, U, alpha=None, return_aux=False, pp_dt=None, visc="LLF", recon
     (Table I).  Reading of GLF: per direction and characteristic field, the
     largest LLF speed over all faces of that direction (the device-wide
     maximum the paper reduces across processes).  recon: "WENO5" (WENO5-JS
-    on the five cells of each side) or "CU6" (WENO-CU6 on all six)."""
+    on the five cells of each side), "CU6" (WENO-CU6 on all six) or "WENO7"
+    (WENO7-JS on seven of eight cells; needs a grid with 4 ghost layers)."""
     assert visc in VISC_TYPES, visc
     assert recon in RECON_TYPES, recon
+    r = stencil_radius(recon)
+    assert grid.ng >= r, (grid.ng, recon)
     nv = th.ns + 4
     assert U.shape == (nv,) + grid.padded, (U.shape, grid.padded)
     with np.errstate(all="ignore"):
@@ -696,25 +769,26 @@ def rhs(th, grid, U, alpha=None, return_aux=False, pp_dt=None, visc="LLF", recon
                 Pd[k] = v[sl + (slice(None),)]
             else:
                 Pd[k] = v[sl]
-        # stencils: (6, ...) with the face index along the sweep axis
-        Ust = _stencils(Ud, ax + 1, g, n)               # (6, nv, z', y', x'')
+        # stencils: (2r, ...) with the face index along the sweep axis
+        W = 2 * r
+        Ust = _stencils(Ud, ax + 1, g, n, r)            # (2r, nv, z', y', x'')
         tshape = Ust.shape[2:]
         nf = int(np.prod(tshape))
-        Ust = np.moveaxis(Ust, 0, 1).reshape(nv, 6, nf)
+        Ust = np.moveaxis(Ust, 0, 1).reshape(nv, W, nf)
         Pst = {}
         for k, v in Pd.items():
             if k == "u":
-                s = _stencils(v, ax + 1, g, n)          # (6, 3, ...)
-                Pst[k] = np.moveaxis(s, 0, 1).reshape(3, 6, nf)
+                s = _stencils(v, ax + 1, g, n, r)       # (2r, 3, ...)
+                Pst[k] = np.moveaxis(s, 0, 1).reshape(3, W, nf)
             elif k == "Y":
-                s = _stencils(v, ax, g, n)              # (6, ..., ns)
-                Pst[k] = s.reshape(6, nf, th.ns)
+                s = _stencils(v, ax, g, n, r)           # (2r, ..., ns)
+                Pst[k] = s.reshape(W, nf, th.ns)
             else:
-                s = _stencils(v, ax, g, n)
-                Pst[k] = s.reshape(6, nf)
+                s = _stencils(v, ax, g, n, r)
+                Pst[k] = s.reshape(W, nf)
         a_in = None if alpha is None else alpha[d]
         if a_in is None and visc == "GLF":
-            lam_c = eigenvalues(th, Pst, d)                           # (nv, 6, F)
+            lam_c = eigenvalues(th, Pst, d)                           # (nv, 2r, F)
             glf = np.max(np.abs(lam_c.real), axis=(1, 2))             # (nv,)
             a_in = np.broadcast_to(glf[:, None], (nv, nf)).copy()
         with np.errstate(all="ignore"):
@@ -761,11 +835,14 @@ def dissipation_scale(th, grid, U, prim=None):
     return v[:, iz, iy, ix].reshape(U.shape[0], -1).max(axis=1)
 
 
-def rhs_at(th, grid, U, cells, return_fmax=False):
+def rhs_at(th, grid, U, cells, return_fmax=False, recon="WENO5"):
     """L(U) at selected interior cells only.  cells: (K, 3) integer array of
     interior indices (i, j, k) = (x, y, z).  Computes the two faces of each
-    cell in every active direction from their own stencils.  Returns (Nv, K)
-    and, with return_fmax, the per-field max |F^| over those faces."""
+    cell in every active direction from their own stencils (LLF speeds).
+    Returns (Nv, K) and, with return_fmax, the per-field max |F^| over those
+    faces."""
+    r = stencil_radius(recon)
+    assert grid.ng >= r, (grid.ng, recon)
     cells = np.asarray(cells, dtype=np.int64).reshape(-1, 3)
     nv = th.ns + 4
     K = len(cells)
@@ -779,15 +856,15 @@ def rhs_at(th, grid, U, cells, return_fmax=False):
         fl = []
         for side in (0, 1):                      # face i-1/2, then i+1/2
             idx = []
-            for m in range(6):
-                off = side - 3 + m               # stencil of face between cells (side-1) and side
+            for m in range(2 * r):
+                off = side - r + m               # stencil of face between cells (side-1) and side
                 idx.append((pz + off * unit[2], py + off * unit[1], px + off * unit[0]))
-            Ust = np.stack([U[:, z, y, x] for (z, y, x) in idx], axis=1)   # (nv, 6, K)
+            Ust = np.stack([U[:, z, y, x] for (z, y, x) in idx], axis=1)   # (nv, 2r, K)
             with np.errstate(all="ignore"):
                 P = primitives(th, Ust)
             Pst = {k: v for k, v in P.items() if k != "flags"}
             with np.errstate(all="ignore"):
-                Fh, _, _ = face_flux(th, d, Ust, Pst)
+                Fh, _, _ = face_flux(th, d, Ust, Pst, recon=recon)
             fl.append(Fh)
             fmax = np.maximum(fmax, np.max(np.abs(Fh.real), axis=1))
         out -= (fl[1] - fl[0]) / grid.d[d]
@@ -798,7 +875,7 @@ def rhs_at(th, grid, U, cells, return_fmax=False):
 # boundary ghosts, CFL and SSP-RK3
 # ---------------------------------------------------------------------------
 def fill_ghosts(grid, U):
-    """Fill 3 ghost layers per active side (boundary conditions of Sec. III.B.4):
+    """Fill the ghost layers of every active side (boundary conditions of Sec. III.B.4):
     periodic = wrap-around copy of the opposite interior layers; outflow =
     zero-gradient copy of the nearest interior cell.  Dimensions are filled in
     the order x, y, z over the whole padded extent of the other axes, so edge
@@ -806,7 +883,7 @@ def fill_ghosts(grid, U):
     U = np.array(U, copy=True)
     for d in grid.active():
         ax = 3 - d                     # array axis of direction d in (nv, z, y, x)
-        g, n = 3, grid.n[d]
+        g, n = grid.g(d), grid.n[d]
         for side in (0, 1):
             bc = grid.bc[2 * d + side]
             for layer in range(g):

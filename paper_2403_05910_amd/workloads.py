@@ -12,7 +12,8 @@ Rankine-Hugoniot post-shock state).  Everything is synthetic and seeded; the
 paper's own thermo data, mechanisms and reference solutions are not used.
 
 Conventions: padded arrays of shape (Nv, Z, Y, X) with 3 ghost layers per
-active dimension (ghost values left at zero: the caller fills them), fields in
+active dimension (Case.with_ghosts gives another width; ghost values are left
+at zero: the caller fills them), fields in
 order rho Y_1..rho Y_N, rho u, rho v, rho w, rho E, SI units.
 """
 from __future__ import annotations
@@ -50,6 +51,24 @@ class Case:
     @property
     def cells(self):
         return int(np.prod(self.n))
+
+    @property
+    def ng(self):
+        """ghost layers per active dimension of U (3 while U is unset)"""
+        if self.U is None:
+            return 3
+        k = next(a for a in range(3) if self.n[a] > 1)
+        return (self.U.shape[3 - k] - self.n[k]) // 2
+
+    def with_ghosts(self, ng):
+        """the same case in a layout with ng ghost layers per active dimension
+        (interior copied, ghosts zero)"""
+        g0 = self.ng
+        U, g = _padded(self.n, self.U.shape[0], ng)
+        nx, ny, nz = self.n
+        gz, gy, gx = (g0 if nz > 1 else 0), (g0 if ny > 1 else 0), (g0 if nx > 1 else 0)
+        _place(U, g, self.U[:, gz:gz + nz, gy:gy + ny, gx:gx + nx])
+        return Case(self.name, self.n, self.d, self.bc, self.thermo, U, dict(self.meta))
 
 
 # ---------------------------------------------------------------------------
@@ -130,8 +149,8 @@ def frozen_sound_speed(tab, Y, T):
     return np.sqrt((1.0 + Rbar / cv) * Rbar * T)
 
 
-def _padded(n, nv):
-    g = [3 if k > 1 else 0 for k in n]
+def _padded(n, nv, ng=3):
+    g = [ng if k > 1 else 0 for k in n]
     shape = (nv, n[2] + 2 * g[2], n[1] + 2 * g[1], n[0] + 2 * g[0])
     return np.zeros(shape), g
 

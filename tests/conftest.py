@@ -18,7 +18,7 @@ def oracle_objects(case):
     """oracle Thermo and Grid for a workloads.Case"""
     import oracle as O
     th = O.Thermo(case.thermo.W, case.thermo.a, case.thermo.T_lo, case.thermo.T_hi)
-    g = O.Grid(case.n[0], case.n[1], case.n[2], case.d[0], case.d[1], case.d[2], tuple(case.bc))
+    g = O.Grid(case.n[0], case.n[1], case.n[2], case.d[0], case.d[1], case.d[2], tuple(case.bc), case.ng)
     return th, g
 
 

@@ -238,3 +238,52 @@ def test_cu6_downwind_candidate_sign_caught(monkeypatch):
     _patch(monkeypatch, "weno_cu6", bad)
     assert _fails(CU.test_sixth_order_on_smooth_data)
     assert _fails(CU.test_cu6_advected_wave_converges)
+
+
+# -- WENO7 (pins in test_oracle_weno7.py) -------------------------------------
+import test_oracle_weno7 as W7  # noqa: E402
+
+
+def test_weno7_swapped_linear_weights_caught(monkeypatch, rng):
+    _patch(monkeypatch, "WENO7_D", (4.0 / 35.0, 18.0 / 35.0, 12.0 / 35.0, 1.0 / 35.0))
+    assert _fails(W7.test_linear_weights_exact_on_sextics, rng)
+    assert _fails(W7.test_seventh_order_on_smooth_data)
+
+
+def test_weno7_candidate_coefficient_caught(monkeypatch, rng):
+    orig = X.weno7_candidates
+
+    def bad(a, b, c, d, e, f, g):
+        q0, q1, q2, q3 = orig(a, b, c, d, e, f, g)
+        return q0, q1, q2 + (c - e) / 12.0, q3                # planted: -c + 7d + 7e - f -> 7d + 6e - f
+    _patch(monkeypatch, "weno7_candidates", bad)
+    assert _fails(W7.test_candidates_exact_on_cubics, rng)
+    assert _fails(W7.test_weno7_advected_wave_converges)
+
+
+def test_weno7_shifted_indicator_stencil_caught(monkeypatch, rng):
+    # planted: the indicator forms built on sub-stencils one cell to the right
+    _patch(monkeypatch, "WENO7_PARTS", [X.smoothness_parts(range(k - 2, k + 2)) for k in range(4)])
+    assert _fails(W7.test_indicators_equal_quadrature_of_a_known_cubic, rng)
+
+
+def test_weno7_mirrored_minus_side_caught(monkeypatch, rng):
+    # planted: the minus side read in the plus side's order (not mirrored)
+    orig = X.weno7
+
+    def flux(th, d, Ust, Pst, alpha=None, visc="LLF", recon="WENO5"):
+        if recon != "WENO7":
+            return orig_ff(th, d, Ust, Pst, alpha, visc, recon)
+        calls = []
+
+        def w(*v):
+            calls.append(1)
+            return orig(*v) if len(calls) % 2 else orig(*v[::-1])
+        monkeypatch.setattr(X, "weno7", w)
+        try:
+            return orig_ff(th, d, Ust, Pst, alpha, visc, recon)
+        finally:
+            monkeypatch.setattr(X, "weno7", orig)
+    orig_ff = X.face_flux
+    _patch(monkeypatch, "face_flux", flux)
+    assert _fails(W7.test_weno7_advected_wave_converges)
