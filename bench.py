@@ -319,11 +319,19 @@ def main():
         ctxp.close()
         del Up
         # the paper's other scheme options on the same FP64 step: ROE and GLF
-        # artificial viscosity, WENO-CU6 reconstruction
+        # artificial viscosity, WENO-CU6 and WENO7 reconstruction (WENO7 on the
+        # same state laid out with four ghost layers)
         out["scheme_options"] = {}
-        for label, visc, recon in (("ROE", "ROE", "WENO5"), ("GLF", "GLF", "WENO5"), ("CU6", "LLF", "CU6")):
-            ctxo = xf.Context.from_case(case, "fp64").set_dissipation(visc).set_reconstruction(recon)
-            Uo = U0.clone()
+        for label, visc, recon in (("ROE", "ROE", "WENO5"), ("GLF", "GLF", "WENO5"), ("CU6", "LLF", "CU6"),
+                                   ("WENO7", "LLF", "WENO7")):
+            if recon == "WENO7":
+                case4 = case.with_ghosts(4)
+                ctxo = xf.Context.from_case(case4, "fp64").set_reconstruction(recon)
+                Uo = ctxo.state_from_numpy(case4.U)
+                del case4
+            else:
+                ctxo = xf.Context.from_case(case, "fp64").set_dissipation(visc).set_reconstruction(recon)
+                Uo = U0.clone()
             ctxo.fill_ghosts(Uo)
             run_steps(ctxo, Uo, dt_dev, 1, a.cfl)
             torch.cuda.synchronize()

@@ -80,7 +80,8 @@ enum {
 
 /* Uniform Cartesian grid (Sec. III.A, Fig. 3).  1 <= n_d <= 65535 (the
  * launch grids put single axes on the y and z grid dimensions); a dimension
- * with n_d > 1 needs n_d >= 3.  bc order: -x, +x, -y, +y, -z, +z; XF_BC_PERIODIC
+ * with n_d > 1 needs n_d >= the ghost width (3, or 4 for xf_create_ghosts
+ * with 4).  bc order: -x, +x, -y, +y, -z, +z; XF_BC_PERIODIC
  * wraps, XF_BC_OUTFLOW copies the nearest interior cell (zero gradient).
  * Periodic sides must come in pairs. */
 typedef struct {
@@ -111,13 +112,23 @@ typedef struct {
 int xf_create(const xf_grid *grid, const xf_thermo *thermo, int precision, xf_ctx **out);
 int xf_destroy(xf_ctx *ctx);
 
+/* xf_create with a chosen ghost width: the number of ghost layers on each
+ * side of every active dimension of the padded state (the halo of Fig. 3).
+ * ghost_width 3 (what xf_create uses) serves the six-cell face stencils of
+ * WENO5 and WENO-CU6; 4 is needed by the eight-cell stencils of WENO7
+ * (XF_RECON_WENO7) and serves the six-cell schemes too, with identical
+ * results.  Every padded array of the context (state, rhs, cotangents,
+ * primitives) takes this width.  Returns XF_EINVAL for another width. */
+int xf_create_ghosts(const xf_grid *grid, const xf_thermo *thermo, int precision, int ghost_width,
+                     xf_ctx **out);
+
 /* Number of doubles in one padded state: Nv * Z * Y * X. */
 size_t xf_state_elems(const xf_ctx *ctx);
 
 /* Bytes of device workspace needed by an operation (XF_OP_*). */
 size_t xf_workspace_bytes(const xf_ctx *ctx, int op);
 
-/* Fill the 3 ghost layers of every active side of U in place: periodic wrap
+/* Fill the ghost layers of every active side of U in place: periodic wrap
  * or zero-gradient outflow (the boundary treatment of Sec. III.B.4), for all
  * fields; dimensions in the order x, y, z over the full padded extent of the
  * other axes, so edges and corners are filled consistently. */
@@ -152,7 +163,8 @@ int xf_rk3_step(xf_ctx *ctx, double *U, double dt, const double *dt_dev, void *w
 
 /* Artificial viscosity of the flux splitting of Eq. 14 (the options of
  * Table I): XF_VISC_LLF (default), per face and characteristic field the
- * largest |lambda| of the field over the six stencil cells; XF_VISC_ROE,
+ * largest |lambda| of the field over the stencil cells (six, or eight for
+ * WENO7); XF_VISC_ROE,
  * |lambda| of the face's Roe state (u~_n - c~, u~_n, u~_n + c~), no entropy
  * fix; XF_VISC_GLF, per direction and field the largest LLF speed over all
  * faces of the direction, reduced on the device after every primitive pass.
@@ -168,10 +180,15 @@ int xf_set_dissipation(xf_ctx *ctx, int type);
  * stencil cells, the downwind one (11 f_i+1 - 7 f_i+2 + 2 f_i+3)/6, linear
  * weights (1, 9, 9, 1)/20, alpha_k = d_k (20 + tau6 / (beta_k + 1e-6)),
  * beta_3 = beta6 the Jiang-Shu smoothness of the six-cell quintic,
- * tau6 = beta6 - (beta_0 + 4 beta_1 + beta_2)/6).  Applies to every later
- * call, the VJPs included (they differentiate the chosen reconstruction with
- * the dissipation speeds held fixed).  Returns XF_EINVAL for another type. */
-enum { XF_RECON_WENO5 = 0, XF_RECON_CU6 = 1 };
+ * tau6 = beta6 - (beta_0 + 4 beta_1 + beta_2)/6), or XF_RECON_WENO7, the
+ * seventh-order WENO-JS (four cubic candidates on cells i-3..i+3 for the
+ * plus side and i+4..i-2 for the minus side, linear weights
+ * (1, 12, 18, 4)/35, alpha_k = d_k / (1e-6 + beta_k)^2), which needs a
+ * context with 4 ghost layers (XF_EUNSUPPORTED otherwise).  Applies to
+ * every later call; the VJPs differentiate WENO5 and CU6 with the
+ * dissipation speeds held fixed and return XF_EUNSUPPORTED for WENO7.
+ * Returns XF_EINVAL for another type. */
+enum { XF_RECON_WENO5 = 0, XF_RECON_CU6 = 1, XF_RECON_WENO7 = 2 };
 int xf_set_reconstruction(xf_ctx *ctx, int type);
 
 /* Positivity-preserving flux blend (Sec. II.C.2, Eq. 17-20) in the SSP-RK3

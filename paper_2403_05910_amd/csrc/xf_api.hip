@@ -246,13 +246,13 @@ hipError_t fill_vjp(xf_ctx *c, double *Ub, hipStream_t s) {
     return timed(c, XF_K_FILL_VJP, s, [&] { return xf::launch_fill_ghosts_vjp(c->lc, c->nv, Ub, s); });
 }
 
-bool grid_ok(const xf_grid *g) {
+bool grid_ok(const xf_grid *g, int ng) {
     const int n[3] = {g->nx, g->ny, g->nz};
     const double d[3] = {g->dx, g->dy, g->dz};
     for (int k = 0; k < 3; ++k) {
         if (n[k] < 1 || n[k] > 65535) return false;
         if (n[k] > 1) {
-            if (n[k] < 3) return false;
+            if (n[k] < ng) return false;
             if (!(d[k] > 0.0)) return false;
             const int a = g->bc[2 * k], b = g->bc[2 * k + 1];
             if ((a != XF_BC_PERIODIC && a != XF_BC_OUTFLOW) || (b != XF_BC_PERIODIC && b != XF_BC_OUTFLOW))
@@ -261,8 +261,8 @@ bool grid_ok(const xf_grid *g) {
         }
     }
     if (n[0] <= 1 && n[1] <= 1 && n[2] <= 1) return false;
-    const double cells = (double)(n[0] + (n[0] > 1 ? 6 : 0)) * (n[1] + (n[1] > 1 ? 6 : 0)) *
-                         (n[2] + (n[2] > 1 ? 6 : 0));
+    const double cells = (double)(n[0] + (n[0] > 1 ? 2 * ng : 0)) * (n[1] + (n[1] > 1 ? 2 * ng : 0)) *
+                         (n[2] + (n[2] > 1 ? 2 * ng : 0));
     return cells < 9.0e18 / 16.0;
 }
 
@@ -296,9 +296,15 @@ void fill_thermo(xf::ThermoK<R> &t, const xf_thermo *th) {
 extern "C" {
 
 int xf_create(const xf_grid *grid, const xf_thermo *thermo, int precision, xf_ctx **out) {
+    return xf_create_ghosts(grid, thermo, precision, 3, out);
+}
+
+int xf_create_ghosts(const xf_grid *grid, const xf_thermo *thermo, int precision, int ghost_width,
+                     xf_ctx **out) {
     if (!out) return XF_EINVAL;
     *out = nullptr;
-    if (!grid || !thermo || !grid_ok(grid)) return XF_EINVAL;
+    if (ghost_width != 3 && ghost_width != 4) return XF_EINVAL;
+    if (!grid || !thermo || !grid_ok(grid, ghost_width)) return XF_EINVAL;
     if (precision != XF_PREC_FP64 && precision != XF_PREC_MIXED) return XF_EINVAL;
     if (thermo->ns < 1 || !thermo->W || !thermo->a) return XF_EINVAL;
     if (thermo->ns > XF_MAX_SPECIES) return XF_EUNSUPPORTED;
@@ -317,9 +323,9 @@ int xf_create(const xf_grid *grid, const xf_thermo *thermo, int precision, xf_ct
     g.nx = grid->nx;
     g.ny = grid->ny;
     g.nz = grid->nz;
-    g.gx = g.nx > 1 ? 3 : 0;
-    g.gy = g.ny > 1 ? 3 : 0;
-    g.gz = g.nz > 1 ? 3 : 0;
+    g.gx = g.nx > 1 ? ghost_width : 0;
+    g.gy = g.ny > 1 ? ghost_width : 0;
+    g.gz = g.nz > 1 ? ghost_width : 0;
     g.px = g.nx + 2 * g.gx;
     g.py = g.ny + 2 * g.gy;
     g.pz = g.nz + 2 * g.gz;
@@ -503,7 +509,9 @@ int xf_set_dissipation(xf_ctx *c, int type) {
 
 int xf_set_reconstruction(xf_ctx *c, int type) {
     if (!c) return XF_EINVAL;
-    if (type != XF_RECON_WENO5 && type != XF_RECON_CU6) return XF_EINVAL;
+    if (type != XF_RECON_WENO5 && type != XF_RECON_CU6 && type != XF_RECON_WENO7) return XF_EINVAL;
+    const xf::Geo &g = c->lc.g;
+    if (type == XF_RECON_WENO7 && (g.gx > 0 ? g.gx : g.gy > 0 ? g.gy : g.gz) < 4) return XF_EUNSUPPORTED;
     c->lc.recon = type;
     return XF_OK;
 }
@@ -530,6 +538,7 @@ int xf_rhs_vjp(xf_ctx *c, const double *U, const double *rbar, double *Ubar, voi
     if (!c || !U || !rbar || !Ubar || !ws || Ubar == U || Ubar == rbar || !aligned8(U) || !aligned8(rbar) ||
         !aligned8(Ubar) || !aligned8(ws))
         return XF_EINVAL;
+    if (c->lc.recon == XF_RECON_WENO7) return XF_EUNSUPPORTED;
     const Layout l = layout(c, XF_OP_VJP);
     return rhs_vjp_into(c, U, rbar, Ubar, at<double>(ws, l.P), at<double>(ws, l.Pbar), at<double>(ws, l.rec),
                         at<unsigned long long>(ws, l.mx), (hipStream_t)stream);
@@ -540,6 +549,7 @@ int xf_rk3_step_vjp(xf_ctx *c, const double *Un, double dt, double *Ubar, void *
         !(dt >= 0.0))
         return XF_EINVAL;
     if (c->pp) return XF_EUNSUPPORTED;   // the adjoint is of the unblended step
+    if (c->lc.recon == XF_RECON_WENO7) return XF_EUNSUPPORTED;
     const Layout l = layout(c, XF_OP_RK3_VJP);
     const hipStream_t s = (hipStream_t)stream;
     const LaunchCtx &lc = c->lc;

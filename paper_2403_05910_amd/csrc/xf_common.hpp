@@ -16,10 +16,10 @@ constexpr int kMaxNs = XF_MAX_SPECIES;
 constexpr double kNewtonTol = 1e-11;
 constexpr int kNewtonMaxIt = 50;
 
-// Geometry of one padded SoA field: x fastest, 3 ghost layers per active axis.
+// Geometry of one padded SoA field: x fastest, 3 or 4 ghost layers per active axis.
 struct Geo {
     int nx, ny, nz;      // interior cells
-    int gx, gy, gz;      // ghost widths (3 or 0)
+    int gx, gy, gz;      // ghost widths (3 or 4; 0 on an inactive axis)
     int px, py, pz;      // padded extents
     long long sy, sz;    // strides of y and z in a field
     long long cells;     // px * py * pz: stride between fields

@@ -197,6 +197,78 @@ XF_HD float weno_cu6(float a, float b, float c, float d, float e, float f) {
     return (w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3) / (w0 + w1 + w2 + w3);
 }
 
+
+// WENO7-JS value at the right edge of the cell holding d, from the seven
+// point values a..g (cells i-3..i+3): four cubic candidates (the edge values
+// of the cubics whose cell averages are the data on i-3..i, ..., i..i+3),
+// linear weights (1, 12, 18, 4)/35, alpha_k = d_k / (1e-6 + beta_k)^2.
+// beta_k is the Jiang-Shu integral of sub-stencil k's cubic over cell i, a
+// quadratic form that vanishes on constants; it is evaluated as
+// D0 z0^2 + D1 z1^2 + D2 z2^2 over the sub-stencil's three first differences
+// (z_j = sum_{l >= j} L_lj delta_l with L, D the exact LDL^T factors of the
+// form, rational constants rounded once), so no large terms cancel.  The
+// candidates are taken times 12 and the linear weights times 35.
+template <typename R>
+XF_HD void weno7_parts(R a, R b, R c, R d, R e, R f, R g, R *q, R *beta) {
+    q[0] = R(-3) * a + R(13) * b - R(23) * c + R(25) * d;
+    q[1] = b - R(5) * c + R(13) * d + R(3) * e;
+    q[2] = -c + R(7) * d + R(7) * e - f;
+    q[3] = R(3) * d + R(13) * e - R(5) * f + g;
+    const R d0 = b - a, d1 = c - b, d2 = d - c, d3 = e - d, d4 = f - e, d5 = g - f;
+    {
+        const R z0 = d0 + R(-1394.0 / 547.0) * d1 + R(927.0 / 547.0) * d2, z1 = d1 + R(-3167.0 / 2126.0) * d2;
+        beta[0] = R(547.0 / 240.0) * z0 * z0 + R(1063.0 / 1641.0) * z1 * z1 + R(10153.0 / 12756.0) * d2 * d2;
+    }
+    {
+        const R z0 = d1 + R(-554.0 / 267.0) * d2 + R(247.0 / 267.0) * d3, z1 = d2 + R(-1345.0 / 2126.0) * d3;
+        beta[1] = R(89.0 / 80.0) * z0 * z0 + R(1063.0 / 801.0) * z1 * z1 + R(10153.0 / 12756.0) * d3 * d3;
+    }
+    {
+        const R z0 = d2 + R(-714.0 / 547.0) * d3 + R(247.0 / 547.0) * d4, z1 = d3 + R(-3167.0 / 7330.0) * d4;
+        beta[2] = R(547.0 / 240.0) * z0 * z0 + R(3665.0 / 1641.0) * z1 * z1 + R(10153.0 / 43980.0) * d4 * d4;
+    }
+    {
+        const R z0 = d3 + R(-2594.0 / 2107.0) * d4 + R(927.0 / 2107.0) * d5, z1 = d4 + R(-13313.0 / 27098.0) * d5;
+        beta[3] = R(2107.0 / 240.0) * z0 * z0 + R(13549.0 / 6321.0) * z1 * z1 + R(10153.0 / 162588.0) * d5 * d5;
+    }
+}
+
+// FP64: one division; alpha_k / sum alpha = d_k prod_{j!=k} s_j / sum(...),
+// s_k = (eps + beta_k)^2, after the four (eps + beta_k) are scaled by one
+// power of two (exact; weights unchanged) so that every product is <= 1.
+XF_HD double weno7(double a, double b, double c, double d, double e, double f, double g) {
+    double q[4], be[4];
+    weno7_parts(a, b, c, d, e, f, g, q, be);
+    double e0 = be[0] + 1e-6, e1 = be[1] + 1e-6, e2 = be[2] + 1e-6, e3 = be[3] + 1e-6;
+    int ex;
+    frexp(fmax(fmax(e0, e1), fmax(e2, e3)), &ex);
+    e0 = ldexp(e0, -ex);
+    e1 = ldexp(e1, -ex);
+    e2 = ldexp(e2, -ex);
+    e3 = ldexp(e3, -ex);
+    const double s0 = e0 * e0, s1 = e1 * e1, s2 = e2 * e2, s3 = e3 * e3;
+    const double p01 = s0 * s1, p23 = s2 * s3;
+    const double w0 = s1 * p23, w1 = 12.0 * (s0 * p23), w2 = 18.0 * (p01 * s3), w3 = 4.0 * (p01 * s2);
+    return (w0 * q[0] + w1 * q[1] + w2 * q[2] + w3 * q[3]) / (12.0 * (w0 + w1 + w2 + w3));
+}
+
+// FP32: the three-factor products of the FP64 form can underflow FP32 when
+// one sub-stencil is far rougher than the others, so the weights are taken
+// as d_k / (eps + beta_k)^2 directly, after the (eps + beta_k) are scaled by
+// the power of two of the smallest (exact): every 1 / (eps + beta_k) is then
+// at most 2 and the smoothest at least 1.
+XF_HD float weno7(float a, float b, float c, float d, float e, float f, float g) {
+    float q[4], be[4];
+    weno7_parts(a, b, c, d, e, f, g, q, be);
+    float e0 = be[0] + 1e-6f, e1 = be[1] + 1e-6f, e2 = be[2] + 1e-6f, e3 = be[3] + 1e-6f;
+    int ex;
+    frexpf(fminf(fminf(e0, e1), fminf(e2, e3)), &ex);
+    const float i0 = 1.0f / ldexpf(e0, -ex), i1 = 1.0f / ldexpf(e1, -ex), i2 = 1.0f / ldexpf(e2, -ex),
+                i3 = 1.0f / ldexpf(e3, -ex);
+    const float w0 = i0 * i0, w1 = 12.0f * (i1 * i1), w2 = 18.0f * (i2 * i2), w3 = 4.0f * (i3 * i3);
+    return (w0 * q[0] + w1 * q[1] + w2 * q[2] + w3 * q[3]) / (12.0f * (w0 + w1 + w2 + w3));
+}
+
 // Blocks are dealt to the 8 XCDs of the chip round robin in dispatch order.
 // xcd_block renumbers them so that each XCD receives a contiguous range of
 // logical blocks (blocks that share stencil rows then share one L2).
@@ -215,13 +287,14 @@ __device__ __forceinline__ void xcd_block(unsigned &bx, unsigned &by, unsigned &
     bz = l / (gx * gy);
 }
 
-// Read-only view of a 6-cell stencil along one axis; S is the storage type
-// (FP64 state, or the FP32 copies the mixed path sweeps read).
+// Read-only view of the stencil of one face along one axis (2 RAD cells:
+// six, or eight for WENO7); S is the storage type (FP64 state, or the FP32
+// copies the mixed path sweeps read).
 template <typename S>
 struct StencilT {
     const S *__restrict__ U;
     const S *__restrict__ P;        // [4][cells]: T, p, c, 1/rho
-    long long base;                 // padded index of stencil cell 0 (= i-2)
+    long long base;                 // padded index of stencil cell 0 (= i-RAD+1)
     long long step;                 // index stride along the sweep axis
     long long cells;                // field stride
     XF_HD S u(int f, int m) const { return U[f * cells + base + m * step]; }
@@ -242,23 +315,29 @@ struct Axes {
 // caller decides where it lives.  flags collects XF_FLAG_C2 if the face c^2
 // is not positive.  FENCE inserts compiler fences between the phases.
 // Artificial viscosity of the flux splitting (Eq. 14; Table I): LLF, the
-// max over the six stencil cells of each field's |lambda|; ROE, |lambda| of
+// max over the stencil cells of each field's |lambda|; ROE, |lambda| of
 // the face's Roe state (u~_n - c~, u~_n, u~_n + c~); GLF, each field's
 // largest LLF speed over all faces of the direction (glf: the three speeds
 // u_n - c, u_n, u_n + c, reduced beforehand).
 constexpr int kViscLlf = 0, kViscRoe = 1, kViscGlf = 2;
-constexpr int kReconWeno5 = 0, kReconCu6 = 1;
+constexpr int kReconWeno5 = 0, kReconCu6 = 1, kReconWeno7 = 2;
 struct Dissip {
     int type;
     const double *glf;
-    int recon;   // kReconWeno5 or kReconCu6
+    int recon;   // kReconWeno5, kReconCu6 or kReconWeno7
 };
 
 // Reconstruction of one characteristic field at the face from the split
-// values of the six cells: WENO5-JS of g+ on cells i-2..i+2 plus g- mirrored
-// on i+3..i-1, or WENO-CU6 of both on all six cells.
-template <bool OPTS, typename R>
+// values of the stencil cells.  RAD = 3 (cells i-2..i+3): WENO5-JS of g+ on
+// cells i-2..i+2 plus g- mirrored on i+3..i-1, or WENO-CU6 of both on all
+// six cells.  RAD = 4 (cells i-3..i+4): WENO7-JS of g+ on i-3..i+3 plus g-
+// mirrored on i+4..i-2.
+template <bool OPTS, int RAD, typename R>
 XF_HD R recon_pair(const R *gp, const R *gm, int recon) {
+    if constexpr (RAD == 4) {
+        return weno7(gp[0], gp[1], gp[2], gp[3], gp[4], gp[5], gp[6]) +
+               weno7(gm[7], gm[6], gm[5], gm[4], gm[3], gm[2], gm[1]);
+    }
     if constexpr (OPTS) {
         if (recon == kReconCu6)
             return weno_cu6(gp[0], gp[1], gp[2], gp[3], gp[4], gp[5]) +
@@ -268,9 +347,14 @@ XF_HD R recon_pair(const R *gp, const R *gm, int recon) {
 }
 
 // VISC = false compiles the default scheme only (LLF speeds, WENO5; ds is
-// ignored); VISC = true follows ds.type and ds.recon at run time.
-template <int NS, typename R, int DIR, bool FENCE = false, bool VISC = false, class St, class Out>
+// ignored); VISC = true follows ds.type and ds.recon at run time.  RAD is the
+// stencil half width: 3 (six cells; WENO5, CU6) or 4 (eight cells; WENO7).
+template <int NS, typename R, int DIR, bool FENCE = false, bool VISC = false, int RAD = 3, class St, class Out>
 XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned &flags, const Dissip &ds) {
+    static_assert(RAD == 3 || RAD == 4, "stencil half width");
+    constexpr int W = 2 * RAD;       // stencil cells
+    constexpr int CL = RAD - 1;      // slot of cell i (left of the face)
+    constexpr int CR = RAD;          // slot of cell i+1
     constexpr int IM = NS;
     constexpr int IE = NS + 3;
     constexpr int IN = NS + Axes<DIR>::n;
@@ -281,23 +365,23 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
     R rL = R(0), rR = R(0);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        rL += R(st.u(s, 2));
-        rR += R(st.u(s, 3));
+        rL += R(st.u(s, CL));
+        rR += R(st.u(s, CR));
     }
     const R sL = xsqrt(rL), sR = xsqrt(rR);
     const R wL = sL / (sL + sR);
     const R wR = R(1) - wL;
-    const R aL = wL * R(st.p(3, 2)), aR = wR * R(st.p(3, 3));   // weights on conservative values
+    const R aL = wL * R(st.p(3, CL)), aR = wR * R(st.p(3, CR));   // weights on conservative values
     R ut[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) ut[k] = aL * R(st.u(IM + k, 2)) + aR * R(st.u(IM + k, 3));
-    const R Ht = aL * (R(st.u(IE, 2)) + R(st.p(1, 2))) + aR * (R(st.u(IE, 3)) + R(st.p(1, 3)));
-    const R Tt = wL * R(st.p(0, 2)) + wR * R(st.p(0, 3));
+    for (int k = 0; k < 3; ++k) ut[k] = aL * R(st.u(IM + k, CL)) + aR * R(st.u(IM + k, CR));
+    const R Ht = aL * (R(st.u(IE, CL)) + R(st.p(1, CL))) + aR * (R(st.u(IE, CR)) + R(st.p(1, CR)));
+    const R Tt = wL * R(st.p(0, CL)) + wR * R(st.p(0, CR));
     R Yt[NS], chi[NS];
     R Rb = R(0), cvb = R(0);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        Yt[s] = aL * R(st.u(s, 2)) + aR * R(st.u(s, 3));
+        Yt[s] = aL * R(st.u(s, CL)) + aR * R(st.u(s, CR));
         Rb += Yt[s] * th.Rs[s];
         cvb += Yt[s] * cv_species(th, s, Tt);
         chi[s] = e_species(th, s, Tt);   // e_s(T~) for now
@@ -318,10 +402,10 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
 
     if (FENCE) XF_FENCE();
     // ---- 2./3. per-cell scalars of the projections, LLF speeds ----------
-    R un[6], DU[6], DF[6], rh[6];
+    R un[W], DU[W], DF[W], rh[W];
     R aM = R(0), a0 = R(0), aP = R(0);
 #pragma unroll
-    for (int m = 0; m < 6; ++m) {
+    for (int m = 0; m < W; ++m) {
         R sc = R(0), sr = R(0);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -360,9 +444,9 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
     // ---- acoustic pair ----------------------------------------------------
     R hm, hp;
     {
-        R gMp[6], gMm[6], gPp[6], gPm[6];
+        R gMp[W], gMm[W], gPp[W], gPm[W];
 #pragma unroll
-        for (int m = 0; m < 6; ++m) {
+        for (int m = 0; m < W; ++m) {
             const R mn = R(st.u(IN, m));
             const R XU = mn - utn * rh[m];
             const R XF = (mn * un[m] + R(st.p(1, m))) - utn * (rh[m] * un[m]);
@@ -373,8 +457,8 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
             gPp[m] = R(0.5) * (wFp + aP * wUp);
             gPm[m] = R(0.5) * (wFp - aP * wUp);
         }
-        hm = recon_pair<VISC>(gMp, gMm, ds.recon);
-        hp = recon_pair<VISC>(gPp, gPm, ds.recon);
+        hm = recon_pair<VISC, RAD>(gMp, gMm, ds.recon);
+        hp = recon_pair<VISC, RAD>(gPp, gPm, ds.recon);
     }
     const R Asum = hm + hp, Dif = hp - hm;
 
@@ -382,23 +466,23 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
     // ---- tangential pair --------------------------------------------------
     R h1, h2;
     {
-        R gp[6], gm[6];
+        R gp[W], gm[W];
 #pragma unroll
-        for (int m = 0; m < 6; ++m) {
+        for (int m = 0; m < W; ++m) {
             const R wU = R(st.u(I1, m)) - ut1 * rh[m];
             const R wF = un[m] * wU;
             gp[m] = R(0.5) * (wF + a0 * wU);
             gm[m] = R(0.5) * (wF - a0 * wU);
         }
-        h1 = recon_pair<VISC>(gp, gm, ds.recon);
+        h1 = recon_pair<VISC, RAD>(gp, gm, ds.recon);
 #pragma unroll
-        for (int m = 0; m < 6; ++m) {
+        for (int m = 0; m < W; ++m) {
             const R wU = R(st.u(I2, m)) - ut2 * rh[m];
             const R wF = un[m] * wU;
             gp[m] = R(0.5) * (wF + a0 * wU);
             gm[m] = R(0.5) * (wF - a0 * wU);
         }
-        h2 = recon_pair<VISC>(gp, gm, ds.recon);
+        h2 = recon_pair<VISC, RAD>(gp, gm, ds.recon);
     }
 
     // ---- species fields, back-projected as they come ----------------------
@@ -407,16 +491,16 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         if (FENCE) XF_FENCE();
-        R gp[6], gm[6];
+        R gp[W], gm[W];
 #pragma unroll
-        for (int m = 0; m < 6; ++m) {
+        for (int m = 0; m < W; ++m) {
             const R r = R(st.u(s, m));
             const R wU = r - Yt[s] * DU[m];
             const R wF = r * un[m] - Yt[s] * DF[m];
             gp[m] = R(0.5) * (wF + a0 * wU);
             gm[m] = R(0.5) * (wF - a0 * wU);
         }
-        const R hs = recon_pair<VISC>(gp, gm, ds.recon);
+        const R hs = recon_pair<VISC, RAD>(gp, gm, ds.recon);
         out(s, Yt[s] * Asum + hs);
         gsum += hs;
         gE += (q2 - chi[s] * iGam) * hs;
@@ -464,24 +548,25 @@ struct PpFloor<double> {
     static constexpr double y = 1e-13;
 };
 
-template <int NS, typename R, int DIR, class St>
+template <int NS, typename R, int DIR, int RAD = 3, class St>
 XF_HD void pp_limit(const St &st, R lam, R *F) {
     constexpr int NV = NS + 4, IE = NS + 3, IN = NS + Axes<DIR>::n;
+    constexpr int CL = RAD - 1, CR = RAD;   // slots of cells i and i+1
     R aM = R(0), aP = R(0);
 #pragma unroll
-    for (int m = 0; m < 6; ++m) {
+    for (int m = 0; m < 2 * RAD; ++m) {
         const R rinv = R(st.p(3, m)), cm = R(st.p(2, m));
         const R unm = R(st.u(IN, m)) * rinv;
         aM = rmax(aM, rabs(unm - cm));
         aP = rmax(aP, rabs(unm + cm));
     }
     const R lf = rmax(aM, aP);
-    const R pL = R(st.p(1, 2)), pR = R(st.p(1, 3));
-    const R unL = R(st.u(IN, 2)) * R(st.p(3, 2)), unR = R(st.u(IN, 3)) * R(st.p(3, 3));
+    const R pL = R(st.p(1, CL)), pR = R(st.p(1, CR));
+    const R unL = R(st.u(IN, CL)) * R(st.p(3, CL)), unR = R(st.u(IN, CR)) * R(st.p(3, CR));
     R FLF[NV];
 #pragma unroll
     for (int f = 0; f < NV; ++f) {
-        const R uL = R(st.u(f, 2)), uR = R(st.u(f, 3));
+        const R uL = R(st.u(f, CL)), uR = R(st.u(f, CR));
         R fL, fR;
         if (f == IE) {
             fL = (uL + pL) * unL;
@@ -499,8 +584,8 @@ XF_HD void pp_limit(const St &st, R lam, R *F) {
     R rhoL = R(0), rhoR = R(0), qH = R(0), qLF = R(0);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        rhoL += R(st.u(s, 2));
-        rhoR += R(st.u(s, 3));
+        rhoL += R(st.u(s, CL));
+        rhoR += R(st.u(s, CR));
         qH += F[s];
         qLF += FLF[s];
     }
@@ -521,8 +606,8 @@ XF_HD void pp_limit(const St &st, R lam, R *F) {
     const R epsL = -R(PpFloor<R>::y) * rhoL, epsR = -R(PpFloor<R>::y) * rhoR;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        bound(R(st.u(s, 2)), R(-1), F[s], FLF[s], epsL);
-        bound(R(st.u(s, 3)), R(1), F[s], FLF[s], epsR);
+        bound(R(st.u(s, CL)), R(-1), F[s], FLF[s], epsL);
+        bound(R(st.u(s, CR)), R(1), F[s], FLF[s], epsR);
     }
     if (theta < R(1)) {
 #pragma unroll

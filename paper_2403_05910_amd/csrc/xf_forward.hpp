@@ -183,7 +183,7 @@ __device__ __forceinline__ void put_result(double *__restrict__ rhs, const Stage
 // ---------------------------------------------------------------------------
 constexpr int kXBlock = 256;
 
-template <int NS, typename R, typename S, bool PP, bool VISC>
+template <int NS, typename R, typename S, bool PP, bool VISC, int RAD>
 __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(SweepTune<R>::waves))) void k_sweep_x(
     const S *__restrict__ U, const S *__restrict__ P, double *__restrict__ rhs, Geo g, ThermoK<R> th, int accumulate,
     StageArgs sa, unsigned *status, Dissip ds) {
@@ -203,14 +203,14 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(SweepTu
         i = (int)(f - row * nfx);
         const int j = (int)(row % g.ny), k = (int)(row / g.ny);
         rowbase = (long long)(g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + g.gx;
-        StencilT<S> st{U, P, rowbase + i - 3, 1, g.cells};
-        face_flux_to<NS, R, 0, SweepTune<R>::fence_face, VISC>(st, th, [&](int q, R v) { sF[q][t] = v; }, flags,
-                                                               ds);
+        StencilT<S> st{U, P, rowbase + i - RAD, 1, g.cells};
+        face_flux_to<NS, R, 0, SweepTune<R>::fence_face, VISC, RAD>(st, th, [&](int q, R v) { sF[q][t] = v; },
+                                                                    flags, ds);
         if constexpr (PP) {
             R Fq[NV];
 #pragma unroll
             for (int q = 0; q < NV; ++q) Fq[q] = sF[q][t];
-            pp_limit<NS, R, 0>(st, pp_lambda<R>(g, sa, g.idx), Fq);
+            pp_limit<NS, R, 0, RAD>(st, pp_lambda<R>(g, sa, g.idx), Fq);
 #pragma unroll
             for (int q = 0; q < NV; ++q) sF[q][t] = Fq[q];
         }
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(SweepTu
 // ---------------------------------------------------------------------------
 constexpr int kTileX = 16, kTileS = 16;
 
-template <int NS, typename R, int DIR, typename S, bool PP, bool VISC>
+template <int NS, typename R, int DIR, typename S, bool PP, bool VISC, int RAD>
 __global__ __launch_bounds__(kTileX *kTileS) __attribute__((amdgpu_waves_per_eu(SweepTune<R>::waves))) void
 k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, double *__restrict__ rhs, Geo g, ThermoK<R> th,
              int accumulate, StageArgs sa, unsigned *status, Dissip ds) {
@@ -257,14 +257,14 @@ k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, double *__restric
                           ((DIR == 1) ? (long long)(g.gz + bz) * g.sz : (long long)(g.gy + bz) * g.sy);
     unsigned flags = 0;
     if (valid) {
-        StencilT<S> st{U, P, col + (long long)(gs + j - 3) * step, step, g.cells};
-        face_flux_to<NS, R, DIR, SweepTune<R>::fence_face, VISC>(st, th, [&](int q, R v) { sF[q][ts][tx] = v; },
-                                                                 flags, ds);
+        StencilT<S> st{U, P, col + (long long)(gs + j - RAD) * step, step, g.cells};
+        face_flux_to<NS, R, DIR, SweepTune<R>::fence_face, VISC, RAD>(
+            st, th, [&](int q, R v) { sF[q][ts][tx] = v; }, flags, ds);
         if constexpr (PP) {
             R Fq[NV];
 #pragma unroll
             for (int q = 0; q < NV; ++q) Fq[q] = sF[q][ts][tx];
-            pp_limit<NS, R, DIR>(st, pp_lambda<R>(g, sa, DIR == 1 ? g.idy : g.idz), Fq);
+            pp_limit<NS, R, DIR, RAD>(st, pp_lambda<R>(g, sa, DIR == 1 ? g.idy : g.idz), Fq);
 #pragma unroll
             for (int q = 0; q < NV; ++q) sF[q][ts][tx] = Fq[q];
         }

@@ -9,7 +9,7 @@ namespace {
 unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 // Ghost layers of direction d: one thread per (field, other two padded
-// coordinates), both sides and all three layers in that thread.  The other
+// coordinates), both sides and all ghost layers in that thread.  The other
 // two coordinates are enumerated with the faster one first so that y and z
 // fills are coalesced along x.
 __device__ __forceinline__ void ghost_geometry(const Geo &g, int d, long long o, long long &base, long long &step,
@@ -37,11 +37,13 @@ __device__ __forceinline__ long long others(const Geo &g, int d) {
 }
 
 // padded source index of ghost layer l on side sd (0 low, 1 high), n interior
-__device__ __forceinline__ int ghost_src(int bc, int sd, int l, int n) {
-    if (sd == 0) return bc == XF_BC_PERIODIC ? n + l : 3;
-    return bc == XF_BC_PERIODIC ? 3 + l : 3 + n - 1;
+// cells, ng ghost layers per side (n >= ng, so periodic sources are interior)
+__device__ __forceinline__ int ghost_src(int bc, int sd, int l, int n, int ng) {
+    if (sd == 0) return bc == XF_BC_PERIODIC ? n + l : ng;
+    return bc == XF_BC_PERIODIC ? ng + l : ng + n - 1;
 }
-__device__ __forceinline__ int ghost_dst(int sd, int l, int n) { return sd == 0 ? l : 3 + n + l; }
+__device__ __forceinline__ int ghost_dst(int sd, int l, int n, int ng) { return sd == 0 ? l : ng + n + l; }
+__device__ __forceinline__ int ghost_width(const Geo &g, int d) { return d == 0 ? g.gx : (d == 1 ? g.gy : g.gz); }
 
 __global__ __launch_bounds__(256) void k_fill(double *U, Geo g, int nv, int d) {
     const long long no = others(g, d);
@@ -52,11 +54,13 @@ __global__ __launch_bounds__(256) void k_fill(double *U, Geo g, int nv, int d) {
     int n;
     ghost_geometry(g, d, o, base, step, n);
     double *u = U + f * g.cells + base;
+    const int ng = ghost_width(g, d);
 #pragma unroll
     for (int sd = 0; sd < 2; ++sd) {
         const int bc = g.bc[2 * d + sd];
 #pragma unroll
-        for (int l = 0; l < 3; ++l) u[ghost_dst(sd, l, n) * step] = u[ghost_src(bc, sd, l, n) * step];
+        for (int l = 0; l < 4; ++l)   // ng <= 4 layers
+            if (l < ng) u[ghost_dst(sd, l, n, ng) * step] = u[ghost_src(bc, sd, l, n, ng) * step];
     }
 }
 
@@ -71,15 +75,17 @@ __global__ __launch_bounds__(256) void k_fill_vjp(double *Ub, Geo g, int nv, int
     int n;
     ghost_geometry(g, d, o, base, step, n);
     double *u = Ub + f * g.cells + base;
+    const int ng = ghost_width(g, d);
 #pragma unroll
     for (int sd = 1; sd >= 0; --sd) {
         const int bc = g.bc[2 * d + sd];
 #pragma unroll
-        for (int l = 2; l >= 0; --l) {
-            const long long dst = ghost_dst(sd, l, n) * step;
+        for (int l = 3; l >= 0; --l) {   // ng <= 4 layers
+            if (l >= ng) continue;
+            const long long dst = ghost_dst(sd, l, n, ng) * step;
             const double v = u[dst];
             u[dst] = 0.0;
-            u[ghost_src(bc, sd, l, n) * step] += v;
+            u[ghost_src(bc, sd, l, n, ng) * step] += v;
         }
     }
 }

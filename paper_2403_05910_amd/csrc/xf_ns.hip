@@ -22,14 +22,14 @@ hipError_t prims(const LaunchCtx &c, const double *U, double *P, float *Uf, floa
     return hipGetLastError();
 }
 
-template <typename R, typename S, bool PP, bool VISC>
+template <typename R, typename S, bool PP, bool VISC, int RAD>
 hipError_t launch_face_sweep(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumulate, const S *U,
                              const S *P, double *rhs, const StageArgs &sa, const Dissip &ds, hipStream_t s) {
     const Geo &g = c.g;
     if (dir == 0) {
         const long long nf = (long long)(g.nx + 1) * g.ny * g.nz;
         const unsigned nb = (unsigned)((nf - 1 + (kXBlock - 2)) / (kXBlock - 1));   // blocks overlap by one face
-        hipLaunchKernelGGL((k_sweep_x<NS, R, S, PP, VISC>), dim3(nb), dim3(kXBlock), 0, s, U, P, rhs, g, th,
+        hipLaunchKernelGGL((k_sweep_x<NS, R, S, PP, VISC, RAD>), dim3(nb), dim3(kXBlock), 0, s, U, P, rhs, g, th,
                            accumulate, sa, c.status, ds);
         return hipGetLastError();
     }
@@ -38,10 +38,10 @@ hipError_t launch_face_sweep(const LaunchCtx &c, const ThermoK<R> &th, int dir, 
     const unsigned tiles = (unsigned)((nsw + kTileS - 2) / (kTileS - 1));
     dim3 grid((g.nx + kTileX - 1) / kTileX, tiles, ntr), block(kTileX, kTileS);
     if (dir == 1)
-        hipLaunchKernelGGL((k_sweep_tile<NS, R, 1, S, PP, VISC>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
+        hipLaunchKernelGGL((k_sweep_tile<NS, R, 1, S, PP, VISC, RAD>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
                            sa, c.status, ds);
     else
-        hipLaunchKernelGGL((k_sweep_tile<NS, R, 2, S, PP, VISC>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
+        hipLaunchKernelGGL((k_sweep_tile<NS, R, 2, S, PP, VISC, RAD>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
                            sa, c.status, ds);
     return hipGetLastError();
 }
@@ -53,12 +53,16 @@ hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumu
     // c.variant (measurement only) 1 or 2 runs the y/z column march (LLF, no
     // positivity blend) instead of the tiled kernel
     if (dir == 0 || c.variant == 0 || sa.pp || ds.type != kViscLlf || ds.recon != kReconWeno5) {
+        // eight-cell stencils (WENO7): their own instances, scheme options on
+        if (ds.recon == kReconWeno7)
+            return sa.pp ? launch_face_sweep<R, S, true, true, 4>(c, th, dir, accumulate, U, P, rhs, sa, ds, s)
+                         : launch_face_sweep<R, S, false, true, 4>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
         const bool v = ds.type != kViscLlf || ds.recon != kReconWeno5;
         if (sa.pp)
-            return v ? launch_face_sweep<R, S, true, true>(c, th, dir, accumulate, U, P, rhs, sa, ds, s)
-                     : launch_face_sweep<R, S, true, false>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
-        return v ? launch_face_sweep<R, S, false, true>(c, th, dir, accumulate, U, P, rhs, sa, ds, s)
-                 : launch_face_sweep<R, S, false, false>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
+            return v ? launch_face_sweep<R, S, true, true, 3>(c, th, dir, accumulate, U, P, rhs, sa, ds, s)
+                     : launch_face_sweep<R, S, true, false, 3>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
+        return v ? launch_face_sweep<R, S, false, true, 3>(c, th, dir, accumulate, U, P, rhs, sa, ds, s)
+                 : launch_face_sweep<R, S, false, false, 3>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
     }
     const int ntr = dir == 1 ? g.nz : g.ny;
     int nseg, seglen;
@@ -159,6 +163,7 @@ hipError_t sweep_vjp(const LaunchCtx &c, int dir, const double *U, const double 
                      double *Ubar, double *Pbar, double *rec, long long nrec, const double *glf, hipStream_t s) {
     const Dissip ds{c.visc, glf, c.recon};
     if (c.visc == kViscGlf && !glf) return hipErrorInvalidValue;
+    if (c.recon == kReconWeno7) return hipErrorInvalidValue;   // six-cell stencils only
     if (c.precision == XF_PREC_MIXED)
         return sweep_vjp_t<float>(c, c.th32, dir, U, P, rbar, Ubar, Pbar, rec, nrec, ds, s);
     return sweep_vjp_t<double>(c, c.th64, dir, U, P, rbar, Ubar, Pbar, rec, nrec, ds, s);

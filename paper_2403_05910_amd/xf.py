@@ -24,8 +24,8 @@ XF_PREC_FP64, XF_PREC_MIXED = 0, 1
 XF_OP_RHS, XF_OP_RK3, XF_OP_VJP, XF_OP_RK3_VJP = 0, 1, 2, 3
 XF_VISC_LLF, XF_VISC_ROE, XF_VISC_GLF = 0, 1, 2
 VISC = {"LLF": XF_VISC_LLF, "ROE": XF_VISC_ROE, "GLF": XF_VISC_GLF}
-XF_RECON_WENO5, XF_RECON_CU6 = 0, 1
-RECON = {"WENO5": XF_RECON_WENO5, "CU6": XF_RECON_CU6}
+XF_RECON_WENO5, XF_RECON_CU6, XF_RECON_WENO7 = 0, 1, 2
+RECON = {"WENO5": XF_RECON_WENO5, "CU6": XF_RECON_CU6, "WENO7": XF_RECON_WENO7}
 FLAGS = {1: "rho<=0", 2: "Y<0", 4: "p<=0 or T<=0", 8: "T out of range", 16: "Newton not converged",
          32: "Roe c^2<=0", 64: "NaN/Inf"}
 
@@ -55,6 +55,8 @@ def _sig(name, res, *args):
 
 
 _create = _sig("xf_create", _c_int, ctypes.POINTER(xf_grid), ctypes.POINTER(xf_thermo), _c_int, ctypes.POINTER(_vp))
+_create_ghosts = _sig("xf_create_ghosts", _c_int, ctypes.POINTER(xf_grid), ctypes.POINTER(xf_thermo), _c_int, _c_int,
+                      ctypes.POINTER(_vp))
 _destroy = _sig("xf_destroy", _c_int, _vp)
 _state_elems = _sig("xf_state_elems", _c_size_t, _vp)
 _ws_bytes = _sig("xf_workspace_bytes", _c_size_t, _vp, _c_int)
@@ -75,7 +77,7 @@ _timing = _sig("xf_timing", _c_int, _vp, _c_int)
 _timing_read = _sig("xf_timing_read", _c_int, _vp, _vp, _dp, ctypes.POINTER(ctypes.c_longlong))
 _strerror = _sig("xf_strerror", ctypes.c_char_p, _c_int)
 
-EXPORTED = ["xf_create", "xf_destroy", "xf_state_elems", "xf_workspace_bytes", "xf_fill_ghosts",
+EXPORTED = ["xf_create", "xf_create_ghosts", "xf_destroy", "xf_state_elems", "xf_workspace_bytes", "xf_fill_ghosts",
             "xf_fill_ghosts_vjp", "xf_rhs", "xf_primitives", "xf_cfl_dt", "xf_rk3_step", "xf_rk3_step_cfl",
             "xf_set_dissipation", "xf_set_reconstruction", "xf_set_positivity", "xf_rhs_vjp", "xf_rk3_step_vjp",
             "xf_status", "xf_strerror", "xf_timing", "xf_timing_read"]
@@ -105,6 +107,13 @@ def xf_strerror(code):
 def xf_create(grid: xf_grid, thermo: xf_thermo, precision: int):
     h = _vp()
     _check(_create(ctypes.byref(grid), ctypes.byref(thermo), precision, ctypes.byref(h)), "xf_create")
+    return h.value
+
+
+def xf_create_ghosts(grid: xf_grid, thermo: xf_thermo, precision: int, ghost_width: int):
+    h = _vp()
+    _check(_create_ghosts(ctypes.byref(grid), ctypes.byref(thermo), precision, ghost_width, ctypes.byref(h)),
+           "xf_create_ghosts")
     return h.value
 
 
@@ -203,10 +212,11 @@ class Context:
 
     n = (nx, ny, nz), d = (dx, dy, dz), bc = 6 ints (-x,+x,-y,+y,-z,+z),
     W (ns,) kg/mol, a (ns, 6) thermo coefficients, [T_lo, T_hi] Newton bracket
-    (T_hi <= 0: none), precision "fp64" or "mixed".
+    (T_hi <= 0: none), precision "fp64" or "mixed", ghost_width 3 or 4 (4 is
+    needed by the WENO7 reconstruction).
     """
 
-    def __init__(self, n, d, bc, W, a, T_lo=0.0, T_hi=0.0, precision="fp64"):
+    def __init__(self, n, d, bc, W, a, T_lo=0.0, T_hi=0.0, precision="fp64", ghost_width=3):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("libxf needs a HIP device")
@@ -221,7 +231,8 @@ class Context:
         self.positivity = False
         self.visc = "LLF"
         self.recon = "WENO5"
-        g = [3 if k > 1 else 0 for k in self.n]
+        self.ghost_width = int(ghost_width)
+        g = [self.ghost_width if k > 1 else 0 for k in self.n]
         self.shape = (self.nv, self.n[2] + 2 * g[2], self.n[1] + 2 * g[1], self.n[0] + 2 * g[0])
         self.interior = (slice(None), slice(g[2], g[2] + self.n[2]), slice(g[1], g[1] + self.n[1]),
                          slice(g[0], g[0] + self.n[0]))
@@ -229,14 +240,14 @@ class Context:
         th = xf_thermo(self.ns, self.W.ctypes.data_as(_dp), self.a.ctypes.data_as(_dp), float(T_lo), float(T_hi))
         prec = {"fp64": XF_PREC_FP64, "mixed": XF_PREC_MIXED}[precision]
         self.device = torch.device("cuda", torch.cuda.current_device())
-        self.handle = xf_create(grid, th, prec)
+        self.handle = xf_create_ghosts(grid, th, prec, self.ghost_width)
         assert xf_state_elems(self.handle) == int(np.prod(self.shape))
         self._ws = {}
 
     @classmethod
     def from_case(cls, case, precision="fp64"):
         t = case.thermo
-        return cls(case.n, case.d, case.bc, t.W, t.a, t.T_lo, t.T_hi, precision)
+        return cls(case.n, case.d, case.bc, t.W, t.a, t.T_lo, t.T_hi, precision, case.ng)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -311,7 +322,8 @@ class Context:
         return self
 
     def set_reconstruction(self, recon="WENO5"):
-        """reconstruction of the characteristic fluxes: "WENO5" or "CU6" """
+        """reconstruction of the characteristic fluxes: "WENO5", "CU6" or
+        "WENO7" (the last needs ghost_width 4)"""
         xf_set_reconstruction(self.handle, RECON[recon])
         self.recon = recon
         return self

@@ -64,6 +64,13 @@ def test_strerror_and_argument_errors_without_device():
     thb = xf.xf_thermo(2, ctypes.cast(W, xf._dp), ctypes.cast(a, xf._dp), 500.0, 400.0)
     assert xf._create(ctypes.byref(good), ctypes.byref(thb), 0, ctypes.byref(h)) == xf.XF_EINVAL
     assert xf._create(None, ctypes.byref(th), 0, ctypes.byref(h)) == xf.XF_EINVAL
+    # ghost width: 3 or 4 only, and an active dimension needs at least that many cells
+    for ng in (0, 2, 5):
+        assert xf._create_ghosts(ctypes.byref(good), ctypes.byref(th), 0, ng, ctypes.byref(h)) == xf.XF_EINVAL
+        assert not h.value
+    three = xf.xf_grid(3, 1, 1, 0.1, 1, 1, (ctypes.c_int * 6)(0, 0, 0, 0, 0, 0))
+    assert xf._create_ghosts(ctypes.byref(three), ctypes.byref(th), 0, 4, ctypes.byref(h)) == xf.XF_EINVAL
+    assert xf._create_ghosts(None, ctypes.byref(th), 0, 4, ctypes.byref(h)) == xf.XF_EINVAL
     # null contexts and buffers are refused before any device work
     assert xf._rhs(None, None, None, None, None) == xf.XF_EINVAL
     assert xf._rk3(None, None, 0.1, None, None, None) == xf.XF_EINVAL

@@ -1,0 +1,132 @@
+"""GPU parity of the WENO7 reconstruction (eight-cell face stencils, four
+ghost layers) against the CPU oracle, through the C ABI.
+
+Same bars as the WENO5 path: per field max |rhs_gpu - rhs_oracle| <=
+1e-12 S_f in FP64 and 2e-5 S_f in the mixed path; copies (the four-layer
+ghost fill) bit-exact.  Also: the six-cell schemes give bit-identical
+residuals on the three- and four-layer layouts, and the operations that do
+not cover WENO7 refuse it.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from conftest import oracle_objects
+from paper_2403_05910_amd import workloads as W
+from test_gpu_parity import CASES, MIXED_RHS_TOL, TOL, _sample_cells, field_err, gpu_rhs, oracle_rhs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+NAMES = ["ragged3d_n3_outflow_x", "n9_3d_mixed_bc", "n1_thermal_3d", "inert_sbi_32", "nine_sbi_32", "plane2d_n3",
+         "y_only_n3", "z_only_n3", "wave1d_600", "sod_400"]
+CASES4 = {k: CASES[k].with_ghosts(4) for k in NAMES}
+
+
+def _xf():
+    from paper_2403_05910_amd import xf
+    return xf
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_rhs_weno7_matches_oracle(name):
+    case = CASES4[name]
+    print(f"[weno7] {name} n={case.n} ns={case.thermo.ns}", flush=True)
+    r_gpu, flags, U_gpu = gpu_rhs(case, recon="WENO7")
+    r_ora, aux, U_ora = oracle_rhs(case, recon="WENO7")
+    assert np.array_equal(U_gpu, U_ora), "four-layer ghost fill must be an exact copy"
+    assert flags == aux["flags"] == 0
+    err = field_err(r_gpu, r_ora, aux["scale_llf"])
+    print(f"[weno7] {name} max err / S_f = {err.max():.3e}", flush=True)
+    assert err.max() <= TOL, err
+    _, g = oracle_objects(case)
+    mask = np.ones(r_gpu.shape[1:], dtype=bool)
+    mask[g.interior()] = False
+    assert np.all(r_gpu[:, mask] == 0.0)
+
+
+@pytest.mark.parametrize("recon", ["WENO5", "CU6"])
+@pytest.mark.parametrize("name", ["n9_3d_mixed_bc", "plane2d_n3", "z_only_n3"])
+def test_six_cell_schemes_identical_on_four_layers(name, recon):
+    c3, c4 = CASES[name], CASES4[name]
+    r3, _, _ = gpu_rhs(c3, recon=recon)
+    r4, _, _ = gpu_rhs(c4, recon=recon)
+    _, g3 = oracle_objects(c3)
+    _, g4 = oracle_objects(c4)
+    assert np.array_equal(r3[(slice(None),) + g3.interior()], r4[(slice(None),) + g4.interior()])
+
+
+def test_full_size_sampled_parity_weno7():
+    """nine-species shock-bubble at 256^3 on four ghost layers: GPU WENO7
+    residual on the whole grid, oracle on sampled cells"""
+    case = W.nine_species_sbi(256).with_ghosts(4)
+    print(f"[weno7] full-size {case.n}", flush=True)
+    r_gpu, flags, U_gpu = gpu_rhs(case, recon="WENO7")
+    assert flags == 0
+    th, g = oracle_objects(case)
+    U_ora = O.fill_ghosts(g, case.U)
+    assert np.array_equal(U_gpu, U_ora)
+    del U_gpu
+    cells = _sample_cells(case, 120, 13)
+    ro, fmax = O.rhs_at(th, g, U_ora, cells, return_fmax=True, recon="WENO7")
+    rg = r_gpu[:, cells[:, 2] + 4, cells[:, 1] + 4, cells[:, 0] + 4]
+    iz, iy, ix = g.interior()
+    sub = np.ascontiguousarray(U_ora[:, iz, iy, ix][:, ::4, ::4, ::4]).reshape(U_ora.shape[0], -1)
+    P = O.primitives(th, sub)
+    lu = np.max((P["c"] + np.max(np.abs(P["u"]), axis=0))[None] * np.abs(sub), axis=1)
+    scale = np.maximum(fmax, lu) / min(g.d)
+    err = field_err(rg, ro, scale)
+    print(f"[weno7] full-size sampled max err / S_f = {err.max():.3e}", flush=True)
+    assert err.max() <= TOL, err
+
+
+@pytest.mark.parametrize("name", ["n9_3d_mixed_bc", "inert_sbi_32", "plane2d_n3"])
+def test_rhs_weno7_mixed_within_fp32_bound(name):
+    case = CASES4[name]
+    r_gpu, flags, _ = gpu_rhs(case, "mixed", recon="WENO7")
+    r_ora, aux, _ = oracle_rhs(case, recon="WENO7")
+    assert flags == 0
+    err = field_err(r_gpu, r_ora, aux["scale_llf"])
+    print(f"[weno7] mixed {name} max err / S_f = {err.max():.3e}", flush=True)
+    assert err.max() <= MIXED_RHS_TOL, err
+
+
+@pytest.mark.parametrize("visc,pp", [("LLF", False), ("ROE", False), ("GLF", True)])
+def test_rk3_weno7_matches_oracle(visc, pp):
+    xf = _xf()
+    case = CASES4["inert_sbi_32"]
+    th, g = oracle_objects(case)
+    Uo = O.fill_ghosts(g, case.U)
+    dt = 0.5 * O.cfl_dt(th, g, Uo, 0.5)
+    ctx = xf.Context.from_case(case).set_reconstruction("WENO7").set_dissipation(visc).set_positivity(pp)
+    U = ctx.state_from_numpy(case.U)
+    for _ in range(3):
+        Uo = O.rk3_step(th, g, Uo, dt, visc=visc, recon="WENO7", pp=pp)
+        ctx.rk3_step(U, dt)
+    assert ctx.status() == 0
+    scale = np.abs(Uo).reshape(Uo.shape[0], -1).max(axis=1)
+    err = field_err(U.cpu().numpy(), Uo, scale)
+    ctx.close()
+    print(f"[weno7] rk3 {visc} pp={pp} inert_sbi_32 max err {err.max():.3e}", flush=True)
+    assert err.max() <= 1e-12, err
+
+
+def test_weno7_refusals():
+    xf = _xf()
+    case3 = CASES["n1_thermal_3d"]
+    ctx3 = xf.Context.from_case(case3)
+    with pytest.raises(xf.XfError) as e:
+        ctx3.set_reconstruction("WENO7")
+    assert e.value.code == xf.XF_EUNSUPPORTED
+    ctx3.close()
+    case = CASES4["n1_thermal_3d"]
+    ctx = xf.Context.from_case(case).set_reconstruction("WENO7")
+    U = ctx.state_from_numpy(case.U)
+    ctx.fill_ghosts(U)
+    with pytest.raises(xf.XfError) as e:
+        ctx.rhs_vjp(U, torch.ones_like(U))
+    assert e.value.code == xf.XF_EUNSUPPORTED
+    with pytest.raises(xf.XfError) as e:
+        ctx.rk3_step_vjp(U, 1e-9, torch.ones_like(U))
+    assert e.value.code == xf.XF_EUNSUPPORTED
+    ctx.close()
