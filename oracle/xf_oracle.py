@@ -922,18 +922,24 @@ def ssp_rk3(L, U, dt):
     return U / 3.0 + 2.0 / 3.0 * (U2 + dt * L(U2))
 
 
-def rk3_step(th, grid, U, dt, alpha=None, pp=False, visc="LLF", recon="WENO5"):
+def rk3_step(th, grid, U, dt, alpha=None, pp=False, visc="LLF", recon="WENO5", transport=None,
+             viscous_terms=7):
     """One SSP-RK3 step of the convective system with ghosts refilled before
     every stage.  alpha: optional list of three frozen-speed dicts, one per
     stage (in stage order).  pp: blend every stage's face fluxes for
     positivity (each SSP-RK3 stage is a convex combination of Euler steps of
-    size dt)."""
+    size dt).  transport: an xf_viscous.Transport to add the viscous and
+    diffusive fluxes (Eq. 1-6; the terms selected by viscous_terms) to every
+    stage's residual."""
     a = list(alpha) if alpha is not None else [None, None, None]
     stage = [0]
 
     def L(V):
         V = fill_ghosts(grid, V)
         r = rhs(th, grid, V, a[stage[0]], pp_dt=dt if pp else None, visc=visc, recon=recon)
+        if transport is not None:
+            from .xf_viscous import viscous_rhs
+            r = r + viscous_rhs(th, transport, grid, V, viscous_terms)
         stage[0] += 1
         return r
 

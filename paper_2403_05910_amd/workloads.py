@@ -20,6 +20,8 @@ from __future__ import annotations
 
 from dataclasses import dataclass, field
 
+from math import comb
+
 import numpy as np
 
 R_UNIVERSAL = 8.314462618
@@ -113,6 +115,52 @@ def sampled_table(W_gmol, seed=0, T_lo=T_BRACKET[0], T_hi=T_BRACKET[1]):
 # ---------------------------------------------------------------------------
 # state assembly (forward direction of the EOS; input preparation only)
 # ---------------------------------------------------------------------------
+# ---------------------------------------------------------------------------
+# transport tables: the fitted form ln eta = sum_k c_k (ln T)^k (four
+# coefficients), synthetic values of the usual magnitudes for gases
+# ---------------------------------------------------------------------------
+@dataclass
+class TransportTable:
+    mu: np.ndarray           # (ns, 4): ln(mu_s / (Pa s)) = sum_k mu[s, k] (ln T)^k
+    kappa: np.ndarray        # (ns, 4): ln(kappa_s / (W/(m K)))
+    D: np.ndarray            # (ns, ns, 4), symmetric: ln(D_st / (m^2/s)) at p_ref
+    p_ref: float = 101325.0
+
+
+def _log_poly_coeffs(v0, b, c2, c3, T0=300.0):
+    """powers of ln T of ln v0 + b L + c2 L^2 + c3 L^3 with L = ln(T / T0)"""
+    l0 = np.log(T0)
+    e = (np.log(v0), b, c2, c3)
+    coef = np.zeros(4)
+    for k, ek in enumerate(e):
+        for n in range(k + 1):
+            coef[n] += ek * comb(k, n) * (-l0) ** (k - n)
+    return coef
+
+
+def sampled_transport(ns, seed=0):
+    """Seeded tables: at 300 K mu_s in [1e-5, 3e-5] Pa s, kappa_s in
+    [0.015, 0.18] W/(m K), D_st in [1e-5, 8e-5] m^2/s at 1 atm; temperature
+    exponents 0.6-0.8, 0.7-0.95 and 1.6-1.8 with small curvature."""
+    rng = np.random.default_rng(seed)
+    mu = np.array([_log_poly_coeffs(rng.uniform(1e-5, 3e-5), rng.uniform(0.6, 0.8), rng.uniform(-0.03, 0.03),
+                                    rng.uniform(-0.005, 0.005)) for _ in range(ns)])
+    kappa = np.array([_log_poly_coeffs(rng.uniform(0.015, 0.18), rng.uniform(0.7, 0.95), rng.uniform(-0.03, 0.03),
+                                       rng.uniform(-0.005, 0.005)) for _ in range(ns)])
+    D = np.zeros((ns, ns, 4))
+    for s_ in range(ns):
+        for t in range(s_, ns):
+            D[s_, t] = D[t, s_] = _log_poly_coeffs(rng.uniform(1e-5, 8e-5), rng.uniform(1.6, 1.8),
+                                                   rng.uniform(-0.03, 0.03), rng.uniform(-0.005, 0.005))
+    return TransportTable(mu, kappa, D)
+
+
+def constant_transport(ns, mu=1.8e-5, kappa=0.026, D=2e-5):
+    """temperature-independent tables (every species alike), for closed forms"""
+    c = lambda v: np.array([np.log(v), 0.0, 0.0, 0.0])  # noqa: E731
+    return TransportTable(np.tile(c(mu), (ns, 1)), np.tile(c(kappa), (ns, 1)), np.tile(c(D), (ns, ns, 1)))
+
+
 def _cp_R(tab, T):
     a = tab.a
     T = np.asarray(T, dtype=np.float64)[..., None]

@@ -287,3 +287,50 @@ def test_weno7_mirrored_minus_side_caught(monkeypatch, rng):
     orig_ff = X.face_flux
     _patch(monkeypatch, "face_flux", flux)
     assert _fails(W7.test_weno7_advected_wave_converges)
+
+
+# -- viscous fluxes (pins in test_oracle_viscous.py) ---------------------------
+import test_oracle_viscous as VI  # noqa: E402
+
+XV = O.xf_viscous
+
+
+def test_viscous_transposed_mixing_factor_caught(monkeypatch, rng):
+    orig = XV.wilke_phi
+    monkeypatch.setattr(XV, "wilke_phi", lambda W_, a: np.swapaxes(orig(W_, a), -1, -2))
+    assert _fails(VI.test_mixing_rule_reductions, rng)
+
+
+def test_viscous_cell_derivative_coefficient_caught(monkeypatch):
+    def bad(q, ax, h):
+        out = np.full(q.shape, np.nan, dtype=q.dtype)
+        L = q.shape[ax]
+
+        def sl(a, b):
+            s = [slice(None)] * q.ndim
+            s[ax] = slice(a, b)
+            return tuple(s)
+        out[sl(2, L - 2)] = (q[sl(0, L - 4)] - 7.0 * q[sl(1, L - 3)] + 7.0 * q[sl(3, L - 1)] - q[sl(4, L)]) / (12.0 * h)
+        return out
+    monkeypatch.setattr(XV, "cell_derivative", bad)
+    assert _fails(VI.test_fourth_order_stress_convergence_2d)
+
+
+def test_viscous_point_flux_difference_caught(monkeypatch):
+    # planted: the plain difference of point fluxes (second order)
+    monkeypatch.setattr(XV, "numerical_flux", lambda Fv, ax: np.take(Fv, np.arange(1, Fv.shape[ax] - 1), axis=ax))
+    assert _fails(VI.test_fourth_order_stress_convergence_2d)
+
+
+def test_viscous_linear_face_interpolation_caught(monkeypatch):
+    def bad(q, n, g, ax):
+        s = XV._face_slices(n, g, ax, q.ndim)
+        return 0.5 * (q[s[1]] + q[s[2]])
+    monkeypatch.setattr(XV, "face_value", bad)
+    assert _fails(VI.test_quadratic_shear_closed_form)
+
+
+def test_viscous_dropped_fit_term_caught(monkeypatch):
+    orig = XV.fit_eval
+    monkeypatch.setattr(XV, "fit_eval", lambda c, T: orig(c[..., :3], T))
+    assert _fails(VI.test_fit_form_reproduces_a_shifted_power_law)
