@@ -143,6 +143,8 @@ def diffusion_into_mixture(W, X, D):
     ns = len(W)
     Wbar = np.sum(X * W, axis=-1)
     out = np.zeros(X.shape)
+    if ns == 1:               # the sums over t != s are empty: a single species does not diffuse
+        return out
     for s in range(ns):
         num = 0.0
         den = 0.0
