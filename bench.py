@@ -323,8 +323,14 @@ def main():
         # same state laid out with four ghost layers)
         out["scheme_options"] = {}
         for label, visc, recon in (("ROE", "ROE", "WENO5"), ("GLF", "GLF", "WENO5"), ("CU6", "LLF", "CU6"),
-                                   ("WENO7", "LLF", "WENO7")):
-            if recon == "WENO7":
+                                   ("WENO7", "LLF", "WENO7"), ("viscous", "LLF", "WENO5")):
+            if label == "viscous":
+                # Navier-Stokes step: the viscous and diffusive fluxes of Eq. 2-6
+                # with seeded gas-like transport tables, all terms
+                from paper_2403_05910_amd import workloads as W
+                ctxo = xf.Context.from_case(case, "fp64").set_viscous(W.sampled_transport(ns, 0))
+                Uo = U0.clone()
+            elif recon == "WENO7":
                 case4 = case.with_ghosts(4)
                 ctxo = xf.Context.from_case(case4, "fp64").set_reconstruction(recon)
                 Uo = ctxo.state_from_numpy(case4.U)

@@ -204,6 +204,40 @@ int xf_set_reconstruction(xf_ctx *ctx, int type);
  * returns XF_EUNSUPPORTED while the blend is on.  enable: 0 or 1. */
 int xf_set_positivity(xf_ctx *ctx, int enable);
 
+/* Viscous and diffusive fluxes F_v of Eq. 2 (Eq. 3-6: Newtonian stress and
+ * its work, Fourier conduction, mass-corrected mixture-averaged species
+ * diffusion -rho (D_sm grad Y_s - Y_s sum_j D_jm grad Y_j) with its enthalpy
+ * flux), added to every residual of the context (xf_rhs, xf_rk3_step,
+ * xf_rk3_step_cfl) as + div F_v (Eq. 1).  Transport per cell from the
+ * fitted form of Eq. 29 with four coefficients per property:
+ *   ln(mu_s / Pa s) = sum_k mu[s*4 + k] (ln T)^k, likewise kappa (W/(m K)),
+ *   ln(D_st / (m^2/s)) = sum_k D[(s*ns + t)*4 + k] (ln T)^k at p_ref, and
+ *   D_st(T, p) = D_st(T, p_ref) p_ref / p (D must be symmetric in s, t);
+ * mixture viscosity and conductivity by the rule of Eq. 22 (Phi from the
+ * ratio of the property being mixed), D_sm by Eq. 26 with the mole
+ * fractions in its sums floored at X_t + 1e-12 (a pure species stays
+ * finite).  Discretisation: fourth order and conservative (face values
+ * (-1, 9, 9, -1)/16, normal derivatives (1, -27, 27, -1)/(24 dx),
+ * tangential ones interpolated from (1, -8, 8, -1)/(12 dy) cell
+ * differences; residual = staggered fourth-order difference of the face
+ * point fluxes).  Computed in FP64 in both precisions.  terms: a bit set of
+ * XF_VISCOUS_*; 0 switches the fluxes off (tr may then be NULL).  Host
+ * tables are copied to the device (the first call allocates that copy; the
+ * call synchronises the device).  The workspaces grow while the fluxes are
+ * on: query xf_workspace_bytes after this call.  The VJPs return
+ * XF_EUNSUPPORTED while they are on; the CFL step stays convective.
+ * Returns XF_EINVAL for a table of another species count, a non-symmetric
+ * D, p_ref <= 0, non-finite coefficients or unknown bits. */
+typedef struct {
+    int ns;
+    const double *mu;      /* [ns][4]      */
+    const double *kappa;   /* [ns][4]      */
+    const double *D;       /* [ns][ns][4]  */
+    double p_ref;          /* Pa           */
+} xf_transport;
+enum { XF_VISCOUS_STRESS = 1, XF_VISCOUS_HEAT = 2, XF_VISCOUS_DIFFUSION = 4 };
+int xf_set_viscous(xf_ctx *ctx, const xf_transport *tr, int terms);
+
 /* xf_rk3_step with the time step of Eq. 17 computed on the device from U^n
  * (the same reduction as xf_cfl_dt, reusing the first stage's primitives)
  * and written to the device double *dt_dev before the stages use it.  This
@@ -250,7 +284,11 @@ enum {
     XF_K_VJP_Z = 10,
     XF_K_PRIMS_VJP = 11,   /* implicit-function VJP of (p, T)(U)                  */
     XF_K_FILL_VJP = 12,    /* adjoint of the ghost fill                          */
-    XF_K_COUNT = 13
+    XF_K_TRANSPORT = 13,   /* transport properties and velocity gradient         */
+    XF_K_VISCOUS_X = 14,   /* x viscous flux difference                          */
+    XF_K_VISCOUS_Y = 15,
+    XF_K_VISCOUS_Z = 16,
+    XF_K_COUNT = 17
 };
 
 /* Per-kernel timing for profiling.  While enabled, every kernel launch of

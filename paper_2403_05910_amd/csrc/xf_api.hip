@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <cmath>
 #include <new>
 #include <vector>
 
@@ -37,6 +38,9 @@ struct xf_ctx {
     // per-kernel timing (off unless xf_timing enabled it)
     bool timing;
     int pp;   // positivity-preserving flux blend in the RK3 step
+    int viscous;                // XF_VISCOUS_* bits, 0 = inviscid
+    xf::TransportK *tk;         // device copy of the transport tables (xf_set_viscous)
+    double W[XF_MAX_SPECIES];   // molar masses, kg/mol
     struct Rec {
         int cls;
         hipEvent_t a, b;
@@ -55,7 +59,7 @@ size_t align_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace carve-up (byte offsets); every piece 256-byte aligned.
 struct Layout {
-    size_t P, Pbar, rec, mx, L, U0, S2, Ly, Lz, V0, V1, V2, lam0, mu, Uf, Pf, total;
+    size_t P, Pbar, rec, mx, L, U0, S2, Ly, Lz, V0, V1, V2, lam0, mu, Uf, Pf, Q, G, total;
 };
 
 Layout layout(const xf_ctx *c, int op) {
@@ -72,6 +76,12 @@ Layout layout(const xf_ctx *c, int op) {
         o += align_up((size_t)c->lc.g.cells * sizeof(float) * c->nv);
         l.Pf = o;
         o += align_up((size_t)c->lc.g.cells * sizeof(float) * 4);
+    }
+    if (c->viscous && (op == XF_OP_RHS || op == XF_OP_RK3)) {   // transport pass and velocity gradient
+        l.Q = o;
+        o += align_up(cell * xf::transport_fields(c->ns));
+        l.G = o;
+        o += align_up(cell * 9);
     }
     if (op == XF_OP_VJP || op == XF_OP_RK3_VJP) {
         l.Pbar = o;
@@ -157,12 +167,36 @@ struct Prim {
     double *P;
     float *Uf, *Pf;
     unsigned long long *mx;   // [0]: CFL maximum; [1 + 3 d .. 3 + 3 d]: GLF speeds of direction d
+    double *Q, *G;            // transport pass and velocity gradient (viscous contexts)
 };
 
 Prim prim_bufs(const xf_ctx *c, const Layout &l, void *ws) {
     const bool mixed = c->lc.precision == XF_PREC_MIXED;
+    const bool visc = c->viscous && l.G != 0;
     return {at<double>(ws, l.P), mixed ? at<float>(ws, l.Uf) : nullptr, mixed ? at<float>(ws, l.Pf) : nullptr,
-            at<unsigned long long>(ws, l.mx)};
+            at<unsigned long long>(ws, l.mx), visc ? at<double>(ws, l.Q) : nullptr,
+            visc ? at<double>(ws, l.G) : nullptr};
+}
+
+// Viscous fluxes of every active direction added to out[d] (the three may
+// be one buffer): the transport pass and the velocity gradient, then one
+// face kernel per direction.
+int viscous_into(xf_ctx *c, const double *U, const Prim &pb, double *const out[3], hipStream_t s) {
+    if (!c->viscous) return XF_OK;
+    if (!pb.Q || !pb.G) return XF_EINVAL;
+    const LaunchCtx &lc = c->lc;
+    const int n[3] = {lc.g.nx, lc.g.ny, lc.g.nz};
+    XF_TRY(timed(c, XF_K_TRANSPORT, s, [&] {
+        hipError_t e = c->ops->transport(lc, U, pb.P, pb.Q, c->tk, s);
+        if (e == hipSuccess) e = xf::launch_vel_grad(lc, pb.Q, pb.G, s);
+        return e;
+    }));
+    for (int d = 0; d < 3; ++d) {
+        if (n[d] <= 1) continue;
+        XF_TRY(timed(c, XF_K_VISCOUS_X + d, s,
+                     [&] { return c->ops->viscous(lc, d, U, pb.P, pb.Q, pb.G, out[d], c->viscous, s); }));
+    }
+    return XF_OK;
 }
 
 // GLF speeds of the active directions from the primitives just computed; a
@@ -183,7 +217,9 @@ const double *glf_of(const xf_ctx *c, const unsigned long long *mx, int d) {
 }
 
 hipError_t prims(xf_ctx *c, const double *U, const Prim &pb, hipStream_t s) {
-    hipError_t e = timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, pb.P, pb.Uf, pb.Pf, 0, s); });
+    // viscous contexts: every padded cell (the tangential derivatives read edge ghosts)
+    hipError_t e = timed(c, XF_K_PRIMS, s,
+                         [&] { return c->ops->prims(c->lc, U, pb.P, pb.Uf, pb.Pf, c->viscous ? 1 : 0, s); });
     if (e == hipSuccess) e = glf_speeds(c, U, pb.P, pb.mx, s);
     return e;
 }
@@ -213,8 +249,10 @@ int sweeps_into(xf_ctx *c, const double *U, double *rhs, const Prim &pb, const x
 int rhs_into(xf_ctx *c, const double *U, double *rhs, const Prim &pb, hipStream_t s) {
     XF_TRY(prims(c, U, pb, s));
     const xf::StageArgs off{};
-    const int r = sweeps_into(c, U, rhs, pb, off, s);
+    int r = sweeps_into(c, U, rhs, pb, off, s);
     if (r != XF_OK) return r;
+    double *const all[3] = {rhs, rhs, rhs};
+    if ((r = viscous_into(c, U, pb, all, s)) != XF_OK) return r;
     XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero_ghosts(c->lc, c->nv, rhs, s); }));
     return XF_OK;
 }
@@ -319,6 +357,9 @@ int xf_create_ghosts(const xf_grid *grid, const xf_thermo *thermo, int precision
     if (!c) return XF_ENOMEM;
     c->timing = false;
     c->pp = 0;
+    c->viscous = 0;
+    c->tk = nullptr;
+    for (int s = 0; s < thermo->ns; ++s) c->W[s] = thermo->W[s];
     xf::Geo &g = c->lc.g;
     g.nx = grid->nx;
     g.ny = grid->ny;
@@ -372,6 +413,7 @@ int xf_destroy(xf_ctx *c) {
         (void)hipEventDestroy(r.b);
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
+    if (c->tk) (void)hipFree(c->tk);
     const hipError_t e = hipFree(c->lc.status);
     delete c;
     return dev_err(e);
@@ -492,6 +534,8 @@ int rk3_step(xf_ctx *c, double *U, double dt, const double *dt_in, double cfl, d
             XF_TRY(timed(c, XF_K_SWEEP_X + d, s,
                          [&] { return c->ops->sweep(lc, d, 0, in[k], P, pb.Uf, pb.Pf, Ld[d], sw, glf_of(c, pb.mx, d), s); }));
         }
+        const int r = viscous_into(c, in[k], pb, Ld, s);
+        if (r != XF_OK) return r;
         XF_TRY(timed(c, XF_K_STAGE, s, [&] {
             return xf::launch_rk3_stage_sum(lc, c->nv, out[k], U, in[k], Lsum, a[k], b[k], dt, h, s);
         }));
@@ -513,6 +557,48 @@ int xf_set_reconstruction(xf_ctx *c, int type) {
     const xf::Geo &g = c->lc.g;
     if (type == XF_RECON_WENO7 && (g.gx > 0 ? g.gx : g.gy > 0 ? g.gy : g.gz) < 4) return XF_EUNSUPPORTED;
     c->lc.recon = type;
+    return XF_OK;
+}
+
+int xf_set_viscous(xf_ctx *c, const xf_transport *tr, int terms) {
+    if (!c) return XF_EINVAL;
+    if (terms & ~(XF_VISCOUS_STRESS | XF_VISCOUS_HEAT | XF_VISCOUS_DIFFUSION)) return XF_EINVAL;
+    if (terms == 0) {
+        c->viscous = 0;
+        return XF_OK;
+    }
+    const int ns = c->ns;
+    if (!tr || tr->ns != ns || !tr->mu || !tr->kappa || !tr->D || !(tr->p_ref > 0.0) || !std::isfinite(tr->p_ref))
+        return XF_EINVAL;
+    xf::TransportK h;
+    memset(&h, 0, sizeof(h));
+    for (int s = 0; s < ns; ++s) {
+        for (int k = 0; k < 4; ++k) {
+            h.mu[s][k] = tr->mu[s * 4 + k];
+            h.kappa[s][k] = tr->kappa[s * 4 + k];
+            if (!std::isfinite(h.mu[s][k]) || !std::isfinite(h.kappa[s][k])) return XF_EINVAL;
+        }
+        for (int t = 0; t < ns; ++t)
+            for (int k = 0; k < 4; ++k) {
+                const double v = tr->D[(s * ns + t) * 4 + k];
+                if (!std::isfinite(v) || v != tr->D[(t * ns + s) * 4 + k]) return XF_EINVAL;
+                h.D[s][t][k] = v;
+            }
+        h.W[s] = c->W[s];
+        h.iW[s] = 1.0 / c->W[s];
+    }
+    for (int s = 0; s < ns; ++s)
+        for (int t = 0; t < ns; ++t) {
+            h.wa[s][t] = 1.0 / (std::sqrt(8.0) * std::sqrt(1.0 + c->W[s] / c->W[t]));
+            h.wb[s][t] = std::pow(c->W[t] / c->W[s], 0.25);
+        }
+    h.ip_ref = 1.0 / tr->p_ref;
+    if (!c->tk && hipMalloc(reinterpret_cast<void **>(&c->tk), sizeof(xf::TransportK)) != hipSuccess) {
+        c->tk = nullptr;
+        return XF_ENOMEM;
+    }
+    if (hipMemcpy(c->tk, &h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess) return XF_EDEVICE;
+    c->viscous = terms;
     return XF_OK;
 }
 
@@ -538,7 +624,7 @@ int xf_rhs_vjp(xf_ctx *c, const double *U, const double *rbar, double *Ubar, voi
     if (!c || !U || !rbar || !Ubar || !ws || Ubar == U || Ubar == rbar || !aligned8(U) || !aligned8(rbar) ||
         !aligned8(Ubar) || !aligned8(ws))
         return XF_EINVAL;
-    if (c->lc.recon == XF_RECON_WENO7) return XF_EUNSUPPORTED;
+    if (c->lc.recon == XF_RECON_WENO7 || c->viscous) return XF_EUNSUPPORTED;
     const Layout l = layout(c, XF_OP_VJP);
     return rhs_vjp_into(c, U, rbar, Ubar, at<double>(ws, l.P), at<double>(ws, l.Pbar), at<double>(ws, l.rec),
                         at<unsigned long long>(ws, l.mx), (hipStream_t)stream);
@@ -549,7 +635,7 @@ int xf_rk3_step_vjp(xf_ctx *c, const double *Un, double dt, double *Ubar, void *
         !(dt >= 0.0))
         return XF_EINVAL;
     if (c->pp) return XF_EUNSUPPORTED;   // the adjoint is of the unblended step
-    if (c->lc.recon == XF_RECON_WENO7) return XF_EUNSUPPORTED;
+    if (c->lc.recon == XF_RECON_WENO7 || c->viscous) return XF_EUNSUPPORTED;
     const Layout l = layout(c, XF_OP_RK3_VJP);
     const hipStream_t s = (hipStream_t)stream;
     const LaunchCtx &lc = c->lc;

@@ -42,6 +42,27 @@ struct ThermoK {
     int bracket;
 };
 
+// Fitted transport (Eq. 29) and the species constants of the mixing rules
+// (Eq. 22, 26), in device memory (too large for kernel arguments):
+//   ln mu_s = sum_k mu[s][k] (ln T)^k, likewise kappa_s, and
+//   ln D_st(T, p_ref) = sum_k D[s][t][k] (ln T)^k, D_st(T, p) = D_st(T, p_ref) p_ref / p;
+//   wa[s][t] = (1 + W_s/W_t)^(-1/2) / sqrt(8), wb[s][t] = (W_t/W_s)^(1/4).
+struct TransportK {
+    double mu[kMaxNs][4];
+    double kappa[kMaxNs][4];
+    double D[kMaxNs][kMaxNs][4];
+    double wa[kMaxNs][kMaxNs];
+    double wb[kMaxNs][kMaxNs];
+    double W[kMaxNs];       // kg/mol
+    double iW[kMaxNs];
+    double ip_ref;          // 1 / p_ref
+};
+// Viscous terms (bit set): stress with its work, Fourier conduction,
+// species diffusion with its enthalpy flux.
+constexpr int kViscousStress = 1, kViscousHeat = 2, kViscousDiffusion = 4;
+// Per-cell fields of the transport pass: mu_bar, kappa_bar, u, v, w, D_sm (NS).
+inline int transport_fields(int ns) { return 5 + ns; }
+
 // Optional fused SSP-RK3 stage on the last sweep of a right-hand side:
 // instead of rhs, write Uout = a U0 + b (Uin + dt L) with L the finished
 // residual (a == 0 skips U0).  dt is *dt_dev when dt_dev is set.
@@ -96,6 +117,13 @@ struct NsOps {
     // CFL reduction: max_i sum_d (|u_d| + c)/dx_d -> atomicMax on *mx (uint64 bits)
     hipError_t (*cfl)(const LaunchCtx &, const double *U, const double *P,
                       unsigned long long *mx, hipStream_t);
+    // transport pass at every padded cell: Q[transport_fields(ns)][cells]
+    hipError_t (*transport)(const LaunchCtx &, const double *U, const double *P, double *Q, const TransportK *tk,
+                            hipStream_t);
+    // viscous fluxes of one direction, added to rhs on the interior; G the
+    // cell-centred velocity gradient [9][cells] (G[3 a + b] = d u_b / d x_a)
+    hipError_t (*viscous)(const LaunchCtx &, int dir, const double *U, const double *P, const double *Q,
+                          const double *G, double *rhs, int terms, hipStream_t);
 };
 
 const NsOps *ops_for_ns(int ns);
@@ -144,6 +172,10 @@ hipError_t launch_rk3_stage_sum(const LaunchCtx &, int nv, double *Uout, const d
 hipError_t launch_axpy_state(long long n, double a, const double *x, double b, double *y,
                              hipStream_t);
 hipError_t launch_cfl_reset(unsigned long long *mx, hipStream_t);
+// cell-centred velocity gradient from the velocity fields Q[2..4] of the
+// transport pass: G[3 a + b][cells], fourth-order differences along every
+// active axis a at the cells two or more layers inside the padded extent
+hipError_t launch_vel_grad(const LaunchCtx &, const double *Q, double *G, hipStream_t);
 hipError_t launch_reset_u64(unsigned long long *p, int n, hipStream_t);
 hipError_t launch_cfl_finish(const unsigned long long *mx, double cfl, double *dt_dev,
                              hipStream_t);

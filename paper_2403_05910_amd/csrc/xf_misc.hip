@@ -190,6 +190,34 @@ __global__ __launch_bounds__(256) void k_copy(long long n, const double *src, do
     if (q < n) dst[q] = src[q];
 }
 
+// Cell-centred velocity gradient G[3 a + b] = d u_b / d x_a by the
+// fourth-order difference (u_{-2} - 8 u_{-1} + 8 u_{+1} - u_{+2}) / (12 dx_a)
+// at every cell two or more layers inside the padded extent along an active
+// axis a (the velocity u_b is Q[2 + b] of the transport pass); the other
+// entries are left as they are (no face stencil reads them).
+__global__ __launch_bounds__(256) void k_vel_grad(const double *__restrict__ Q, double *__restrict__ G, Geo g) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.cells) return;
+    const long long C = g.cells;
+    const int x = (int)(idx % g.px);
+    const long long r = idx / g.px;
+    const int co[3] = {x, (int)(r % g.py), (int)(r / g.py)};
+    const int n[3] = {g.nx, g.ny, g.nz}, p[3] = {g.px, g.py, g.pz};
+    const long long st[3] = {1, g.sy, g.sz};
+    const double ih[3] = {g.idx, g.idy, g.idz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (n[a] <= 1 || co[a] < 2 || co[a] >= p[a] - 2) continue;
+        const long long s = st[a];
+        const double f = ih[a] * (1.0 / 12.0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const double *u = Q + (2 + b) * C + idx;
+            G[(3 * a + b) * C + idx] = (u[-2 * s] - 8.0 * u[-s] + 8.0 * u[s] - u[2 * s]) * f;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_zero(long long n, double *dst) {
     const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (q < n) dst[q] = 0.0;
@@ -254,6 +282,11 @@ hipError_t launch_rk3_stage_sum(const LaunchCtx &c, int nv, double *Uout, const 
 
 hipError_t launch_axpy_state(long long n, double a, const double *x, double b, double *y, hipStream_t s) {
     hipLaunchKernelGGL(k_axpby, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, a, x, b, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_vel_grad(const LaunchCtx &c, const double *Q, double *G, hipStream_t s) {
+    hipLaunchKernelGGL(k_vel_grad, dim3(blocks_for(c.g.cells, 256)), dim3(256), 0, s, Q, G, c.g);
     return hipGetLastError();
 }
 

@@ -2,6 +2,7 @@
 // count.  Compiled once per N with -DXF_NS=N; each object exports
 // xf::ops_ns<N>(), which the C ABI collects into its dispatch table.
 #include "xf_forward.hpp"
+#include "xf_viscous.hpp"
 #include "xf_vjp.hpp"
 
 #ifndef XF_NS
@@ -194,7 +195,32 @@ hipError_t cfl(const LaunchCtx &c, const double *U, const double *P, unsigned lo
     return hipGetLastError();
 }
 
-const NsOps kOps = {prims, sweep, sweep_vjp, glf, prims_vjp, cfl};
+hipError_t transport(const LaunchCtx &c, const double *U, const double *P, double *Q, const TransportK *tk,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_transport<NS>, dim3(blocks_for(c.g.cells, 256)), dim3(256), 0, s, U, P, Q, c.g, tk);
+    return hipGetLastError();
+}
+
+hipError_t viscous(const LaunchCtx &c, int dir, const double *U, const double *P, const double *Q, const double *G,
+                   double *rhs, int terms, hipStream_t s) {
+    const Geo &g = c.g;
+    if (dir == 0) {
+        const long long nf = ((long long)g.nx + 3) * g.ny * g.nz;
+        const unsigned nb = (unsigned)((nf - 3 + (kViscXBlock - 4)) / (kViscXBlock - 3));   // blocks overlap by three
+        hipLaunchKernelGGL(k_visc_x<NS>, dim3(nb), dim3(kViscXBlock), 0, s, U, P, Q, G, rhs, g, c.th64, terms);
+        return hipGetLastError();
+    }
+    const int nsw = dir == 1 ? g.ny : g.nz;
+    const int ntr = dir == 1 ? g.nz : g.ny;
+    dim3 grid((g.nx + kViscTX - 1) / kViscTX, (nsw + kViscTS - 4) / (kViscTS - 3), ntr), block(kViscTX, kViscTS);
+    if (dir == 1)
+        hipLaunchKernelGGL((k_visc_tile<NS, 1>), grid, block, 0, s, U, P, Q, G, rhs, g, c.th64, terms);
+    else
+        hipLaunchKernelGGL((k_visc_tile<NS, 2>), grid, block, 0, s, U, P, Q, G, rhs, g, c.th64, terms);
+    return hipGetLastError();
+}
+
+const NsOps kOps = {prims, sweep, sweep_vjp, glf, prims_vjp, cfl, transport, viscous};
 
 }  // namespace
 

@@ -47,6 +47,10 @@ class xf_thermo(ctypes.Structure):
     _fields_ = [("ns", _c_int), ("W", _dp), ("a", _dp), ("T_lo", _c_double), ("T_hi", _c_double)]
 
 
+class xf_transport(ctypes.Structure):
+    _fields_ = [("ns", _c_int), ("mu", _dp), ("kappa", _dp), ("D", _dp), ("p_ref", _c_double)]
+
+
 def _sig(name, res, *args):
     f = getattr(_lib, name)
     f.restype = res
@@ -69,6 +73,7 @@ _rk3 = _sig("xf_rk3_step", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
 _set_pp = _sig("xf_set_positivity", _c_int, _vp, _c_int)
 _set_visc = _sig("xf_set_dissipation", _c_int, _vp, _c_int)
 _set_recon = _sig("xf_set_reconstruction", _c_int, _vp, _c_int)
+_set_viscous = _sig("xf_set_viscous", _c_int, _vp, ctypes.POINTER(xf_transport), _c_int)
 _rk3_cfl = _sig("xf_rk3_step_cfl", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
 _rhs_vjp = _sig("xf_rhs_vjp", _c_int, _vp, _vp, _vp, _vp, _vp, _vp)
 _rk3_vjp = _sig("xf_rk3_step_vjp", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
@@ -79,10 +84,13 @@ _strerror = _sig("xf_strerror", ctypes.c_char_p, _c_int)
 
 EXPORTED = ["xf_create", "xf_create_ghosts", "xf_destroy", "xf_state_elems", "xf_workspace_bytes", "xf_fill_ghosts",
             "xf_fill_ghosts_vjp", "xf_rhs", "xf_primitives", "xf_cfl_dt", "xf_rk3_step", "xf_rk3_step_cfl",
-            "xf_set_dissipation", "xf_set_reconstruction", "xf_set_positivity", "xf_rhs_vjp", "xf_rk3_step_vjp",
+            "xf_set_dissipation", "xf_set_reconstruction", "xf_set_positivity", "xf_set_viscous", "xf_rhs_vjp", "xf_rk3_step_vjp",
             "xf_status", "xf_strerror", "xf_timing", "xf_timing_read"]
+XF_VISCOUS_STRESS, XF_VISCOUS_HEAT, XF_VISCOUS_DIFFUSION = 1, 2, 4
+VISCOUS_TERMS = {"stress": XF_VISCOUS_STRESS, "heat": XF_VISCOUS_HEAT, "diffusion": XF_VISCOUS_DIFFUSION}
 KERNEL_CLASSES = ["prims", "sweep_x", "sweep_y", "sweep_z", "fill", "stage", "cfl", "zero",
-                  "vjp_x", "vjp_y", "vjp_z", "prims_vjp", "fill_vjp"]
+                  "vjp_x", "vjp_y", "vjp_z", "prims_vjp", "fill_vjp", "transport", "viscous_x", "viscous_y",
+                  "viscous_z"]
 
 
 class XfError(RuntimeError):
@@ -165,6 +173,11 @@ def xf_set_positivity(ctx, enable):
     return _check(_set_pp(ctx, int(bool(enable))), "xf_set_positivity")
 
 
+def xf_set_viscous(ctx, transport, terms):
+    ptr = None if transport is None else ctypes.byref(transport)
+    return _check(_set_viscous(ctx, ptr, int(terms)), "xf_set_viscous")
+
+
 def xf_rk3_step_cfl(ctx, U, cfl, dt_dev, ws, stream):
     return _check(_rk3_cfl(ctx, U, cfl, dt_dev, ws, stream), "xf_rk3_step_cfl")
 
@@ -231,6 +244,7 @@ class Context:
         self.positivity = False
         self.visc = "LLF"
         self.recon = "WENO5"
+        self.viscous = 0
         self.ghost_width = int(ghost_width)
         g = [self.ghost_width if k > 1 else 0 for k in self.n]
         self.shape = (self.nv, self.n[2] + 2 * g[2], self.n[1] + 2 * g[1], self.n[0] + 2 * g[0])
@@ -326,6 +340,27 @@ class Context:
         "WENO7" (the last needs ghost_width 4)"""
         xf_set_reconstruction(self.handle, RECON[recon])
         self.recon = recon
+        return self
+
+    def set_viscous(self, table, terms=("stress", "heat", "diffusion")):
+        """viscous and diffusive fluxes in every residual of the context:
+        table with mu (ns, 4), kappa (ns, 4), D (ns, ns, 4) and p_ref (the
+        fitted transport), terms a subset of "stress", "heat", "diffusion"
+        (an empty one, or table None, switches them off)"""
+        bits = 0
+        for t in terms:
+            bits |= VISCOUS_TERMS[t]
+        if table is None or bits == 0:
+            xf_set_viscous(self.handle, None, 0)
+        else:
+            mu = np.ascontiguousarray(table.mu, dtype=np.float64).reshape(self.ns, 4)
+            kappa = np.ascontiguousarray(table.kappa, dtype=np.float64).reshape(self.ns, 4)
+            D = np.ascontiguousarray(table.D, dtype=np.float64).reshape(self.ns, self.ns, 4)
+            tr = xf_transport(self.ns, mu.ctypes.data_as(_dp), kappa.ctypes.data_as(_dp), D.ctypes.data_as(_dp),
+                              float(table.p_ref))
+            xf_set_viscous(self.handle, tr, bits)
+        self.viscous = bits if table is not None else 0
+        self._ws.clear()          # the workspaces grow while the fluxes are on
         return self
 
     def set_positivity(self, enable=True):
