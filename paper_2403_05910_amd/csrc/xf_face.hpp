@@ -327,31 +327,34 @@ struct Dissip {
     int recon;   // kReconWeno5, kReconCu6 or kReconWeno7
 };
 
+// Stencil half width of a reconstruction: 3 (six cells i-2..i+3; WENO5,
+// CU6) or 4 (eight cells i-3..i+4; WENO7).
+constexpr int stencil_radius(int rec) { return rec == kReconWeno7 ? 4 : 3; }
+
 // Reconstruction of one characteristic field at the face from the split
-// values of the stencil cells.  RAD = 3 (cells i-2..i+3): WENO5-JS of g+ on
-// cells i-2..i+2 plus g- mirrored on i+3..i-1, or WENO-CU6 of both on all
-// six cells.  RAD = 4 (cells i-3..i+4): WENO7-JS of g+ on i-3..i+3 plus g-
-// mirrored on i+4..i-2.
-template <bool OPTS, int RAD, typename R>
-XF_HD R recon_pair(const R *gp, const R *gm, int recon) {
-    if constexpr (RAD == 4) {
+// values of the stencil cells: WENO5-JS of g+ on cells i-2..i+2 plus g-
+// mirrored on i+3..i-1; WENO-CU6 of both on all six cells; WENO7-JS of g+
+// on i-3..i+3 plus g- mirrored on i+4..i-2.
+template <int REC, typename R>
+XF_HD R recon_pair(const R *gp, const R *gm) {
+    if constexpr (REC == kReconWeno7)
         return weno7(gp[0], gp[1], gp[2], gp[3], gp[4], gp[5], gp[6]) +
                weno7(gm[7], gm[6], gm[5], gm[4], gm[3], gm[2], gm[1]);
-    }
-    if constexpr (OPTS) {
-        if (recon == kReconCu6)
-            return weno_cu6(gp[0], gp[1], gp[2], gp[3], gp[4], gp[5]) +
-                   weno_cu6(gm[5], gm[4], gm[3], gm[2], gm[1], gm[0]);
-    }
-    return weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
+    else if constexpr (REC == kReconCu6)
+        return weno_cu6(gp[0], gp[1], gp[2], gp[3], gp[4], gp[5]) +
+               weno_cu6(gm[5], gm[4], gm[3], gm[2], gm[1], gm[0]);
+    else
+        return weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
 }
 
-// VISC = false compiles the default scheme only (LLF speeds, WENO5; ds is
-// ignored); VISC = true follows ds.type and ds.recon at run time.  RAD is the
-// stencil half width: 3 (six cells; WENO5, CU6) or 4 (eight cells; WENO7).
-template <int NS, typename R, int DIR, bool FENCE = false, bool VISC = false, int RAD = 3, class St, class Out>
+// SPD (kVisc*) and REC (kRecon*) select the artificial viscosity and the
+// reconstruction at compile time, so every combination is its own code with
+// no run-time switch left in it (ROE and GLF skip the stencil maxima
+// altogether); ds supplies the GLF speeds.
+template <int NS, typename R, int DIR, bool FENCE = false, int SPD = kViscLlf, int REC = kReconWeno5, class St,
+          class Out>
 XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned &flags, const Dissip &ds) {
-    static_assert(RAD == 3 || RAD == 4, "stencil half width");
+    constexpr int RAD = stencil_radius(REC);
     constexpr int W = 2 * RAD;       // stencil cells
     constexpr int CL = RAD - 1;      // slot of cell i (left of the face)
     constexpr int CR = RAD;          // slot of cell i+1
@@ -424,20 +427,22 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
         DU[m] = dpU * ic2;
         DF[m] = dpF * ic2;
         rh[m] = sr;
-        aM = rmax(aM, rabs(unm - cm));
-        a0 = rmax(a0, rabs(unm));
-        aP = rmax(aP, rabs(unm + cm));
-    }
-    if constexpr (VISC) {
-        if (ds.type == kViscRoe) {
-            aM = rabs(utn - ct);
-            a0 = rabs(utn);
-            aP = rabs(utn + ct);
-        } else if (ds.type == kViscGlf) {
-            aM = R(ds.glf[0]);
-            a0 = R(ds.glf[1]);
-            aP = R(ds.glf[2]);
+        if constexpr (SPD == kViscLlf) {
+            aM = rmax(aM, rabs(unm - cm));
+            a0 = rmax(a0, rabs(unm));
+            aP = rmax(aP, rabs(unm + cm));
+        } else {
+            (void)cm;
         }
+    }
+    if constexpr (SPD == kViscRoe) {
+        aM = rabs(utn - ct);
+        a0 = rabs(utn);
+        aP = rabs(utn + ct);
+    } else if constexpr (SPD == kViscGlf) {
+        aM = R(ds.glf[0]);
+        a0 = R(ds.glf[1]);
+        aP = R(ds.glf[2]);
     }
 
     if (FENCE) XF_FENCE();
@@ -457,8 +462,8 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
             gPp[m] = R(0.5) * (wFp + aP * wUp);
             gPm[m] = R(0.5) * (wFp - aP * wUp);
         }
-        hm = recon_pair<VISC, RAD>(gMp, gMm, ds.recon);
-        hp = recon_pair<VISC, RAD>(gPp, gPm, ds.recon);
+        hm = recon_pair<REC>(gMp, gMm);
+        hp = recon_pair<REC>(gPp, gPm);
     }
     const R Asum = hm + hp, Dif = hp - hm;
 
@@ -474,7 +479,7 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
             gp[m] = R(0.5) * (wF + a0 * wU);
             gm[m] = R(0.5) * (wF - a0 * wU);
         }
-        h1 = recon_pair<VISC, RAD>(gp, gm, ds.recon);
+        h1 = recon_pair<REC>(gp, gm);
 #pragma unroll
         for (int m = 0; m < W; ++m) {
             const R wU = R(st.u(I2, m)) - ut2 * rh[m];
@@ -482,7 +487,7 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
             gp[m] = R(0.5) * (wF + a0 * wU);
             gm[m] = R(0.5) * (wF - a0 * wU);
         }
-        h2 = recon_pair<VISC, RAD>(gp, gm, ds.recon);
+        h2 = recon_pair<REC>(gp, gm);
     }
 
     // ---- species fields, back-projected as they come ----------------------
@@ -500,7 +505,7 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
             gp[m] = R(0.5) * (wF + a0 * wU);
             gm[m] = R(0.5) * (wF - a0 * wU);
         }
-        const R hs = recon_pair<VISC, RAD>(gp, gm, ds.recon);
+        const R hs = recon_pair<REC>(gp, gm);
         out(s, Yt[s] * Asum + hs);
         gsum += hs;
         gE += (q2 - chi[s] * iGam) * hs;

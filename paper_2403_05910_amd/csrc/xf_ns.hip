@@ -23,14 +23,14 @@ hipError_t prims(const LaunchCtx &c, const double *U, double *P, float *Uf, floa
     return hipGetLastError();
 }
 
-template <typename R, typename S, bool PP, bool VISC, int RAD>
+template <typename R, typename S, bool PP, int SPD, int REC>
 hipError_t launch_face_sweep(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumulate, const S *U,
                              const S *P, double *rhs, const StageArgs &sa, const Dissip &ds, hipStream_t s) {
     const Geo &g = c.g;
     if (dir == 0) {
         const long long nf = (long long)(g.nx + 1) * g.ny * g.nz;
         const unsigned nb = (unsigned)((nf - 1 + (kXBlock - 2)) / (kXBlock - 1));   // blocks overlap by one face
-        hipLaunchKernelGGL((k_sweep_x<NS, R, S, PP, VISC, RAD>), dim3(nb), dim3(kXBlock), 0, s, U, P, rhs, g, th,
+        hipLaunchKernelGGL((k_sweep_x<NS, R, S, PP, SPD, REC>), dim3(nb), dim3(kXBlock), 0, s, U, P, rhs, g, th,
                            accumulate, sa, c.status, ds);
         return hipGetLastError();
     }
@@ -39,12 +39,41 @@ hipError_t launch_face_sweep(const LaunchCtx &c, const ThermoK<R> &th, int dir, 
     const unsigned tiles = (unsigned)((nsw + kTileS - 2) / (kTileS - 1));
     dim3 grid((g.nx + kTileX - 1) / kTileX, tiles, ntr), block(kTileX, kTileS);
     if (dir == 1)
-        hipLaunchKernelGGL((k_sweep_tile<NS, R, 1, S, PP, VISC, RAD>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
+        hipLaunchKernelGGL((k_sweep_tile<NS, R, 1, S, PP, SPD, REC>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
                            sa, c.status, ds);
     else
-        hipLaunchKernelGGL((k_sweep_tile<NS, R, 2, S, PP, VISC, RAD>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
+        hipLaunchKernelGGL((k_sweep_tile<NS, R, 2, S, PP, SPD, REC>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
                            sa, c.status, ds);
     return hipGetLastError();
+}
+
+// One instance per (positivity blend, artificial viscosity, reconstruction).
+template <typename R, typename S, bool PP, int SPD>
+hipError_t face_sweep_rec(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumulate, const S *U, const S *P,
+                          double *rhs, const StageArgs &sa, const Dissip &ds, hipStream_t s) {
+    switch (ds.recon) {
+        case kReconCu6: return launch_face_sweep<R, S, PP, SPD, kReconCu6>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
+        case kReconWeno7:
+            return launch_face_sweep<R, S, PP, SPD, kReconWeno7>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
+        default: return launch_face_sweep<R, S, PP, SPD, kReconWeno5>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
+    }
+}
+
+template <typename R, typename S, bool PP>
+hipError_t face_sweep_spd(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumulate, const S *U, const S *P,
+                          double *rhs, const StageArgs &sa, const Dissip &ds, hipStream_t s) {
+    switch (ds.type) {
+        case kViscRoe: return face_sweep_rec<R, S, PP, kViscRoe>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
+        case kViscGlf: return face_sweep_rec<R, S, PP, kViscGlf>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
+        default: return face_sweep_rec<R, S, PP, kViscLlf>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
+    }
+}
+
+template <typename R, typename S>
+hipError_t face_sweep_scheme(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumulate, const S *U,
+                             const S *P, double *rhs, const StageArgs &sa, const Dissip &ds, hipStream_t s) {
+    return sa.pp ? face_sweep_spd<R, S, true>(c, th, dir, accumulate, U, P, rhs, sa, ds, s)
+                 : face_sweep_spd<R, S, false>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
 }
 
 template <typename R, typename S>
@@ -53,18 +82,8 @@ hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumu
     const Geo &g = c.g;
     // c.variant (measurement only) 1 or 2 runs the y/z column march (LLF, no
     // positivity blend) instead of the tiled kernel
-    if (dir == 0 || c.variant == 0 || sa.pp || ds.type != kViscLlf || ds.recon != kReconWeno5) {
-        // eight-cell stencils (WENO7): their own instances, scheme options on
-        if (ds.recon == kReconWeno7)
-            return sa.pp ? launch_face_sweep<R, S, true, true, 4>(c, th, dir, accumulate, U, P, rhs, sa, ds, s)
-                         : launch_face_sweep<R, S, false, true, 4>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
-        const bool v = ds.type != kViscLlf || ds.recon != kReconWeno5;
-        if (sa.pp)
-            return v ? launch_face_sweep<R, S, true, true, 3>(c, th, dir, accumulate, U, P, rhs, sa, ds, s)
-                     : launch_face_sweep<R, S, true, false, 3>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
-        return v ? launch_face_sweep<R, S, false, true, 3>(c, th, dir, accumulate, U, P, rhs, sa, ds, s)
-                 : launch_face_sweep<R, S, false, false, 3>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
-    }
+    if (dir == 0 || c.variant == 0 || sa.pp || ds.type != kViscLlf || ds.recon != kReconWeno5)
+        return face_sweep_scheme<R, S>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
     const int ntr = dir == 1 ? g.nz : g.ny;
     int nseg, seglen;
     march_shape(g, dir, &nseg, &seglen);
