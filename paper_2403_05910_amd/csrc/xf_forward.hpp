@@ -238,20 +238,32 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(sweep_w
 
 // ---------------------------------------------------------------------------
 // Tiled y/z sweep: one face per thread, like the x sweep.  A block is a tile
-// of kTileX x-columns by kTileS consecutive faces along the sweep axis (in one
-// plane of the third axis); tiles overlap by one face along the sweep axis,
-// so each finishes kTileS - 1 cells per column.  Lanes run along x, so every
-// stencil load of a wave reads whole rows (16 doubles = one 128-byte line).
+// of TileShape<R>::x x-columns by TileShape<R>::s consecutive faces along
+// the sweep axis (in one plane of the third axis); tiles overlap by one face
+// along the sweep axis, so each finishes s - 1 cells per column.  Lanes run
+// along x, so every stencil load of a wave reads whole rows (one 128-byte
+// line: 16 doubles or 32 floats).
 // Tiles that are neighbours along the sweep axis share six stencil rows and
 // are numbered to run on the same XCD.
 // ---------------------------------------------------------------------------
-constexpr int kTileX = 16, kTileS = 16;
+// Tile shape per arithmetic type (measured at 256^3, nine species, among
+// 16 x 16, 32 x 8, 64 x 4, 64 x 8, 32 x 16): FP64 16 x 16 (y/z 2.78/2.96 ms;
+// the others 1-12 % slower); FP32 32 x 8 (1.61/1.67 ms against 1.72/1.81).
+template <typename R>
+struct TileShape {
+    static constexpr int x = 32, s = 8;
+};
+template <>
+struct TileShape<double> {
+    static constexpr int x = 16, s = 16;
+};
 
 template <int NS, typename R, int DIR, typename S, bool PP, int SPD, int REC>
-__global__ __launch_bounds__(kTileX *kTileS) __attribute__((amdgpu_waves_per_eu(sweep_waves<R, REC>()))) void
+__global__ __launch_bounds__(TileShape<R>::x *TileShape<R>::s) __attribute__((amdgpu_waves_per_eu(sweep_waves<R, REC>()))) void
 k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, double *__restrict__ rhs, Geo g, ThermoK<R> th,
              int accumulate, StageArgs sa, unsigned *status, Dissip ds) {
     constexpr int NV = NS + 4;
+    constexpr int kTileX = TileShape<R>::x, kTileS = TileShape<R>::s;
     __shared__ R sF[NV][kTileS][kTileX];
     unsigned bx, by, bz;
     xcd_block(bx, by, bz);

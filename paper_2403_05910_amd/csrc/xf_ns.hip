@@ -36,8 +36,9 @@ hipError_t launch_face_sweep(const LaunchCtx &c, const ThermoK<R> &th, int dir, 
     }
     const int ntr = dir == 1 ? g.nz : g.ny;
     const int nsw = dir == 1 ? g.ny : g.nz;
-    const unsigned tiles = (unsigned)((nsw + kTileS - 2) / (kTileS - 1));
-    dim3 grid((g.nx + kTileX - 1) / kTileX, tiles, ntr), block(kTileX, kTileS);
+    constexpr int TX = TileShape<R>::x, TS = TileShape<R>::s;
+    const unsigned tiles = (unsigned)((nsw + TS - 2) / (TS - 1));
+    dim3 grid((g.nx + TX - 1) / TX, tiles, ntr), block(TX, TS);
     if (dir == 1)
         hipLaunchKernelGGL((k_sweep_tile<NS, R, 1, S, PP, SPD, REC>), grid, block, 0, s, U, P, rhs, g, th, accumulate,
                            sa, c.status, ds);
