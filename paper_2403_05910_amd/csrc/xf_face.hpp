@@ -77,7 +77,8 @@ XF_HD R e_species(const ThermoK<R> &th, int s, R T) {
 // linear weights times 10 (1, 6, 3), and the candidates times 6, their 1/6
 // applied once to the denominator;
 // alpha_k / sum alpha = d_k prod_{j!=k} s_j / sum(...), s_k = (eps + beta_k)^2.
-XF_HD double weno5(double a, double b, double c, double d, double e) {
+// The value as numerator over denominator, N / D.
+XF_HD void weno5_nd(double a, double b, double c, double d, double e, double &N, double &D) {
     const double q0 = 2.0 * a - 7.0 * b + 11.0 * c;
     const double q1 = -b + 5.0 * c + 2.0 * d;
     const double q2 = 2.0 * c + 5.0 * d - e;
@@ -91,7 +92,42 @@ XF_HD double weno5(double a, double b, double c, double d, double e) {
     s1 *= s1;
     s2 *= s2;
     const double w0 = s1 * s2, w1 = 6.0 * (s0 * s2), w2 = 3.0 * (s0 * s1);
-    return (w0 * q0 + w1 * q1 + w2 * q2) / (6.0 * (w0 + w1 + w2));
+    N = w0 * q0 + w1 * q1 + w2 * q2;
+    D = 6.0 * (w0 + w1 + w2);
+}
+
+XF_HD double weno5(double a, double b, double c, double d, double e) {
+    double N, D;
+    weno5_nd(a, b, c, d, e, N, D);
+    return N / D;
+}
+
+// FP64 reciprocal of a positive normal number: the hardware estimate refined
+// by two Newton-Raphson steps r <- r + r (1 - x r) (each step squares the
+// relative error), about 1 ulp, in 5 instructions where the IEEE division
+// sequence takes 11.
+XF_HD double rcp_nr(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+    double r = __builtin_amdgcn_rcp(x);
+#else
+    double r = 1.0 / x;
+#endif
+    double e = fma(-x, r, 1.0);
+    r = fma(e, r, r);
+    e = fma(-x, r, 1.0);
+    return fma(e, r, r);
+}
+
+// Both sides of one characteristic field: weno5(a..e) + weno5(f..j) with one
+// reciprocal, N_p / D_p + N_m / D_m = (N_p D_m + N_m D_p) / (D_p D_m).  Each
+// D lies between 1e-19 ((12e-6)^4) and about 1e170 for any characteristic
+// flux below 1e20, so the product stays a normal double.
+XF_HD double weno5_pair(double a, double b, double c, double d, double e, double f, double g, double h,
+                        double i, double j) {
+    double Np, Dp, Nm, Dm;
+    weno5_nd(a, b, c, d, e, Np, Dp);
+    weno5_nd(f, g, h, i, j, Nm, Dm);
+    return (Np * Dm + Nm * Dp) * rcp_nr(Dp * Dm);
 }
 
 // FP32 form.  The (eps + beta)^2 products can overflow FP32, so the three
@@ -343,6 +379,8 @@ XF_HD R recon_pair(const R *gp, const R *gm) {
     else if constexpr (REC == kReconCu6)
         return weno_cu6(gp[0], gp[1], gp[2], gp[3], gp[4], gp[5]) +
                weno_cu6(gm[5], gm[4], gm[3], gm[2], gm[1], gm[0]);
+    else if constexpr (sizeof(R) == 8)
+        return weno5_pair(gp[0], gp[1], gp[2], gp[3], gp[4], gm[5], gm[4], gm[3], gm[2], gm[1]);
     else
         return weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
 }
