@@ -923,14 +923,24 @@ def ssp_rk3(L, U, dt):
 
 
 def rk3_step(th, grid, U, dt, alpha=None, pp=False, visc="LLF", recon="WENO5", transport=None,
-             viscous_terms=7):
+             viscous_terms=7, mechanism=None, n_sub=1, splitting="strang"):
     """One SSP-RK3 step of the convective system with ghosts refilled before
     every stage.  alpha: optional list of three frozen-speed dicts, one per
     stage (in stage order).  pp: blend every stage's face fluxes for
     positivity (each SSP-RK3 stage is a convex combination of Euler steps of
     size dt).  transport: an xf_viscous.Transport to add the viscous and
     diffusive fluxes (Eq. 1-6; the terms selected by viscous_terms) to every
-    stage's residual."""
+    stage's residual.  mechanism: an xf_reaction.Mechanism to split the
+    reaction source off the flow step (Sec. II.C.4): "strang" takes
+    R(dt/2) F(dt) R(dt/2), "lie" F(dt) R(dt), each R with n_sub alpha-QSS
+    sub-steps."""
+    if mechanism is not None:
+        from .xf_reaction import react
+        U0 = fill_ghosts(grid, U)
+        if splitting == "strang":
+            U0 = fill_ghosts(grid, react(th, mechanism, grid, U0, 0.5 * dt, n_sub))
+        flow = rk3_step(th, grid, U0, dt, alpha, pp, visc, recon, transport, viscous_terms)
+        return fill_ghosts(grid, react(th, mechanism, grid, flow, dt if splitting == "lie" else 0.5 * dt, n_sub))
     a = list(alpha) if alpha is not None else [None, None, None]
     stage = [0]
 

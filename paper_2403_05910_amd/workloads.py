@@ -161,6 +161,91 @@ def constant_transport(ns, mu=1.8e-5, kappa=0.026, D=2e-5):
     return TransportTable(np.tile(c(mu), (ns, 1)), np.tile(c(kappa), (ns, 1)), np.tile(c(D), (ns, ns, 1)))
 
 
+# ---------------------------------------------------------------------------
+# synthetic reaction mechanism (the paper's H2-O2 mechanisms are not used)
+# ---------------------------------------------------------------------------
+@dataclass
+class MechanismTable:
+    nu_f: np.ndarray         # (nr, ns) reactant coefficients
+    nu_b: np.ndarray         # (nr, ns) product coefficients
+    A: np.ndarray            # (nr,) Arrhenius factor, SI units of the reaction order
+    B: np.ndarray            # (nr,) temperature exponent
+    E: np.ndarray            # (nr,) activation energy, J/mol
+    third: np.ndarray        # (nr,) bool: a third body M takes part
+    eff: np.ndarray          # (nr, ns) third-body efficiencies
+    reversible: np.ndarray   # (nr,) bool
+    s0: np.ndarray           # (ns,) entropy constants a6 of the species
+
+    @property
+    def nr(self):
+        return self.nu_f.shape[0]
+
+
+def synthetic_mechanism(W_gmol, tab, seed=0, n_reactions=12, T_ref=1500.0):
+    """Seeded mass-balanced reactions among species of the given molar
+    masses: exchanges A + B = C + D (W_A + W_B = W_C + W_D) and dissociations
+    A + M = B + C + M (W_A = W_B + W_C), found by searching the masses;
+    n_reactions of them drawn without replacement.  Rate constants are drawn
+    at T_ref (10^2..10^4 in SI units for exchanges, 10^1..10^3 for the
+    three-body ones), then A follows from a temperature exponent in
+    [-1, 1.5] and an activation energy in [0, 1.5e5] J/mol; efficiencies in
+    [0.5, 3]; every reaction reversible.  The entropy constants a6 are set so
+    that every species' S/R - h/(R T) at T_ref is a draw in [-2, 2] (random
+    constants would put the equilibrium constants of the table tab at
+    e^+-30 and make the backward rates absurd)."""
+    rng = np.random.default_rng(seed)
+    W = np.asarray(W_gmol, dtype=np.float64)
+    ns = len(W)
+    cands = []
+    for a in range(ns):
+        for b in range(a, ns):
+            for c in range(ns):
+                for d in range(c, ns):
+                    if {a, b} == {c, d} or (c, d) < (a, b):
+                        continue
+                    if abs(W[a] + W[b] - W[c] - W[d]) < 1e-9:
+                        cands.append(("x", (a, b), (c, d)))
+    for a in range(ns):
+        for b in range(ns):
+            for c in range(b, ns):
+                if a not in (b, c) and abs(W[a] - W[b] - W[c]) < 1e-9:
+                    cands.append(("d", (a,), (b, c)))
+    pick = rng.choice(len(cands), size=min(n_reactions, len(cands)), replace=False)
+    nr = len(pick)
+    nu_f = np.zeros((nr, ns), dtype=np.int64)
+    nu_b = np.zeros((nr, ns), dtype=np.int64)
+    third = np.zeros(nr, dtype=bool)
+    k_ref = np.zeros(nr)
+    for r, i in enumerate(sorted(pick)):
+        kind, lhs, rhs_ = cands[i]
+        for sp in lhs:
+            nu_f[r, sp] += 1
+        for sp in rhs_:
+            nu_b[r, sp] += 1
+        third[r] = kind == "d"
+        k_ref[r] = 10.0 ** rng.uniform(1.0, 3.0) if third[r] else 10.0 ** rng.uniform(2.0, 4.0)
+    B = rng.uniform(-1.0, 1.5, nr)
+    E = rng.uniform(0.0, 1.5e5, nr)
+    A = k_ref / (T_ref ** B * np.exp(-E / (R_UNIVERSAL * T_ref)))
+    eff = rng.uniform(0.5, 3.0, (nr, ns))
+    a = np.asarray(tab.a)
+    T = T_ref
+    s_var = a[:, 0] * np.log(T) + a[:, 1] * T + a[:, 2] * T ** 2 / 2 + a[:, 3] * T ** 3 / 3 + a[:, 4] * T ** 4 / 4
+    h_RT = (a[:, 0] * T + a[:, 1] * T ** 2 / 2 + a[:, 2] * T ** 3 / 3 + a[:, 3] * T ** 4 / 4 + a[:, 4] * T ** 5 / 5
+            + a[:, 5]) / T
+    s0 = rng.uniform(-2.0, 2.0, ns) + h_RT - s_var
+    return MechanismTable(nu_f, nu_b, A, B, E, third, eff, np.ones(nr, dtype=bool), s0)
+
+
+def with_formation_enthalpies(tab, seed=0, lo=-1000.0, hi=1000.0):
+    """the table with seeded enthalpy constants a5 (K, i.e. h/R at T = 0),
+    so that reactions release or absorb heat"""
+    rng = np.random.default_rng(seed)
+    a = tab.a.copy()
+    a[:, 5] = rng.uniform(lo, hi, len(tab.W))
+    return ThermoTable(tab.W, a, tab.T_lo, tab.T_hi)
+
+
 def _cp_R(tab, T):
     a = tab.a
     T = np.asarray(T, dtype=np.float64)[..., None]

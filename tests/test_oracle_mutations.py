@@ -334,3 +334,44 @@ def test_viscous_dropped_fit_term_caught(monkeypatch):
     orig = XV.fit_eval
     monkeypatch.setattr(XV, "fit_eval", lambda c, T: orig(c[..., :3], T))
     assert _fails(VI.test_fit_form_reproduces_a_shifted_power_law)
+
+
+# -- reaction source (pins in test_oracle_reaction.py) --------------------------
+import test_oracle_reaction as RE  # noqa: E402
+
+XR = O.xf_reaction
+
+
+def test_reaction_constant_alpha_caught(monkeypatch):
+    monkeypatch.setattr(XR, "alpha", lambda r: 0.5 + 0.0 * np.asarray(r, dtype=np.float64))
+    assert _fails(RE.test_alpha_limits_and_exactness)
+    assert _fails(RE.test_first_order_decay_is_exponential)
+
+
+def test_reaction_inverted_equilibrium_constant_caught(monkeypatch):
+    orig = XR.equilibrium_constants
+    monkeypatch.setattr(XR, "equilibrium_constants", lambda th, mech, T: 1.0 / orig(th, mech, T))
+    assert _fails(RE.test_reversible_pair_reaches_its_equilibrium_constant)
+
+
+def test_reaction_backward_direction_dropped_caught(monkeypatch):
+    orig = XR.production_loss
+
+    def bad(th, mech, rho, Y, T):
+        # planted: every reaction treated as irreversible (no backward rate)
+        m = XR.Mechanism(mech.nu_f, mech.nu_b, mech.A, mech.B, mech.E, mech.third, mech.eff,
+                         np.zeros_like(mech.reversible), mech.s0)
+        return orig(th, m, rho, Y, T)
+    monkeypatch.setattr(XR, "production_loss", bad)
+    assert _fails(RE.test_reversible_pair_reaches_its_equilibrium_constant)
+
+
+def test_reaction_arrhenius_sign_caught(monkeypatch):
+    orig = XR.production_loss
+
+    def bad(th, mech, rho, Y, T):
+        m = XR.Mechanism(mech.nu_f, mech.nu_b, mech.A, mech.B, -mech.E, mech.third, mech.eff, mech.reversible,
+                         mech.s0)
+        return orig(th, m, rho, Y, T)
+    monkeypatch.setattr(XR, "production_loss", bad)
+    assert _fails(RE.test_forward_rate_grows_with_temperature)
