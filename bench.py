@@ -323,8 +323,20 @@ def main():
         # same state laid out with four ghost layers)
         out["scheme_options"] = {}
         for label, visc, recon in (("ROE", "ROE", "WENO5"), ("GLF", "GLF", "WENO5"), ("CU6", "LLF", "CU6"),
-                                   ("WENO7", "LLF", "WENO7"), ("viscous", "LLF", "WENO5")):
-            if label == "viscous":
+                                   ("WENO7", "LLF", "WENO7"), ("viscous", "LLF", "WENO5"),
+                                   ("reacting", "LLF", "WENO5")):
+            if label == "reacting":
+                # reaction source split off the step (Strang, 4 alpha-QSS
+                # sub-steps per half step) with the seeded synthetic mechanism
+                # and formation enthalpies; every rate is evaluated in every
+                # cell whatever its temperature
+                from paper_2403_05910_amd import workloads as W
+                caser = W.rethermo(case, W.with_formation_enthalpies(case.thermo, 1))
+                mech = W.synthetic_mechanism(list(1e3 * caser.thermo.W), caser.thermo, 0, 12)
+                ctxo = xf.Context.from_case(caser, "fp64").set_reactions(mech, 4, "strang")
+                Uo = ctxo.state_from_numpy(caser.U)
+                del caser
+            elif label == "viscous":
                 # Navier-Stokes step: the viscous and diffusive fluxes of Eq. 2-6
                 # with seeded gas-like transport tables, all terms
                 from paper_2403_05910_amd import workloads as W

@@ -238,6 +238,44 @@ typedef struct {
 enum { XF_VISCOUS_STRESS = 1, XF_VISCOUS_HEAT = 2, XF_VISCOUS_DIFFUSION = 4 };
 int xf_set_viscous(xf_ctx *ctx, const xf_transport *tr, int terms);
 
+/* Reaction source of Eq. 1 (S: Eq. 8-12) split off the flow step
+ * (Sec. II.C.4).  Mass-action kinetics with [X_s] = rho Y_s / W_s,
+ * k_f = A T^B exp(-E / (R_u T)), k_b = k_f / K_c for reversible reactions
+ * with K_c = (p0 / (R_u T))^(sum nu) exp(sum_s nu_s (S_s/R_s - h_s/(R_s T)))
+ * (p0 = 1 atm, S_s/R_s = a0 ln T + a1 T + a2 T^2/2 + a3 T^3/3 + a4 T^4/4 +
+ * s0[s], a0..a5 the context's thermo table), third bodies
+ * sum_s eff[r*ns + s] [X_s] on both directions.  The reaction step keeps
+ * rho, momentum and E (formation enthalpies live in a5, so the heat release
+ * of Eq. 8 shows as a change of T) and advances the mass fractions by
+ * `substeps` equal alpha-QSS predictor-corrector steps (Eq. 27-28, alpha(r)
+ * = 1/(1 - e^-r) - 1/r), renormalised to unit sum after each.  splitting
+ * XF_SPLIT_STRANG: xf_rk3_step and xf_rk3_step_cfl take R(dt/2) F(dt)
+ * R(dt/2); XF_SPLIT_LIE: F(dt) R(dt) (F the SSP-RK3 flow step; with the
+ * CFL variant dt comes from U^n before the first reaction step).  A NULL
+ * mechanism or substeps = 0 switches reactions off.  Stoichiometric
+ * coefficients 0..3; 1 <= nr <= XF_MAX_REACTIONS; every reaction must
+ * conserve mass (sum_s W_s (nu'' - nu') = 0 within 1e-9 W_max).  Tables are
+ * copied to the device (the first call allocates that copy and the call
+ * synchronises).  The VJPs return XF_EUNSUPPORTED while reactions are on.
+ * Returns XF_EINVAL for bad tables, counts or flags. */
+#define XF_MAX_REACTIONS 32
+typedef struct {
+    int ns, nr;
+    const int *nu_f, *nu_b;       /* [nr][ns] nu' and nu''           */
+    const double *A, *B, *E;      /* [nr]: SI, -, J/mol              */
+    const int *third;             /* [nr] 0/1                        */
+    const double *eff;            /* [nr][ns] third-body efficiency  */
+    const int *reversible;        /* [nr] 0/1                        */
+    const double *s0;             /* [ns] entropy constants (a6)     */
+} xf_mechanism;
+enum { XF_SPLIT_STRANG = 0, XF_SPLIT_LIE = 1 };
+int xf_set_reactions(xf_ctx *ctx, const xf_mechanism *mech, int substeps, int splitting);
+
+/* One reaction step over dt (or *dt_dev when not NULL) on the interior of U,
+ * in place, with the context's mechanism and substeps; the ghosts are filled
+ * afterwards.  Returns XF_EUNSUPPORTED when no mechanism is set. */
+int xf_react(xf_ctx *ctx, double *U, double dt, const double *dt_dev, void *stream);
+
 /* xf_rk3_step with the time step of Eq. 17 computed on the device from U^n
  * (the same reduction as xf_cfl_dt, reusing the first stage's primitives)
  * and written to the device double *dt_dev before the stages use it.  This
@@ -288,7 +326,8 @@ enum {
     XF_K_VISCOUS_X = 14,   /* x viscous flux difference                          */
     XF_K_VISCOUS_Y = 15,
     XF_K_VISCOUS_Z = 16,
-    XF_K_COUNT = 17
+    XF_K_REACT = 17,       /* reaction step (alpha-QSS sub-steps)                */
+    XF_K_COUNT = 18
 };
 
 /* Per-kernel timing for profiling.  While enabled, every kernel launch of

@@ -41,6 +41,10 @@ struct xf_ctx {
     int viscous;                // XF_VISCOUS_* bits, 0 = inviscid
     xf::TransportK *tk;         // device copy of the transport tables (xf_set_viscous)
     double W[XF_MAX_SPECIES];   // molar masses, kg/mol
+    double a[XF_MAX_SPECIES][6];   // thermo coefficients a0..a5 of the table
+    xf::ReactK *rk;             // device copy of the reaction mechanism (xf_set_reactions)
+    int react_sub;              // alpha-QSS sub-steps per reaction step, 0 = no reactions
+    int react_split;            // XF_SPLIT_STRANG or XF_SPLIT_LIE
     struct Rec {
         int cls;
         hipEvent_t a, b;
@@ -359,7 +363,13 @@ int xf_create_ghosts(const xf_grid *grid, const xf_thermo *thermo, int precision
     c->pp = 0;
     c->viscous = 0;
     c->tk = nullptr;
-    for (int s = 0; s < thermo->ns; ++s) c->W[s] = thermo->W[s];
+    c->rk = nullptr;
+    c->react_sub = 0;
+    c->react_split = XF_SPLIT_STRANG;
+    for (int s = 0; s < thermo->ns; ++s) {
+        c->W[s] = thermo->W[s];
+        for (int k = 0; k < 6; ++k) c->a[s][k] = thermo->a[s * 6 + k];
+    }
     xf::Geo &g = c->lc.g;
     g.nx = grid->nx;
     g.ny = grid->ny;
@@ -414,6 +424,7 @@ int xf_destroy(xf_ctx *c) {
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
     if (c->tk) (void)hipFree(c->tk);
+    if (c->rk) (void)hipFree(c->rk);
     const hipError_t e = hipFree(c->lc.status);
     delete c;
     return dev_err(e);
@@ -499,8 +510,47 @@ int xf_cfl_dt(xf_ctx *c, const double *U, double cfl, double *dt_dev, void *ws, 
 // stage buffers S1, S2; stage 3 writes U in place).  With cfl > 0 the time
 // step is reduced on the device from the stage-1 primitives of U^n and
 // written to *dt_out before it is used.
+int flow_rk3_step(xf_ctx *c, double *U, double dt, const double *dt_in, double cfl, double *dt_out, void *ws,
+                  hipStream_t s);
+
+// One reaction step over scale * dt (or *dt_dev), then the ghost fill.
+int react_into(xf_ctx *c, double *U, double dt, const double *dt_dev, double scale, hipStream_t s) {
+    XF_TRY(timed(c, XF_K_REACT, s,
+                 [&] { return c->ops->react(c->lc, U, c->rk, dt, dt_dev, scale, c->react_sub, s); }));
+    return fill(c, U, s) == hipSuccess ? XF_OK : XF_EDEVICE;
+}
+
+// The step of the context: the flow step alone, or split with the
+// reaction step (Strang R(dt/2) F(dt) R(dt/2), or Lie-Trotter F(dt) R(dt)).
+// With cfl > 0 and reactions, dt comes from U^n before the first reaction
+// step and the flow step then uses it.
 int rk3_step(xf_ctx *c, double *U, double dt, const double *dt_in, double cfl, double *dt_out, void *ws,
              hipStream_t s) {
+    if (!c->react_sub) return flow_rk3_step(c, U, dt, dt_in, cfl, dt_out, ws, s);
+    const double *h = dt_in;
+    if (cfl > 0.0) {
+        const Layout l = layout(c, XF_OP_RK3);
+        const Prim pb = prim_bufs(c, l, ws);
+        XF_TRY(fill(c, U, s));
+        XF_TRY(prims(c, U, pb, s));
+        XF_TRY(timed(c, XF_K_CFL, s, [&] {
+            hipError_t e = xf::launch_cfl_reset(pb.mx, s);
+            if (e == hipSuccess) e = c->ops->cfl(c->lc, U, pb.P, pb.mx, s);
+            if (e == hipSuccess) e = xf::launch_cfl_finish(pb.mx, cfl, dt_out, s);
+            return e;
+        }));
+        h = dt_out;
+    }
+    int r;
+    if (c->react_split == XF_SPLIT_STRANG) {
+        if ((r = react_into(c, U, dt, h, 0.5, s)) != XF_OK) return r;
+    }
+    if ((r = flow_rk3_step(c, U, dt, h, 0.0, nullptr, ws, s)) != XF_OK) return r;
+    return react_into(c, U, dt, h, c->react_split == XF_SPLIT_STRANG ? 0.5 : 1.0, s);
+}
+
+int flow_rk3_step(xf_ctx *c, double *U, double dt, const double *dt_in, double cfl, double *dt_out, void *ws,
+                  hipStream_t s) {
     const Layout l = layout(c, XF_OP_RK3);
     const LaunchCtx &lc = c->lc;
     const int n[3] = {lc.g.nx, lc.g.ny, lc.g.nz};
@@ -602,6 +652,71 @@ int xf_set_viscous(xf_ctx *c, const xf_transport *tr, int terms) {
     return XF_OK;
 }
 
+int xf_set_reactions(xf_ctx *c, const xf_mechanism *m, int substeps, int splitting) {
+    if (!c) return XF_EINVAL;
+    if (!m || substeps == 0) {
+        c->react_sub = 0;
+        return XF_OK;
+    }
+    const int ns = c->ns;
+    if (substeps < 0 || (splitting != XF_SPLIT_STRANG && splitting != XF_SPLIT_LIE)) return XF_EINVAL;
+    if (m->ns != ns || m->nr < 1 || m->nr > XF_MAX_REACTIONS || !m->nu_f || !m->nu_b || !m->A || !m->B || !m->E ||
+        !m->third || !m->eff || !m->reversible || !m->s0)
+        return XF_EINVAL;
+    xf::ReactK h;
+    memset(&h, 0, sizeof(h));
+    h.nr = m->nr;
+    double wmax = 0.0;
+    for (int s = 0; s < ns; ++s) wmax = c->W[s] > wmax ? c->W[s] : wmax;
+    for (int r = 0; r < m->nr; ++r) {
+        if (!(m->A[r] > 0.0) || !std::isfinite(m->A[r]) || !std::isfinite(m->B[r]) || !std::isfinite(m->E[r]))
+            return XF_EINVAL;
+        if ((m->third[r] != 0 && m->third[r] != 1) || (m->reversible[r] != 0 && m->reversible[r] != 1))
+            return XF_EINVAL;
+        double dm = 0.0;
+        int dn = 0;
+        for (int s = 0; s < ns; ++s) {
+            const int f = m->nu_f[r * ns + s], b = m->nu_b[r * ns + s];
+            if (f < 0 || f > 3 || b < 0 || b > 3) return XF_EINVAL;
+            const double e = m->eff[r * ns + s];
+            if (!std::isfinite(e) || e < 0.0) return XF_EINVAL;
+            h.nf[r][s] = f;
+            h.nb[r][s] = b;
+            h.eff[r][s] = e;
+            dn += b - f;
+            dm += c->W[s] * (b - f);
+        }
+        if (std::fabs(dm) > 1e-9 * wmax) return XF_EINVAL;   // the reaction must conserve mass
+        h.dn[r] = dn;
+        h.third[r] = m->third[r];
+        h.rev[r] = m->reversible[r];
+        h.lnA[r] = std::log(m->A[r]);
+        h.B[r] = m->B[r];
+        h.ER[r] = m->E[r] / xf::kRu;
+    }
+    for (int s = 0; s < ns; ++s) {
+        if (!std::isfinite(m->s0[s])) return XF_EINVAL;
+        for (int k = 0; k < 6; ++k) h.a[s][k] = c->a[s][k];
+        h.a[s][6] = m->s0[s];
+        h.W[s] = c->W[s];
+        h.iW[s] = 1.0 / c->W[s];
+    }
+    if (!c->rk && hipMalloc(reinterpret_cast<void **>(&c->rk), sizeof(xf::ReactK)) != hipSuccess) {
+        c->rk = nullptr;
+        return XF_ENOMEM;
+    }
+    if (hipMemcpy(c->rk, &h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess) return XF_EDEVICE;
+    c->react_sub = substeps;
+    c->react_split = splitting;
+    return XF_OK;
+}
+
+int xf_react(xf_ctx *c, double *U, double dt, const double *dt_dev, void *stream) {
+    if (!c || !U || !aligned8(U) || !(dt >= 0.0)) return XF_EINVAL;
+    if (!c->react_sub) return XF_EUNSUPPORTED;
+    return react_into(c, U, dt, dt_dev, 1.0, (hipStream_t)stream);
+}
+
 int xf_set_positivity(xf_ctx *c, int enable) {
     if (!c) return XF_EINVAL;
     c->pp = enable != 0;
@@ -624,7 +739,7 @@ int xf_rhs_vjp(xf_ctx *c, const double *U, const double *rbar, double *Ubar, voi
     if (!c || !U || !rbar || !Ubar || !ws || Ubar == U || Ubar == rbar || !aligned8(U) || !aligned8(rbar) ||
         !aligned8(Ubar) || !aligned8(ws))
         return XF_EINVAL;
-    if (c->lc.recon == XF_RECON_WENO7 || c->viscous) return XF_EUNSUPPORTED;
+    if (c->lc.recon == XF_RECON_WENO7 || c->viscous || c->react_sub) return XF_EUNSUPPORTED;
     const Layout l = layout(c, XF_OP_VJP);
     return rhs_vjp_into(c, U, rbar, Ubar, at<double>(ws, l.P), at<double>(ws, l.Pbar), at<double>(ws, l.rec),
                         at<unsigned long long>(ws, l.mx), (hipStream_t)stream);
@@ -635,7 +750,7 @@ int xf_rk3_step_vjp(xf_ctx *c, const double *Un, double dt, double *Ubar, void *
         !(dt >= 0.0))
         return XF_EINVAL;
     if (c->pp) return XF_EUNSUPPORTED;   // the adjoint is of the unblended step
-    if (c->lc.recon == XF_RECON_WENO7 || c->viscous) return XF_EUNSUPPORTED;
+    if (c->lc.recon == XF_RECON_WENO7 || c->viscous || c->react_sub) return XF_EUNSUPPORTED;
     const Layout l = layout(c, XF_OP_RK3_VJP);
     const hipStream_t s = (hipStream_t)stream;
     const LaunchCtx &lc = c->lc;

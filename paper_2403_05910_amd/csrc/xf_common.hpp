@@ -63,6 +63,22 @@ constexpr int kViscousStress = 1, kViscousHeat = 2, kViscousDiffusion = 4;
 // Per-cell fields of the transport pass: mu_bar, kappa_bar, u, v, w, D_sm (NS).
 inline int transport_fields(int ns) { return 5 + ns; }
 
+// Reaction mechanism (Eq. 9-12) in device memory: stoichiometric
+// coefficients nu' (nf) and nu'' (nb), Arrhenius ln A, B and E / R_u, third
+// bodies with efficiencies, reversibility, and per species the thermo
+// coefficients a0..a5 with the entropy constant a6 (for Eq. 12).
+constexpr int kMaxReactions = XF_MAX_REACTIONS;
+struct ReactK {
+    int nr;
+    int nf[kMaxReactions][kMaxNs], nb[kMaxReactions][kMaxNs];
+    int dn[kMaxReactions];          // sum_s (nu'' - nu')
+    int third[kMaxReactions], rev[kMaxReactions];
+    double lnA[kMaxReactions], B[kMaxReactions], ER[kMaxReactions];
+    double eff[kMaxReactions][kMaxNs];
+    double a[kMaxNs][7];            // a0..a5 of the thermo table, a6 of the mechanism
+    double W[kMaxNs], iW[kMaxNs];
+};
+
 // Optional fused SSP-RK3 stage on the last sweep of a right-hand side:
 // instead of rhs, write Uout = a U0 + b (Uin + dt L) with L the finished
 // residual (a == 0 skips U0).  dt is *dt_dev when dt_dev is set.
@@ -124,6 +140,10 @@ struct NsOps {
     // cell-centred velocity gradient [9][cells] (G[3 a + b] = d u_b / d x_a)
     hipError_t (*viscous)(const LaunchCtx &, int dir, const double *U, const double *P, const double *Q,
                           const double *G, double *rhs, int terms, hipStream_t);
+    // reaction step on the interior cells, in place: n_sub alpha-QSS
+    // sub-steps over scale * (dt_dev ? *dt_dev : dt)
+    hipError_t (*react)(const LaunchCtx &, double *U, const ReactK *rk, double dt, const double *dt_dev,
+                        double scale, int n_sub, hipStream_t);
 };
 
 const NsOps *ops_for_ns(int ns);

@@ -237,6 +237,17 @@ def synthetic_mechanism(W_gmol, tab, seed=0, n_reactions=12, T_ref=1500.0):
     return MechanismTable(nu_f, nu_b, A, B, E, third, eff, np.ones(nr, dtype=bool), s0)
 
 
+def rethermo(case, tab):
+    """the same flow (rho, u, T, Y) under the table tab, which differs from
+    the case's only in the enthalpy constants a5: E gains
+    sum_s rho Y_s R_s (a5_new - a5_old), so every cell keeps its temperature"""
+    da = (np.asarray(tab.a)[:, 5] - np.asarray(case.thermo.a)[:, 5]) * R_UNIVERSAL / np.asarray(tab.W)
+    U = case.U.copy()
+    ns = len(tab.W)
+    U[ns + 3] += np.tensordot(da, U[:ns], axes=(0, 0))
+    return Case(case.name, case.n, case.d, case.bc, tab, U, dict(case.meta))
+
+
 def with_formation_enthalpies(tab, seed=0, lo=-1000.0, hi=1000.0):
     """the table with seeded enthalpy constants a5 (K, i.e. h/R at T = 0),
     so that reactions release or absorb heat"""

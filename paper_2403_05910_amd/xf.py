@@ -47,6 +47,14 @@ class xf_thermo(ctypes.Structure):
     _fields_ = [("ns", _c_int), ("W", _dp), ("a", _dp), ("T_lo", _c_double), ("T_hi", _c_double)]
 
 
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+class xf_mechanism(ctypes.Structure):
+    _fields_ = [("ns", _c_int), ("nr", _c_int), ("nu_f", _ip), ("nu_b", _ip), ("A", _dp), ("B", _dp), ("E", _dp),
+                ("third", _ip), ("eff", _dp), ("reversible", _ip), ("s0", _dp)]
+
+
 class xf_transport(ctypes.Structure):
     _fields_ = [("ns", _c_int), ("mu", _dp), ("kappa", _dp), ("D", _dp), ("p_ref", _c_double)]
 
@@ -74,6 +82,8 @@ _set_pp = _sig("xf_set_positivity", _c_int, _vp, _c_int)
 _set_visc = _sig("xf_set_dissipation", _c_int, _vp, _c_int)
 _set_recon = _sig("xf_set_reconstruction", _c_int, _vp, _c_int)
 _set_viscous = _sig("xf_set_viscous", _c_int, _vp, ctypes.POINTER(xf_transport), _c_int)
+_set_reactions = _sig("xf_set_reactions", _c_int, _vp, ctypes.POINTER(xf_mechanism), _c_int, _c_int)
+_react = _sig("xf_react", _c_int, _vp, _vp, _c_double, _vp, _vp)
 _rk3_cfl = _sig("xf_rk3_step_cfl", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
 _rhs_vjp = _sig("xf_rhs_vjp", _c_int, _vp, _vp, _vp, _vp, _vp, _vp)
 _rk3_vjp = _sig("xf_rk3_step_vjp", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
@@ -84,13 +94,15 @@ _strerror = _sig("xf_strerror", ctypes.c_char_p, _c_int)
 
 EXPORTED = ["xf_create", "xf_create_ghosts", "xf_destroy", "xf_state_elems", "xf_workspace_bytes", "xf_fill_ghosts",
             "xf_fill_ghosts_vjp", "xf_rhs", "xf_primitives", "xf_cfl_dt", "xf_rk3_step", "xf_rk3_step_cfl",
-            "xf_set_dissipation", "xf_set_reconstruction", "xf_set_positivity", "xf_set_viscous", "xf_rhs_vjp", "xf_rk3_step_vjp",
+            "xf_set_dissipation", "xf_set_reconstruction", "xf_set_positivity", "xf_set_viscous", "xf_set_reactions", "xf_react", "xf_rhs_vjp", "xf_rk3_step_vjp",
             "xf_status", "xf_strerror", "xf_timing", "xf_timing_read"]
 XF_VISCOUS_STRESS, XF_VISCOUS_HEAT, XF_VISCOUS_DIFFUSION = 1, 2, 4
 VISCOUS_TERMS = {"stress": XF_VISCOUS_STRESS, "heat": XF_VISCOUS_HEAT, "diffusion": XF_VISCOUS_DIFFUSION}
 KERNEL_CLASSES = ["prims", "sweep_x", "sweep_y", "sweep_z", "fill", "stage", "cfl", "zero",
                   "vjp_x", "vjp_y", "vjp_z", "prims_vjp", "fill_vjp", "transport", "viscous_x", "viscous_y",
-                  "viscous_z"]
+                  "viscous_z", "react"]
+XF_SPLIT_STRANG, XF_SPLIT_LIE = 0, 1
+SPLITTING = {"strang": XF_SPLIT_STRANG, "lie": XF_SPLIT_LIE}
 
 
 class XfError(RuntimeError):
@@ -173,6 +185,15 @@ def xf_set_positivity(ctx, enable):
     return _check(_set_pp(ctx, int(bool(enable))), "xf_set_positivity")
 
 
+def xf_set_reactions(ctx, mechanism, substeps, splitting):
+    ptr = None if mechanism is None else ctypes.byref(mechanism)
+    return _check(_set_reactions(ctx, ptr, int(substeps), int(splitting)), "xf_set_reactions")
+
+
+def xf_react(ctx, U, dt, dt_dev, stream):
+    return _check(_react(ctx, U, float(dt), dt_dev, stream), "xf_react")
+
+
 def xf_set_viscous(ctx, transport, terms):
     ptr = None if transport is None else ctypes.byref(transport)
     return _check(_set_viscous(ctx, ptr, int(terms)), "xf_set_viscous")
@@ -245,6 +266,7 @@ class Context:
         self.visc = "LLF"
         self.recon = "WENO5"
         self.viscous = 0
+        self.reactions = None
         self.ghost_width = int(ghost_width)
         g = [self.ghost_width if k > 1 else 0 for k in self.n]
         self.shape = (self.nv, self.n[2] + 2 * g[2], self.n[1] + 2 * g[1], self.n[0] + 2 * g[0])
@@ -362,6 +384,40 @@ class Context:
         self.viscous = bits if table is not None else 0
         self._ws.clear()          # the workspaces grow while the fluxes are on
         return self
+
+    def set_reactions(self, mech, substeps=4, splitting="strang"):
+        """reaction source split off every step (xf_rk3_step): mech with
+        nu_f, nu_b (nr, ns) ints, A, B, E (nr,), third (nr,), eff (nr, ns),
+        reversible (nr,) and s0 (ns,), or None to switch reactions off"""
+        if mech is None or substeps == 0:
+            xf_set_reactions(self.handle, None, 0, 0)
+            self.reactions = None
+            return self
+        nr = int(np.asarray(mech.A).shape[0])
+        arr = {
+            "nu_f": np.ascontiguousarray(mech.nu_f, dtype=np.int32).reshape(nr, self.ns),
+            "nu_b": np.ascontiguousarray(mech.nu_b, dtype=np.int32).reshape(nr, self.ns),
+            "A": np.ascontiguousarray(mech.A, dtype=np.float64), "B": np.ascontiguousarray(mech.B, dtype=np.float64),
+            "E": np.ascontiguousarray(mech.E, dtype=np.float64),
+            "third": np.ascontiguousarray(mech.third, dtype=np.int32),
+            "eff": np.ascontiguousarray(mech.eff, dtype=np.float64).reshape(nr, self.ns),
+            "reversible": np.ascontiguousarray(mech.reversible, dtype=np.int32),
+            "s0": np.ascontiguousarray(mech.s0, dtype=np.float64)}
+        ptr = {k: v.ctypes.data_as(_ip if v.dtype == np.int32 else _dp) for k, v in arr.items()}
+        m = xf_mechanism(self.ns, nr, ptr["nu_f"], ptr["nu_b"], ptr["A"], ptr["B"], ptr["E"], ptr["third"],
+                         ptr["eff"], ptr["reversible"], ptr["s0"])
+        xf_set_reactions(self.handle, m, substeps, SPLITTING[splitting])
+        self.reactions = (substeps, splitting)
+        return self
+
+    def react(self, U, dt):
+        """one reaction step over dt (float or one-element device tensor) in place; ghosts refilled"""
+        torch = _torch()
+        if isinstance(dt, torch.Tensor):
+            xf_react(self.handle, self._ptr(U), 0.0, dt.data_ptr(), self._stream())
+        else:
+            xf_react(self.handle, self._ptr(U), float(dt), None, self._stream())
+        return U
 
     def set_positivity(self, enable=True):
         """positivity-preserving flux blend in rk3_step / rk3_step_cfl"""
