@@ -371,7 +371,7 @@ constexpr int stencil_radius(int rec) { return rec == kReconWeno7 ? 4 : 3; }
 // values of the stencil cells: WENO5-JS of g+ on cells i-2..i+2 plus g-
 // mirrored on i+3..i-1; WENO-CU6 of both on all six cells; WENO7-JS of g+
 // on i-3..i+3 plus g- mirrored on i+4..i-2.
-template <int REC, typename R>
+template <int REC, bool PAIR, typename R>
 XF_HD R recon_pair(const R *gp, const R *gm) {
     if constexpr (REC == kReconWeno7)
         return weno7(gp[0], gp[1], gp[2], gp[3], gp[4], gp[5], gp[6]) +
@@ -379,7 +379,7 @@ XF_HD R recon_pair(const R *gp, const R *gm) {
     else if constexpr (REC == kReconCu6)
         return weno_cu6(gp[0], gp[1], gp[2], gp[3], gp[4], gp[5]) +
                weno_cu6(gm[5], gm[4], gm[3], gm[2], gm[1], gm[0]);
-    else if constexpr (sizeof(R) == 8)
+    else if constexpr (sizeof(R) == 8 && PAIR)
         return weno5_pair(gp[0], gp[1], gp[2], gp[3], gp[4], gm[5], gm[4], gm[3], gm[2], gm[1]);
     else
         return weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
@@ -388,9 +388,11 @@ XF_HD R recon_pair(const R *gp, const R *gm) {
 // SPD (kVisc*) and REC (kRecon*) select the artificial viscosity and the
 // reconstruction at compile time, so every combination is its own code with
 // no run-time switch left in it (ROE and GLF skip the stencil maxima
-// altogether); ds supplies the GLF speeds.
-template <int NS, typename R, int DIR, bool FENCE = false, int SPD = kViscLlf, int REC = kReconWeno5, class St,
-          class Out>
+// altogether); ds supplies the GLF speeds.  PAIR takes both sides of an
+// FP64 WENO5 field with one reciprocal (off where the extra live values
+// spill, as next to the positivity blend).
+template <int NS, typename R, int DIR, bool FENCE = false, int SPD = kViscLlf, int REC = kReconWeno5,
+          bool PAIR = true, class St, class Out>
 XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned &flags, const Dissip &ds) {
     constexpr int RAD = stencil_radius(REC);
     constexpr int W = 2 * RAD;       // stencil cells
@@ -500,8 +502,8 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
             gPp[m] = R(0.5) * (wFp + aP * wUp);
             gPm[m] = R(0.5) * (wFp - aP * wUp);
         }
-        hm = recon_pair<REC>(gMp, gMm);
-        hp = recon_pair<REC>(gPp, gPm);
+        hm = recon_pair<REC, PAIR>(gMp, gMm);
+        hp = recon_pair<REC, PAIR>(gPp, gPm);
     }
     const R Asum = hm + hp, Dif = hp - hm;
 
@@ -517,7 +519,7 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
             gp[m] = R(0.5) * (wF + a0 * wU);
             gm[m] = R(0.5) * (wF - a0 * wU);
         }
-        h1 = recon_pair<REC>(gp, gm);
+        h1 = recon_pair<REC, PAIR>(gp, gm);
 #pragma unroll
         for (int m = 0; m < W; ++m) {
             const R wU = R(st.u(I2, m)) - ut2 * rh[m];
@@ -525,7 +527,7 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
             gp[m] = R(0.5) * (wF + a0 * wU);
             gm[m] = R(0.5) * (wF - a0 * wU);
         }
-        h2 = recon_pair<REC>(gp, gm);
+        h2 = recon_pair<REC, PAIR>(gp, gm);
     }
 
     // ---- species fields, back-projected as they come ----------------------
@@ -543,7 +545,7 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
             gp[m] = R(0.5) * (wF + a0 * wU);
             gm[m] = R(0.5) * (wF - a0 * wU);
         }
-        const R hs = recon_pair<REC>(gp, gm);
+        const R hs = recon_pair<REC, PAIR>(gp, gm);
         out(s, Yt[s] * Asum + hs);
         gsum += hs;
         gE += (q2 - chi[s] * iGam) * hs;

@@ -213,8 +213,8 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(sweep_w
         rowbase = (long long)(g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + g.gx;
         constexpr int RAD = stencil_radius(REC);
         StencilT<S> st{U, P, rowbase + i - RAD, 1, g.cells};
-        face_flux_to<NS, R, 0, SweepTune<R>::fence_face, SPD, REC>(st, th, [&](int q, R v) { sF[q][t] = v; },
-                                                                   flags, ds);
+        face_flux_to<NS, R, 0, SweepTune<R>::fence_face, SPD, REC, !PP>(
+            st, th, [&](int q, R v) { sF[q][t] = v; }, flags, ds);
         if constexpr (PP) {
             R Fq[NV];
 #pragma unroll
@@ -280,7 +280,7 @@ k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, double *__restric
     if (valid) {
         constexpr int RAD = stencil_radius(REC);
         StencilT<S> st{U, P, col + (long long)(gs + j - RAD) * step, step, g.cells};
-        face_flux_to<NS, R, DIR, SweepTune<R>::fence_face, SPD, REC>(
+        face_flux_to<NS, R, DIR, SweepTune<R>::fence_face, SPD, REC, !PP>(
             st, th, [&](int q, R v) { sF[q][ts][tx] = v; }, flags, ds);
         if constexpr (PP) {
             R Fq[NV];
