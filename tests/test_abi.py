@@ -80,5 +80,8 @@ def test_strerror_and_argument_errors_without_device():
     assert xf._set_pp(None, 1) == xf.XF_EINVAL
     assert xf._set_visc(None, 1) == xf.XF_EINVAL
     assert xf._set_recon(None, 1) == xf.XF_EINVAL
+    assert xf._set_viscous(None, None, 7) == xf.XF_EINVAL
+    assert xf._set_reactions(None, None, 4, 0) == xf.XF_EINVAL
+    assert xf._react(None, None, 1e-6, None, None) == xf.XF_EINVAL
     assert xf._state_elems(None) == 0
     assert xf._ws_bytes(None, 0) == 0
