@@ -174,3 +174,27 @@ def test_reaction_refusals():
         ctx.rhs_vjp(U, torch.ones_like(U))
     assert e.value.code == xf.XF_EUNSUPPORTED
     ctx.close()
+
+
+def test_all_terms_together_match_oracle():
+    """one split step with everything on at once: WENO7 on four ghost
+    layers, GLF speeds, the positivity blend, viscous and diffusive fluxes
+    and the reaction source (Strang)"""
+    xf = _xf()
+    case, mt = reacting_case("n9_1500K")
+    case = case.with_ghosts(4)
+    th, g = oracle_objects(case)
+    tr = W.sampled_transport(th.ns, 0)
+    otr = O.xf_viscous.Transport(tr.mu, tr.kappa, tr.D, tr.p_ref)
+    Uo = O.fill_ghosts(g, case.U)
+    dt = 0.3 * O.cfl_dt(th, g, Uo, 0.5)
+    Uo = O.rk3_step(th, g, Uo, dt, pp=True, visc="GLF", recon="WENO7", transport=otr, mechanism=_omech(mt), n_sub=4)
+    ctx = (xf.Context.from_case(case).set_reconstruction("WENO7").set_dissipation("GLF").set_positivity(True)
+           .set_viscous(tr).set_reactions(mt, 4))
+    U = ctx.state_from_numpy(case.U)
+    ctx.rk3_step(U, dt)
+    assert ctx.status() == 0
+    err = _state_err(U.cpu().numpy(), Uo)
+    ctx.close()
+    print(f"[react] all terms (WENO7, GLF, blend, viscous, reactions) max err {err.max():.3e}", flush=True)
+    assert err.max() <= TOL, err
