@@ -59,7 +59,9 @@ __global__ __launch_bounds__(256) void k_transport(const double *__restrict__ U,
             isa[s] = 1.0 / sa[s];
         }
         double out = 0.0;
-#pragma unroll
+        // one row of the pair tables at a time (unrolled, all 2 NS^2
+        // table values are loaded up front and spill the scalar registers)
+#pragma unroll 1
         for (int s = 0; s < NS; ++s) {
             double den = 0.0;
 #pragma unroll
