@@ -696,11 +696,21 @@ int xf_set_reactions(xf_ctx *c, const xf_mechanism *m, int substeps, int splitti
     }
     for (int s = 0; s < ns; ++s) {
         if (!std::isfinite(m->s0[s])) return XF_EINVAL;
-        for (int k = 0; k < 6; ++k) h.a[s][k] = c->a[s][k];
-        h.a[s][6] = m->s0[s];
         h.W[s] = c->W[s];
         h.iW[s] = 1.0 / c->W[s];
     }
+    // g_s = S/R - h/(R T) = a0 (ln T - 1) + a1 T/2 + a2 T^2/6 + a3 T^3/12
+    //       + a4 T^4/20 - a5/T + a6, summed with the net coefficients
+    static const double kGibbs[7] = {1.0, 1.0 / 2.0, 1.0 / 6.0, 1.0 / 12.0, 1.0 / 20.0, -1.0, 1.0};
+    for (int r = 0; r < m->nr; ++r)
+        for (int k = 0; k < 7; ++k) {
+            double acc = 0.0;
+            for (int s = 0; s < ns; ++s) {
+                const int nu = h.nb[r][s] - h.nf[r][s];
+                if (nu) acc += nu * (k < 6 ? c->a[s][k] : m->s0[s]);
+            }
+            h.G[r][k] = acc * kGibbs[k];
+        }
     if (!c->rk && hipMalloc(reinterpret_cast<void **>(&c->rk), sizeof(xf::ReactK)) != hipSuccess) {
         c->rk = nullptr;
         return XF_ENOMEM;

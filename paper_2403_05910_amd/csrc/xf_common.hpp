@@ -75,7 +75,10 @@ struct ReactK {
     int third[kMaxReactions], rev[kMaxReactions];
     double lnA[kMaxReactions], B[kMaxReactions], ER[kMaxReactions];
     double eff[kMaxReactions][kMaxNs];
-    double a[kMaxNs][7];            // a0..a5 of the thermo table, a6 of the mechanism
+    // sum_s (nu'' - nu') g_s(T), with g_s = S_s/R_s - h_s/(R_s T) linear in the
+    // species' NASA coefficients, folded per reaction:
+    // dg = G0 (ln T - 1) + G1 T + G2 T^2 + G3 T^3 + G4 T^4 + G5 / T + G6
+    double G[kMaxReactions][7];
     double W[kMaxNs], iW[kMaxNs];
 };
 

@@ -15,7 +15,8 @@
 // to unit sum after each sub-step.  Rates: [X_s] = rho Y_s / W_s,
 // k_f = A T^B exp(-E / (R_u T)), k_b = k_f / K_c with
 // K_c = (p0 / (R_u T))^(sum nu) exp(sum_s nu_s (S_s/R_s - h_s/(R_s T))),
-// p0 = 1 atm, S/R = a0 ln T + a1 T + a2 T^2/2 + a3 T^3/3 + a4 T^4/4 + a6;
+// p0 = 1 atm, S/R = a0 ln T + a1 T + a2 T^2/2 + a3 T^3/3 + a4 T^4/4 + a6
+// (the sum over species folded per reaction on the host);
 // third bodies Gamma_r = sum_s eff_rs [X_s]; production q_s from the
 // creation terms and loss p_s Y_s from the destruction terms of both
 // directions, p_s = loss / Y_s (0 where Y_s <= 0).
@@ -32,25 +33,21 @@ __device__ __forceinline__ double qss_alpha(double r) {
     return 1.0 / (-expm1(-r)) - 1.0 / r;
 }
 
-// production q_s and loss rate p_s (1/s) at (rho, Y, T)
+// production q_s and loss rate p_s (1/s) at (rho, Y, T); the species' Gibbs
+// functions enter only through each reaction's net sum, whose coefficients
+// the host folds (ReactK::G), so no per-species thermo table is held here
 template <int NS>
 __device__ __forceinline__ void qss_rates(const ReactK *__restrict__ rk, double rho, const double *Y, double T,
                                           double *q, double *p) {
-    const double lt = log(T), iT = 1.0 / T;
-    double conc[NS], gs[NS], loss[NS];
+    const double lt = log(T), iT = 1.0 / T, lt1 = lt - 1.0;
+    const double lp = log(kP0 / (kRu * T));
+    double conc[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         conc[s] = rho * Y[s] * rk->iW[s];
-        const double *a = rk->a[s];
-        // S/R - h/(R T) of species s
-        const double sR = a[0] * lt + (((a[4] * 0.25 * T + a[3] * (1.0 / 3.0)) * T + a[2] * 0.5) * T + a[1]) * T + a[6];
-        const double hRT = (((a[4] * 0.2 * T + a[3] * 0.25) * T + a[2] * (1.0 / 3.0)) * T + a[1] * 0.5) * T + a[0] +
-                           a[5] * iT;
-        gs[s] = sR - hRT;
         q[s] = 0.0;
-        loss[s] = 0.0;
+        p[s] = 0.0;   // the loss p_s Y_s until the end
     }
-    const double lp = log(kP0 / (kRu * T));
     const int nr = rk->nr;
     for (int r = 0; r < nr; ++r) {
         const double lkf = rk->lnA[r] + rk->B[r] * lt - rk->ER[r] * iT;
@@ -60,22 +57,26 @@ __device__ __forceinline__ void qss_rates(const ReactK *__restrict__ rk, double 
 #pragma unroll
             for (int s = 0; s < NS; ++s) gam += rk->eff[r][s] * conc[s];
         }
-        double pf = 1.0, pb = 1.0, dg = 0.0;
+        double pf = 1.0, pb = 1.0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int f = rk->nf[r][s], b = rk->nb[r][s];
             for (int k = 0; k < f; ++k) pf *= conc[s];
             for (int k = 0; k < b; ++k) pb *= conc[s];
-            dg += double(b - f) * gs[s];
         }
         const double Rf = gam * exp(lkf) * pf;
-        const double Rb = rk->rev[r] ? gam * exp(lkf - (rk->dn[r] * lp + dg)) * pb : 0.0;
+        double Rb = 0.0;
+        if (rk->rev[r]) {
+            const double *G = rk->G[r];
+            const double dg = G[0] * lt1 + (((G[4] * T + G[3]) * T + G[2]) * T + G[1]) * T + G[5] * iT + G[6];
+            Rb = gam * exp(lkf - (rk->dn[r] * lp + dg)) * pb;
+        }
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int f = rk->nf[r][s], b = rk->nb[r][s];
             if (f | b) {
                 q[s] += b * Rf + f * Rb;
-                loss[s] += f * Rf + b * Rb;
+                p[s] += f * Rf + b * Rb;
             }
         }
     }
@@ -83,13 +84,16 @@ __device__ __forceinline__ void qss_rates(const ReactK *__restrict__ rk, double 
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         q[s] *= rk->W[s] * ir;
-        const double l = loss[s] * rk->W[s] * ir;
+        const double l = p[s] * rk->W[s] * ir;
         p[s] = Y[s] > 0.0 ? l / Y[s] : 0.0;
     }
 }
 
+// two waves per SIMD: the nine-species predictor and corrector rate arrays
+// fit 256 registers per lane with a few bytes of spill, against one wave (and
+// its unhidden FP64 latency) at the compiler's own choice
 template <int NS>
-__global__ __launch_bounds__(256) void k_react(double *__restrict__ U, Geo g, ThermoK<double> th,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_react(double *__restrict__ U, Geo g, ThermoK<double> th,
                                                const ReactK *__restrict__ rk, double dt, const double *dt_dev,
                                                double scale, int n_sub, unsigned *status) {
     const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
