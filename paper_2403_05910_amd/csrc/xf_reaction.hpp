@@ -89,14 +89,18 @@ __device__ __forceinline__ void qss_rates(const ReactK *__restrict__ rk, double 
     }
 }
 
-// two waves per SIMD: the nine-species predictor and corrector rate arrays
-// fit 256 registers per lane with a few bytes of spill, against one wave (and
-// its unhidden FP64 latency) at the compiler's own choice
+// The predictor's rates q0 and p0 wait out the corrector's rate evaluation in
+// LDS (one slot per thread, conflict-free rows of 256 doubles) instead of 2 NS
+// registers, and the kernel is held to 128 registers per lane (four waves per
+// SIMD) so that more waves hide the FP64 latency; at nine species that costs
+// a few hundred bytes of spill per lane and still wins over two or three waves.
 template <int NS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_react(double *__restrict__ U, Geo g, ThermoK<double> th,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_react(double *__restrict__ U, Geo g, ThermoK<double> th,
                                                const ReactK *__restrict__ rk, double dt, const double *dt_dev,
                                                double scale, int n_sub, unsigned *status) {
-    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double held[2 * NS][256];
+    const int t = threadIdx.x;
+    const long long q = (long long)blockIdx.x * blockDim.x + t;
     const long long nint = (long long)g.nx * g.ny * g.nz;
     if (q >= nint) return;
     const int i = (int)(q % g.nx);
@@ -119,22 +123,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const double h = (dt_dev ? *dt_dev : dt) * scale / n_sub;
     unsigned flags = 0;
     for (int it = 0; it < n_sub; ++it) {
-        double T0, Tp, q0[NS], p0[NS], qp[NS], pp[NS], Yp[NS];
-        if (!newton_T<NS>(th, Y, e, T0)) flags |= XF_FLAG_NEWTON;
-        qss_rates<NS>(rk, rho, Y, T0, q0, p0);
+        double T0, Tp, qp[NS], pp[NS], Yp[NS];
+        {
+            double q0[NS], p0[NS];
+            if (!newton_T<NS>(th, Y, e, T0)) flags |= XF_FLAG_NEWTON;
+            qss_rates<NS>(rk, rho, Y, T0, q0, p0);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const double a0 = qss_alpha(p0[s] * h);
-            Yp[s] = Y[s] + h * (q0[s] - p0[s] * Y[s]) / (1.0 + a0 * p0[s] * h);
+            for (int s = 0; s < NS; ++s) {
+                const double a0 = qss_alpha(p0[s] * h);
+                Yp[s] = Y[s] + h * (q0[s] - p0[s] * Y[s]) / (1.0 + a0 * p0[s] * h);
+                held[s][t] = q0[s];
+                held[NS + s][t] = p0[s];
+            }
         }
+        // each thread reads back only its own slots; the fence keeps the
+        // compiler from carrying the stored values in registers instead
+        asm volatile("" ::: "memory");
         if (!newton_T<NS>(th, Yp, e, Tp)) flags |= XF_FLAG_NEWTON;
         qss_rates<NS>(rk, rho, Yp, Tp, qp, pp);
+        asm volatile("" ::: "memory");
         double sum = 0.0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const double pb = 0.5 * (p0[s] + pp[s]);
+            const double q0 = held[s][t], p0 = held[NS + s][t];
+            const double pb = 0.5 * (p0 + pp[s]);
             const double ab = qss_alpha(pb * h);
-            const double ql = ab * qp[s] + (1.0 - ab) * q0[s];
+            const double ql = ab * qp[s] + (1.0 - ab) * q0;
             Y[s] = Y[s] + h * (ql - pb * Y[s]) / (1.0 + ab * pb * h);
             sum += Y[s];
         }
