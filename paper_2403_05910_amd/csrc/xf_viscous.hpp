@@ -206,8 +206,12 @@ __device__ __forceinline__ void visc_point_flux(const double *__restrict__ U, co
 // ---------------------------------------------------------------------------
 constexpr int kViscXBlock = 256;
 
+// Both viscous face kernels ask for at least five waves per SIMD: the
+// compiler's default of four left them latency-bound (at nine species the x
+// kernel then keeps 96 registers with a few dozen bytes of spill, the tile
+// kernel 80 registers with none, which gives it six).
 template <int NS>
-__global__ __launch_bounds__(kViscXBlock) void k_visc_x(const double *__restrict__ U, const double *__restrict__ P,
+__global__ __launch_bounds__(kViscXBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_visc_x(const double *__restrict__ U, const double *__restrict__ P,
                                                        const double *__restrict__ Q, const double *__restrict__ G,
                                                        double *__restrict__ rhs, Geo g, ThermoK<double> th,
                                                        int terms) {
@@ -249,7 +253,7 @@ __global__ __launch_bounds__(kViscXBlock) void k_visc_x(const double *__restrict
 constexpr int kViscTX = 16, kViscTS = 16;
 
 template <int NS, int DIR>
-__global__ __launch_bounds__(kViscTX *kViscTS) void k_visc_tile(const double *__restrict__ U,
+__global__ __launch_bounds__(kViscTX *kViscTS) __attribute__((amdgpu_waves_per_eu(5))) void k_visc_tile(const double *__restrict__ U,
                                                                const double *__restrict__ P,
                                                                const double *__restrict__ Q,
                                                                const double *__restrict__ G,
