@@ -375,3 +375,38 @@ def test_reaction_arrhenius_sign_caught(monkeypatch):
         return orig(th, m, rho, Y, T)
     monkeypatch.setattr(XR, "production_loss", bad)
     assert _fails(RE.test_forward_rate_grows_with_temperature)
+
+
+def _roe_with(th, pL, pR, Y_mean=False, T_mean=False):
+    """the oracle's Roe state with one weighting replaced by the arithmetic mean"""
+    sL, sR = np.sqrt(pL["rho"]), np.sqrt(pR["rho"])
+    wL = sL / (sL + sR)
+    wR = 1.0 - wL
+    u = wL * pL["u"] + wR * pR["u"]
+    H = wL * pL["H"] + wR * pR["H"]
+    Y = 0.5 * (pL["Y"] + pR["Y"]) if Y_mean else wL[..., None] * pL["Y"] + wR[..., None] * pR["Y"]
+    T = 0.5 * (pL["T"] + pR["T"]) if T_mean else wL * pL["T"] + wR * pR["T"]
+    Gam = X.mixture_R(th, Y) / X.mixture_cv(th, Y, T)
+    q2 = u[0] ** 2 + u[1] ** 2 + u[2] ** 2
+    chi = Gam[..., None] * (0.5 * q2[..., None] - X.species_e(th, T)) + th.R * T[..., None]
+    c2 = np.sum(Y * chi, axis=-1) + Gam * (H - q2)
+    return dict(u=u, H=H, Y=Y, T=T, Gam=Gam, chi=chi, c2=c2, c=np.sqrt(c2), q2=q2)
+
+
+def test_roe_arithmetic_mean_mass_fractions_caught(monkeypatch, rng):
+    _patch(monkeypatch, "roe_state", lambda th, pL, pR: _roe_with(th, pL, pR, Y_mean=True))
+    assert _fails(P.test_roe_condition_calorically_perfect_mixture, 5, rng)
+
+
+def test_roe_arithmetic_mean_temperature_caught(monkeypatch, rng):
+    _patch(monkeypatch, "roe_state", lambda th, pL, pR: _roe_with(th, pL, pR, T_mean=True))
+    assert _fails(P.test_roe_condition_calorically_perfect_mixture, 5, rng)
+
+
+def test_rk3_first_stage_only_caught(monkeypatch):
+    """an RK3 that stops after its first (forward Euler) stage keeps the
+    residual's fifth order but not the one-period accuracy"""
+    def euler(L, U, dt):
+        return U + dt * L(U)
+    _patch(monkeypatch, "ssp_rk3", euler)
+    assert _fails(P.test_rk3_one_period_fifth_order)
