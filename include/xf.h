@@ -34,7 +34,9 @@
  * stream.  Every call except xf_create, xf_destroy and xf_status is
  * asynchronous on that stream and never synchronises the host.
  *
- * Errors.  Functions return an int status: XF_OK (0) or a negative code.
+ * Errors (the error catching of Sec. III.B.6: the solver detects
+ * non-physical states and stops with a report instead of running on).
+ * Functions return an int status: XF_OK (0) or a negative code.
  * Argument errors are detected on the host before anything is enqueued.
  * Non-physical states met by the kernels (rho <= 0, p <= 0, T out of its
  * bracket, Newton not converged, Roe c^2 <= 0, NaN) set bits in a device
@@ -139,6 +141,28 @@ int xf_fill_ghosts(xf_ctx *ctx, double *U, void *stream);
  * layers must be valid (xf_fill_ghosts).  U and rhs must not overlap.
  * ws: xf_workspace_bytes(ctx, XF_OP_RHS) bytes. */
 int xf_rhs(xf_ctx *ctx, const double *U, double *rhs, void *ws, void *stream);
+
+/* xf_rhs with the dissipation speeds of the flux splitting (the Lambda~ of
+ * Eq. 14; Table I's artificial-viscosity options) passed in and out, for
+ * checks of the linearisation at fixed speeds (the VJPs hold them fixed).
+ * Layout of both alpha buffers (FP64, device): for each active direction in
+ * the order x, y, z, a block [3][nf_d] holding the speeds of the u-c field,
+ * of the middle fields and of the u+c field at every face of the direction,
+ * nf_x = (nx+1) ny nz, nf_y = nx (ny+1) nz, nf_z = nx ny (nz+1) (0 for an
+ * inactive direction), face index x: i + (nx+1)(j + ny k), y:
+ * i + nx (j + (ny+1) k), z: i + nx (j + ny k) (i, j, k from 0; the face
+ * with index i along its direction lies before interior cell i); total
+ * 3 (nf_x + nf_y + nf_z) doubles.  alpha_out (may be NULL) receives, in
+ * FP64, the speeds the context's scheme takes at U (LLF stencil maxima,
+ * the ROE face speeds or the GLF direction maxima); alpha_in (may be
+ * NULL) replaces them in the flux splitting (both may be the same buffer:
+ * the speeds are written before they are read).  With both NULL this is
+ * xf_rhs.  The residual is otherwise computed as by xf_rhs (its precision,
+ * reconstruction and viscous terms); with alpha_in, directions are summed in
+ * the order z, y, x as there.  ws: xf_workspace_bytes(ctx, XF_OP_RHS) bytes.
+ * Caller-owned buffers; returns XF_EINVAL for null or misaligned pointers. */
+int xf_rhs_alpha(xf_ctx *ctx, const double *U, const double *alpha_in, double *alpha_out, double *rhs,
+                 void *ws, void *stream);
 
 /* Primitive variables of every cell (interior and ghosts): prim is
  * [4][cells] FP64 (cells = xf_state_elems / Nv, the padded extent), holding
@@ -340,10 +364,14 @@ int xf_timing(xf_ctx *ctx, int enable);
 int xf_timing_read(xf_ctx *ctx, void *stream, double *ms, long long *launches);
 
 /* Synchronise `stream`, return the accumulated status bits in *flags_out
- * and clear them.  Returns XF_ENONPHYS when any bit was set, else XF_OK. */
+ * and clear them.  Returns XF_ENONPHYS when any bit was set, else XF_OK.
+ * This is the report of the error catching of Sec. III.B.6 (a
+ * non-physical state stops the run with a message instead of going on):
+ * the kernels flag, the caller decides. */
 int xf_status(xf_ctx *ctx, void *stream, unsigned *flags_out);
 
-/* Static description of a status code. */
+/* Static description of a status code (the messages of the error catching
+ * of Sec. III.B.6). */
 const char *xf_strerror(int code);
 
 #ifdef __cplusplus

@@ -395,10 +395,6 @@ int xf_create_ghosts(const xf_grid *grid, const xf_thermo *thermo, int precision
     c->lc.precision = precision;
     c->lc.visc = XF_VISC_LLF;
     c->lc.recon = XF_RECON_WENO5;
-    {
-        const char *v = getenv("XF_KERNEL_VARIANT");
-        c->lc.variant = v ? atoi(v) : 0;
-    }
     c->ns = thermo->ns;
     c->nv = thermo->ns + 4;
     c->ops = ops;
@@ -479,6 +475,59 @@ int xf_rhs(xf_ctx *c, const double *U, double *rhs, void *ws, void *stream) {
         return XF_EINVAL;
     const Layout l = layout(c, XF_OP_RHS);
     return rhs_into(c, U, rhs, prim_bufs(c, l, ws), (hipStream_t)stream);
+}
+
+int xf_rhs_alpha(xf_ctx *c, const double *U, const double *alpha_in, double *alpha_out, double *rhs, void *ws,
+                 void *stream) {
+    if (!c || !U || !rhs || !ws || U == rhs || !aligned8(U) || !aligned8(rhs) || !aligned8(ws) ||
+        !aligned8(alpha_in) || !aligned8(alpha_out))
+        return XF_EINVAL;
+    if (!alpha_in && !alpha_out) return xf_rhs(c, U, rhs, ws, stream);
+    const Layout l = layout(c, XF_OP_RHS);
+    const Prim pb = prim_bufs(c, l, ws);
+    const hipStream_t s = (hipStream_t)stream;
+    const LaunchCtx &lc = c->lc;
+    XF_TRY(prims(c, U, pb, s));
+    // per direction: [3][face count] speeds, directions in the order x, y, z
+    long long off = 0;
+    for (int d = 0; d < 3; ++d) {
+        const long long nf = xf::face_count(lc.g, d);
+        if (!nf) continue;
+        if (alpha_out)
+            XF_TRY(timed(c, XF_K_CFL, s, [&] {
+                return c->ops->face_speeds(lc, d, U, pb.P, glf_of(c, pb.mx, d), alpha_out + off, nf, s);
+            }));
+        off += 3 * nf;
+    }
+    if (!alpha_in) {
+        const xf::StageArgs none{};
+        const int r = sweeps_into(c, U, rhs, pb, none, s);
+        if (r != XF_OK) return r;
+    } else {
+        // every direction writes its own difference, then the sum goes to rhs
+        // in the order z, y, x of the plain right-hand side
+        off = 0;
+        long long offs[3] = {0, 0, 0};
+        for (int d = 0; d < 3; ++d) {
+            offs[d] = off;
+            off += 3 * xf::face_count(lc.g, d);
+        }
+        bool first = true;
+        for (int d = 2; d >= 0; --d) {
+            const long long nf = xf::face_count(lc.g, d);
+            if (!nf) continue;
+            XF_TRY(timed(c, XF_K_SWEEP_X + d, s, [&] {
+                return c->ops->sweep_frozen(lc, d, first ? 0 : 1, U, pb.P, pb.Uf, pb.Pf, rhs, alpha_in + offs[d], nf,
+                                            s);
+            }));
+            first = false;
+        }
+    }
+    double *const all[3] = {rhs, rhs, rhs};
+    const int r = viscous_into(c, U, pb, all, s);
+    if (r != XF_OK) return r;
+    XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero_ghosts(c->lc, c->nv, rhs, s); }));
+    return XF_OK;
 }
 
 int xf_primitives(xf_ctx *c, const double *U, double *prim, void *stream) {

@@ -104,7 +104,6 @@ struct LaunchCtx {
     int precision;       // XF_PREC_*
     int visc;            // artificial viscosity: kViscLlf, kViscRoe or kViscGlf
     int recon;           // reconstruction: kReconWeno5 or kReconCu6
-    int variant;         // kernel variant for measurements (environment XF_KERNEL_VARIANT), 0 = default
 };
 
 // Per species-count entry points (one translation unit per N).
@@ -126,6 +125,16 @@ struct NsOps {
     hipError_t (*sweep_vjp)(const LaunchCtx &, int dir, const double *U, const double *P,
                             const double *rbar, double *Ubar, double *Pbar, double *rec, long long nrec,
                             const double *glf, hipStream_t);
+    // one direction of the flux difference with the dissipation speeds of
+    // every face given (alpha [3][astride], astride the direction's face
+    // count); otherwise as sweep with no stage
+    hipError_t (*sweep_frozen)(const LaunchCtx &, int dir, int accumulate, const double *U, const double *P,
+                               const float *Uf, const float *Pf, double *rhs, const double *alpha, long long astride,
+                               hipStream_t);
+    // the dissipation speeds the context's scheme takes at every face of one
+    // direction, FP64, into alpha [3][astride] (glf: the direction's GLF speeds)
+    hipError_t (*face_speeds)(const LaunchCtx &, int dir, const double *U, const double *P, const double *glf,
+                              double *alpha, long long astride, hipStream_t);
     // GLF speeds of one direction: atomicMax of |u_d - c|, |u_d|, |u_d + c|
     // (uint64 bits of positive doubles) into mx[0..2], which must start at 0
     hipError_t (*glf)(const LaunchCtx &, int dir, const double *U, const double *P, unsigned long long *mx,
@@ -150,6 +159,14 @@ struct NsOps {
 };
 
 const NsOps *ops_for_ns(int ns);
+
+// Faces of direction d (0 when the direction is inactive): the interior
+// count plus one along d.
+inline long long face_count(const Geo &g, int d) {
+    const int n[3] = {g.nx, g.ny, g.nz};
+    if (n[d] <= 1) return 0;
+    return (long long)(g.nx + (d == 0)) * (g.ny + (d == 1)) * (g.nz + (d == 2));
+}
 
 // Launch geometry of the face VJP (shared by the launchers and the workspace
 // layout).  x: waves of 64 consecutive faces in one z-plane, launch groups of
@@ -204,8 +221,5 @@ hipError_t launch_cfl_finish(const unsigned long long *mx, double cfl, double *d
                              hipStream_t);
 hipError_t launch_copy(long long n, const double *src, double *dst, hipStream_t);
 hipError_t launch_zero(long long n, double *dst, hipStream_t);
-
-// Number of grid blocks of the marching (y/z) sweeps and their segment length.
-void march_shape(const Geo &g, int dir, int *nseg, int *seglen);
 
 }  // namespace xf

@@ -355,12 +355,17 @@ struct Axes {
 // the face's Roe state (u~_n - c~, u~_n, u~_n + c~); GLF, each field's
 // largest LLF speed over all faces of the direction (glf: the three speeds
 // u_n - c, u_n, u_n + c, reduced beforehand).
-constexpr int kViscLlf = 0, kViscRoe = 1, kViscGlf = 2;
+// kViscFrozen is no scheme of its own: the three speeds of every face are
+// given (alpha[k * astride + fidx], k = u-c, u, u+c fields; fidx the face's
+// index in its direction), for checks of the linearisation at fixed speeds.
+constexpr int kViscLlf = 0, kViscRoe = 1, kViscGlf = 2, kViscFrozen = 3;
 constexpr int kReconWeno5 = 0, kReconCu6 = 1, kReconWeno7 = 2;
 struct Dissip {
     int type;
     const double *glf;
     int recon;   // kReconWeno5, kReconCu6 or kReconWeno7
+    const double *alpha = nullptr;   // kViscFrozen: [3][astride] speeds of the direction's faces
+    long long astride = 0, fidx = 0;
 };
 
 // Stencil half width of a reconstruction: 3 (six cells i-2..i+3; WENO5,
@@ -483,6 +488,10 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
         aM = R(ds.glf[0]);
         a0 = R(ds.glf[1]);
         aP = R(ds.glf[2]);
+    } else if constexpr (SPD == kViscFrozen) {
+        aM = R(ds.alpha[ds.fidx]);
+        a0 = R(ds.alpha[ds.astride + ds.fidx]);
+        aP = R(ds.alpha[2 * ds.astride + ds.fidx]);
     }
 
     if (FENCE) XF_FENCE();

@@ -2,7 +2,7 @@
 //
 //   k_prims       primitive recovery with the Newton temperature (Eq. 7, 21)
 //   k_sweep_x     x-direction flux difference, one face per thread
-//   k_sweep_march y/z-direction flux difference, one column per thread
+//   k_sweep_tile  y/z-direction flux difference, tiles of one face per thread
 //   k_cfl         CFL reduction (Eq. 17), wavefront max + one 64-bit atomic
 #pragma once
 
@@ -136,19 +136,16 @@ __global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, dou
 // ---------------------------------------------------------------------------
 // Phase fences and occupancy per kernel flavour, chosen from the compiler's
 // resource report and timings: the FP64 face-per-thread sweeps keep below 256
-// registers (two waves per SIMD) when the face's phases are fenced; the FP64
-// marching sweep runs best unfenced at one wave per SIMD (forcing two spills
-// inside its face loop); the FP32 sweeps fit three waves unforced.
+// registers (two waves per SIMD) when the face's phases are fenced; the FP32
+// sweeps fit three waves unforced.
 template <typename R>
 struct SweepTune {
     static constexpr bool fence_face = false;   // face-per-thread sweeps (x, tiled y/z)
-    static constexpr bool fence_march = true;
     static constexpr int waves = 1;             // minimum waves per SIMD asked of the compiler
 };
 template <>
 struct SweepTune<double> {
     static constexpr bool fence_face = true;
-    static constexpr bool fence_march = false;
     static constexpr int waves = 2;
 };
 // Waves per SIMD asked of a face-per-thread sweep: the eight-cell WENO7 face
@@ -213,6 +210,7 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(sweep_w
         rowbase = (long long)(g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + g.gx;
         constexpr int RAD = stencil_radius(REC);
         StencilT<S> st{U, P, rowbase + i - RAD, 1, g.cells};
+        if constexpr (SPD == kViscFrozen) ds.fidx = f;   // x faces: i + (nx + 1) (j + ny k)
         face_flux_to<NS, R, 0, SweepTune<R>::fence_face, SPD, REC, !PP>(
             st, th, [&](int q, R v) { sF[q][t] = v; }, flags, ds);
         if constexpr (PP) {
@@ -280,6 +278,9 @@ k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, double *__restric
     if (valid) {
         constexpr int RAD = stencil_radius(REC);
         StencilT<S> st{U, P, col + (long long)(gs + j - RAD) * step, step, g.cells};
+        if constexpr (SPD == kViscFrozen)   // y faces: i + nx (j + (ny + 1) k); z faces: i + nx (j + ny k)
+            ds.fidx = DIR == 1 ? x + (long long)g.nx * (j + (long long)(g.ny + 1) * bz)
+                               : x + (long long)g.nx * (bz + (long long)g.ny * j);
         face_flux_to<NS, R, DIR, SweepTune<R>::fence_face, SPD, REC, !PP>(
             st, th, [&](int q, R v) { sF[q][ts][tx] = v; }, flags, ds);
         if constexpr (PP) {
@@ -300,74 +301,6 @@ k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, double *__restric
         for (int q = 0; q < NV; ++q)
             put_result(rhs, sa, q * g.cells + cell, double((sF[q][ts - 1][tx] - sF[q][ts][tx]) * id), h,
                        accumulate);
-    }
-    if (flags) atomicOr(status, flags);
-}
-
-// ---------------------------------------------------------------------------
-// y/z sweeps: lanes run along x (coalesced), each thread marches one column
-// through a segment of the sweep axis, computing faces j-1/2 for j = j0..j1
-// and finishing cell j-1 as soon as face j-1/2 is known; the previous face's
-// flux waits in a per-thread LDS slot.  Segments are disjoint, so every cell
-// is written by one thread.  Blocks are numbered so that the x-blocks that
-// share the same rows run on the same XCD (blocks are dealt to the 8 XCDs
-// round robin), which keeps the six-row reuse window in one L2.
-// ---------------------------------------------------------------------------
-// VAR 0: the previous face's flux waits in a per-thread LDS slot; VAR 1: in
-// registers (two NV-vectors live across the face computation).
-template <int NS, typename R, int DIR, int VAR, typename S>
-__global__ __launch_bounds__(256) void k_sweep_march(const S *__restrict__ U, const S *__restrict__ P,
-                                                     double *__restrict__ rhs, Geo g, ThermoK<R> th,
-                                                     int seglen, int accumulate, StageArgs sa, unsigned *status) {
-    constexpr int NV = NS + 4;
-    __shared__ R sFp[VAR == 0 ? NV : 1][256];
-    unsigned bx, by, bz;
-    xcd_block(bx, by, bz);
-    const int x = bx * 64 + threadIdx.x;
-    const int tr = by * 4 + threadIdx.y;
-    const int tid = threadIdx.y * 64 + threadIdx.x;
-    const int ntr = (DIR == 1) ? g.nz : g.ny;
-    const int nsw = (DIR == 1) ? g.ny : g.nz;
-    if (x >= g.nx || tr >= ntr) return;
-    const int j0 = bz * seglen;
-    if (j0 >= nsw) return;
-    const int j1 = min(j0 + seglen, nsw);
-    const long long step = (DIR == 1) ? g.sy : g.sz;
-    const int gs = (DIR == 1) ? g.gy : g.gz;
-    const long long col = (long long)(g.gx + x) +
-                          ((DIR == 1) ? (long long)(g.gz + tr) * g.sz : (long long)(g.gy + tr) * g.sy);
-    const R id = R((DIR == 1) ? g.idy : g.idz);
-    const double h = sa.on ? (sa.dt_dev ? *sa.dt_dev : sa.dt) : 0.0;
-    unsigned flags = 0;
-    if constexpr (VAR == 0) {
-        for (int j = j0; j <= j1; ++j) {
-            StencilT<S> st{U, P, col + (long long)(gs + j - 3) * step, step, g.cells};
-            const long long cell = col + (long long)(gs + j - 1) * step;
-            const bool emit = j > j0;
-            face_flux_to<NS, R, DIR, SweepTune<R>::fence_march>(
-                st, th,
-                [&](int q, R v) {
-                    if (emit)
-                        put_result(rhs, sa, q * g.cells + cell, double((sFp[q][tid] - v) * id), h, accumulate);
-                    sFp[q][tid] = v;
-                },
-                flags, Dissip{kViscLlf, nullptr});
-        }
-    } else {
-        R Fp[NV], F[NV];
-        for (int j = j0; j <= j1; ++j) {
-            StencilT<S> st{U, P, col + (long long)(gs + j - 3) * step, step, g.cells};
-            face_flux_to<NS, R, DIR, SweepTune<R>::fence_march>(st, th, [&](int q, R v) { F[q] = v; }, flags,
-                                                               Dissip{kViscLlf, nullptr});
-            if (j > j0) {
-                const long long cell = col + (long long)(gs + j - 1) * step;
-#pragma unroll
-                for (int q = 0; q < NV; ++q)
-                    put_result(rhs, sa, q * g.cells + cell, double((Fp[q] - F[q]) * id), h, accumulate);
-            }
-#pragma unroll
-            for (int q = 0; q < NV; ++q) Fp[q] = F[q];
-        }
     }
     if (flags) atomicOr(status, flags);
 }

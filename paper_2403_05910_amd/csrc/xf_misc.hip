@@ -316,18 +316,4 @@ hipError_t launch_zero(long long n, double *dst, hipStream_t s) {
     return hipGetLastError();
 }
 
-void march_shape(const Geo &g, int dir, int *nseg, int *seglen) {
-    // enough waves to fill 256 CUs several times over, segments of >= 8 cells
-    const int nsw = dir == 1 ? g.ny : g.nz;
-    const int ntr = dir == 1 ? g.nz : g.ny;
-    const long long waves_per_seg = (long long)((g.nx + 63) / 64) * ntr;
-    long long segs = (8192 + waves_per_seg - 1) / waves_per_seg;
-    long long maxsegs = nsw / 8 > 0 ? nsw / 8 : 1;
-    if (segs > maxsegs) segs = maxsegs;
-    if (segs < 1) segs = 1;
-    int L = (int)((nsw + segs - 1) / segs);
-    *seglen = L;
-    *nseg = (nsw + L - 1) / L;
-}
-
 }  // namespace xf

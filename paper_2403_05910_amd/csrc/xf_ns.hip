@@ -64,6 +64,11 @@ hipError_t face_sweep_rec(const LaunchCtx &c, const ThermoK<R> &th, int dir, int
 template <typename R, typename S, bool PP>
 hipError_t face_sweep_spd(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumulate, const S *U, const S *P,
                           double *rhs, const StageArgs &sa, const Dissip &ds, hipStream_t s) {
+    if constexpr (!PP) {   // given speeds: right-hand sides only, never the blended step
+        if (ds.type == kViscFrozen) return face_sweep_rec<R, S, PP, kViscFrozen>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
+    } else {
+        if (ds.type == kViscFrozen) return hipErrorInvalidValue;
+    }
     switch (ds.type) {
         case kViscRoe: return face_sweep_rec<R, S, PP, kViscRoe>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
         case kViscGlf: return face_sweep_rec<R, S, PP, kViscGlf>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
@@ -78,44 +83,47 @@ hipError_t face_sweep_scheme(const LaunchCtx &c, const ThermoK<R> &th, int dir, 
                  : face_sweep_spd<R, S, false>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
 }
 
-template <typename R, typename S>
-hipError_t sweep_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumulate, const S *U, const S *P,
-                   double *rhs, const StageArgs &sa, const Dissip &ds, hipStream_t s) {
-    const Geo &g = c.g;
-    // c.variant (measurement only) 1 or 2 runs the y/z column march (LLF, no
-    // positivity blend) instead of the tiled kernel
-    if (dir == 0 || c.variant == 0 || sa.pp || ds.type != kViscLlf || ds.recon != kReconWeno5)
-        return face_sweep_scheme<R, S>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
-    const int ntr = dir == 1 ? g.nz : g.ny;
-    int nseg, seglen;
-    march_shape(g, dir, &nseg, &seglen);
-    dim3 grid((g.nx + 63) / 64, (ntr + 3) / 4, nseg), block(64, 4);
-    const bool regs = c.variant != 2;
-    if (dir == 1) {
-        if (regs)
-            hipLaunchKernelGGL((k_sweep_march<NS, R, 1, 1, S>), grid, block, 0, s, U, P, rhs, g, th, seglen,
-                               accumulate, sa, c.status);
-        else
-            hipLaunchKernelGGL((k_sweep_march<NS, R, 1, 0, S>), grid, block, 0, s, U, P, rhs, g, th, seglen,
-                               accumulate, sa, c.status);
-    } else {
-        if (regs)
-            hipLaunchKernelGGL((k_sweep_march<NS, R, 2, 1, S>), grid, block, 0, s, U, P, rhs, g, th, seglen,
-                               accumulate, sa, c.status);
-        else
-            hipLaunchKernelGGL((k_sweep_march<NS, R, 2, 0, S>), grid, block, 0, s, U, P, rhs, g, th, seglen,
-                               accumulate, sa, c.status);
-    }
-    return hipGetLastError();
-}
-
 hipError_t sweep(const LaunchCtx &c, int dir, int accumulate, const double *U, const double *P, const float *Uf,
                  const float *Pf, double *rhs, const StageArgs &sa, const double *glf, hipStream_t s) {
     const Dissip ds{c.visc, glf, c.recon};
     if (c.visc == kViscGlf && !glf) return hipErrorInvalidValue;
     if (c.precision == XF_PREC_MIXED)
-        return sweep_t<float, float>(c, c.th32, dir, accumulate, Uf, Pf, rhs, sa, ds, s);
-    return sweep_t<double, double>(c, c.th64, dir, accumulate, U, P, rhs, sa, ds, s);
+        return face_sweep_scheme<float, float>(c, c.th32, dir, accumulate, Uf, Pf, rhs, sa, ds, s);
+    return face_sweep_scheme<double, double>(c, c.th64, dir, accumulate, U, P, rhs, sa, ds, s);
+}
+
+hipError_t sweep_frozen(const LaunchCtx &c, int dir, int accumulate, const double *U, const double *P, const float *Uf,
+                        const float *Pf, double *rhs, const double *alpha, long long astride, hipStream_t s) {
+    Dissip ds{kViscFrozen, nullptr, c.recon};
+    ds.alpha = alpha;
+    ds.astride = astride;
+    const StageArgs off{};
+    if (c.precision == XF_PREC_MIXED)
+        return face_sweep_rec<float, float, false, kViscFrozen>(c, c.th32, dir, accumulate, Uf, Pf, rhs, off, ds, s);
+    return face_sweep_rec<double, double, false, kViscFrozen>(c, c.th64, dir, accumulate, U, P, rhs, off, ds, s);
+}
+
+hipError_t face_speeds(const LaunchCtx &c, int dir, const double *U, const double *P, const double *glf,
+                       double *alpha, long long astride, hipStream_t s) {
+    if (c.visc == kViscGlf && !glf) return hipErrorInvalidValue;
+    const dim3 grid(blocks_for(astride, 256)), block(256);
+    const bool w7 = c.recon == kReconWeno7;
+#define XF_SPEEDS(D)                                                                                              \
+    if (w7)                                                                                                    \
+        hipLaunchKernelGGL((k_face_speeds<NS, D, 4>), grid, block, 0, s, U, P, c.g, c.th64, c.visc, glf, alpha, \
+                           astride);                                                                           \
+    else                                                                                                       \
+        hipLaunchKernelGGL((k_face_speeds<NS, D, 3>), grid, block, 0, s, U, P, c.g, c.th64, c.visc, glf, alpha, \
+                           astride);
+    if (dir == 0) {
+        XF_SPEEDS(0)
+    } else if (dir == 1) {
+        XF_SPEEDS(1)
+    } else {
+        XF_SPEEDS(2)
+    }
+#undef XF_SPEEDS
+    return hipGetLastError();
 }
 
 template <typename R, int HALF, bool CU6>
@@ -134,7 +142,7 @@ hipError_t launch_vjp_group(const LaunchCtx &c, const ThermoK<R> &th, int dir, i
         dim3 grid((unsigned)((waves + wpb - 1) / wpb), g.nz), block(64 * wpb);
         hipLaunchKernelGGL((k_face_vjp_x<NS, R, HALF, CU6>), grid, block, per_wave * wpb, s, U, P, rbar, Ubar, Pbar, rec,
                            nrec, g, th, W, grp, ds);
-    } else if (c.variant != 4) {
+    } else {
         const int nsw = dir == 1 ? g.ny : g.nz;
         const int xt = (g.nx + kVjpTX - 1) / kVjpTX;
         const int nfb = (nsw + 1 + kVjpFB - 1) / kVjpFB;
@@ -146,15 +154,6 @@ hipError_t launch_vjp_group(const LaunchCtx &c, const ThermoK<R> &th, int dir, i
         else
             hipLaunchKernelGGL((k_face_vjp_yz<NS, R, 2, HALF, CU6>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec,
                                g, th, grp, ds);
-    } else {
-        const int nsw = dir == 1 ? g.ny : g.nz;
-        dim3 grid((g.nx + 63) / 64, (nsw / 6 + 1 + 3) / 4, dir == 1 ? g.nz : g.ny), block(64, 4);
-        if (dir == 1)
-            hipLaunchKernelGGL((k_face_vjp<NS, R, 1, HALF, CU6>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec, g,
-                               th, grp, ds);
-        else
-            hipLaunchKernelGGL((k_face_vjp<NS, R, 2, HALF, CU6>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec, g,
-                               th, grp, ds);
     }
     return hipGetLastError();
 }
@@ -167,8 +166,7 @@ hipError_t sweep_vjp_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, const 
                        hipStream_t s) {
     const Geo &g = c.g;
     const int nsw = dir == 1 ? g.ny : g.nz;
-    const long long ngrp = dir == 0 ? vjp_x_waves_per_plane(g)
-                                    : (c.variant == 4 ? nsw + 1 : (nsw + 1 + kVjpFB - 1) / kVjpFB);
+    const long long ngrp = dir == 0 ? vjp_x_waves_per_plane(g) : (nsw + 1 + kVjpFB - 1) / kVjpFB;
     for (int grp = 0; grp < kVjpGroups && grp < ngrp; ++grp) {
         // the second half does not depend on the reconstruction
         hipError_t e = ds.recon == kReconCu6
@@ -249,7 +247,7 @@ hipError_t react(const LaunchCtx &c, double *U, const ReactK *rk, double dt, con
     return hipGetLastError();
 }
 
-const NsOps kOps = {prims, sweep, sweep_vjp, glf, prims_vjp, cfl, transport, viscous, react};
+const NsOps kOps = {prims, sweep, sweep_vjp, sweep_frozen, face_speeds, glf, prims_vjp, cfl, transport, viscous, react};
 
 }  // namespace
 

@@ -692,54 +692,6 @@ __global__ __launch_bounds__(256) void k_face_vjp_x(const double *__restrict__ U
 }
 
 // ---------------------------------------------------------------------------
-// y and z directions: one thread per face, lanes along x (coalesced),
-// threadIdx.y / blockIdx.y over the faces of a class, blockIdx.z over the
-// third axis.  Launch p (p = 0..5) takes the faces j = p, p + 6, ... of every
-// line along the sweep axis (face j lies between cells j-1 and j); their
-// six-cell windows j-3..j+2 are disjoint, so each read-modify-write of a
-// cotangent is the only one in flight for its cell and every cell receives
-// its contributions in a fixed order.
-// ---------------------------------------------------------------------------
-template <int NS, typename R, int DIR, int HALF, bool CU6>
-__global__ __launch_bounds__(256) void k_face_vjp(const double *__restrict__ U, const double *__restrict__ P,
-                                                  const double *__restrict__ rbar, double *__restrict__ Ubar,
-                                                  double *__restrict__ Pbar, double *__restrict__ rec, long long nrec,
-                                                  Geo g, ThermoK<R> th, int p, Dissip ds) {
-    constexpr int NV = NS + 4;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = p + 6 * (int)(blockIdx.y * blockDim.y + threadIdx.y);
-    const int nsw = DIR == 1 ? g.ny : g.nz;
-    if (x >= g.nx || j > nsw) return;
-    const long long ss = DIR == 1 ? g.sy : g.sz;
-    const double id = DIR == 1 ? g.idy : g.idz;
-    const long long col = (long long)(g.gx + x) + (DIR == 1 ? (long long)(g.gz + blockIdx.z) * g.sz + (long long)g.gy * g.sy
-                                                            : (long long)(g.gy + blockIdx.z) * g.sy + (long long)g.gz * g.sz);
-    const long long C = g.cells;
-    // rhs_{j-1} = (F_{j-1/2} - F_{j+1/2}) / dx and rhs_j = (F_{j+1/2} - ...):
-    // the cotangent of this face's flux is (rbar_j - rbar_{j-1}) / dx
-    R Fb[NV];
-    bool any = false;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        const double rr = j < nsw ? rbar[q * C + col + (long long)j * ss] : 0.0;
-        const double rl = j > 0 ? rbar[q * C + col + (long long)(j - 1) * ss] : 0.0;
-        Fb[q] = R((rr - rl) * id);
-        any = any || (Fb[q] != R(0));
-    }
-    if (!any) return;
-    const long long base = col + (long long)(j - 3) * ss;
-    Stencil st{U, P, base, ss, C};
-    Sink sk{Ubar, Pbar, base, ss, C};
-    const long long tid = ((long long)(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) *
-                              (blockDim.x * blockDim.y) + threadIdx.y * blockDim.x + threadIdx.x;
-    const VjpRec<NS> rc{rec, nrec, tid};
-    if constexpr (HALF == 0)
-        face_vjp_a<NS, R, DIR, CU6>(st, th, Fb, sk, rc, ds);
-    else
-        face_vjp_b<NS, R, DIR>(st, th, sk, rc);
-}
-
-// ---------------------------------------------------------------------------
 // y and z directions, blocked: a block takes 16 x-columns by 16 consecutive
 // faces j0..j0+15 of the sweep axis (j0 = 16 b) in one plane of the third
 // axis; wave w of the block takes faces j0+4w..j0+4w+3 (lane = 16 ts + tx),
@@ -824,6 +776,54 @@ __global__ __launch_bounds__(256) void k_face_vjp_yz(const double *__restrict__ 
                 Pbar[(q - NV) * C + cell] += v;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// The dissipation speeds of every face of one direction, in FP64, as the
+// context's scheme takes them (LLF: the stencil maxima of |u_n - c|, |u_n|,
+// |u_n + c| over the 2 RAD cells; ROE: those of the face's Roe state; GLF:
+// the direction's three reduced speeds), written to alpha[k * astride + f]
+// with the face index f of the frozen-speed sweeps (x: i + (nx+1)(j + ny k),
+// y: i + nx (j + (ny+1) k), z: i + nx (j + ny k)).  These are the speeds the
+// VJP holds fixed.
+// ---------------------------------------------------------------------------
+template <int NS, int DIR, int RAD>
+__global__ __launch_bounds__(256) void k_face_speeds(const double *__restrict__ U, const double *__restrict__ P, Geo g,
+                                                     ThermoK<double> th, int type, const double *__restrict__ glf,
+                                                     double *__restrict__ alpha, long long astride) {
+    const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int ex = g.nx + (DIR == 0), ey = g.ny + (DIR == 1);
+    if (f >= astride) return;
+    const int i = (int)(f % ex);
+    const long long r = f / ex;
+    const int j = (int)(r % ey), k = (int)(r / ey);
+    const long long step = DIR == 0 ? 1 : DIR == 1 ? g.sy : g.sz;
+    // left cell of the face: one back along the sweep axis
+    const long long left = (long long)(g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + (g.gx + i) - step;
+    double aM = 0.0, a0 = 0.0, aP = 0.0;
+    if (type == kViscGlf) {
+        aM = glf[0];
+        a0 = glf[1];
+        aP = glf[2];
+    } else if (type == kViscRoe) {
+        const Stencil st{U, P, left - 2 * step, step, g.cells};
+        const RoeFwd<NS, double> rf(st, th);
+        const double un = rf.ut[DIR];
+        aM = fabs(un - rf.ct);
+        a0 = fabs(un);
+        aP = fabs(un + rf.ct);
+    } else {
+        for (int m = 1 - RAD; m <= RAD; ++m) {
+            const long long q = left + m * step;
+            const double un = U[(NS + DIR) * g.cells + q] * P[3 * g.cells + q], c = P[2 * g.cells + q];
+            aM = fmax(aM, fabs(un - c));
+            a0 = fmax(a0, fabs(un));
+            aP = fmax(aP, fabs(un + c));
+        }
+    }
+    alpha[f] = aM;
+    alpha[astride + f] = a0;
+    alpha[2 * astride + f] = aP;
 }
 
 // Per-cell backward of (p, T)(U): p = T sum_s rho_s R_s, and T from

@@ -75,6 +75,7 @@ _ws_bytes = _sig("xf_workspace_bytes", _c_size_t, _vp, _c_int)
 _fill = _sig("xf_fill_ghosts", _c_int, _vp, _vp, _vp)
 _fill_vjp = _sig("xf_fill_ghosts_vjp", _c_int, _vp, _vp, _vp)
 _rhs = _sig("xf_rhs", _c_int, _vp, _vp, _vp, _vp, _vp)
+_rhs_alpha = _sig("xf_rhs_alpha", _c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp)
 _prims = _sig("xf_primitives", _c_int, _vp, _vp, _vp, _vp)
 _cfl = _sig("xf_cfl_dt", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
 _rk3 = _sig("xf_rk3_step", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
@@ -93,7 +94,7 @@ _timing_read = _sig("xf_timing_read", _c_int, _vp, _vp, _dp, ctypes.POINTER(ctyp
 _strerror = _sig("xf_strerror", ctypes.c_char_p, _c_int)
 
 EXPORTED = ["xf_create", "xf_create_ghosts", "xf_destroy", "xf_state_elems", "xf_workspace_bytes", "xf_fill_ghosts",
-            "xf_fill_ghosts_vjp", "xf_rhs", "xf_primitives", "xf_cfl_dt", "xf_rk3_step", "xf_rk3_step_cfl",
+            "xf_fill_ghosts_vjp", "xf_rhs", "xf_rhs_alpha", "xf_primitives", "xf_cfl_dt", "xf_rk3_step", "xf_rk3_step_cfl",
             "xf_set_dissipation", "xf_set_reconstruction", "xf_set_positivity", "xf_set_viscous", "xf_set_reactions", "xf_react", "xf_rhs_vjp", "xf_rk3_step_vjp",
             "xf_status", "xf_strerror", "xf_timing", "xf_timing_read"]
 XF_VISCOUS_STRESS, XF_VISCOUS_HEAT, XF_VISCOUS_DIFFUSION = 1, 2, 4
@@ -159,6 +160,10 @@ def xf_fill_ghosts_vjp(ctx, Ubar, stream):
 
 def xf_rhs(ctx, U, rhs, ws, stream):
     return _check(_rhs(ctx, U, rhs, ws, stream), "xf_rhs")
+
+
+def xf_rhs_alpha(ctx, U, alpha_in, alpha_out, rhs, ws, stream):
+    return _check(_rhs_alpha(ctx, U, alpha_in, alpha_out, rhs, ws, stream), "xf_rhs_alpha")
 
 
 def xf_primitives(ctx, U, prim, stream):
@@ -336,6 +341,31 @@ class Context:
     def rhs(self, U, out=None):
         out = self.new_state() if out is None else out
         xf_rhs(self.handle, self._ptr(U), self._ptr(out), self.workspace(XF_OP_RHS), self._stream())
+        return out
+
+    def face_counts(self):
+        """faces of the x, y and z directions (0 for an inactive one)"""
+        nx, ny, nz = self.n
+        return tuple(0 if self.n[d] <= 1 else (nx + (d == 0)) * (ny + (d == 1)) * (nz + (d == 2)) for d in range(3))
+
+    def alpha_elems(self):
+        """doubles of an alpha buffer of rhs_alpha: 3 per face of every direction"""
+        return 3 * sum(self.face_counts())
+
+    def rhs_alpha(self, U, alpha_in=None, alpha_out=None, out=None):
+        """xf_rhs with the dissipation speeds given (alpha_in) and/or returned
+        (alpha_out): float64 device tensors of alpha_elems() entries"""
+        torch = _torch()
+        out = self.new_state() if out is None else out
+
+        def aptr(a):
+            if a is None:
+                return None
+            if not (a.is_cuda and a.dtype == torch.float64 and a.is_contiguous() and a.numel() == self.alpha_elems()):
+                raise ValueError(f"expected a contiguous float64 device tensor of {self.alpha_elems()} entries")
+            return a.data_ptr()
+        xf_rhs_alpha(self.handle, self._ptr(U), aptr(alpha_in), aptr(alpha_out), self._ptr(out),
+                     self.workspace(XF_OP_RHS), self._stream())
         return out
 
     def primitives(self, U, out=None):
