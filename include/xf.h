@@ -60,7 +60,8 @@ enum {
     XF_EDEVICE = -2,       /* HIP runtime error (launch, copy, no device)          */
     XF_ENOMEM = -3,        /* allocation inside xf_create failed                  */
     XF_ENONPHYS = -4,      /* xf_status: a non-physical state was flagged          */
-    XF_EUNSUPPORTED = -5   /* valid request this build does not provide (e.g. N)  */
+    XF_EUNSUPPORTED = -5,  /* valid request this build does not provide (e.g. N)  */
+    XF_ETOOLARGE = -6      /* xf_rhs_noalloc: workspace exceeds XF_NOALLOC_BYTES   */
 };
 
 enum { XF_BC_PERIODIC = 0, XF_BC_OUTFLOW = 1 };
@@ -141,6 +142,24 @@ int xf_fill_ghosts(xf_ctx *ctx, double *U, void *stream);
  * layers must be valid (xf_fill_ghosts).  U and rhs must not overlap.
  * ws: xf_workspace_bytes(ctx, XF_OP_RHS) bytes. */
 int xf_rhs(xf_ctx *ctx, const double *U, double *rhs, void *ws, void *stream);
+
+/* xf_rhs for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same residual, bit for bit, with the workspace taken from a static device
+ * array of the library (XF_NOALLOC_BYTES, held on every device the library
+ * runs on until the process ends) instead of a caller buffer.  The call
+ * itself allocates nothing and creates no event (per-kernel timing does not
+ * record it).  The caller still owns U and rhs (device, layout as xf_rhs).
+ * The current device must be the context's.  Every call on one device shares
+ * that device's array, whose contents the next call overwrites: calls that
+ * overlap on one device (different streams or host threads) race, and must
+ * be serialised by the caller.  Returns XF_ETOOLARGE when
+ * xf_workspace_bytes(ctx, XF_OP_RHS) exceeds XF_NOALLOC_BYTES (about
+ * 2 million padded cells in FP64, 700 thousand in a mixed nine-species
+ * context), XF_EINVAL for null, overlapping or misaligned buffers or another
+ * current device. */
+#define XF_NOALLOC_BYTES ((size_t)64 << 20)
+int xf_rhs_noalloc(xf_ctx *ctx, const double *U, double *rhs, void *stream);
 
 /* xf_rhs with the dissipation speeds of the flux splitting (the Lambda~ of
  * Eq. 14; Table I's artificial-viscosity options) passed in and out, for

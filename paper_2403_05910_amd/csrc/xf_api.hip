@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -30,6 +31,33 @@ const NsOps *ops_for_ns(int ns) {
 }
 }  // namespace xf
 
+// Static device scratch of xf_rhs_noalloc: the workspace of a right-hand
+// side for callers that cannot allocate.  Each device holds its own copy for
+// the life of the process.  Host code never passes `scratch` itself (on the
+// host it only names the symbol): it passes the device address resolved by
+// hipGetSymbolAddress once per device (scratch_on_current_device).
+constexpr size_t kScratchBytes = XF_NOALLOC_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device (resolved on the first
+// call per device), or nullptr when it cannot be resolved.
+void *scratch_on_current_device(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
 struct xf_ctx {
     xf::LaunchCtx lc;
     int ns, nv;
@@ -45,6 +73,7 @@ struct xf_ctx {
     xf::ReactK *rk;             // device copy of the reaction mechanism (xf_set_reactions)
     int react_sub;              // alpha-QSS sub-steps per reaction step, 0 = no reactions
     int react_split;            // XF_SPLIT_STRANG or XF_SPLIT_LIE
+    void *scratch;              // device address of the static scratch on this context's device
     struct Rec {
         int cls;
         hipEvent_t a, b;
@@ -399,6 +428,11 @@ int xf_create_ghosts(const xf_grid *grid, const xf_thermo *thermo, int precision
     c->nv = thermo->ns + 4;
     c->ops = ops;
     c->device = dev;
+    c->scratch = scratch_on_current_device(dev);
+    if (!c->scratch) {
+        delete c;
+        return XF_EDEVICE;
+    }
     if (hipMalloc(reinterpret_cast<void **>(&c->lc.status), kAlign) != hipSuccess) {
         delete c;
         return XF_ENOMEM;
@@ -475,6 +509,20 @@ int xf_rhs(xf_ctx *c, const double *U, double *rhs, void *ws, void *stream) {
         return XF_EINVAL;
     const Layout l = layout(c, XF_OP_RHS);
     return rhs_into(c, U, rhs, prim_bufs(c, l, ws), (hipStream_t)stream);
+}
+
+int xf_rhs_noalloc(xf_ctx *c, const double *U, double *rhs, void *stream) {
+    if (!c || !U || !rhs || U == rhs || !aligned8(U) || !aligned8(rhs)) return XF_EINVAL;
+    const Layout l = layout(c, XF_OP_RHS);
+    if (l.total > kScratchBytes) return XF_ETOOLARGE;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != c->device) return XF_EINVAL;
+    // no event is created here: per-kernel timing skips this call's launches
+    const bool timing = c->timing;
+    c->timing = false;
+    const int r = rhs_into(c, U, rhs, prim_bufs(c, l, c->scratch), (hipStream_t)stream);
+    c->timing = timing;
+    return r;
 }
 
 int xf_rhs_alpha(xf_ctx *c, const double *U, const double *alpha_in, double *alpha_out, double *rhs, void *ws,
@@ -874,6 +922,7 @@ const char *xf_strerror(int code) {
         case XF_ENOMEM: return "device allocation failed";
         case XF_ENONPHYS: return "non-physical state flagged by the kernels";
         case XF_EUNSUPPORTED: return "unsupported request (species count or operation)";
+        case XF_ETOOLARGE: return "problem too large for the library's static scratch buffer";
         default: return "unknown status code";
     }
 }

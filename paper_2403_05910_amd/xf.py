@@ -18,7 +18,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libxf.so")
 
-XF_OK, XF_EINVAL, XF_EDEVICE, XF_ENOMEM, XF_ENONPHYS, XF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+XF_OK, XF_EINVAL, XF_EDEVICE, XF_ENOMEM, XF_ENONPHYS, XF_EUNSUPPORTED, XF_ETOOLARGE = 0, -1, -2, -3, -4, -5, -6
+XF_NOALLOC_BYTES = 64 << 20
 XF_BC_PERIODIC, XF_BC_OUTFLOW = 0, 1
 XF_PREC_FP64, XF_PREC_MIXED = 0, 1
 XF_OP_RHS, XF_OP_RK3, XF_OP_VJP, XF_OP_RK3_VJP = 0, 1, 2, 3
@@ -75,6 +76,7 @@ _ws_bytes = _sig("xf_workspace_bytes", _c_size_t, _vp, _c_int)
 _fill = _sig("xf_fill_ghosts", _c_int, _vp, _vp, _vp)
 _fill_vjp = _sig("xf_fill_ghosts_vjp", _c_int, _vp, _vp, _vp)
 _rhs = _sig("xf_rhs", _c_int, _vp, _vp, _vp, _vp, _vp)
+_rhs_noalloc = _sig("xf_rhs_noalloc", _c_int, _vp, _vp, _vp, _vp)
 _rhs_alpha = _sig("xf_rhs_alpha", _c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp)
 _prims = _sig("xf_primitives", _c_int, _vp, _vp, _vp, _vp)
 _cfl = _sig("xf_cfl_dt", _c_int, _vp, _vp, _c_double, _vp, _vp, _vp)
@@ -94,7 +96,7 @@ _timing_read = _sig("xf_timing_read", _c_int, _vp, _vp, _dp, ctypes.POINTER(ctyp
 _strerror = _sig("xf_strerror", ctypes.c_char_p, _c_int)
 
 EXPORTED = ["xf_create", "xf_create_ghosts", "xf_destroy", "xf_state_elems", "xf_workspace_bytes", "xf_fill_ghosts",
-            "xf_fill_ghosts_vjp", "xf_rhs", "xf_rhs_alpha", "xf_primitives", "xf_cfl_dt", "xf_rk3_step", "xf_rk3_step_cfl",
+            "xf_fill_ghosts_vjp", "xf_rhs", "xf_rhs_noalloc", "xf_rhs_alpha", "xf_primitives", "xf_cfl_dt", "xf_rk3_step", "xf_rk3_step_cfl",
             "xf_set_dissipation", "xf_set_reconstruction", "xf_set_positivity", "xf_set_viscous", "xf_set_reactions", "xf_react", "xf_rhs_vjp", "xf_rk3_step_vjp",
             "xf_status", "xf_strerror", "xf_timing", "xf_timing_read"]
 XF_VISCOUS_STRESS, XF_VISCOUS_HEAT, XF_VISCOUS_DIFFUSION = 1, 2, 4
@@ -160,6 +162,10 @@ def xf_fill_ghosts_vjp(ctx, Ubar, stream):
 
 def xf_rhs(ctx, U, rhs, ws, stream):
     return _check(_rhs(ctx, U, rhs, ws, stream), "xf_rhs")
+
+
+def xf_rhs_noalloc(ctx, U, rhs, stream):
+    return _check(_rhs_noalloc(ctx, U, rhs, stream), "xf_rhs_noalloc")
 
 
 def xf_rhs_alpha(ctx, U, alpha_in, alpha_out, rhs, ws, stream):
