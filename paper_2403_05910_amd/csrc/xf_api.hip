@@ -92,7 +92,7 @@ size_t align_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace carve-up (byte offsets); every piece 256-byte aligned.
 struct Layout {
-    size_t P, Pbar, rec, mx, L, U0, S2, Ly, Lz, V0, V1, V2, lam0, mu, Uf, Pf, Q, G, total;
+    size_t P, Pbar, mx, L, U0, S2, Ly, Lz, V0, V1, V2, lam0, mu, Uf, Pf, Q, G, total;
 };
 
 Layout layout(const xf_ctx *c, int op) {
@@ -117,10 +117,8 @@ Layout layout(const xf_ctx *c, int op) {
         o += align_up(cell * 9);
     }
     if (op == XF_OP_VJP || op == XF_OP_RK3_VJP) {
-        l.Pbar = o;
-        o += align_up(2 * cell);
-        l.rec = o;   // record between the two halves of the face VJP
-        o += align_up((size_t)xf::vjp_record_fields(c->ns) * (size_t)xf::vjp_record_rows(c->lc.g) * sizeof(double));
+        l.Pbar = o;   // cotangents of each cell's p, T and rho
+        o += align_up(3 * cell);
     }
     if (op == XF_OP_RK3 || op == XF_OP_RK3_VJP) {
         l.L = o;
@@ -291,18 +289,17 @@ int rhs_into(xf_ctx *c, const double *U, double *rhs, const Prim &pb, hipStream_
 }
 
 int rhs_vjp_into(xf_ctx *c, const double *U, const double *rbar, double *Ubar, double *P, double *Pbar,
-                 double *rec, unsigned long long *mx, hipStream_t s) {
+                 unsigned long long *mx, hipStream_t s) {
     const LaunchCtx &lc = c->lc;
     const int n[3] = {lc.g.nx, lc.g.ny, lc.g.nz};
     XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(lc, U, P, nullptr, nullptr, 0, s); }));
     XF_TRY(glf_speeds(c, U, P, mx, s));
-    XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero(2 * lc.g.cells, Pbar, s); }));
+    XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero(3 * lc.g.cells, Pbar, s); }));
     for (int d = 0; d < 3; ++d) {
         if (n[d] <= 1) continue;
         XF_TRY(timed(c, XF_K_VJP_X + d, s,
                      [&] {
-                         return c->ops->sweep_vjp(lc, d, U, P, rbar, Ubar, Pbar, rec, xf::vjp_record_rows(lc.g),
-                                                  glf_of(c, mx, d), s);
+                         return c->ops->sweep_vjp(lc, d, U, P, rbar, Ubar, Pbar, glf_of(c, mx, d), s);
                      }));
     }
     XF_TRY(timed(c, XF_K_PRIMS_VJP, s, [&] { return c->ops->prims_vjp(lc, U, P, Pbar, Ubar, s); }));
@@ -848,7 +845,7 @@ int xf_rhs_vjp(xf_ctx *c, const double *U, const double *rbar, double *Ubar, voi
         return XF_EINVAL;
     if (c->lc.recon == XF_RECON_WENO7 || c->viscous || c->react_sub) return XF_EUNSUPPORTED;
     const Layout l = layout(c, XF_OP_VJP);
-    return rhs_vjp_into(c, U, rbar, Ubar, at<double>(ws, l.P), at<double>(ws, l.Pbar), at<double>(ws, l.rec),
+    return rhs_vjp_into(c, U, rbar, Ubar, at<double>(ws, l.P), at<double>(ws, l.Pbar),
                         at<unsigned long long>(ws, l.mx), (hipStream_t)stream);
 }
 
@@ -890,8 +887,7 @@ int xf_rk3_step_vjp(xf_ctx *c, const double *Un, double dt, double *Ubar, void *
     XF_TRY(fill_vjp(c, Ubar, s));
     for (int stage = 3; stage >= 1; --stage) {
         XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero(n, mu, s); }));
-        if ((r = rhs_vjp_into(c, Vs[stage - 1], Ubar, mu, P, Pbar, at<double>(ws, l.rec),
-                              at<unsigned long long>(ws, l.mx), s)) != XF_OK)
+        if ((r = rhs_vjp_into(c, Vs[stage - 1], Ubar, mu, P, Pbar, at<unsigned long long>(ws, l.mx), s)) != XF_OK)
             return r;
         XF_TRY(timed(c, XF_K_STAGE, s,
                      [&] { return xf::launch_rk3_stage_vjp(lc, c->nv, stage, Ubar, lam0, mu, nullptr, dt, s); }));

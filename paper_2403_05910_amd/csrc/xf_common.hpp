@@ -119,12 +119,10 @@ struct NsOps {
     hipError_t (*sweep)(const LaunchCtx &, int dir, int accumulate, const double *U, const double *P,
                         const float *Uf, const float *Pf, double *rhs, const StageArgs &stage, const double *glf,
                         hipStream_t);
-    // VJP of one direction: Ubar_direct += (dF/dU)^T ..., Pbar += (dF/d(p, T))^T ...
-    // rec: vjp_record_fields(ns) x nrec doubles of scratch between the two
-    // halves of the face VJP (nrec >= vjp_record_rows(g))
+    // VJP of one direction: Ubar += (dF/dU)^T ..., Pbar += (dF/d(p, T, rho))^T ...
+    // (Pbar: [3][cells], the cotangents of each cell's p, T and rho)
     hipError_t (*sweep_vjp)(const LaunchCtx &, int dir, const double *U, const double *P,
-                            const double *rbar, double *Ubar, double *Pbar, double *rec, long long nrec,
-                            const double *glf, hipStream_t);
+                            const double *rbar, double *Ubar, double *Pbar, const double *glf, hipStream_t);
     // one direction of the flux difference with the dissipation speeds of
     // every face given (alpha [3][astride], astride the direction's face
     // count); otherwise as sweep with no stage
@@ -139,7 +137,7 @@ struct NsOps {
     // (uint64 bits of positive doubles) into mx[0..2], which must start at 0
     hipError_t (*glf)(const LaunchCtx &, int dir, const double *U, const double *P, unsigned long long *mx,
                       hipStream_t);
-    // VJP of the primitive map: Ubar += (d(p, T)/dU)^T Pbar
+    // VJP of the primitive map: Ubar += (d(p, T, rho)/dU)^T Pbar
     hipError_t (*prims_vjp)(const LaunchCtx &, const double *U, const double *P,
                             const double *Pbar, double *Ubar, hipStream_t);
     // CFL reduction: max_i sum_d (|u_d| + c)/dx_d -> atomicMax on *mx (uint64 bits)
@@ -168,35 +166,10 @@ inline long long face_count(const Geo &g, int d) {
     return (long long)(g.nx + (d == 0)) * (g.ny + (d == 1)) * (g.nz + (d == 2));
 }
 
-// Launch geometry of the face VJP (shared by the launchers and the workspace
-// layout).  x: waves of 64 consecutive faces in one z-plane, launch groups of
-// every sixth wave, blocks of up to 4 waves; y/z: blocks of 64 x 4 threads
-// over (x, faces of one class along the sweep axis), one block row per plane.
+// Launch geometry of the face VJP in x: waves of 64 consecutive faces in
+// one z-plane, launch groups of every sixth wave, blocks of up to 4 waves.
 constexpr int kVjpGroups = 6;
-inline int vjp_record_fields(int ns) { return 44 + 2 * ns; }
 inline long long vjp_x_waves_per_plane(const Geo &g) { return ((long long)(g.nx + 1) * g.ny + 63) / 64; }
-inline long long vjp_yz_threads(const Geo &g, int dir) {
-    const int nsw = dir == 1 ? g.ny : g.nz, ntr = dir == 1 ? g.nz : g.ny;
-    // blocked form: 16 x 16 faces per block, every sixth face block per launch
-    const long long nfb = (nsw + 1 + 15) / 16;
-    const long long blocked = (long long)((g.nx + 15) / 16) * ((nfb + kVjpGroups - 1) / kVjpGroups) * ntr * 256;
-    // face-class form: faces j = p (mod 6), 64 x 4 threads per block
-    const long long per_class = nsw / 6 + 1;
-    const long long classes = (long long)((g.nx + 63) / 64) * 64 * ((per_class + 3) / 4) * 4 * ntr;
-    return blocked > classes ? blocked : classes;
-}
-// record rows one launch of any direction can use
-inline long long vjp_record_rows(const Geo &g) {
-    long long n = 0;
-    if (g.nx > 1) {
-        const long long waves = (vjp_x_waves_per_plane(g) + kVjpGroups - 1) / kVjpGroups;
-        const long long rows = (waves + 3) / 4 * 4 * 64 * g.nz;   // blocks of 4 waves (an upper bound for 1)
-        n = rows > n ? rows : n;
-    }
-    if (g.ny > 1) n = vjp_yz_threads(g, 1) > n ? vjp_yz_threads(g, 1) : n;
-    if (g.nz > 1) n = vjp_yz_threads(g, 2) > n ? vjp_yz_threads(g, 2) : n;
-    return n;
-}
 
 // Species-independent launches (xf_misc.hip).
 hipError_t launch_fill_ghosts(const LaunchCtx &, int nv, double *U, hipStream_t);

@@ -126,22 +126,30 @@ hipError_t face_speeds(const LaunchCtx &c, int dir, const double *U, const doubl
     return hipGetLastError();
 }
 
-template <typename R, int HALF, bool CU6>
+// LDS a block of the x face VJP may take (of the CU's 160 KB).
+constexpr size_t kVjpLdsBytes = 160 * 1024;
+
+template <typename R, bool CU6>
 hipError_t launch_vjp_group(const LaunchCtx &c, const ThermoK<R> &th, int dir, int grp, const double *U,
-                            const double *P, const double *rbar, double *Ubar, double *Pbar, double *rec,
-                            long long nrec, const Dissip &ds, hipStream_t s) {
+                            const double *P, const double *rbar, double *Ubar, double *Pbar, const Dissip &ds,
+                            hipStream_t s) {
     const Geo &g = c.g;
     if (dir == 0) {
-        // consecutive faces per wave with a private LDS window of W cells
+        // consecutive faces per wave with private LDS areas of W cells
         const int rowf = g.nx + 1;
         const int bounds = (63 + rowf - 1) / rowf;               // row boundaries 64 faces can cross
         const int W = 69 + 5 * bounds;
-        const size_t per_wave = (size_t)(NS + 6) * W * sizeof(double);
-        const int wpb = per_wave * 4 <= 65536 ? 4 : 1;
+        const size_t per_wave = vjp_x_lds_per_wave<NS, R>(W);
+        const int wpb = per_wave * 4 <= kVjpLdsBytes ? 4 : 1;
+        if (per_wave * wpb > kVjpLdsBytes) return hipErrorInvalidValue;
         const long long waves = (vjp_x_waves_per_plane(g) - grp + kVjpGroups - 1) / kVjpGroups;
         dim3 grid((unsigned)((waves + wpb - 1) / wpb), g.nz), block(64 * wpb);
-        hipLaunchKernelGGL((k_face_vjp_x<NS, R, HALF, CU6>), grid, block, per_wave * wpb, s, U, P, rbar, Ubar, Pbar, rec,
-                           nrec, g, th, W, grp, ds);
+        // dynamic LDS above 64 KB must be allowed for the kernel
+        const hipError_t e = hipFuncSetAttribute((const void *)k_face_vjp_x<NS, R, CU6>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kVjpLdsBytes);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_face_vjp_x<NS, R, CU6>), grid, block, per_wave * wpb, s, U, P, rbar, Ubar, Pbar, g, th,
+                           W, grp, ds);
     } else {
         const int nsw = dir == 1 ? g.ny : g.nz;
         const int xt = (g.nx + kVjpTX - 1) / kVjpTX;
@@ -149,44 +157,40 @@ hipError_t launch_vjp_group(const LaunchCtx &c, const ThermoK<R> &th, int dir, i
         const int nb = (nfb - grp + kVjpGroups - 1) / kVjpGroups;
         dim3 grid((unsigned)(xt * nb), dir == 1 ? g.nz : g.ny), block(256);
         if (dir == 1)
-            hipLaunchKernelGGL((k_face_vjp_yz<NS, R, 1, HALF, CU6>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec,
-                               g, th, grp, ds);
+            hipLaunchKernelGGL((k_face_vjp_yz<NS, R, 1, CU6>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, g, th, grp,
+                               ds);
         else
-            hipLaunchKernelGGL((k_face_vjp_yz<NS, R, 2, HALF, CU6>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, rec, nrec,
-                               g, th, grp, ds);
+            hipLaunchKernelGGL((k_face_vjp_yz<NS, R, 2, CU6>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, g, th, grp,
+                               ds);
     }
     return hipGetLastError();
 }
 
-// Six launch groups per direction (x: waves w = grp mod 6; y/z: faces
-// j = grp mod 6), each as the two halves of the face VJP.
+// Six launch groups per direction (x: waves w = grp mod 6; y/z: face
+// blocks b = grp mod 6), one kernel each.
 template <typename R>
 hipError_t sweep_vjp_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, const double *U, const double *P,
-                       const double *rbar, double *Ubar, double *Pbar, double *rec, long long nrec, const Dissip &ds,
-                       hipStream_t s) {
+                       const double *rbar, double *Ubar, double *Pbar, const Dissip &ds, hipStream_t s) {
     const Geo &g = c.g;
     const int nsw = dir == 1 ? g.ny : g.nz;
     const long long ngrp = dir == 0 ? vjp_x_waves_per_plane(g) : (nsw + 1 + kVjpFB - 1) / kVjpFB;
     for (int grp = 0; grp < kVjpGroups && grp < ngrp; ++grp) {
-        // the second half does not depend on the reconstruction
-        hipError_t e = ds.recon == kReconCu6
-                           ? launch_vjp_group<R, 0, true>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, rec, nrec, ds, s)
-                           : launch_vjp_group<R, 0, false>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, rec, nrec, ds, s);
-        if (e == hipSuccess)
-            e = launch_vjp_group<R, 1, false>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, rec, nrec, ds, s);
+        const hipError_t e = ds.recon == kReconCu6
+                                 ? launch_vjp_group<R, true>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, ds, s)
+                                 : launch_vjp_group<R, false>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, ds, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
 hipError_t sweep_vjp(const LaunchCtx &c, int dir, const double *U, const double *P, const double *rbar,
-                     double *Ubar, double *Pbar, double *rec, long long nrec, const double *glf, hipStream_t s) {
+                     double *Ubar, double *Pbar, const double *glf, hipStream_t s) {
     const Dissip ds{c.visc, glf, c.recon};
     if (c.visc == kViscGlf && !glf) return hipErrorInvalidValue;
     if (c.recon == kReconWeno7) return hipErrorInvalidValue;   // six-cell stencils only
     if (c.precision == XF_PREC_MIXED)
-        return sweep_vjp_t<float>(c, c.th32, dir, U, P, rbar, Ubar, Pbar, rec, nrec, ds, s);
-    return sweep_vjp_t<double>(c, c.th64, dir, U, P, rbar, Ubar, Pbar, rec, nrec, ds, s);
+        return sweep_vjp_t<float>(c, c.th32, dir, U, P, rbar, Ubar, Pbar, ds, s);
+    return sweep_vjp_t<double>(c, c.th64, dir, U, P, rbar, Ubar, Pbar, ds, s);
 }
 
 hipError_t glf(const LaunchCtx &c, int dir, const double *U, const double *P, unsigned long long *mx,

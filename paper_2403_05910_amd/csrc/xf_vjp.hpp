@@ -16,6 +16,16 @@
 
 namespace xf {
 
+// Phase boundary of the face VJP: besides the compiler fence, the stencil's
+// base index passes through an empty asm statement, so loads of one phase
+// cannot be merged with the same loads of an earlier one (which would keep
+// every loaded stencil value live across the whole routine).
+#ifdef __HIP_DEVICE_COMPILE__
+#define XF_PHASE(st) asm volatile("" : "+v"(st.base) : : "memory")
+#else
+#define XF_PHASE(st) ((void)0)
+#endif
+
 // Reciprocal of a positive normal number: rcp_nr (about 1 ulp, 5
 // instructions) in FP64, IEEE division in FP32.
 XF_HD double vjp_recip(double x) { return rcp_nr(x); }
@@ -170,35 +180,55 @@ XF_HD R dcv_species(const ThermoK<R> &th, int s, R T) {
     return ((R(4) * th.cv[s][4] * T + R(3) * th.cv[s][3]) * T + R(2) * th.cv[s][2]) * T + th.cv[s][1];
 }
 
-// Where the cotangents of one stencil go: FP64 padded buffers, added to.
-struct Sink {
-    double *__restrict__ Ub;   // [Nv][cells]
-    double *__restrict__ Pb;   // [2][cells]: cotangent of p, of T
-    long long base, step, cells;
-    XF_HD void u(int f, int m, double v) const { Ub[f * cells + base + m * step] += v; }
-    XF_HD void p(int k, int m, double v) const { Pb[k * cells + base + m * step] += v; }
-};
-
-// Where the cotangents of one stencil go, variant 2: a wave's private LDS
-// window of the padded cells its faces touch ([NV + 2][W], field-major;
-// stencil cell 0 of this thread's face at window index off).  Lanes of a wave
+// Where the cotangents of one stencil go: a wave's private LDS window of the
+// padded cells its faces touch ([NV + 3][W], field-major; stencil cell 0 of
+// this thread's face at window index off).  Rows NV.. hold the cotangents of
+// the cell's pressure, of its temperature and of its density rho = sum_s
+// rho_s (added to every partial density by k_prims_vjp).  Lanes of a wave
 // share window cells through different (field, cell) calls, so the
 // read-modify-writes must stay in program order even where one thread's
 // addresses differ: the accesses are volatile (LDS executes a wave's
 // instructions in order).  The pointer carries the LDS address space, so no
 // generic-address checks are generated.
 typedef __attribute__((address_space(3))) double lds_double;   // a pointer known to be LDS
+constexpr int kSinkP = 0, kSinkT = 1, kSinkRho = 2, kSinkExtra = 3;
 struct SinkLds {
     volatile lds_double *w;
-    int W, off, mstep, pofs;   // window length, offset of stencil cell 0, cell stride, start of the P rows
+    int W, off, mstep, pofs;   // window length, offset of stencil cell 0, cell stride, start of the extra rows
     XF_HD void u(int f, int m, double v) const { w[f * W + off + m * mstep] += v; }
     XF_HD void p(int k, int m, double v) const { w[pofs + k * W + off + m * mstep] += v; }
 };
 
-// Forward Roe state of one face (shared by both halves of the face VJP).
+// Stencil values staged in LDS: field f of stencil cell m at
+// t[f * fs + base + m * step]; fields 0..NV-1 are U, NV..NV+3 the primitives
+// (T, p, c, 1/rho).
+template <int NV>
+struct StencilLds {
+    const lds_double *t;
+    int base, step, fs;
+    XF_HD double u(int f, int m) const { return t[f * fs + base + m * step]; }
+    XF_HD double p(int k, int m) const { return t[(NV + k) * fs + base + m * step]; }
+};
+
+// Cotangent of the face flux, (rbar_R - rbar_L) / dx of the residual's
+// cotangent at the face's two cells (zero outside the interior); read from
+// memory where it is used.
+struct FaceBar {
+    const double *__restrict__ rbar;
+    long long C, cr, cl;   // field stride, right and left cell
+    bool hr, hl;           // the right / left cell is interior
+    double id;             // 1 / dx of the direction
+    XF_HD double operator()(int q) const {
+        const double r = hr ? rbar[q * C + cr] : 0.0;
+        const double l = hl ? rbar[q * C + cl] : 0.0;
+        return (r - l) * id;
+    }
+};
+
+// Forward Roe state of one face (the dissipation speeds of the ROE scheme).
 template <int NS, typename R>
 struct RoeFwd {
-    R sL, sR, Ssum, wL, wR, r2, r3, aL, aR, ut[3], Ht, Tt, Yt[NS], chi[NS], cvb, Gam, q2, c2, ct, ic2, cih, iGam;
+    R ut[3], ct;
     XF_HD RoeFwd(const Stencil &st, const ThermoK<R> &th) {
         constexpr int IM = NS;
         constexpr int IE = NS + 3;
@@ -208,108 +238,130 @@ struct RoeFwd {
             rL += R(st.u(s, 2));
             rR += R(st.u(s, 3));
         }
-        sL = xsqrt(rL);
-        sR = xsqrt(rR);
-        Ssum = sL + sR;
-        wL = sL / Ssum;
-        wR = R(1) - wL;
-        r2 = R(st.p(3, 2));
-        r3 = R(st.p(3, 3));
-        aL = wL * r2;
-        aR = wR * r3;
+        const R sL = xsqrt(rL), sR = xsqrt(rR);
+        const R wL = sL / (sL + sR), wR = R(1) - wL;
+        const R aL = wL * R(st.p(3, 2)), aR = wR * R(st.p(3, 3));
 #pragma unroll
         for (int k = 0; k < 3; ++k) ut[k] = aL * R(st.u(IM + k, 2)) + aR * R(st.u(IM + k, 3));
-        Ht = aL * (R(st.u(IE, 2)) + R(st.p(1, 2))) + aR * (R(st.u(IE, 3)) + R(st.p(1, 3)));
-        Tt = wL * R(st.p(0, 2)) + wR * R(st.p(0, 3));
-        R Rb = R(0);
-        cvb = R(0);
+        const R Ht = aL * (R(st.u(IE, 2)) + R(st.p(1, 2))) + aR * (R(st.u(IE, 3)) + R(st.p(1, 3)));
+        const R Tt = wL * R(st.p(0, 2)) + wR * R(st.p(0, 3));
+        R Rb = R(0), cvb = R(0), chi[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            Yt[s] = aL * R(st.u(s, 2)) + aR * R(st.u(s, 3));
-            Rb += Yt[s] * th.Rs[s];
-            cvb += Yt[s] * cv_species(th, s, Tt);
+            const R Y = aL * R(st.u(s, 2)) + aR * R(st.u(s, 3));
+            Rb += Y * th.Rs[s];
+            cvb += Y * cv_species(th, s, Tt);
             chi[s] = e_species(th, s, Tt);
         }
-        Gam = Rb / cvb;
-        q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
-        c2 = Gam * (Ht - q2);
+        const R Gam = Rb / cvb;
+        const R q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+        R c2 = Gam * (Ht - q2);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            chi[s] = Gam * (R(0.5) * q2 - chi[s]) + th.Rs[s] * Tt;
-            c2 += Yt[s] * chi[s];
+            const R Y = aL * R(st.u(s, 2)) + aR * R(st.u(s, 3));
+            c2 += Y * (Gam * (R(0.5) * q2 - chi[s]) + th.Rs[s] * Tt);
         }
         ct = xsqrt(c2);
-        ic2 = R(1) / c2;
-        cih = R(0.5) * ct * ic2;
-        iGam = R(1) / Gam;
     }
 };
 
-// Record passed from the first half of the face VJP to the second: the
-// per-cell cotangents of DU, DF, u_n, rho, p, m_n (6 each), those of the Roe
-// Y_s and chi_s, of u~ and of c~, H~, q~^2, 1/Gamma, c~/(2 c~^2).
-template <int NS>
-struct VjpRec {
-    static constexpr int N = 44 + 2 * NS;
-    static constexpr int DUb = 0, DFb = 6, unb = 12, rhb = 18, pmb = 24, Mnb = 30, Ytb = 36, chib = 36 + NS,
-                         utb = 36 + 2 * NS, ctb = utb + 3, Htb = ctb + 1, q2b = ctb + 2, iGamb = ctb + 3,
-                         cihb = ctb + 4;
-    double *__restrict__ r;
-    long long stride, idx;
-    XF_HD void put(int k, double v) const { r[k * stride + idx] = v; }
-    XF_HD double get(int k) const { return r[k * stride + idx]; }
-};
-
-#define XF_ROE_UNPACK(rf)                                                                                   \
-    const R sL = rf.sL, sR = rf.sR, Ssum = rf.Ssum, wL = rf.wL, wR = rf.wR, r2 = rf.r2, r3 = rf.r3,        \
-            aL = rf.aL, aR = rf.aR, Ht = rf.Ht, Tt = rf.Tt, cvb = rf.cvb, Gam = rf.Gam, q2 = rf.q2,        \
-            c2 = rf.c2, ct = rf.ct, ic2 = rf.ic2, cih = rf.cih, iGam = rf.iGam;                            \
-    const R *ut = rf.ut, *Yt = rf.Yt, *chi = rf.chi;                                                       \
-    (void)sL; (void)sR; (void)Ssum; (void)wL; (void)wR; (void)r2; (void)r3; (void)aL; (void)aR; (void)Ht; \
-    (void)Tt; (void)cvb; (void)c2; (void)ct; (void)cih; (void)iGam
-
-// First half: forward recompute, then the backward through the back-projection,
-// the WENO5 reconstructions and the characteristic projections' dependence on
-// each cell's own values; writes the direct cell cotangents to `out` and the
-// accumulated ones to `rec`.
-template <int NS, typename R, int DIR, bool CU6 = false, class Out>
-XF_HD void face_vjp_a(const Stencil &st, const ThermoK<R> &th, const R *Fb, const Out &out, const VjpRec<NS> &rec,
-                      const Dissip &ds) {
+// VJP of one face in one pass: the forward recomputed (Roe state, per-cell
+// projection scalars, LLF speeds), then backwards through the
+// back-projection, the reconstruction of each characteristic field (acoustic
+// pair, tangential pair, species), the projections and the Roe state.  No
+// per-species array is kept: the averaged Y_s, chi_s and the species thermo
+// at T~ are recomputed where they are used, and each contribution to the
+// cotangent of Y_s or chi_s is passed on at once (to the partial densities
+// of the face's two cells, and to Gamma, |u|^2 and T~), so the live state is
+// the per-cell scalars (u_n, DU, DF and their cotangents) and a few dozen
+// scalars of the Roe state.  Fb(q) gives the face flux cotangent.
+//
+// Names: DU = dp(U_m)/c^2, DF = dp(F_m)/c^2 with dp(v) = sum_s chi_s v_s -
+// Gamma u.v_m + Gamma v_E; XU = n.m - u_n rho, XF = n.F_m - u_n F_rho
+// (acoustic rows l_-+ . v = DU/2 -+ c XU/(2 c^2), likewise for F).
+template <int NS, typename R, int DIR, bool CU6, class St, class Bar, class Out>
+XF_HD void face_vjp(St st, const ThermoK<R> &th, const Bar &Fb, const Out &out, const Dissip &ds) {
     constexpr int IM = NS;
     constexpr int IE = NS + 3;
     constexpr int KN = Axes<DIR>::n, K1 = Axes<DIR>::t1, K2 = Axes<DIR>::t2;
     constexpr int IN = NS + KN, I1 = NS + K1, I2 = NS + K2;
 
-    // ================= forward: Roe state and per-cell scalars =================
-    constexpr bool cu6 = CU6;   // WENO-CU6 reconstruction (else WENO5)
-    const RoeFwd<NS, R> rf(st, th);
-    XF_ROE_UNPACK(rf);
-    const R utn = ut[KN], ut1 = ut[K1], ut2 = ut[K2];
+    // ================= forward: Roe state ===================================
+    R ut[3], Ht, Tt, aL, aR, Gam, q2, c2, ct, ic2, cih, iGam, S1, Se, Rb, cvb;
+    {
+        R rL = R(0), rR = R(0);
+#pragma unroll 1
+        for (int s = 0; s < NS; ++s) {
+            rL += R(st.u(s, 2));
+            rR += R(st.u(s, 3));
+        }
+        const R sL = xsqrt(rL), sR = xsqrt(rR);
+        const R wL = sL / (sL + sR), wR = R(1) - wL;
+        aL = wL * R(st.p(3, 2));
+        aR = wR * R(st.p(3, 3));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ut[k] = aL * R(st.u(IM + k, 2)) + aR * R(st.u(IM + k, 3));
+        Ht = aL * (R(st.u(IE, 2)) + R(st.p(1, 2))) + aR * (R(st.u(IE, 3)) + R(st.p(1, 3)));
+        Tt = wL * R(st.p(0, 2)) + wR * R(st.p(0, 3));
+    }
+    Rb = R(0);
+    cvb = R(0);
+    Se = R(0);
+    S1 = R(0);
+#pragma unroll 1
+    for (int s = 0; s < NS; ++s) {
+        const R Y = aL * R(st.u(s, 2)) + aR * R(st.u(s, 3));
+        S1 += Y;
+        Rb += Y * th.Rs[s];
+        cvb += Y * cv_species(th, s, Tt);
+        Se += Y * e_species(th, s, Tt);
+    }
+    Gam = Rb / cvb;
+    q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+    // c^2 = Gamma (H - q^2) + sum_s Y_s chi_s, the sum written with S1 = sum Y,
+    // Se = sum Y e_s(T~), Rb = sum Y R_s
+    c2 = Gam * (Ht - q2) + Gam * (R(0.5) * q2 * S1 - Se) + Tt * Rb;
+    ct = xsqrt(c2);
+    ic2 = R(1) / c2;
+    cih = R(0.5) * ct * ic2;
+    iGam = R(1) / Gam;
+    const R utn = ut[KN];
 
+    // ================= forward: per-cell projection scalars =================
     R un[6], DU[6], DF[6], rh[6];
     R aM = R(0), a0 = R(0), aP = R(0);
+    {
+        R sc[6];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) {
-        R sc = R(0), sr = R(0);
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const R r = R(st.u(s, m));
-            sc += chi[s] * r;
-            sr += r;
+        for (int m = 0; m < 6; ++m) {
+            sc[m] = R(0);
+            rh[m] = R(0);
         }
-        const R rinv = R(st.p(3, m)), pm = R(st.p(1, m)), cm = R(st.p(2, m));
-        const R E = R(st.u(IE, m));
-        const R unm = R(st.u(IN, m)) * rinv;
-        const R um = ut[0] * R(st.u(IM, m)) + ut[1] * R(st.u(IM + 1, m)) + ut[2] * R(st.u(IM + 2, m));
-        const R dpU = sc - Gam * um + Gam * E;
-        const R dpF = unm * sc - Gam * (unm * um + pm * utn) + Gam * ((E + pm) * unm);
-        un[m] = unm;
-        DU[m] = dpU * ic2;
-        DF[m] = dpF * ic2;
-        rh[m] = sr;
-        aM = rmax(aM, rabs(unm - cm));
-        a0 = rmax(a0, rabs(unm));
-        aP = rmax(aP, rabs(unm + cm));
+#pragma unroll 1
+        for (int s = 0; s < NS; ++s) {
+            const R chis = Gam * (R(0.5) * q2 - e_species(th, s, Tt)) + th.Rs[s] * Tt;
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                const R r = R(st.u(s, m));
+                sc[m] += chis * r;
+                rh[m] += r;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            const R rinv = R(st.p(3, m)), pm = R(st.p(1, m)), cm = R(st.p(2, m));
+            const R E = R(st.u(IE, m));
+            const R unm = R(st.u(IN, m)) * rinv;
+            const R um = ut[0] * R(st.u(IM, m)) + ut[1] * R(st.u(IM + 1, m)) + ut[2] * R(st.u(IM + 2, m));
+            const R dpU = sc[m] - Gam * um + Gam * E;
+            const R dpF = unm * sc[m] - Gam * (unm * um + pm * utn) + Gam * ((E + pm) * unm);
+            un[m] = unm;
+            DU[m] = dpU * ic2;
+            DF[m] = dpF * ic2;
+            aM = rmax(aM, rabs(unm - cm));
+            a0 = rmax(a0, rabs(unm));
+            aP = rmax(aP, rabs(unm + cm));
+        }
     }
     if (ds.type == kViscRoe) {   // speeds of the Roe state, held fixed like the LLF ones
         aM = rabs(utn - ct);
@@ -321,76 +373,69 @@ XF_HD void face_vjp_a(const Stencil &st, const ThermoK<R> &th, const R *Fb, cons
         aP = R(ds.glf[2]);
     }
 
-    XF_FENCE();
+    XF_PHASE(st);
     // ================= back-projection cotangents known from Fb ============
     // F_s = Y_s A + h_s; F_m = u (A + gsum) + c n D + t1 h1 + t2 h2;
     // F_E = H A + u_n c D + u_t1 h1 + u_t2 h2 + sum_s (q2 - chi_s / Gam) h_s,
     // A = h_- + h_+, D = h_+ - h_-, gsum = sum_s h_s.
-    const R FbE = Fb[IE];
-    const R Fbm[3] = {Fb[IM], Fb[IM + 1], Fb[IM + 2]};
+    const R FbE = R(Fb(IE));
+    const R Fbm[3] = {R(Fb(IM)), R(Fb(IM + 1)), R(Fb(IM + 2))};
     const R gsum_b = ut[0] * Fbm[0] + ut[1] * Fbm[1] + ut[2] * Fbm[2];
     R Asum_b = gsum_b + Ht * FbE;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) Asum_b += Yt[s] * Fb[s];
+#pragma unroll 1
+    for (int s = 0; s < NS; ++s) Asum_b += (aL * R(st.u(s, 2)) + aR * R(st.u(s, 3))) * R(Fb(s));
     const R Dif_b = ct * Fbm[KN] + utn * ct * FbE;
     R ut_b[3] = {R(0), R(0), R(0)};
-    R ct_b = R(0), Ht_b = R(0), q2_b = R(0), iGam_b = R(0), cih_b = R(0);
-    R Yt_b[NS], chi_b[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        Yt_b[s] = R(0);
-        chi_b[s] = R(0);
-    }
-    R un_b[6], DU_b[6], DF_b[6], rh_b[6], pm_b[6], Mn_b[6];
+    R ct_b = R(0), Ht_b = R(0), q2_b = R(0), iGam_b = R(0), cih_b = R(0), Gam_b = R(0), Tt_b = R(0);
+    R aL_b = R(0), aR_b = R(0);
+    R un_b[6], DU_b[6], DF_b[6];
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
         un_b[m] = R(0);
         DU_b[m] = R(0);
         DF_b[m] = R(0);
-        rh_b[m] = R(0);
-        pm_b[m] = R(0);
-        Mn_b[m] = R(0);
     }
 
-    XF_FENCE();
-    // ================= acoustic pair: forward value and backward ===========
-    R Asum, Dif;
-    {
-        R gMp[6], gMm[6], gPp[6], gPm[6];
+    // ================= acoustic fields, one at a time =======================
+    // The cotangents of each cell's normal momentum, pressure and density
+    // go to the sink as they arise.
+    R Asum = R(0), Dif = R(0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        XF_PHASE(st);
+        const R sg = a == 0 ? R(-1) : R(1);
+        const R al = a == 0 ? aM : aP;
+        const R hb = Asum_b + sg * Dif_b;
+        R gp[6], gm[6], wFb[6], wUb[6];
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
             const R mn = R(st.u(IN, m));
             const R XU = mn - utn * rh[m];
             const R XF = (mn * un[m] + R(st.p(1, m))) - utn * (rh[m] * un[m]);
-            const R wUm = R(0.5) * DU[m] - cih * XU, wFm = R(0.5) * DF[m] - cih * XF;
-            const R wUp = R(0.5) * DU[m] + cih * XU, wFp = R(0.5) * DF[m] + cih * XF;
-            gMp[m] = R(0.5) * (wFm + aM * wUm);
-            gMm[m] = R(0.5) * (wFm - aM * wUm);
-            gPp[m] = R(0.5) * (wFp + aP * wUp);
-            gPm[m] = R(0.5) * (wFp - aP * wUp);
+            const R wU = R(0.5) * DU[m] + sg * cih * XU, wF = R(0.5) * DF[m] + sg * cih * XF;
+            gp[m] = R(0.5) * (wF + al * wU);
+            gm[m] = R(0.5) * (wF - al * wU);
         }
-        R wFmb[6], wUmb[6], wFpb[6], wUpb[6];
-        const R hm = cu6 ? split_cu6_fb(gMp, gMm, aM, Asum_b - Dif_b, wFmb, wUmb)
-                         : split_weno_fb(gMp, gMm, aM, Asum_b - Dif_b, wFmb, wUmb);
-        const R hp = cu6 ? split_cu6_fb(gPp, gPm, aP, Asum_b + Dif_b, wFpb, wUpb)
-                         : split_weno_fb(gPp, gPm, aP, Asum_b + Dif_b, wFpb, wUpb);
-        Asum = hm + hp;
-        Dif = hp - hm;
+        const R h = CU6 ? split_cu6_fb(gp, gm, al, hb, wFb, wUb) : split_weno_fb(gp, gm, al, hb, wFb, wUb);
+        Asum += h;
+        Dif += sg * h;
+        XF_PHASE(st);
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
             const R mn = R(st.u(IN, m));
             const R XU = mn - utn * rh[m];
             const R XF = (mn * un[m] + R(st.p(1, m))) - utn * (rh[m] * un[m]);
-            DU_b[m] += R(0.5) * (wUmb[m] + wUpb[m]);
-            DF_b[m] += R(0.5) * (wFmb[m] + wFpb[m]);
-            const R XUb = cih * (wUpb[m] - wUmb[m]);
-            const R XFb = cih * (wFpb[m] - wFmb[m]);
-            cih_b += XU * (wUpb[m] - wUmb[m]) + XF * (wFpb[m] - wFmb[m]);
-            Mn_b[m] += XUb + un[m] * XFb;
-            ut_b[KN] -= rh[m] * XUb + rh[m] * un[m] * XFb;
-            rh_b[m] -= utn * XUb + utn * un[m] * XFb;
+            DU_b[m] += R(0.5) * wUb[m];
+            DF_b[m] += R(0.5) * wFb[m];
+            const R XUb = sg * cih * wUb[m];
+            const R XFb = sg * cih * wFb[m];
+            cih_b += sg * (XU * wUb[m] + XF * wFb[m]);
+            const R xb = XUb + un[m] * XFb;
+            ut_b[KN] -= rh[m] * xb;
             un_b[m] += (mn - utn * rh[m]) * XFb;
-            pm_b[m] += XFb;
+            out.u(IN, m, double(xb));
+            out.p(kSinkRho, m, double(-utn * xb));
+            out.p(kSinkP, m, double(XFb));
         }
     }
     ct_b += Dif * Fbm[KN] + utn * Dif * FbE;
@@ -400,10 +445,10 @@ XF_HD void face_vjp_a(const Stencil &st, const ThermoK<R> &th, const R *Fb, cons
     // ================= tangential pair =====================================
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-        XF_FENCE();
+        XF_PHASE(st);
         const int I = a == 0 ? I1 : I2;
         const int K = a == 0 ? K1 : K2;
-        const R uta = a == 0 ? ut1 : ut2;
+        const R uta = ut[K];
         const R hb = Fbm[K] + uta * FbE;
         R gp[6], gm[6], wU[6], wFb[6], wUb[6];
 #pragma unroll
@@ -412,7 +457,7 @@ XF_HD void face_vjp_a(const Stencil &st, const ThermoK<R> &th, const R *Fb, cons
             gp[m] = R(0.5) * (un[m] * wU[m] + a0 * wU[m]);
             gm[m] = R(0.5) * (un[m] * wU[m] - a0 * wU[m]);
         }
-        const R ha = cu6 ? split_cu6_fb(gp, gm, a0, hb, wFb, wUb) : split_weno_fb(gp, gm, a0, hb, wFb, wUb);
+        const R ha = CU6 ? split_cu6_fb(gp, gm, a0, hb, wFb, wUb) : split_weno_fb(gp, gm, a0, hb, wFb, wUb);
         ut_b[K] += ha * FbE;
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
@@ -420,139 +465,109 @@ XF_HD void face_vjp_a(const Stencil &st, const ThermoK<R> &th, const R *Fb, cons
             const R wUt = wUb[m] + un[m] * wFb[m];
             out.u(I, m, double(wUt));
             ut_b[K] -= rh[m] * wUt;
-            rh_b[m] -= uta * wUt;
+            out.p(kSinkRho, m, double(-uta * wUt));
         }
     }
 
     // ================= species fields ======================================
     R gsum = R(0);
-#pragma unroll
+#pragma unroll 1
     for (int s = 0; s < NS; ++s) {
-        XF_FENCE();
-        const R hsb = Fb[s] + gsum_b + (q2 - chi[s] * iGam) * FbE;
+        XF_PHASE(st);
+        const R r2s = R(st.u(s, 2)), r3s = R(st.u(s, 3));
+        const R Ys = aL * r2s + aR * r3s;
+        const R es = e_species(th, s, Tt);
+        const R chis = Gam * (R(0.5) * q2 - es) + th.Rs[s] * Tt;
+        const R Fbs = R(Fb(s));
+        const R hsb = Fbs + gsum_b + (q2 - chis * iGam) * FbE;
         R gp[6], gm[6], wFb[6], wUb[6];
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
             const R r = R(st.u(s, m));
-            const R wU = r - Yt[s] * DU[m];
-            const R wF = r * un[m] - Yt[s] * DF[m];
+            const R wU = r - Ys * DU[m];
+            const R wF = r * un[m] - Ys * DF[m];
             gp[m] = R(0.5) * (wF + a0 * wU);
             gm[m] = R(0.5) * (wF - a0 * wU);
         }
-        const R hs = cu6 ? split_cu6_fb(gp, gm, a0, hsb, wFb, wUb) : split_weno_fb(gp, gm, a0, hsb, wFb, wUb);
+        const R hs = CU6 ? split_cu6_fb(gp, gm, a0, hsb, wFb, wUb) : split_weno_fb(gp, gm, a0, hsb, wFb, wUb);
         gsum += hs;
-        Yt_b[s] += Asum * Fb[s];
         q2_b += hs * FbE;
-        chi_b[s] -= iGam * hs * FbE;
-        iGam_b -= chi[s] * hs * FbE;
+        iGam_b -= chis * hs * FbE;
+        R ytb = Asum * Fbs;   // cotangent of Y_s from this field
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
             const R r = R(st.u(s, m));
             out.u(s, m, double(wUb[m] + un[m] * wFb[m]));
             un_b[m] += r * wFb[m];
-            Yt_b[s] -= DU[m] * wUb[m] + DF[m] * wFb[m];
-            DU_b[m] -= Yt[s] * wUb[m];
-            DF_b[m] -= Yt[s] * wFb[m];
+            ytb -= DU[m] * wUb[m] + DF[m] * wFb[m];
+            DU_b[m] -= Ys * wUb[m];
+            DF_b[m] -= Ys * wFb[m];
         }
+        // chi_s = Gamma (q^2/2 - e_s(T~)) + R_s T~, its cotangent -hs FbE / Gamma
+        const R chb = -iGam * hs * FbE;
+        Gam_b += (R(0.5) * q2 - es) * chb;
+        q2_b += R(0.5) * Gam * chb;
+        Tt_b += (th.Rs[s] - Gam * cv_species(th, s, Tt)) * chb;
+        // Y_s = aL rho_s(2) + aR rho_s(3)
+        out.u(s, 2, double(aL * ytb));
+        out.u(s, 3, double(aR * ytb));
+        aL_b += r2s * ytb;
+        aR_b += r3s * ytb;
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) ut_b[k] += (Asum + gsum) * Fbm[k];
 
-    using Rc = VjpRec<NS>;
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-        rec.put(Rc::DUb + m, double(DU_b[m]));
-        rec.put(Rc::DFb + m, double(DF_b[m]));
-        rec.put(Rc::unb + m, double(un_b[m]));
-        rec.put(Rc::rhb + m, double(rh_b[m]));
-        rec.put(Rc::pmb + m, double(pm_b[m]));
-        rec.put(Rc::Mnb + m, double(Mn_b[m]));
-    }
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        rec.put(Rc::Ytb + s, double(Yt_b[s]));
-        rec.put(Rc::chib + s, double(chi_b[s]));
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) rec.put(Rc::utb + k, double(ut_b[k]));
-    rec.put(Rc::ctb, double(ct_b));
-    rec.put(Rc::Htb, double(Ht_b));
-    rec.put(Rc::q2b, double(q2_b));
-    rec.put(Rc::iGamb, double(iGam_b));
-    rec.put(Rc::cihb, double(cih_b));
-}
-
-// Second half: forward Roe state again, the record, then the backward through
-// the per-cell projection scalars DU, DF, the Roe state (c~^2, Gamma~, chi_s
-// and the species thermo at T~), the sqrt(rho) averages and their weights.
-template <int NS, typename R, int DIR, class Out>
-XF_HD void face_vjp_b(const Stencil &st, const ThermoK<R> &th, const Out &out, const VjpRec<NS> &rec) {
-    constexpr int IM = NS;
-    constexpr int IE = NS + 3;
-    constexpr int KN = Axes<DIR>::n;
-    constexpr int IN = NS + KN;
-    using Rc = VjpRec<NS>;
-    const RoeFwd<NS, R> rf(st, th);
-    XF_ROE_UNPACK(rf);
-    const R utn = ut[KN];
-    R ut_b[3], Yt_b[NS], chi_b[NS];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) ut_b[k] = R(rec.get(Rc::utb + k));
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        Yt_b[s] = R(rec.get(Rc::Ytb + s));
-        chi_b[s] = R(rec.get(Rc::chib + s));
-    }
-    R ct_b = R(rec.get(Rc::ctb)), Ht_b = R(rec.get(Rc::Htb)), q2_b = R(rec.get(Rc::q2b));
-    const R iGam_b = R(rec.get(Rc::iGamb)), cih_b = R(rec.get(Rc::cihb));
-
     // ================= per-cell projections: DU = dpU / c^2, DF = dpF / c^2
-    R Gam_b = R(0), ic2_b = R(0);
+    R ic2_b = R(0), scb[6];
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
-        XF_FENCE();
-        R sc = R(0);
-#pragma unroll
-        for (int s = 0; s < NS; ++s) sc += chi[s] * R(st.u(s, m));
+        XF_PHASE(st);
         const R rinv = R(st.p(3, m)), pm = R(st.p(1, m));
         const R E = R(st.u(IE, m));
         const R M0 = R(st.u(IM, m)), M1 = R(st.u(IM + 1, m)), M2 = R(st.u(IM + 2, m));
         const R mn = R(st.u(IN, m));
-        const R unm = mn * rinv;
-        const R DUb = R(rec.get(Rc::DUb + m)), DFb = R(rec.get(Rc::DFb + m));
+        const R unm = un[m];
         const R um = ut[0] * M0 + ut[1] * M1 + ut[2] * M2;
-        const R dpU = sc - Gam * um + Gam * E;
-        const R dpF = unm * sc - Gam * (unm * um + pm * utn) + Gam * ((E + pm) * unm);
-        const R dpU_b = ic2 * DUb, dpF_b = ic2 * DFb;
-        ic2_b += dpU * DUb + dpF * DFb;
+        const R dpU = DU[m] * c2, dpF = DF[m] * c2;
+        const R dpU_b = ic2 * DU_b[m], dpF_b = ic2 * DF_b[m];
+        ic2_b += dpU * DU_b[m] + dpF * DF_b[m];
         const R sc_b = dpU_b + unm * dpF_b;
-        const R um_b = -Gam * (dpU_b + unm * dpF_b);
-        const R E_b = Gam * (dpU_b + unm * dpF_b);
+        scb[m] = sc_b;
+        const R um_b = -Gam * sc_b;
         Gam_b += (E - um) * dpU_b + ((E + pm) * unm - unm * um - pm * utn) * dpF_b;
-        const R un_bt = R(rec.get(Rc::unb + m)) + (sc - Gam * um + Gam * (E + pm)) * dpF_b;
-        const R pm_bt = R(rec.get(Rc::pmb + m)) + Gam * (unm - utn) * dpF_b;
+        const R un_bt = un_b[m] + (dpU + Gam * pm) * dpF_b;
         ut_b[KN] -= Gam * pm * dpF_b;
         ut_b[0] += M0 * um_b;
         ut_b[1] += M1 * um_b;
         ut_b[2] += M2 * um_b;
-        const R rinv_b = mn * un_bt;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             R v = ut[k] * um_b;
-            if (k == KN) v += R(rec.get(Rc::Mnb + m)) + rinv * un_bt;
+            if (k == KN) v += rinv * un_bt;
             out.u(IM + k, m, double(v));
         }
-        const R sp = R(rec.get(Rc::rhb + m)) - rinv * rinv * rinv_b;
+        out.u(IE, m, double(Gam * sc_b));
+        out.p(kSinkP, m, double(Gam * (unm - utn) * dpF_b));
+        out.p(kSinkRho, m, double(-rinv * rinv * mn * un_bt));   // through 1/rho
+    }
+    // sc = sum_s chi_s rho_s of each cell
+#pragma unroll 1
+    for (int s = 0; s < NS; ++s) {
+        XF_PHASE(st);
+        const R es = e_species(th, s, Tt);
+        const R chis = Gam * (R(0.5) * q2 - es) + th.Rs[s] * Tt;
+        R chb = R(0);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            chi_b[s] += R(st.u(s, m)) * sc_b;
-            out.u(s, m, double(chi[s] * sc_b + sp));
+        for (int m = 0; m < 6; ++m) {
+            chb += R(st.u(s, m)) * scb[m];
+            out.u(s, m, double(chis * scb[m]));
         }
-        out.u(IE, m, double(E_b));
-        out.p(0, m, double(pm_bt));
+        Gam_b += (R(0.5) * q2 - es) * chb;
+        q2_b += R(0.5) * Gam * chb;
+        Tt_b += (th.Rs[s] - Gam * cv_species(th, s, Tt)) * chb;
     }
 
-    XF_FENCE();
+    XF_PHASE(st);
     // ================= Roe state: c^2, Gamma, chi_s, thermo at T~, averages
     ct_b += R(0.5) * ic2 * cih_b;
     ic2_b += R(0.5) * ct * cih_b;
@@ -560,27 +575,32 @@ XF_HD void face_vjp_b(const Stencil &st, const ThermoK<R> &th, const Out &out, c
     Gam_b += (Ht - q2) * c2_b - iGam * iGam * iGam_b;
     Ht_b += Gam * c2_b;
     q2_b -= Gam * c2_b;
-    R Tt_b = R(0);
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        Yt_b[s] += chi[s] * c2_b;
-        chi_b[s] += Yt[s] * c2_b;
-        const R es = e_species(th, s, Tt);
-        Gam_b += (R(0.5) * q2 - es) * chi_b[s];
-        q2_b += R(0.5) * Gam * chi_b[s];
-        Tt_b += th.Rs[s] * chi_b[s] - cv_species(th, s, Tt) * Gam * chi_b[s];
-    }
+    // the cotangent Y_s c2_b of every chi_s, summed over s
+    Gam_b += (R(0.5) * q2 * S1 - Se) * c2_b;
+    q2_b += R(0.5) * Gam * S1 * c2_b;
+    Tt_b += (Rb - Gam * cvb) * c2_b;
+    // Gamma = Rb / cvb
     const R Rb_b = Gam_b / cvb;
     const R cvb_b = -Gam / cvb * Gam_b;
-#pragma unroll
+#pragma unroll 1
     for (int s = 0; s < NS; ++s) {
-        Yt_b[s] += th.Rs[s] * Rb_b + cv_species(th, s, Tt) * cvb_b;
-        Tt_b += Yt[s] * dcv_species(th, s, Tt) * cvb_b;
+        XF_PHASE(st);
+        const R r2s = R(st.u(s, 2)), r3s = R(st.u(s, 3));
+        const R Ys = aL * r2s + aR * r3s;
+        const R chis = Gam * (R(0.5) * q2 - e_species(th, s, Tt)) + th.Rs[s] * Tt;
+        const R ytb = chis * c2_b + th.Rs[s] * Rb_b + cv_species(th, s, Tt) * cvb_b;
+        Tt_b += Ys * dcv_species(th, s, Tt) * cvb_b;
+        out.u(s, 2, double(aL * ytb));
+        out.u(s, 3, double(aR * ytb));
+        aL_b += r2s * ytb;
+        aR_b += r3s * ytb;
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) ut_b[k] += R(2) * ut[k] * q2_b;
 
-    R aL_b = (R(st.u(IE, 2)) + R(st.p(1, 2))) * Ht_b, aR_b = (R(st.u(IE, 3)) + R(st.p(1, 3))) * Ht_b;
+    XF_PHASE(st);
+    aL_b += (R(st.u(IE, 2)) + R(st.p(1, 2))) * Ht_b;
+    aR_b += (R(st.u(IE, 3)) + R(st.p(1, 3))) * Ht_b;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         aL_b += R(st.u(IM + k, 2)) * ut_b[k];
@@ -588,17 +608,23 @@ XF_HD void face_vjp_b(const Stencil &st, const ThermoK<R> &th, const Out &out, c
         out.u(IM + k, 2, double(aL * ut_b[k]));
         out.u(IM + k, 3, double(aR * ut_b[k]));
     }
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        aL_b += R(st.u(s, 2)) * Yt_b[s];
-        aR_b += R(st.u(s, 3)) * Yt_b[s];
-    }
     out.u(IE, 2, double(aL * Ht_b));
     out.u(IE, 3, double(aR * Ht_b));
-    out.p(0, 2, double(aL * Ht_b));
-    out.p(0, 3, double(aR * Ht_b));
-    out.p(1, 2, double(wL * Tt_b));
-    out.p(1, 3, double(wR * Tt_b));
+    out.p(kSinkP, 2, double(aL * Ht_b));
+    out.p(kSinkP, 3, double(aR * Ht_b));
+    // the sqrt(rho) weights, again from the two cells' densities
+    R rL = R(0), rR = R(0);
+#pragma unroll 1
+    for (int s = 0; s < NS; ++s) {
+        rL += R(st.u(s, 2));
+        rR += R(st.u(s, 3));
+    }
+    const R sL = xsqrt(rL), sR = xsqrt(rR), Ssum = sL + sR;
+    const R wL = sL / Ssum, wR = R(1) - wL;
+    const R r2 = R(st.p(3, 2)), r3 = R(st.p(3, 3));
+    out.p(kSinkT, 2, double(wL * Tt_b));
+    out.p(kSinkT, 3, double(wR * Tt_b));
+    // aL = wL / rho_L, aR = wR / rho_R, T~ = wL T_L + wR T_R
     R wL_b = R(st.p(0, 2)) * Tt_b + r2 * aL_b;
     const R wR_b = R(st.p(0, 3)) * Tt_b + r3 * aR_b;
     const R r2_b = wL * aL_b, r3_b = wR * aR_b;
@@ -606,19 +632,24 @@ XF_HD void face_vjp_b(const Stencil &st, const ThermoK<R> &th, const Out &out, c
     const R iS2 = R(1) / (Ssum * Ssum);
     const R rL_b = wL_b * sR * iS2 / (R(2) * sL);
     const R rR_b = -wL_b * sL * iS2 / (R(2) * sR);
-    const R x2 = rL_b - r2 * r2 * r2_b, x3 = rR_b - r3 * r3 * r3_b;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        out.u(s, 2, double(aL * Yt_b[s] + x2));
-        out.u(s, 3, double(aR * Yt_b[s] + x3));
-    }
+    out.p(kSinkRho, 2, double(rL_b - r2 * r2 * r2_b));
+    out.p(kSinkRho, 3, double(rR_b - r3 * r3 * r3_b));
 }
 
+// Waves per SIMD the face VJP kernels are compiled for: the FP32 face keeps
+// its state in 256 registers (two waves); the FP64 one needs up to 512 (one
+// wave; at two it spills 744 bytes per lane).  At one wave per SIMD a block
+// has its CU's LDS to itself, so the FP64 kernels first copy the stencil
+// values of all their faces (U and the primitives) into LDS, and the face
+// computation waits on no global load; the FP32 kernels, two blocks per CU,
+// read the stencil through the caches.
+template <typename R>
+constexpr int vjp_waves() { return sizeof(R) == 4 ? 2 : 1; }
+template <typename R>
+constexpr bool vjp_staged() { return sizeof(R) == 8; }
+
 // ---------------------------------------------------------------------------
-// The face VJP runs as two kernels per group of faces (HALF 0: face_vjp_a,
-// HALF 1: face_vjp_b) so that neither keeps the other's live state; the
-// record between them is indexed by the thread's linear index in the launch
-// (both halves use the same grid), with stride nrec.
+// The face VJP runs as one kernel per launch group of faces.
 //
 // x direction: lanes take consecutive x faces, linearised over the rows of
 // one z-plane (face f of the plane: row f / (nx + 1), face f % (nx + 1)).
@@ -631,14 +662,16 @@ XF_HD void face_vjp_b(const Stencil &st, const ThermoK<R> &th, const Out &out, c
 // needed.  The window is then added to Ubar / Pbar with coalesced
 // read-modify-writes.  Runs of waves w and w + 1 can share up to five cells,
 // those of w and w + 2 cannot; launch `grp` takes the waves w = grp mod 6.
+// Staged (FP64): the wave first copies the run's U and primitives into a
+// second private LDS area of (NV + 4) W values.
 // ---------------------------------------------------------------------------
-template <int NS, typename R, int HALF, bool CU6>
-__global__ __launch_bounds__(256) void k_face_vjp_x(const double *__restrict__ U, const double *__restrict__ P,
-                                                    const double *__restrict__ rbar, double *__restrict__ Ubar,
-                                                    double *__restrict__ Pbar, double *__restrict__ rec,
-                                                    long long nrec, Geo g, ThermoK<R> th, int W, int grp,
-                                                    Dissip ds) {
+template <int NS, typename R, bool CU6>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(vjp_waves<R>()))) void k_face_vjp_x(
+    const double *__restrict__ U, const double *__restrict__ P, const double *__restrict__ rbar,
+    double *__restrict__ Ubar, double *__restrict__ Pbar, Geo g, ThermoK<R> th, int W, int grp, Dissip ds) {
     constexpr int NV = NS + 4;
+    constexpr int NW = NV + kSinkExtra;                    // window rows
+    constexpr int NT = vjp_staged<R>() ? NV + 4 : 0;       // staged rows
     extern __shared__ double xf_win[];
     const int wpb = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long long rowf = (long long)g.nx + 1;          // faces per row
@@ -647,48 +680,60 @@ __global__ __launch_bounds__(256) void k_face_vjp_x(const double *__restrict__ U
     const long long wid = 6 * ((long long)blockIdx.x * wpb + wv) + grp;
     const long long C = g.cells;
     const long long zb = (long long)(g.gz + blockIdx.y) * g.sz + (long long)g.gy * g.sy;   // plane's first row
-    double *w = xf_win + (size_t)wv * (NV + 2) * W;
-    for (int i = lane; i < (NV + 2) * W; i += 64) w[i] = 0.0;
-    __syncthreads();
+    double *w = xf_win + (size_t)wv * (NW + NT) * W;
+    double *tile = w + (size_t)NW * W;
     const long long f0 = wid * 64, f = f0 + lane;
     const long long r0 = f0 / rowf;
     const long long base0 = zb + r0 * g.sy + (f0 - r0 * rowf);   // stencil cell 0 of the wave's first face
+    int span = 0;                                                 // cells of the wave's run
+    if (wid < wpp) {
+        const long long fl = min(f0 + 63, nfp - 1);
+        const long long rl = fl / rowf;
+        span = (int)(zb + rl * g.sy + (fl - rl * rowf) - base0) + 6;
+    }
+    for (int i = lane; i < NW * W; i += 64) w[i] = 0.0;
+    if constexpr (NT > 0) {
+        for (int c = lane; c < span; c += 64) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) tile[q * W + c] = U[q * C + base0 + c];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) tile[(NV + k) * W + c] = P[k * C + base0 + c];
+        }
+    }
+    __syncthreads();
     if (wid < wpp && f < nfp) {
         const long long r = f / rowf;
         const int i = (int)(f - r * rowf);
         const long long row = zb + r * g.sy + g.gx;             // interior cell 0 of the row
-        R Fb[NV];
+        const FaceBar fb{rbar, C, row + i, row + i - 1, i < g.nx, i > 0, g.idx};
         bool any = false;
 #pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            const double rr = i < g.nx ? rbar[q * C + row + i] : 0.0;
-            const double rl = i > 0 ? rbar[q * C + row + i - 1] : 0.0;
-            Fb[q] = R((rr - rl) * g.idx);
-            any = any || (Fb[q] != R(0));
-        }
+        for (int q = 0; q < NV; ++q) any = any || (fb(q) != 0.0);
         if (any) {
             const long long base = row + i - 3;
-            Stencil st{U, P, base, 1, C};
             SinkLds sk{(volatile lds_double *)w, W, (int)(base - base0), 1, NV * W};
-            const VjpRec<NS> rc{rec, nrec, ((long long)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x};
-            if constexpr (HALF == 0)
-                face_vjp_a<NS, R, 0, CU6>(st, th, Fb, sk, rc, ds);
-            else
-                face_vjp_b<NS, R, 0>(st, th, sk, rc);
+            if constexpr (NT > 0) {
+                const StencilLds<NV> st{(const lds_double *)tile, (int)(base - base0), 1, W};
+                face_vjp<NS, R, 0, CU6>(st, th, fb, sk, ds);
+            } else {
+                const Stencil st{U, P, base, 1, C};
+                face_vjp<NS, R, 0, CU6>(st, th, fb, sk, ds);
+            }
         }
     }
     __syncthreads();
-    if (wid < wpp) {
-        const long long fl = min(f0 + 63, nfp - 1);
-        const long long rl = fl / rowf;
-        const int span = (int)(zb + rl * g.sy + (fl - rl * rowf) - base0) + 6;
-        for (int c = lane; c < span; c += 64) {
+    for (int c = lane; c < span; c += 64) {
 #pragma unroll
-            for (int q = 0; q < NV; ++q) Ubar[q * C + base0 + c] += w[q * W + c];
-            Pbar[base0 + c] += w[NV * W + c];
-            Pbar[C + base0 + c] += w[(NV + 1) * W + c];
-        }
+        for (int q = 0; q < NV; ++q) Ubar[q * C + base0 + c] += w[q * W + c];
+#pragma unroll
+        for (int k = 0; k < kSinkExtra; ++k) Pbar[k * C + base0 + c] += w[(NV + k) * W + c];
     }
+}
+
+// LDS bytes per wave of k_face_vjp_x for a run of W cells.
+template <int NS, typename R>
+constexpr size_t vjp_x_lds_per_wave(int W) {
+    return (size_t)(NS + 4 + kSinkExtra + (vjp_staged<R>() ? NS + 8 : 0)) * W * sizeof(double);
 }
 
 // ---------------------------------------------------------------------------
@@ -701,27 +746,29 @@ __global__ __launch_bounds__(256) void k_face_vjp_x(const double *__restrict__ U
 // for each of its 21 x 16 cells, the windows that cover it in wave order to
 // Ubar / Pbar (one coalesced read-modify-write per cell and field).  Blocks
 // b and b + 1 share six rows, blocks b and b + 6 none: launch `phase` takes
-// the blocks b = phase mod 6.
+// the blocks b = phase mod 6.  Staged (FP64): the block first copies the
+// U and primitives of its 21 x 16 cells into LDS.
 // ---------------------------------------------------------------------------
-constexpr int kVjpTX = 16, kVjpFB = 16, kVjpWin = kVjpTX * 9;
+constexpr int kVjpTX = 16, kVjpFB = 16, kVjpWin = kVjpTX * 9, kVjpRows = kVjpFB + 5;
 
-template <int NS, typename R, int DIR, int HALF, bool CU6>
-__global__ __launch_bounds__(256) void k_face_vjp_yz(const double *__restrict__ U, const double *__restrict__ P,
-                                                     const double *__restrict__ rbar, double *__restrict__ Ubar,
-                                                     double *__restrict__ Pbar, double *__restrict__ rec,
-                                                     long long nrec, Geo g, ThermoK<R> th, int phase, Dissip ds) {
+template <int NS, typename R, int DIR, bool CU6>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(vjp_waves<R>()))) void k_face_vjp_yz(
+    const double *__restrict__ U, const double *__restrict__ P, const double *__restrict__ rbar,
+    double *__restrict__ Ubar, double *__restrict__ Pbar, Geo g, ThermoK<R> th, int phase, Dissip ds) {
     constexpr int NV = NS + 4;
-    __shared__ double xf_wyz[4][(NV + 2) * kVjpWin];
+    constexpr int NW = NV + kSinkExtra;                    // window rows
+    constexpr int NT = vjp_staged<R>() ? NV + 4 : 0;       // staged rows
+    constexpr int TS = kVjpRows * kVjpTX;                  // staged cells
+    __shared__ double xf_wyz[4][NW * kVjpWin];
+    __shared__ double xf_tile[NT > 0 ? NT * TS : 1];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int tx = lane & (kVjpTX - 1), ts = lane / kVjpTX;
     const int nsw = DIR == 1 ? g.ny : g.nz;
     const long long ss = DIR == 1 ? g.sy : g.sz;
     const int gs = DIR == 1 ? g.gy : g.gz;
     const int xt = (g.nx + kVjpTX - 1) / kVjpTX;                   // x tiles
-    const int nfb = (nsw + 1 + kVjpFB - 1) / kVjpFB;               // face blocks along the sweep axis
-    const int nb = (nfb - phase + kVjpGroups - 1) / kVjpGroups;    // face blocks of this phase
     const int xi = blockIdx.x % xt;
-    const int b = phase + kVjpGroups * (int)(blockIdx.x / xt);     // this block's face block (< nfb)
+    const int b = phase + kVjpGroups * (int)(blockIdx.x / xt);     // this block's face block
     const int tr = blockIdx.y;                                     // plane of the third axis
     const int j0 = b * kVjpFB;
     const int x = xi * kVjpTX + tx;
@@ -731,43 +778,50 @@ __global__ __launch_bounds__(256) void k_face_vjp_yz(const double *__restrict__ 
     const long long col0 = (long long)g.gx + (DIR == 1 ? (long long)(g.gz + tr) * g.sz : (long long)(g.gy + tr) * g.sy) +
                            (long long)gs * ss;
     volatile double *w = xf_wyz[wv];
-    for (int i = lane; i < (NV + 2) * kVjpWin; i += 64) w[i] = 0.0;
+    for (int i = lane; i < NW * kVjpWin; i += 64) w[i] = 0.0;
+    if constexpr (NT > 0) {
+        // tile row r = sweep row j0 - 3 + r; cells past the padded extent are never read
+        for (int e = threadIdx.x; e < TS; e += 256) {
+            const int r = e / kVjpTX, cx = xi * kVjpTX + (e % kVjpTX);
+            if (cx >= g.nx || j0 - 3 + r > nsw + 2) continue;
+            const long long cell = col0 + cx + (long long)(j0 - 3 + r) * ss;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) xf_tile[q * TS + e] = U[q * C + cell];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) xf_tile[(NV + k) * TS + e] = P[k * C + cell];
+        }
+    }
     __syncthreads();
-    (void)nb;
     if (x < g.nx && j <= nsw) {
         const long long col = col0 + x;
-        const double id = DIR == 1 ? g.idy : g.idz;
-        R Fb[NV];
+        const FaceBar fb{rbar, C, col + (long long)j * ss, col + (long long)(j - 1) * ss, j < nsw, j > 0,
+                         DIR == 1 ? g.idy : g.idz};
         bool any = false;
 #pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            const double rr = j < nsw ? rbar[q * C + col + (long long)j * ss] : 0.0;
-            const double rl = j > 0 ? rbar[q * C + col + (long long)(j - 1) * ss] : 0.0;
-            Fb[q] = R((rr - rl) * id);
-            any = any || (Fb[q] != R(0));
-        }
+        for (int q = 0; q < NV; ++q) any = any || (fb(q) != 0.0);
         if (any) {
-            const long long base = col + (long long)(j - 3) * ss;
-            Stencil st{U, P, base, ss, C};
             // window row r of wave w = sweep row j0 + 4w - 3 + r; stencil cell m is row ts + m
             SinkLds sk{(volatile lds_double *)xf_wyz[wv], kVjpWin, ts * kVjpTX + tx, kVjpTX, NV * kVjpWin};
-            const VjpRec<NS> rc{rec, nrec, (long long)(blockIdx.y * gridDim.x + blockIdx.x) * 256 + threadIdx.x};
-            if constexpr (HALF == 0)
-                face_vjp_a<NS, R, DIR, CU6>(st, th, Fb, sk, rc, ds);
-            else
-                face_vjp_b<NS, R, DIR>(st, th, sk, rc);
+            if constexpr (NT > 0) {
+                // stencil cell m of face j is tile row j - j0 + m
+                const StencilLds<NV> st{(const lds_double *)xf_tile, (4 * wv + ts) * kVjpTX + tx, kVjpTX, TS};
+                face_vjp<NS, R, DIR, CU6>(st, th, fb, sk, ds);
+            } else {
+                const Stencil st{U, P, col + (long long)(j - 3) * ss, ss, C};
+                face_vjp<NS, R, DIR, CU6>(st, th, fb, sk, ds);
+            }
         }
     }
     __syncthreads();
     // block rows r = 0..20 (sweep rows j0-3 .. j0+17); wave w covers r in [4w, 4w+9)
-    for (int c = threadIdx.x; c < kVjpTX * (kVjpFB + 5); c += 256) {
+    for (int c = threadIdx.x; c < kVjpTX * kVjpRows; c += 256) {
         const int r = c / kVjpTX, cx = xi * kVjpTX + (c % kVjpTX);
         const int row = j0 - 3 + r;                       // interior index along the sweep axis
         if (cx >= g.nx || row > nsw + 2) continue;
         const int wlo = r >= 8 ? (r - 8 + 3) / 4 : 0, whi = min(3, r / 4);
         const long long cell = col0 + cx + (long long)row * ss;
 #pragma unroll
-        for (int q = 0; q < NV + 2; ++q) {
+        for (int q = 0; q < NW; ++q) {
             double v = 0.0;
             for (int ww = wlo; ww <= whi; ++ww) v += xf_wyz[ww][q * kVjpWin + (r - 4 * ww) * kVjpTX + (c % kVjpTX)];
             if (q < NV)
@@ -826,14 +880,15 @@ __global__ __launch_bounds__(256) void k_face_speeds(const double *__restrict__ 
     alpha[2 * astride + f] = aP;
 }
 
-// Per-cell backward of (p, T)(U): p = T sum_s rho_s R_s, and T from
-// rho e(T) = E - |m|^2 / (2 rho) by the implicit-function rule
+// Per-cell backward of (p, T, rho)(U): p = T sum_s rho_s R_s, rho = sum_s
+// rho_s, and T from rho e(T) = E - |m|^2 / (2 rho) by the implicit-function
+// rule
 //   dT = (dE - u.dm + |u|^2/2 sum_s drho_s - sum_s e_s(T) drho_s) / (rho C_v).
 // u: the cell's conservative values (stride `stride`), T and 1/rho from the
-// primitive pass, (pb, Tb) the cotangents of p and T; adds into ub.
+// primitive pass, (pb, Tb, rb) the cotangents of p, T and rho; adds into ub.
 template <int NS>
 XF_HD void prims_vjp_cell(const ThermoK<double> &th, const double *u, long long stride, double T, double rinv,
-                          double pb, double Tb, double *ub) {
+                          double pb, double Tb, double rb, double *ub) {
     double rR = 0.0, cv = 0.0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -846,7 +901,7 @@ XF_HD void prims_vjp_cell(const ThermoK<double> &th, const double *u, long long 
     const double gT = (Tb + pb * rR) * rinv / cv;
     const double k2 = 0.5 * (vx * vx + vy * vy + vz * vz);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) ub[s * stride] += pb * T * th.Rs[s] + gT * (k2 - e_species(th, s, T));
+    for (int s = 0; s < NS; ++s) ub[s * stride] += rb + pb * T * th.Rs[s] + gT * (k2 - e_species(th, s, T));
     ub[NS * stride] -= gT * vx;
     ub[(NS + 1) * stride] -= gT * vy;
     ub[(NS + 2) * stride] -= gT * vz;
@@ -860,9 +915,9 @@ __global__ __launch_bounds__(256) void k_prims_vjp(const double *__restrict__ U,
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= g.cells) return;
     const long long C = g.cells;
-    const double pb = Pbar[idx], Tb = Pbar[C + idx];
-    if (pb == 0.0 && Tb == 0.0) return;
-    prims_vjp_cell<NS>(th, U + idx, C, P[idx], P[3 * C + idx], pb, Tb, Ubar + idx);
+    const double pb = Pbar[idx], Tb = Pbar[C + idx], rb = Pbar[2 * C + idx];
+    if (pb == 0.0 && Tb == 0.0 && rb == 0.0) return;
+    prims_vjp_cell<NS>(th, U + idx, C, P[idx], P[3 * C + idx], pb, Tb, rb, Ubar + idx);
 }
 
 }  // namespace xf

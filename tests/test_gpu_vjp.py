@@ -6,7 +6,11 @@ its central differences are taken with the speeds frozen at the base state.
 Checks are dot products <rbar, J w> = <J^T rbar, w> with random directions,
 plus the ghost-fill adjoint, the RK3-step adjoint and a checkpointed rollout
 gradient.  FP64 bar 1e-12 relative (complex step) / 1e-7 (central FD with
-h = 1e-6 relative); the mixed path is held to a declared 1e-4.
+h = 1e-6 relative); the mixed path is held to a declared 2e-4 (FP32
+projections, weights and their derivatives; on the 16^3 shock-bubble the
+relative error over seeds 3-6 spreads over 1.4e-5 .. 1.1e-4, for the
+two-kernel adjoint with its per-face record as for the fused one, so the
+first declared 1e-4 passed by the choice of seed).
 """
 import numpy as np
 import pytest
@@ -110,7 +114,7 @@ def test_rhs_vjp_mixed_dot_product(name):
     got, ref, mag = vjp_dot_check(case, "mixed", 3)
     rel = abs(got - ref) / mag
     print(f"[vjp] mixed {name}: rel {rel:.3e}", flush=True)
-    assert rel <= 1e-4, (got, ref, rel)
+    assert rel <= 2e-4, (got, ref, rel)
 
 
 def _c4_crop():
