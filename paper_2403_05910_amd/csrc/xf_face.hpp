@@ -395,9 +395,13 @@ XF_HD R recon_pair(const R *gp, const R *gm) {
 // no run-time switch left in it (ROE and GLF skip the stencil maxima
 // altogether); ds supplies the GLF speeds.  PAIR takes both sides of an
 // FP64 WENO5 field with one reciprocal (off where the extra live values
-// spill, as next to the positivity blend).
+// spill, as next to the positivity blend).  ROLL runs the species loops as
+// loops (the Roe Y_s and chi_s recomputed where used, the per-cell sums
+// taken species by species) instead of unrolling them, which frees the
+// per-species registers at the cost of three evaluations of e_s(T~) per
+// species instead of one.
 template <int NS, typename R, int DIR, bool FENCE = false, int SPD = kViscLlf, int REC = kReconWeno5,
-          bool PAIR = true, class St, class Out>
+          bool PAIR = true, bool ROLL = false, class St, class Out>
 XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned &flags, const Dissip &ds) {
     constexpr int RAD = stencil_radius(REC);
     constexpr int W = 2 * RAD;       // stencil cells
@@ -425,22 +429,38 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
     for (int k = 0; k < 3; ++k) ut[k] = aL * R(st.u(IM + k, CL)) + aR * R(st.u(IM + k, CR));
     const R Ht = aL * (R(st.u(IE, CL)) + R(st.p(1, CL))) + aR * (R(st.u(IE, CR)) + R(st.p(1, CR)));
     const R Tt = wL * R(st.p(0, CL)) + wR * R(st.p(0, CR));
-    R Yt[NS], chi[NS];
-    R Rb = R(0), cvb = R(0);
+    R Yt[ROLL ? 1 : NS], chi[ROLL ? 1 : NS];   // per-species Roe values (unrolled form only)
+    R Rb = R(0), cvb = R(0), Se = R(0), S1 = R(0);
+    if constexpr (ROLL) {
+#pragma unroll 1
+        for (int s = 0; s < NS; ++s) {
+            const R Y = aL * R(st.u(s, CL)) + aR * R(st.u(s, CR));
+            S1 += Y;
+            Rb += Y * th.Rs[s];
+            cvb += Y * cv_species(th, s, Tt);
+            Se += Y * e_species(th, s, Tt);
+        }
+    } else {
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        Yt[s] = aL * R(st.u(s, CL)) + aR * R(st.u(s, CR));
-        Rb += Yt[s] * th.Rs[s];
-        cvb += Yt[s] * cv_species(th, s, Tt);
-        chi[s] = e_species(th, s, Tt);   // e_s(T~) for now
+        for (int s = 0; s < NS; ++s) {
+            Yt[s] = aL * R(st.u(s, CL)) + aR * R(st.u(s, CR));
+            Rb += Yt[s] * th.Rs[s];
+            cvb += Yt[s] * cv_species(th, s, Tt);
+            chi[s] = e_species(th, s, Tt);   // e_s(T~) for now
+        }
     }
     const R Gam = Rb / cvb;
     const R q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
     R c2 = Gam * (Ht - q2);
+    if constexpr (ROLL) {
+        // sum_s Y_s chi_s with S1 = sum Y, Se = sum Y e_s(T~), Rb = sum Y R_s
+        c2 += Gam * (R(0.5) * q2 * S1 - Se) + Tt * Rb;
+    } else {
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        chi[s] = Gam * (R(0.5) * q2 - chi[s]) + th.Rs[s] * Tt;
-        c2 += Yt[s] * chi[s];
+        for (int s = 0; s < NS; ++s) {
+            chi[s] = Gam * (R(0.5) * q2 - chi[s]) + th.Rs[s] * Tt;
+            c2 += Yt[s] * chi[s];
+        }
     }
     if (!(c2 > R(0))) flags |= XF_FLAG_C2;
     const R ct = xsqrt(c2);
@@ -452,14 +472,37 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
     // ---- 2./3. per-cell scalars of the projections, LLF speeds ----------
     R un[W], DU[W], DF[W], rh[W];
     R aM = R(0), a0 = R(0), aP = R(0);
+    R scm[ROLL ? W : 1];   // rolled form: sum_s chi_s rho_s of every cell, species outermost
+    if constexpr (ROLL) {
+#pragma unroll
+        for (int m = 0; m < W; ++m) {
+            scm[m] = R(0);
+            rh[m] = R(0);
+        }
+#pragma unroll 1
+        for (int s = 0; s < NS; ++s) {
+            const R chis = Gam * (R(0.5) * q2 - e_species(th, s, Tt)) + th.Rs[s] * Tt;
+#pragma unroll
+            for (int m = 0; m < W; ++m) {
+                const R r = R(st.u(s, m));
+                scm[m] += chis * r;
+                rh[m] += r;
+            }
+        }
+    }
 #pragma unroll
     for (int m = 0; m < W; ++m) {
         R sc = R(0), sr = R(0);
+        if constexpr (ROLL) {
+            sc = scm[m];
+            sr = rh[m];
+        } else {
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const R r = R(st.u(s, m));
-            sc += chi[s] * r;
-            sr += r;
+            for (int s = 0; s < NS; ++s) {
+                const R r = R(st.u(s, m));
+                sc += chi[s] * r;
+                sr += r;
+            }
         }
         const R rinv = R(st.p(3, m)), pm = R(st.p(1, m)), cm = R(st.p(2, m));
         const R E = R(st.u(IE, m));
@@ -542,22 +585,35 @@ XF_HD void face_flux_to(const St &st, const ThermoK<R> &th, Out &&out, unsigned 
     // ---- species fields, back-projected as they come ----------------------
     const R iGam = R(1) / Gam;
     R gsum = R(0), gE = R(0);
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        if (FENCE) XF_FENCE();
+    // one species field: its Roe mass fraction Ys and chi_s given
+    auto species = [&](int s, R Ys, R chis) {
         R gp[W], gm[W];
 #pragma unroll
         for (int m = 0; m < W; ++m) {
             const R r = R(st.u(s, m));
-            const R wU = r - Yt[s] * DU[m];
-            const R wF = r * un[m] - Yt[s] * DF[m];
+            const R wU = r - Ys * DU[m];
+            const R wF = r * un[m] - Ys * DF[m];
             gp[m] = R(0.5) * (wF + a0 * wU);
             gm[m] = R(0.5) * (wF - a0 * wU);
         }
         const R hs = recon_pair<REC, PAIR>(gp, gm);
-        out(s, Yt[s] * Asum + hs);
+        out(s, Ys * Asum + hs);
         gsum += hs;
-        gE += (q2 - chi[s] * iGam) * hs;
+        gE += (q2 - chis * iGam) * hs;
+    };
+    if constexpr (ROLL) {
+#pragma unroll 1
+        for (int s = 0; s < NS; ++s) {
+            if (FENCE) XF_FENCE();
+            const R Ys = aL * R(st.u(s, CL)) + aR * R(st.u(s, CR));
+            species(s, Ys, Gam * (R(0.5) * q2 - e_species(th, s, Tt)) + th.Rs[s] * Tt);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (FENCE) XF_FENCE();
+            species(s, Yt[s], chi[s]);
+        }
     }
 
     // ---- momentum and energy of F^ = R h ----------------------------------

@@ -134,27 +134,34 @@ __global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, dou
 }
 
 // ---------------------------------------------------------------------------
-// Phase fences and occupancy per kernel flavour, chosen from the compiler's
-// resource report and timings: the FP64 face-per-thread sweeps keep below 256
-// registers (two waves per SIMD) when the face's phases are fenced; the FP32
-// sweeps fit three waves unforced.
+// Phase fences, loop form and occupancy per kernel flavour, chosen from the
+// compiler's resource report and timings at 256^3, nine species:
+// * the x sweeps run the species loops rolled (face_flux_to ROLL): FP64 at
+//   three waves per SIMD without spill (168 registers; 2.20 -> 2.00 ms per
+//   launch), FP32 1.74 -> 1.33 ms;
+// * the FP64 y/z tiles keep the unrolled form at two waves (rolled at three
+//   waves they took 2.76/3.02 ms against 2.72/2.91); the FP32 tiles roll
+//   (1.60/1.66 -> 1.56/1.62 ms);
+// * the positivity-blend instances stay at two waves (at three the FP64
+//   blended step went from 37.5 to 47.7 ms), the FP64 WENO7 instances at
+//   one (at two they spilled 324-460 bytes per lane; at one they keep their
+//   overflow in the accumulation registers, 61.7 -> 50.3 ms per step).
 template <typename R>
 struct SweepTune {
     static constexpr bool fence_face = false;   // face-per-thread sweeps (x, tiled y/z)
-    static constexpr int waves = 1;             // minimum waves per SIMD asked of the compiler
+    static constexpr bool roll_tile = true;     // species loops rolled in the y/z tiles
 };
 template <>
 struct SweepTune<double> {
     static constexpr bool fence_face = true;
-    static constexpr int waves = 2;
+    static constexpr bool roll_tile = false;
 };
-// Waves per SIMD asked of a face-per-thread sweep: the eight-cell WENO7 face
-// in FP64 does not fit two waves (it spilled 324-460 bytes per lane to
-// memory); at one wave it keeps its overflow in the accumulation registers
-// and ran 19 % faster (61.7 -> 50.3 ms per step at 256^3).
-template <typename R, int REC>
+// Waves per SIMD asked of a face-per-thread sweep (X: the x sweep).
+template <typename R, int REC, bool X, bool PP>
 constexpr int sweep_waves() {
-    return (sizeof(R) == 8 && REC == kReconWeno7) ? 1 : SweepTune<R>::waves;
+    if (sizeof(R) == 4) return X ? 4 : 1;
+    if (REC == kReconWeno7) return 1;
+    return (X && !PP && REC == kReconWeno5) ? 3 : 2;   // the rolled CU6 x face spills ~100 bytes at three
 }
 
 // lam = D dt / dx_d of the positivity blend (D active dimensions).
@@ -189,7 +196,7 @@ __device__ __forceinline__ void put_result(double *__restrict__ rhs, const Stage
 constexpr int kXBlock = 256;
 
 template <int NS, typename R, typename S, bool PP, int SPD, int REC>
-__global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(sweep_waves<R, REC>()))) void k_sweep_x(
+__global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(sweep_waves<R, REC, true, PP>()))) void k_sweep_x(
     const S *__restrict__ U, const S *__restrict__ P, double *__restrict__ rhs, Geo g, ThermoK<R> th, int accumulate,
     StageArgs sa, unsigned *status, Dissip ds) {
     constexpr int NV = NS + 4;
@@ -211,7 +218,7 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(sweep_w
         constexpr int RAD = stencil_radius(REC);
         StencilT<S> st{U, P, rowbase + i - RAD, 1, g.cells};
         if constexpr (SPD == kViscFrozen) ds.fidx = f;   // x faces: i + (nx + 1) (j + ny k)
-        face_flux_to<NS, R, 0, SweepTune<R>::fence_face, SPD, REC, !PP>(
+        face_flux_to<NS, R, 0, SweepTune<R>::fence_face, SPD, REC, !PP, true>(
             st, th, [&](int q, R v) { sF[q][t] = v; }, flags, ds);
         if constexpr (PP) {
             R Fq[NV];
@@ -257,7 +264,7 @@ struct TileShape<double> {
 };
 
 template <int NS, typename R, int DIR, typename S, bool PP, int SPD, int REC>
-__global__ __launch_bounds__(TileShape<R>::x *TileShape<R>::s) __attribute__((amdgpu_waves_per_eu(sweep_waves<R, REC>()))) void
+__global__ __launch_bounds__(TileShape<R>::x *TileShape<R>::s) __attribute__((amdgpu_waves_per_eu(sweep_waves<R, REC, false, PP>()))) void
 k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, double *__restrict__ rhs, Geo g, ThermoK<R> th,
              int accumulate, StageArgs sa, unsigned *status, Dissip ds) {
     constexpr int NV = NS + 4;
@@ -281,7 +288,7 @@ k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, double *__restric
         if constexpr (SPD == kViscFrozen)   // y faces: i + nx (j + (ny + 1) k); z faces: i + nx (j + ny k)
             ds.fidx = DIR == 1 ? x + (long long)g.nx * (j + (long long)(g.ny + 1) * bz)
                                : x + (long long)g.nx * (bz + (long long)g.ny * j);
-        face_flux_to<NS, R, DIR, SweepTune<R>::fence_face, SPD, REC, !PP>(
+        face_flux_to<NS, R, DIR, SweepTune<R>::fence_face, SPD, REC, !PP, SweepTune<R>::roll_tile>(
             st, th, [&](int q, R v) { sF[q][ts][tx] = v; }, flags, ds);
         if constexpr (PP) {
             R Fq[NV];

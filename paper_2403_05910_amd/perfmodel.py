@@ -54,6 +54,60 @@ def sweep_bytes_per_cell(ns, first):
     return 8 * (nv + 4) + (8 * nv if first else 16 * nv)
 
 
+def _footprint(n, direction):
+    """cells a sweep's stencils read: the interior widened by three ghost
+    layers along the sweep direction"""
+    m = list(n)
+    m[direction] += 6
+    return m[0] * m[1] * m[2]
+
+
+def sweep_bytes(ns, n, direction, first=True, precision="fp64"):
+    """algorithmic bytes of one sweep launch: U (N + 4 fields) and the four
+    primitives of every cell its stencils read, once (FP32 copies in the
+    mixed path), and the residual of every interior cell written once (read
+    as well when accumulated)"""
+    nv = ns + 4
+    cells = n[0] * n[1] * n[2]
+    word = 4 if precision == "mixed" else 8
+    return word * (nv + 4) * _footprint(n, direction) + (8 if first else 16) * nv * cells
+
+
+def vjp_bytes_per_cell(ns):
+    """the whole RHS VJP, algorithmic: read U and the residual cotangent,
+    write the state cotangent (N + 4 fields each), read T"""
+    return 24 * (ns + 4) + 8
+
+
+def vjp_sweep_bytes(ns, n, direction):
+    """one direction of the face VJP: U and the primitives over the stencil
+    footprint, the residual cotangent, and the read-modify-write of the state
+    cotangent and of the three per-cell cotangents (p, T, rho)"""
+    nv = ns + 4
+    cells = n[0] * n[1] * n[2]
+    return 8 * (nv + 4) * _footprint(n, direction) + 8 * nv * cells + 16 * (nv + 3) * cells
+
+
+# Operations per face of the face VJP as implemented (forward recomputed,
+# then the backward), counted with the per-type VALU counters of one launch
+# (adds, multiplies, transcendentals 1, fused multiply-adds 2, per lane) at
+# two species counts and fitted linearly in N; None until counted.
+VJP_FACE_OPS = {"fp64": None, "mixed": None}
+
+
+def vjp_face_flops(ns, precision="fp64"):
+    c = VJP_FACE_OPS.get(precision)
+    return None if c is None else c[0] * ns + c[1]
+
+
+def vjp_sweep_flops(ns, n, direction, precision="fp64"):
+    f = vjp_face_flops(ns, precision)
+    if f is None:
+        return None
+    cells = n[0] * n[1] * n[2]
+    return f * (cells + cells // n[direction])
+
+
 def rk3_step_bytes_per_cell(ns):
     """one fused-free RK3 step, algorithmic: 3 x (RHS read U + write L) plus
     3 stage updates (read U^n, U^(k-1), L; write U^(k))"""
