@@ -346,8 +346,8 @@ def adjoint_part(torch, xf, case, ctx, ctxm, U0, a, secs64):
         for _ in range(2):
             fwd()
             bwd()
-        tf = per_call_times(torch, fwd, 20)
-        tb = per_call_times(torch, bwd, 20)
+        tf = per_call_times(torch, fwd, a.reps)
+        tb = per_call_times(torch, bwd, a.reps)
         kv = kernel_pass(torch, c, bwd, 3)
         res[label] = {"value": cells / median(tb), "unit": "cell adjoint-evals/s", "ms_per_vjp": median(tb) * 1e3,
                       "ms_per_rhs": median(tf) * 1e3, "adjoint_over_forward": median(tb) / median(tf),
@@ -549,6 +549,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="FP64 headline only")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the 512 x 256 x 256 workload")
+    ap.add_argument("--no-options", action="store_true", help="skip the scheme options")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other workloads and the rollouts")
+    ap.add_argument("--reps", type=int, default=20, help="repetitions of the RHS and VJP timings")
     ap.add_argument("--quick", action="store_true", help="smaller CPU samples")
     ap.add_argument("--calib", action="store_true",
                     help="first run a plain device copy of 1 GiB (counter calibration for rocprofv3 --pmc)")
@@ -563,7 +566,7 @@ def main():
     log("[bench] building workloads")
     cases["nine_species_sbi_256"] = W.nine_species_sbi(n=256)
     case = cases["nine_species_sbi_256"]
-    if not a.no_extras:
+    if not a.no_extras and not (a.no_configs and a.no_cpu):
         cases["inert_sbi_128"] = W.inert_sbi(128)
         cases["periodic_mixture_64"] = W.periodic_mixture(64)
     cpu = None
@@ -619,16 +622,20 @@ def main():
         log(f"[bench] mixed: {out['mixed']['ms_per_step']:.2f} ms/step")
         out["adjoint"] = adjoint_part(torch, xf, case, ctx, ctxm, U0, a, secs)
         ctxm.close()
-        out["adjoint"]["rollout"] = rollout_part(torch, xf, cases["periodic_mixture_64"], 64, 8, ("fp64", "mixed"))
-        out["scheme_options"] = options_part(torch, xf, case, U0, a)
+        if not a.no_configs:
+            out["adjoint"]["rollout"] = rollout_part(torch, xf, cases["periodic_mixture_64"], 64, 8,
+                                                     ("fp64", "mixed"))
+        if not a.no_options:
+            out["scheme_options"] = options_part(torch, xf, case, U0, a)
         ctx.close()
         del U0
         torch.cuda.empty_cache()
-        out["configs"] = {"wave_1d_200": wave_part(torch, xf),
-                          "inert_sbi_128": inert_part(torch, xf, cases["inert_sbi_128"], a)}
-        log(f"[bench] wave L1(rho) {out['configs']['wave_1d_200']['L1_rho']:.3e}, "
-            f"inert {out['configs']['inert_sbi_128']['ms_per_step']:.2f} ms/step")
-        if not a.no_large:
+        if not a.no_configs:
+            out["configs"] = {"wave_1d_200": wave_part(torch, xf),
+                              "inert_sbi_128": inert_part(torch, xf, cases["inert_sbi_128"], a)}
+            log(f"[bench] wave L1(rho) {out['configs']['wave_1d_200']['L1_rho']:.3e}, "
+                f"inert {out['configs']['inert_sbi_128']['ms_per_step']:.2f} ms/step")
+        if not a.no_large and not a.no_configs:
             del cases
             log("[bench] building the 512 x 256 x 256 workload")
             large = W.two_bubble_sbi()

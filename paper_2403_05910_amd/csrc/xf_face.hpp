@@ -119,15 +119,19 @@ XF_HD double rcp_nr(double x) {
 }
 
 // Both sides of one characteristic field: weno5(a..e) + weno5(f..j) with one
-// reciprocal, N_p / D_p + N_m / D_m = (N_p D_m + N_m D_p) / (D_p D_m).  Each
-// D lies between 1e-19 ((12e-6)^4) and about 1e170 for any characteristic
-// flux below 1e20, so the product stays a normal double.
+// reciprocal, N_p / D_p + N_m / D_m = (N_p D_m + N_m D_p) / (D_p D_m).  With
+// |values| <= v each D lies between 1e-19 ((12e-6)^4) and about 1.5e12 v^8,
+// so D_p D_m and N_p D_m stay finite for v up to about 1e16; past a product
+// of 1e280 (never reached by fluxes at SI scales) the two sides are divided
+// separately.
 XF_HD double weno5_pair(double a, double b, double c, double d, double e, double f, double g, double h,
                         double i, double j) {
     double Np, Dp, Nm, Dm;
     weno5_nd(a, b, c, d, e, Np, Dp);
     weno5_nd(f, g, h, i, j, Nm, Dm);
-    return (Np * Dm + Nm * Dp) * rcp_nr(Dp * Dm);
+    const double P = Dp * Dm;
+    if (P < 1e280) return (Np * Dm + Nm * Dp) * rcp_nr(P);
+    return Np / Dp + Nm / Dm;
 }
 
 // FP32 form.  The (eps + beta)^2 products can overflow FP32, so the three

@@ -266,7 +266,7 @@ def _cp_R(tab, T):
 def _e_species(tab, T):
     """e_s(T) = R_s (int_0^T cp_s/R_s dT + a5 - T)"""
     a = tab.a
-    Tn = np.asarray(T, dtype=np.float64)[..., None]
+    Tn = np.asarray(T, dtype=np.result_type(T, np.float64))[..., None]   # complex T stays complex
     hR = ((((a[:, 4] / 5 * Tn + a[:, 3] / 4) * Tn + a[:, 2] / 3) * Tn + a[:, 1] / 2) * Tn + a[:, 0]) * Tn + a[:, 5]
     return R_UNIVERSAL / tab.W * (hR - Tn)
 
@@ -545,10 +545,9 @@ def _fourier_field(X, Y, Z, rng, kmax=4):
     return f / np.max(np.abs(f))
 
 
-def periodic_mixture(n=64, seed=2, thermo_seed=0, T_lo=20.0):
-    """3D periodic 5-species thermally perfect mixture on [0,1]^3: rho = 1.2,
-    p = 1e5, u = 0, Y = 0.2 each, plus seeded Fourier perturbations (|k| <= 4,
-    5 % amplitude) of rho, u, v, w and every Y_k (renormalised); p uniform."""
+def periodic_mixture_fields(n=64, seed=2, thermo_seed=0, T_lo=20.0):
+    """The primitive fields of periodic_mixture: (table, n, d, rho, vel, Y, p),
+    interior arrays (rho (Z, Y, X), vel (3, ...), Y (5, ...)), p = 1e5 uniform."""
     nn = (n, n, n) if np.isscalar(n) else tuple(n)
     tab = sampled_table(W5, thermo_seed, T_lo=T_lo)
     d = tuple(1.0 / k for k in nn)
@@ -565,8 +564,23 @@ def periodic_mixture(n=64, seed=2, thermo_seed=0, T_lo=20.0):
     vel = np.stack([0.05 * c0 * v for v in dv])
     Yf = np.stack([0.2 * (1.0 + 0.05 * v) for v in dY])
     Yf = Yf / np.sum(Yf, axis=0, keepdims=True)
-    T = 1e5 / (rho * mixture_R(tab, Yf))
-    interior = assemble(tab, rho, vel, T, Yf)
+    return tab, nn, d, rho, vel, Yf, 1e5, c0
+
+
+def state_at_fixed_rho_u_p(tab, rho, vel, p, Y):
+    """Conservative interior fields of mass fractions Y (any dtype, complex
+    included) at given density, velocity and pressure: T = p / (rho R(Y)),
+    partial densities rho Y_k (Y is not renormalised)."""
+    T = p / (rho * mixture_R(tab, Y))
+    return assemble(tab, rho, vel, T, Y)
+
+
+def periodic_mixture(n=64, seed=2, thermo_seed=0, T_lo=20.0):
+    """3D periodic 5-species thermally perfect mixture on [0,1]^3: rho = 1.2,
+    p = 1e5, u = 0, Y = 0.2 each, plus seeded Fourier perturbations (|k| <= 4,
+    5 % amplitude) of rho, u, v, w and every Y_k (renormalised); p uniform."""
+    tab, nn, d, rho, vel, Yf, p, c0 = periodic_mixture_fields(n, seed, thermo_seed, T_lo)
+    interior = state_at_fixed_rho_u_p(tab, rho, vel, p, Yf)
     U, g = _padded(nn, 9)
     _place(U, g, interior)
     return Case("periodic_mixture", nn, d, (0,) * 6, tab, U, meta=dict(c0=c0))

@@ -13,7 +13,7 @@ import pytest
 import oracle as O
 from conftest import oracle_objects
 from paper_2403_05910_amd import workloads as W
-from test_gpu_parity import CASES, MIXED_RHS_TOL, TOL, _sample_cells, field_err, gpu_rhs, oracle_rhs
+from test_gpu_parity import CASES, MIXED_RHS_TOL, TOL, _sample_cells, field_err, gpu_rhs, oracle_rhs, r12_err
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -36,8 +36,7 @@ def test_rhs_weno7_matches_oracle(name):
     r_ora, aux, U_ora = oracle_rhs(case, recon="WENO7")
     assert np.array_equal(U_gpu, U_ora), "four-layer ghost fill must be an exact copy"
     assert flags == aux["flags"] == 0
-    err = field_err(r_gpu, r_ora, aux["scale_llf"])
-    print(f"[weno7] {name} max err / S_f = {err.max():.3e}", flush=True)
+    err = r12_err(r_gpu, r_ora, aux, f"WENO7 {name}")
     assert err.max() <= TOL, err
     _, g = oracle_objects(case)
     mask = np.ones(r_gpu.shape[1:], dtype=bool)

@@ -742,3 +742,25 @@ def test_rankine_hugoniot_residuals():
     assert abs(1.2 * v0 - rho1 * v1) <= 1e-12 * 1.2 * v0
     assert abs(101325.0 + 1.2 * v0 ** 2 - p1 - rho1 * v1 ** 2) <= 1e-12 * (101325.0 + 1.2 * v0 ** 2)
     assert abs(hh(101325.0, 1.2) + v0 ** 2 / 2 - hh(p1, rho1) - v1 ** 2 / 2) <= 1e-12 * hh(101325.0, 1.2)
+
+
+def test_c4_rollout_golden_matches_current_generators():
+    """the stored rollout reference (tests/golden/c4_rollout_16.json, written
+    by make_c4_rollout.py from the oracle) belongs to the current seeded
+    state: its fixed time step is the oracle's CFL-0.5 step of that state"""
+    import json
+    import os
+    from paper_2403_05910_amd import workloads as W
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c4_rollout_16.json")
+    with open(path) as f:
+        gold = json.load(f)
+    tab, nn, d, rho, vel, Y, p, _ = W.periodic_mixture_fields(gold["n"])
+    th = O.Thermo(tab.W, tab.a, tab.T_lo, tab.T_hi)
+    g = O.Grid(nn[0], nn[1], nn[2], d[0], d[1], d[2], (0,) * 6)
+    iz, iy, ix = g.interior()
+    U = np.zeros((9,) + tuple(k + 6 for k in nn[::-1]))
+    U[:, iz, iy, ix] = W.state_at_fixed_rho_u_p(tab, rho, vel, p, Y)
+    U = O.fill_ghosts(g, U)
+    assert abs(O.cfl_dt(th, g, U, 0.5) - gold["dt"]) <= 1e-15 * gold["dt"]
+    Y1 = Y[0]
+    assert 0.1 < gold["J"] < 0.25 and abs(gold["J"] - np.sum(Y1 * (1 - Y1)) * d[0] * d[1] * d[2]) < 1e-3
