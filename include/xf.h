@@ -155,7 +155,7 @@ int xf_rhs(xf_ctx *ctx, const double *U, double *rhs, void *ws, void *stream);
  * overlap on one device (different streams or host threads) race, and must
  * be serialised by the caller.  Returns XF_ETOOLARGE when
  * xf_workspace_bytes(ctx, XF_OP_RHS) exceeds XF_NOALLOC_BYTES (about
- * 2 million padded cells in FP64, 700 thousand in a mixed nine-species
+ * 2 million padded cells in FP64, 260 thousand in a mixed nine-species
  * context), XF_EINVAL for null, overlapping or misaligned buffers or another
  * current device. */
 #define XF_NOALLOC_BYTES ((size_t)64 << 20)

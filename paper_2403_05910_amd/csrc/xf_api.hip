@@ -92,7 +92,7 @@ size_t align_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace carve-up (byte offsets); every piece 256-byte aligned.
 struct Layout {
-    size_t P, Pbar, mx, L, U0, S2, Ly, Lz, V0, V1, V2, lam0, mu, Uf, Pf, Q, G, total;
+    size_t P, Pbar, mx, L, U0, S2, Ly, Lz, V0, V1, V2, lam0, mu, Uf, Pf, Q, G, Lf, Lv, total;
 };
 
 Layout layout(const xf_ctx *c, int op) {
@@ -120,19 +120,32 @@ Layout layout(const xf_ctx *c, int op) {
         l.Pbar = o;   // cotangents of each cell's p, T and rho
         o += align_up(3 * cell);
     }
-    if (op == XF_OP_RK3 || op == XF_OP_RK3_VJP) {
+    const bool mixed = c->lc.precision == XF_PREC_MIXED;
+    if (mixed) {   // FP32 per-direction differences of the mixed sweeps, [3][Nv][cells]
+        l.Lf = o;
+        o += align_up((size_t)c->lc.g.cells * sizeof(float) * c->nv * 3);
+    }
+    if (op == XF_OP_RK3 && mixed && c->viscous) {   // FP64 viscous residual of a mixed step
+        l.Lv = o;
+        o += align_up(state);
+    }
+    if (op == XF_OP_RK3_VJP || (op == XF_OP_RK3 && !mixed)) {
         l.L = o;
         o += align_up(state);
+    }
+    if (op == XF_OP_RK3 || op == XF_OP_RK3_VJP) {
         l.U0 = o;
         o += align_up(state);
     }
     if (op == XF_OP_RK3) {
         l.S2 = o;
         o += align_up(state);
-        l.Ly = o;
-        o += align_up(state);
-        l.Lz = o;
-        o += align_up(state);
+        if (!mixed) {
+            l.Ly = o;
+            o += align_up(state);
+            l.Lz = o;
+            o += align_up(state);
+        }
     }
     if (op == XF_OP_RK3_VJP) {
         l.V0 = o;
@@ -189,24 +202,30 @@ hipError_t timed(xf_ctx *c, int cls, hipStream_t s, F &&launch) {
     return hipSuccess;
 }
 
-// Primitives, then the active sweeps.  Without a fused stage the residual
-// goes to rhs (ghosts zeroed); with one, the last sweep writes the stage
-// combination and rhs only holds the partial sums of the earlier sweeps.
 // Primitive-variable buffers of one call: P (FP64), and for mixed-precision
-// contexts the FP32 copies Uf, Pf that the sweeps read.
+// contexts the FP32 copies Uf, Pf that the sweeps read and the FP32
+// per-direction differences they write.
 struct Prim {
     double *P;
     float *Uf, *Pf;
     unsigned long long *mx;   // [0]: CFL maximum; [1 + 3 d .. 3 + 3 d]: GLF speeds of direction d
     double *Q, *G;            // transport pass and velocity gradient (viscous contexts)
+    float *Lf;                // mixed: FP32 differences of direction d at Lf + d Nv cells
+    long long lstride;        // Nv cells
+    float *lf(int d) const { return Lf + d * lstride; }
 };
 
 Prim prim_bufs(const xf_ctx *c, const Layout &l, void *ws) {
     const bool mixed = c->lc.precision == XF_PREC_MIXED;
     const bool visc = c->viscous && l.G != 0;
-    return {at<double>(ws, l.P), mixed ? at<float>(ws, l.Uf) : nullptr, mixed ? at<float>(ws, l.Pf) : nullptr,
-            at<unsigned long long>(ws, l.mx), visc ? at<double>(ws, l.Q) : nullptr,
-            visc ? at<double>(ws, l.G) : nullptr};
+    return {at<double>(ws, l.P),
+            mixed ? at<float>(ws, l.Uf) : nullptr,
+            mixed ? at<float>(ws, l.Pf) : nullptr,
+            at<unsigned long long>(ws, l.mx),
+            visc ? at<double>(ws, l.Q) : nullptr,
+            visc ? at<double>(ws, l.G) : nullptr,
+            mixed ? at<float>(ws, l.Lf) : nullptr,
+            (long long)c->lc.g.cells * c->nv};
 }
 
 // Viscous fluxes of every active direction added to out[d] (the three may
@@ -255,32 +274,36 @@ hipError_t prims(xf_ctx *c, const double *U, const Prim &pb, hipStream_t s) {
     return e;
 }
 
-int sweeps_into(xf_ctx *c, const double *U, double *rhs, const Prim &pb, const xf::StageArgs &stage,
-                hipStream_t s) {
+// The active sweeps into rhs, z, then y, then x.  FP64 contexts accumulate
+// in rhs; mixed ones write one FP32 buffer per direction and sum them into
+// rhs in FP64, in the same order.
+int sweeps_into(xf_ctx *c, const double *U, double *rhs, const Prim &pb, hipStream_t s) {
     const LaunchCtx &lc = c->lc;
     const int n[3] = {lc.g.nx, lc.g.ny, lc.g.nz};
-    // z, then y, then x: the x sweep (one face per thread, fully coalesced)
-    // is the last one and carries the fused stage
-    int last = -1;
-    for (int d = 2; d >= 0; --d)
-        if (n[d] > 1) last = d;
-    xf::StageArgs off{};
+    const bool mixed = lc.precision == XF_PREC_MIXED;
+    const xf::StageArgs off{};
     bool first = true;
     for (int d = 2; d >= 0; --d) {
         if (n[d] <= 1) continue;
         const int acc = first ? 0 : 1;
-        const xf::StageArgs &sa = d == last ? stage : off;
-        XF_TRY(timed(c, XF_K_SWEEP_X + d, s, [&] { return c->ops->sweep(lc, d, acc, U, pb.P, pb.Uf, pb.Pf, rhs, sa, glf_of(c, pb.mx, d), s); }));
+        XF_TRY(timed(c, XF_K_SWEEP_X + d, s, [&] {
+            return c->ops->sweep(lc, d, mixed ? 0 : acc, U, pb.P, pb.Uf, pb.Pf, rhs, mixed ? pb.lf(d) : nullptr, off,
+                                 glf_of(c, pb.mx, d), s);
+        }));
         first = false;
     }
-    if (last < 0) return XF_EUNSUPPORTED;   // no active dimension (rejected by xf_create)
+    if (first) return XF_EUNSUPPORTED;   // no active dimension (rejected by xf_create)
+    if (mixed) {
+        const float *const L[3] = {n[0] > 1 ? pb.lf(0) : nullptr, n[1] > 1 ? pb.lf(1) : nullptr,
+                                   n[2] > 1 ? pb.lf(2) : nullptr};
+        XF_TRY(timed(c, XF_K_STAGE, s, [&] { return xf::launch_sum_dirs(lc, c->nv, rhs, L, s); }));
+    }
     return XF_OK;
 }
 
 int rhs_into(xf_ctx *c, const double *U, double *rhs, const Prim &pb, hipStream_t s) {
     XF_TRY(prims(c, U, pb, s));
-    const xf::StageArgs off{};
-    int r = sweeps_into(c, U, rhs, pb, off, s);
+    int r = sweeps_into(c, U, rhs, pb, s);
     if (r != XF_OK) return r;
     double *const all[3] = {rhs, rhs, rhs};
     if ((r = viscous_into(c, U, pb, all, s)) != XF_OK) return r;
@@ -545,8 +568,7 @@ int xf_rhs_alpha(xf_ctx *c, const double *U, const double *alpha_in, double *alp
         off += 3 * nf;
     }
     if (!alpha_in) {
-        const xf::StageArgs none{};
-        const int r = sweeps_into(c, U, rhs, pb, none, s);
+        const int r = sweeps_into(c, U, rhs, pb, s);
         if (r != XF_OK) return r;
     } else {
         // every direction writes its own difference, then the sum goes to rhs
@@ -557,15 +579,22 @@ int xf_rhs_alpha(xf_ctx *c, const double *U, const double *alpha_in, double *alp
             offs[d] = off;
             off += 3 * xf::face_count(lc.g, d);
         }
+        const bool mixed = lc.precision == XF_PREC_MIXED;
         bool first = true;
         for (int d = 2; d >= 0; --d) {
             const long long nf = xf::face_count(lc.g, d);
             if (!nf) continue;
             XF_TRY(timed(c, XF_K_SWEEP_X + d, s, [&] {
-                return c->ops->sweep_frozen(lc, d, first ? 0 : 1, U, pb.P, pb.Uf, pb.Pf, rhs, alpha_in + offs[d], nf,
-                                            s);
+                return c->ops->sweep_frozen(lc, d, (first || mixed) ? 0 : 1, U, pb.P, pb.Uf, pb.Pf, rhs,
+                                            mixed ? pb.lf(d) : nullptr, alpha_in + offs[d], nf, s);
             }));
             first = false;
+        }
+        if (mixed) {
+            const float *const L[3] = {xf::face_count(lc.g, 0) ? pb.lf(0) : nullptr,
+                                       xf::face_count(lc.g, 1) ? pb.lf(1) : nullptr,
+                                       xf::face_count(lc.g, 2) ? pb.lf(2) : nullptr};
+            XF_TRY(timed(c, XF_K_STAGE, s, [&] { return xf::launch_sum_dirs(lc, c->nv, rhs, L, s); }));
         }
     }
     double *const all[3] = {rhs, rhs, rhs};
@@ -599,9 +628,10 @@ int xf_cfl_dt(xf_ctx *c, const double *U, double cfl, double *dt_dev, void *ws, 
 }
 
 // One SSP-RK3 step.  Every sweep writes its own residual buffer (stores
-// only: no read-modify-write inside the register-heavy sweep kernels), and a
-// light stage kernel sums them and applies the stage combination (ping-pong
-// stage buffers S1, S2; stage 3 writes U in place).  With cfl > 0 the time
+// only: no read-modify-write inside the register-heavy sweep kernels; FP32
+// buffers in mixed contexts, whose sweeps compute the differences in FP32),
+// and a light stage kernel sums them in FP64 and applies the stage
+// combination (ping-pong stage buffers S1, S2; stage 3 writes U in place).  With cfl > 0 the time
 // step is reduced on the device from the stage-1 primitives of U^n and
 // written to *dt_out before it is used.
 int flow_rk3_step(xf_ctx *c, double *U, double dt, const double *dt_in, double cfl, double *dt_out, void *ws,
@@ -648,11 +678,31 @@ int flow_rk3_step(xf_ctx *c, double *U, double dt, const double *dt_in, double c
     const Layout l = layout(c, XF_OP_RK3);
     const LaunchCtx &lc = c->lc;
     const int n[3] = {lc.g.nx, lc.g.ny, lc.g.nz};
+    const bool mixed = lc.precision == XF_PREC_MIXED;
     const Prim pb = prim_bufs(c, l, ws);
     double *P = pb.P;
     double *S1 = at<double>(ws, l.U0), *S2 = at<double>(ws, l.S2);
-    double *Ld[3] = {at<double>(ws, l.L), at<double>(ws, l.Ly), at<double>(ws, l.Lz)};
-    const double *Lsum[3] = {n[0] > 1 ? Ld[0] : nullptr, n[1] > 1 ? Ld[1] : nullptr, n[2] > 1 ? Ld[2] : nullptr};
+    // per-direction residuals: FP64 buffers, or the FP32 ones of a mixed context
+    double *Ld[3] = {nullptr, nullptr, nullptr};
+    if (!mixed) {
+        Ld[0] = at<double>(ws, l.L);
+        Ld[1] = at<double>(ws, l.Ly);
+        Ld[2] = at<double>(ws, l.Lz);
+    }
+    const double *L64[3] = {nullptr, nullptr, nullptr};
+    const float *L32[3] = {nullptr, nullptr, nullptr};
+    for (int d = 0; d < 3; ++d) {
+        if (n[d] <= 1) continue;
+        if (mixed)
+            L32[d] = pb.lf(d);
+        else
+            L64[d] = Ld[d];
+    }
+    // the viscous residual: into each direction's FP64 buffer, or into one
+    // FP64 buffer of its own in a mixed context
+    double *Lv = mixed && c->viscous ? at<double>(ws, l.Lv) : nullptr;
+    double *const vout[3] = {Lv ? Lv : Ld[0], Lv ? Lv : Ld[1], Lv ? Lv : Ld[2]};
+    const long long nstate = lc.g.cells * c->nv;
     unsigned long long *mx = at<unsigned long long>(ws, l.mx);
     const double *h = dt_in;
     double *in[3] = {U, S1, S2};
@@ -671,17 +721,20 @@ int flow_rk3_step(xf_ctx *c, double *U, double dt, const double *dt_in, double c
             }));
             h = dt_out;
         }
-        // no fused stage; the step size only for the positivity blend
-        const xf::StageArgs sw{nullptr, nullptr, nullptr, 0.0, 0.0, dt, h, 0, c->pp};
+        // the step size only for the positivity blend
+        const xf::StageArgs sw{dt, h, c->pp};
         for (int d = 2; d >= 0; --d) {
             if (n[d] <= 1) continue;
-            XF_TRY(timed(c, XF_K_SWEEP_X + d, s,
-                         [&] { return c->ops->sweep(lc, d, 0, in[k], P, pb.Uf, pb.Pf, Ld[d], sw, glf_of(c, pb.mx, d), s); }));
+            XF_TRY(timed(c, XF_K_SWEEP_X + d, s, [&] {
+                return c->ops->sweep(lc, d, 0, in[k], P, pb.Uf, pb.Pf, Ld[d], mixed ? pb.lf(d) : nullptr, sw,
+                                     glf_of(c, pb.mx, d), s);
+            }));
         }
-        const int r = viscous_into(c, in[k], pb, Ld, s);
+        if (Lv) XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero(nstate, Lv, s); }));
+        const int r = viscous_into(c, in[k], pb, vout, s);
         if (r != XF_OK) return r;
         XF_TRY(timed(c, XF_K_STAGE, s, [&] {
-            return xf::launch_rk3_stage_sum(lc, c->nv, out[k], U, in[k], Lsum, a[k], b[k], dt, h, s);
+            return c->ops->stage(lc, out[k], U, in[k], L64, L32, Lv, a[k], b[k], dt, h, s);
         }));
     }
     XF_TRY(fill(c, U, s));

@@ -82,16 +82,11 @@ struct ReactK {
     double W[kMaxNs], iW[kMaxNs];
 };
 
-// Optional fused SSP-RK3 stage on the last sweep of a right-hand side:
-// instead of rhs, write Uout = a U0 + b (Uin + dt L) with L the finished
-// residual (a == 0 skips U0).  dt is *dt_dev when dt_dev is set.
+// Step size seen by the sweeps, for the positivity blend: dt, or *dt_dev
+// when dt_dev is set; pp switches the blend on.
 struct StageArgs {
-    const double *U0;
-    const double *Uin;
-    double *Uout;
-    double a, b, dt;
+    double dt;
     const double *dt_dev;
-    int on;   // write the stage combination instead of the residual
     int pp;   // blend the face fluxes for positivity with the step dt (or *dt_dev)
 };
 
@@ -113,12 +108,14 @@ struct NsOps {
     // and P for the mixed-precision sweeps
     hipError_t (*prims)(const LaunchCtx &, const double *U, double *P, float *Uf, float *Pf, int all_cells,
                         hipStream_t);
-    // one direction of the convective flux difference; accumulate: rhs += or
-    // rhs =.  FP64 sweeps read U, P; mixed-precision sweeps read Uf, Pf.
+    // one direction of the convective flux difference.  FP64 sweeps read U,
+    // P and write rhs (accumulate: rhs +=, else rhs =); mixed-precision
+    // sweeps read Uf, Pf and write the FP32 differences to rhs32 (no
+    // accumulation: every direction has its own buffer).
     // glf: the direction's three GLF speeds (device) when lc.visc is GLF
     hipError_t (*sweep)(const LaunchCtx &, int dir, int accumulate, const double *U, const double *P,
-                        const float *Uf, const float *Pf, double *rhs, const StageArgs &stage, const double *glf,
-                        hipStream_t);
+                        const float *Uf, const float *Pf, double *rhs, float *rhs32, const StageArgs &stage,
+                        const double *glf, hipStream_t);
     // VJP of one direction: Ubar += (dF/dU)^T ..., Pbar += (dF/d(p, T, rho))^T ...
     // (Pbar: [3][cells], the cotangents of each cell's p, T and rho)
     hipError_t (*sweep_vjp)(const LaunchCtx &, int dir, const double *U, const double *P,
@@ -127,8 +124,8 @@ struct NsOps {
     // every face given (alpha [3][astride], astride the direction's face
     // count); otherwise as sweep with no stage
     hipError_t (*sweep_frozen)(const LaunchCtx &, int dir, int accumulate, const double *U, const double *P,
-                               const float *Uf, const float *Pf, double *rhs, const double *alpha, long long astride,
-                               hipStream_t);
+                               const float *Uf, const float *Pf, double *rhs, float *rhs32, const double *alpha,
+                               long long astride, hipStream_t);
     // the dissipation speeds the context's scheme takes at every face of one
     // direction, FP64, into alpha [3][astride] (glf: the direction's GLF speeds)
     hipError_t (*face_speeds)(const LaunchCtx &, int dir, const double *U, const double *P, const double *glf,
@@ -154,6 +151,14 @@ struct NsOps {
     // sub-steps over scale * (dt_dev ? *dt_dev : dt)
     hipError_t (*react)(const LaunchCtx &, double *U, const ReactK *rk, double dt, const double *dt_dev,
                         double scale, int n_sub, hipStream_t);
+    // SSP-RK3 stage on the interior: Uout = a U0 + b (Uin + h (((Lx + Ly) + Lz) + Lv)),
+    // h = dt_dev ? *dt_dev : dt, a == 0 skipping U0; L[d] null for an
+    // inactive direction, FP64 (L64) in FP64 contexts and FP32 (L32) in mixed
+    // ones, Lv (FP64, may be null) the viscous residual of a mixed context.
+    // Uout may alias U0.
+    hipError_t (*stage)(const LaunchCtx &, double *Uout, const double *U0, const double *Uin,
+                        const double *const L64[3], const float *const L32[3], const double *Lv, double a, double b,
+                        double dt, const double *dt_dev, hipStream_t);
 };
 
 const NsOps *ops_for_ns(int ns);
@@ -175,13 +180,12 @@ inline long long vjp_x_waves_per_plane(const Geo &g) { return ((long long)(g.nx 
 hipError_t launch_fill_ghosts(const LaunchCtx &, int nv, double *U, hipStream_t);
 hipError_t launch_fill_ghosts_vjp(const LaunchCtx &, int nv, double *Ubar, hipStream_t);
 hipError_t launch_zero_ghosts(const LaunchCtx &, int nv, double *A, hipStream_t);
-hipError_t launch_rk3_stage(const LaunchCtx &, int nv, int stage, double *U, double *U0,
-                            const double *L, double dt, const double *dt_dev, hipStream_t);
 hipError_t launch_rk3_stage_vjp(const LaunchCtx &, int nv, int stage, double *lam, double *lam0,
                                 double *mu, const double *dt_dev, double dt, hipStream_t);
-hipError_t launch_rk3_stage_sum(const LaunchCtx &, int nv, double *Uout, const double *U0, const double *Uin,
-                                const double *const L[3], double a, double b, double dt, const double *dt_dev,
-                                hipStream_t);
+// rhs = ((Lz + Ly) + Lx) on the interior (FP32 per-direction differences of
+// a mixed context, summed in FP64 in the order of the FP64 sweeps; null for
+// an inactive direction)
+hipError_t launch_sum_dirs(const LaunchCtx &, int nv, double *rhs, const float *const L[3], hipStream_t);
 hipError_t launch_axpy_state(long long n, double a, const double *x, double b, double *y,
                              hipStream_t);
 hipError_t launch_cfl_reset(unsigned long long *mx, hipStream_t);

@@ -4,6 +4,7 @@
 //   k_sweep_x     x-direction flux difference, one face per thread
 //   k_sweep_tile  y/z-direction flux difference, tiles of one face per thread
 //   k_cfl         CFL reduction (Eq. 17), wavefront max + one 64-bit atomic
+//   k_stage_sum   SSP-RK3 stage (Eq. 16) from the per-direction residuals
 #pragma once
 
 #include "xf_face.hpp"
@@ -133,6 +134,30 @@ __global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, dou
     if (flags) atomicOr(status, flags);
 }
 
+// SSP-RK3 stage of Eq. 16 on the interior cells, one thread per value
+// (field, cell): Uout = a U0 + b (Uin + h L), L = ((Lx + Ly) + Lz) + Lv.
+template <typename LT>
+__global__ __launch_bounds__(256) void k_stage_sum(double *Uout, const double *U0, const double *Uin, const LT *Lx,
+                                                   const LT *Ly, const LT *Lz, const double *Lv, Geo g, int nv,
+                                                   double a, double b, double dt, const double *dt_dev) {
+    const long long nint = (long long)g.nx * g.ny * g.nz;
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nint * nv) return;
+    const long long f = q / nint, r = q - f * nint;
+    const int i = (int)(r % g.nx);
+    const long long r2 = r / g.nx;
+    const int j = (int)(r2 % g.ny), k = (int)(r2 / g.ny);
+    const long long o = f * g.cells + (long long)(g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + (g.gx + i);
+    const double h = dt_dev ? *dt_dev : dt;
+    double L = 0.0;
+    if (Lx) L = (double)Lx[o];
+    if (Ly) L = L + (double)Ly[o];
+    if (Lz) L = L + (double)Lz[o];
+    if (Lv) L = L + Lv[o];
+    const double v = Uin[o] + h * L;
+    Uout[o] = a == 0.0 ? b * v : a * U0[o] + b * v;
+}
+
 // ---------------------------------------------------------------------------
 // Phase fences, loop form and occupancy per kernel flavour, chosen from the
 // compiler's resource report and timings at 256^3, nine species:
@@ -154,7 +179,7 @@ struct SweepTune {
 template <>
 struct SweepTune<double> {
     static constexpr bool fence_face = true;
-    static constexpr bool roll_tile = false;
+    static constexpr bool roll_tile = true;
 };
 // Waves per SIMD asked of a face-per-thread sweep (X: the x sweep).
 template <typename R, int REC, bool X, bool PP>
@@ -172,18 +197,12 @@ __device__ __forceinline__ R pp_lambda(const Geo &g, const StageArgs &sa, double
     return R(D * h * idx);
 }
 
-// Write the finished residual d of one field at one cell: to rhs (=, or +=
-// when accumulating), or, when the stage is fused, the stage combination
-// Uout = a U0 + b (Uin + h L) with L the complete residual.
-__device__ __forceinline__ void put_result(double *__restrict__ rhs, const StageArgs &sa, long long o, double d,
-                                           double h, int accumulate) {
-    const double L = accumulate ? rhs[o] + d : d;
-    if (!sa.on) {
-        rhs[o] = L;
-        return;
-    }
-    const double v = sa.Uin[o] + h * L;
-    sa.Uout[o] = sa.a == 0.0 ? sa.b * v : sa.a * sa.U0[o] + sa.b * v;
+// Write the finished residual d of one field at one cell: rhs = d, or
+// rhs += d when accumulating (FP64 output only; an FP32 difference is stored
+// as computed, exactly).
+template <typename OT>
+__device__ __forceinline__ void put_result(OT *__restrict__ rhs, long long o, double d, int accumulate) {
+    rhs[o] = accumulate ? OT(rhs[o] + d) : OT(d);
 }
 
 // ---------------------------------------------------------------------------
@@ -197,7 +216,7 @@ constexpr int kXBlock = 256;
 
 template <int NS, typename R, typename S, bool PP, int SPD, int REC>
 __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(sweep_waves<R, REC, true, PP>()))) void k_sweep_x(
-    const S *__restrict__ U, const S *__restrict__ P, double *__restrict__ rhs, Geo g, ThermoK<R> th, int accumulate,
+    const S *__restrict__ U, const S *__restrict__ P, R *__restrict__ rhs, Geo g, ThermoK<R> th, int accumulate,
     StageArgs sa, unsigned *status, Dissip ds) {
     constexpr int NV = NS + 4;
     __shared__ R sF[NV][kXBlock];
@@ -233,10 +252,9 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(sweep_w
     if (valid && t > 0 && i > 0) {
         const R id = R(g.idx);
         const long long cell = rowbase + i - 1;
-        const double h = sa.on ? (sa.dt_dev ? *sa.dt_dev : sa.dt) : 0.0;
 #pragma unroll
         for (int q = 0; q < NV; ++q)
-            put_result(rhs, sa, q * g.cells + cell, double((sF[q][t - 1] - sF[q][t]) * id), h, accumulate);
+            put_result(rhs, q * g.cells + cell, double((sF[q][t - 1] - sF[q][t]) * id), accumulate);
     }
     if (flags) atomicOr(status, flags);
 }
@@ -265,7 +283,7 @@ struct TileShape<double> {
 
 template <int NS, typename R, int DIR, typename S, bool PP, int SPD, int REC>
 __global__ __launch_bounds__(TileShape<R>::x *TileShape<R>::s) __attribute__((amdgpu_waves_per_eu(sweep_waves<R, REC, false, PP>()))) void
-k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, double *__restrict__ rhs, Geo g, ThermoK<R> th,
+k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, R *__restrict__ rhs, Geo g, ThermoK<R> th,
              int accumulate, StageArgs sa, unsigned *status, Dissip ds) {
     constexpr int NV = NS + 4;
     constexpr int kTileX = TileShape<R>::x, kTileS = TileShape<R>::s;
@@ -303,11 +321,9 @@ k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, double *__restric
     if (valid && ts > 0) {
         const R id = R((DIR == 1) ? g.idy : g.idz);
         const long long cell = col + (long long)(gs + j - 1) * step;
-        const double h = sa.on ? (sa.dt_dev ? *sa.dt_dev : sa.dt) : 0.0;
 #pragma unroll
         for (int q = 0; q < NV; ++q)
-            put_result(rhs, sa, q * g.cells + cell, double((sF[q][ts - 1][tx] - sF[q][ts][tx]) * id), h,
-                       accumulate);
+            put_result(rhs, q * g.cells + cell, double((sF[q][ts - 1][tx] - sF[q][ts][tx]) * id), accumulate);
     }
     if (flags) atomicOr(status, flags);
 }

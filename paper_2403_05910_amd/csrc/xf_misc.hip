@@ -45,7 +45,8 @@ __device__ __forceinline__ int ghost_src(int bc, int sd, int l, int n, int ng) {
 __device__ __forceinline__ int ghost_dst(int sd, int l, int n, int ng) { return sd == 0 ? l : ng + n + l; }
 __device__ __forceinline__ int ghost_width(const Geo &g, int d) { return d == 0 ? g.gx : (d == 1 ? g.gy : g.gz); }
 
-__global__ __launch_bounds__(256) void k_fill(double *U, Geo g, int nv, int d) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T *U, Geo g, int nv, int d) {
     const long long no = others(g, d);
     const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= no * nv) return;
@@ -53,7 +54,7 @@ __global__ __launch_bounds__(256) void k_fill(double *U, Geo g, int nv, int d) {
     long long base, step;
     int n;
     ghost_geometry(g, d, o, base, step, n);
-    double *u = U + f * g.cells + base;
+    T *u = U + f * g.cells + base;
     const int ng = ghost_width(g, d);
 #pragma unroll
     for (int sd = 0; sd < 2; ++sd) {
@@ -102,33 +103,10 @@ __global__ __launch_bounds__(256) void k_zero_ghosts(double *A, Geo g, int nv) {
     if (ghost) A[q] = 0.0;
 }
 
-// Stage k of Eq. 16 over the whole padded state (ghosts are refilled before
-// the next use):  1: U0 = U, U = U + dt L;  2: U = 3/4 U0 + 1/4 (U + dt L);
-// 3: U = 1/3 U0 + 2/3 (U + dt L).
-__global__ __launch_bounds__(256) void k_rk3_stage(double *U, double *U0, const double *L, long long n, int stage,
-                                                   double dt, const double *dt_dev) {
-    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    const double h = dt_dev ? *dt_dev : dt;
-    const double u = U[q];
-    const double v = u + h * L[q];
-    if (stage == 1) {
-        U0[q] = u;
-        U[q] = v;
-    } else if (stage == 2) {
-        U[q] = 0.75 * U0[q] + 0.25 * v;
-    } else {
-        U[q] = U0[q] / 3.0 + 2.0 / 3.0 * v;
-    }
-}
-
-// Stage k of Eq. 16 from per-direction residuals, over the interior cells:
-// Uout = a U0 + b (Uin + h ((Lx + Ly) + Lz)) (a == 0 skips U0; a null L is an
-// inactive direction).  The residual is summed in the x, y, z order.  Uout
-// may alias U0 (each cell is read and written by one thread).
-__global__ __launch_bounds__(256) void k_rk3_stage_sum(double *Uout, const double *U0, const double *Uin,
-                                                       const double *Lx, const double *Ly, const double *Lz, Geo g,
-                                                       int nv, double a, double b, double dt, const double *dt_dev) {
+// rhs = ((Lz + Ly) + Lx) on the interior cells from FP32 per-direction
+// differences (the order in which the FP64 sweeps accumulate).
+__global__ __launch_bounds__(256) void k_sum_dirs(double *rhs, const float *Lx, const float *Ly, const float *Lz,
+                                                  Geo g, int nv) {
     const long long nint = (long long)g.nx * g.ny * g.nz;
     const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nint * nv) return;
@@ -137,13 +115,18 @@ __global__ __launch_bounds__(256) void k_rk3_stage_sum(double *Uout, const doubl
     const long long r2 = r / g.nx;
     const int j = (int)(r2 % g.ny), k = (int)(r2 / g.ny);
     const long long o = f * g.cells + (long long)(g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + (g.gx + i);
-    const double h = dt_dev ? *dt_dev : dt;
     double L = 0.0;
-    if (Lx) L = Lx[o];
-    if (Ly) L = L + Ly[o];
-    if (Lz) L = L + Lz[o];
-    const double v = Uin[o] + h * L;
-    Uout[o] = a == 0.0 ? b * v : a * U0[o] + b * v;
+    bool first = true;
+    if (Lz) {
+        L = (double)Lz[o];
+        first = false;
+    }
+    if (Ly) {
+        L = first ? (double)Ly[o] : L + (double)Ly[o];
+        first = false;
+    }
+    if (Lx) L = first ? (double)Lx[o] : L + (double)Lx[o];
+    rhs[o] = L;
 }
 
 // y = a x + b y (b == 0 ignores the old y, so y may hold anything)
@@ -225,17 +208,22 @@ __global__ __launch_bounds__(256) void k_zero(long long n, double *dst) {
 
 }  // namespace
 
-hipError_t launch_fill_ghosts(const LaunchCtx &c, int nv, double *U, hipStream_t s) {
+template <typename T>
+hipError_t fill_ghosts_t(const LaunchCtx &c, int nv, T *U, hipStream_t s) {
     const Geo &g = c.g;
     const int n[3] = {g.nx, g.ny, g.nz};
     for (int d = 0; d < 3; ++d) {
         if (n[d] <= 1) continue;
         const long long no = d == 0 ? (long long)g.py * g.pz : (d == 1 ? (long long)g.px * g.pz : (long long)g.px * g.py);
-        hipLaunchKernelGGL(k_fill, dim3(blocks_for(no * nv, 256)), dim3(256), 0, s, U, g, nv, d);
+        hipLaunchKernelGGL(k_fill<T>, dim3(blocks_for(no * nv, 256)), dim3(256), 0, s, U, g, nv, d);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_fill_ghosts(const LaunchCtx &c, int nv, double *U, hipStream_t s) {
+    return fill_ghosts_t(c, nv, U, s);
 }
 
 hipError_t launch_fill_ghosts_vjp(const LaunchCtx &c, int nv, double *Ub, hipStream_t s) {
@@ -256,13 +244,6 @@ hipError_t launch_zero_ghosts(const LaunchCtx &c, int nv, double *A, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_rk3_stage(const LaunchCtx &c, int nv, int stage, double *U, double *U0, const double *L,
-                            double dt, const double *dt_dev, hipStream_t s) {
-    const long long n = c.g.cells * nv;
-    hipLaunchKernelGGL(k_rk3_stage, dim3(blocks_for(n, 256)), dim3(256), 0, s, U, U0, L, n, stage, dt, dt_dev);
-    return hipGetLastError();
-}
-
 hipError_t launch_rk3_stage_vjp(const LaunchCtx &c, int nv, int stage, double *lam, double *lam0, double *mu,
                                 const double *dt_dev, double dt, hipStream_t s) {
     const long long n = c.g.cells * nv;
@@ -271,12 +252,9 @@ hipError_t launch_rk3_stage_vjp(const LaunchCtx &c, int nv, int stage, double *l
     return hipGetLastError();
 }
 
-hipError_t launch_rk3_stage_sum(const LaunchCtx &c, int nv, double *Uout, const double *U0, const double *Uin,
-                                const double *const L[3], double a, double b, double dt, const double *dt_dev,
-                                hipStream_t s) {
+hipError_t launch_sum_dirs(const LaunchCtx &c, int nv, double *rhs, const float *const L[3], hipStream_t s) {
     const long long n = (long long)c.g.nx * c.g.ny * c.g.nz * nv;
-    hipLaunchKernelGGL(k_rk3_stage_sum, dim3(blocks_for(n, 256)), dim3(256), 0, s, Uout, U0, Uin, L[0], L[1], L[2],
-                       c.g, nv, a, b, dt, dt_dev);
+    hipLaunchKernelGGL(k_sum_dirs, dim3(blocks_for(n, 256)), dim3(256), 0, s, rhs, L[0], L[1], L[2], c.g, nv);
     return hipGetLastError();
 }
 

@@ -26,7 +26,7 @@ hipError_t prims(const LaunchCtx &c, const double *U, double *P, float *Uf, floa
 
 template <typename R, typename S, bool PP, int SPD, int REC>
 hipError_t launch_face_sweep(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumulate, const S *U,
-                             const S *P, double *rhs, const StageArgs &sa, const Dissip &ds, hipStream_t s) {
+                             const S *P, R *rhs, const StageArgs &sa, const Dissip &ds, hipStream_t s) {
     const Geo &g = c.g;
     if (dir == 0) {
         const long long nf = (long long)(g.nx + 1) * g.ny * g.nz;
@@ -52,7 +52,7 @@ hipError_t launch_face_sweep(const LaunchCtx &c, const ThermoK<R> &th, int dir, 
 // One instance per (positivity blend, artificial viscosity, reconstruction).
 template <typename R, typename S, bool PP, int SPD>
 hipError_t face_sweep_rec(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumulate, const S *U, const S *P,
-                          double *rhs, const StageArgs &sa, const Dissip &ds, hipStream_t s) {
+                          R *rhs, const StageArgs &sa, const Dissip &ds, hipStream_t s) {
     switch (ds.recon) {
         case kReconCu6: return launch_face_sweep<R, S, PP, SPD, kReconCu6>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
         case kReconWeno7:
@@ -63,7 +63,7 @@ hipError_t face_sweep_rec(const LaunchCtx &c, const ThermoK<R> &th, int dir, int
 
 template <typename R, typename S, bool PP>
 hipError_t face_sweep_spd(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumulate, const S *U, const S *P,
-                          double *rhs, const StageArgs &sa, const Dissip &ds, hipStream_t s) {
+                          R *rhs, const StageArgs &sa, const Dissip &ds, hipStream_t s) {
     if constexpr (!PP) {   // given speeds: right-hand sides only, never the blended step
         if (ds.type == kViscFrozen) return face_sweep_rec<R, S, PP, kViscFrozen>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
     } else {
@@ -78,29 +78,47 @@ hipError_t face_sweep_spd(const LaunchCtx &c, const ThermoK<R> &th, int dir, int
 
 template <typename R, typename S>
 hipError_t face_sweep_scheme(const LaunchCtx &c, const ThermoK<R> &th, int dir, int accumulate, const S *U,
-                             const S *P, double *rhs, const StageArgs &sa, const Dissip &ds, hipStream_t s) {
+                             const S *P, R *rhs, const StageArgs &sa, const Dissip &ds, hipStream_t s) {
     return sa.pp ? face_sweep_spd<R, S, true>(c, th, dir, accumulate, U, P, rhs, sa, ds, s)
                  : face_sweep_spd<R, S, false>(c, th, dir, accumulate, U, P, rhs, sa, ds, s);
 }
 
 hipError_t sweep(const LaunchCtx &c, int dir, int accumulate, const double *U, const double *P, const float *Uf,
-                 const float *Pf, double *rhs, const StageArgs &sa, const double *glf, hipStream_t s) {
+                 const float *Pf, double *rhs, float *rhs32, const StageArgs &sa, const double *glf, hipStream_t s) {
     const Dissip ds{c.visc, glf, c.recon};
     if (c.visc == kViscGlf && !glf) return hipErrorInvalidValue;
-    if (c.precision == XF_PREC_MIXED)
-        return face_sweep_scheme<float, float>(c, c.th32, dir, accumulate, Uf, Pf, rhs, sa, ds, s);
+    if (c.precision == XF_PREC_MIXED) {
+        if (!rhs32 || accumulate) return hipErrorInvalidValue;   // FP32 differences: one buffer per direction
+        return face_sweep_scheme<float, float>(c, c.th32, dir, 0, Uf, Pf, rhs32, sa, ds, s);
+    }
     return face_sweep_scheme<double, double>(c, c.th64, dir, accumulate, U, P, rhs, sa, ds, s);
 }
 
 hipError_t sweep_frozen(const LaunchCtx &c, int dir, int accumulate, const double *U, const double *P, const float *Uf,
-                        const float *Pf, double *rhs, const double *alpha, long long astride, hipStream_t s) {
+                        const float *Pf, double *rhs, float *rhs32, const double *alpha, long long astride,
+                        hipStream_t s) {
     Dissip ds{kViscFrozen, nullptr, c.recon};
     ds.alpha = alpha;
     ds.astride = astride;
     const StageArgs off{};
-    if (c.precision == XF_PREC_MIXED)
-        return face_sweep_rec<float, float, false, kViscFrozen>(c, c.th32, dir, accumulate, Uf, Pf, rhs, off, ds, s);
+    if (c.precision == XF_PREC_MIXED) {
+        if (!rhs32 || accumulate) return hipErrorInvalidValue;
+        return face_sweep_rec<float, float, false, kViscFrozen>(c, c.th32, dir, 0, Uf, Pf, rhs32, off, ds, s);
+    }
     return face_sweep_rec<double, double, false, kViscFrozen>(c, c.th64, dir, accumulate, U, P, rhs, off, ds, s);
+}
+
+hipError_t stage(const LaunchCtx &c, double *Uout, const double *U0, const double *Uin, const double *const L64[3],
+                 const float *const L32[3], const double *Lv, double a, double b, double dt, const double *dt_dev,
+                 hipStream_t s) {
+    const long long m = (long long)c.g.nx * c.g.ny * c.g.nz * (NS + 4);
+    if (c.precision == XF_PREC_MIXED)
+        hipLaunchKernelGGL(k_stage_sum<float>, dim3(blocks_for(m, 256)), dim3(256), 0, s, Uout, U0, Uin, L32[0],
+                           L32[1], L32[2], Lv, c.g, NS + 4, a, b, dt, dt_dev);
+    else
+        hipLaunchKernelGGL(k_stage_sum<double>, dim3(blocks_for(m, 256)), dim3(256), 0, s, Uout, U0, Uin, L64[0],
+                           L64[1], L64[2], Lv, c.g, NS + 4, a, b, dt, dt_dev);
+    return hipGetLastError();
 }
 
 hipError_t face_speeds(const LaunchCtx &c, int dir, const double *U, const double *P, const double *glf,
@@ -251,7 +269,8 @@ hipError_t react(const LaunchCtx &c, double *U, const ReactK *rk, double dt, con
     return hipGetLastError();
 }
 
-const NsOps kOps = {prims, sweep, sweep_vjp, sweep_frozen, face_speeds, glf, prims_vjp, cfl, transport, viscous, react};
+const NsOps kOps = {prims, sweep, sweep_vjp, sweep_frozen, face_speeds, glf, prims_vjp, cfl, transport, viscous, react,
+                    stage};
 
 }  // namespace
 
