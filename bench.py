@@ -119,14 +119,18 @@ def profile_data():
     return data if data.get("source_hash") == kernel_source_hash() else None
 
 
-def measured_traffic(kernel_class, precision):
-    """HBM bytes per launch of a kernel class from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE, calibrated against a device copy);
-    None when the summary is missing or the kernels changed since"""
+def measured_counters(kernel_class, precision):
+    """counters per launch of a kernel class from the committed summary
+    (calibrated FETCH_SIZE + WRITE_SIZE bytes, VALU instructions, executed
+    flops); None when the summary is missing or the kernels changed since"""
     data = profile_data()
     if data is None:
         return None
-    row = data.get("traffic_bytes_per_launch", {}).get(precision, {}).get(kernel_class)
+    return data.get("traffic_bytes_per_launch", {}).get(precision, {}).get(kernel_class)
+
+
+def measured_traffic(kernel_class, precision):
+    row = measured_counters(kernel_class, precision)
     return None if row is None else row["fetch"] + row["write"]
 
 
@@ -154,6 +158,16 @@ def roofline_of(kernels, case, precision):
            "hbm_frac_algorithmic": alg_bytes / avg_s / 1e9 / pm.PEAK["hbm_GBs"]}
     if traffic is not None:
         out["hbm_frac_measured"] = traffic / avg_s / 1e9 / pm.PEAK["hbm_GBs"]
+    cnt = measured_counters(name, precision)
+    if cnt is not None:
+        # what limits the kernel: neither roof is reached, so report the VALU
+        # issue fraction (wave instructions x 4 cycles over the 1024 SIMDs'
+        # cycles of the launch) beside the executed-flop rate
+        out["executed_flops_per_launch"] = cnt["executed_flops"]
+        out["achieved_executed"] = cnt["executed_flops"] / avg_s / 1e12
+        out["valu_issue_frac"] = cnt["valu_instr"] * 4 / (pm.SIMDS * pm.CLOCK_HZ * avg_s)
+        out["limiter"] = "latency (VALU issue {:.0%}, measured HBM {:.0%} of peak)".format(
+            out["valu_issue_frac"], out.get("hbm_frac_measured", 0.0))
     return out
 
 

@@ -88,20 +88,30 @@ def vjp_sweep_bytes(ns, n, direction):
     return 8 * (nv + 4) * _footprint(n, direction) + 8 * nv * cells + 16 * (nv + 3) * cells
 
 
-# Operations per face of the face VJP as implemented (forward recomputed,
-# then the backward), counted with the per-type VALU counters of one launch
-# (adds, multiplies, transcendentals 1, fused multiply-adds 2, per lane) at
-# two species counts and fitted linearly in N; None until counted.
-VJP_FACE_OPS = {"fp64": None, "mixed": None}
+# Operations per face of the face VJP as implemented (the forward recomputed,
+# then the backward), counted with rocprofv3's per-type VALU counters on one
+# launch group of each direction at 256^3, nine species: 64 x (adds +
+# multiplies + transcendentals + 2 x fused multiply-adds) of the arithmetic
+# type over the group's faces (profiles/vjp_nine_species_sbi_256.md).  The
+# y/z kernels execute about 7 % more than the x kernel.  Measured at nine
+# species only: other species counts return None.
+VJP_FACE_OPS = {("fp64", 9): (10180, 10880, 10880), ("mixed", 9): (10363, 11030, 11030)}
+
+# Operations per face of the forward sweeps as executed, counted the same way
+# (x sweep, nine species): FP64 3985, FP32 4155 -- about 19 % above the
+# algorithmic count F(9) = 3360 of face_flops, for the divide and square-root
+# sequences (counted once in F) and the rolled species loops, which
+# evaluate e_s(T~) three times per species.
+EXECUTED_FACE_OPS = {("fp64", 9): 3985, ("mixed", 9): 4155}
 
 
-def vjp_face_flops(ns, precision="fp64"):
-    c = VJP_FACE_OPS.get(precision)
-    return None if c is None else c[0] * ns + c[1]
+def vjp_face_flops(ns, precision="fp64", direction=0):
+    c = VJP_FACE_OPS.get((precision, ns))
+    return None if c is None else c[direction]
 
 
 def vjp_sweep_flops(ns, n, direction, precision="fp64"):
-    f = vjp_face_flops(ns, precision)
+    f = vjp_face_flops(ns, precision, direction)
     if f is None:
         return None
     cells = n[0] * n[1] * n[2]
@@ -114,6 +124,9 @@ def rk3_step_bytes_per_cell(ns):
     nv = ns + 4
     return 3 * 16 * nv + 3 * 32 * nv
 
+
+SIMDS = 1024          # 256 compute units x 4 SIMDs
+CLOCK_HZ = 2.4e9      # peak engine clock
 
 PEAK = {
     "hbm_GBs": 8000.0,
