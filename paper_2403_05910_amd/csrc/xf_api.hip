@@ -829,6 +829,9 @@ int xf_set_reactions(xf_ctx *c, const xf_mechanism *m, int substeps, int splitti
             if (!std::isfinite(e) || e < 0.0) return XF_EINVAL;
             h.nf[r][s] = f;
             h.nb[r][s] = b;
+            if (f | b) h.part[r] |= 1u << s;
+            h.cf[r] |= (unsigned)f << (2 * s);
+            h.cb[r] |= (unsigned)b << (2 * s);
             h.eff[r][s] = e;
             dn += b - f;
             dm += c->W[s] * (b - f);
@@ -841,6 +844,7 @@ int xf_set_reactions(xf_ctx *c, const xf_mechanism *m, int substeps, int splitti
         h.B[r] = m->B[r];
         h.ER[r] = m->E[r] / xf::kRu;
     }
+    h.th = c->lc.th64;
     for (int s = 0; s < ns; ++s) {
         if (!std::isfinite(m->s0[s])) return XF_EINVAL;
         h.W[s] = c->W[s];

@@ -80,6 +80,11 @@ struct ReactK {
     // dg = G0 (ln T - 1) + G1 T + G2 T^2 + G3 T^3 + G4 T^4 + G5 / T + G6
     double G[kMaxReactions][7];
     double W[kMaxNs], iW[kMaxNs];
+    // per reaction, for one scalar load ahead of the species loops: bit s of
+    // part is set where nu'_s or nu''_s is nonzero; cf and cb hold nu' and
+    // nu'' in two bits per species (bits 2s, 2s + 1)
+    unsigned part[kMaxReactions], cf[kMaxReactions], cb[kMaxReactions];
+    ThermoK<double> th;   // the context's species tables, for the temperature solves
 };
 
 // Step size seen by the sweeps, for the positivity blend: dt, or *dt_dev
@@ -160,6 +165,12 @@ struct NsOps {
                         const double *const L64[3], const float *const L32[3], const double *Lv, double a, double b,
                         double dt, const double *dt_dev, hipStream_t);
 };
+
+// The reaction launcher of one species count, from its own translation unit
+// (xf_react.hip, built with different code-motion settings).
+template <int N>
+hipError_t react_launch(const LaunchCtx &, double *U, const ReactK *rk, double dt, const double *dt_dev, double scale,
+                        int n_sub, hipStream_t);
 
 const NsOps *ops_for_ns(int ns);
 

@@ -2,7 +2,6 @@
 // count.  Compiled once per N with -DXF_NS=N; each object exports
 // xf::ops_ns<N>(), which the C ABI collects into its dispatch table.
 #include "xf_forward.hpp"
-#include "xf_reaction.hpp"
 #include "xf_viscous.hpp"
 #include "xf_vjp.hpp"
 
@@ -261,15 +260,7 @@ hipError_t viscous(const LaunchCtx &c, int dir, const double *U, const double *P
     return hipGetLastError();
 }
 
-hipError_t react(const LaunchCtx &c, double *U, const ReactK *rk, double dt, const double *dt_dev, double scale,
-                 int n_sub, hipStream_t s) {
-    const long long n = (long long)c.g.nx * c.g.ny * c.g.nz;
-    hipLaunchKernelGGL(k_react<NS>, dim3(blocks_for(n, 256)), dim3(256), 0, s, U, c.g, c.th64, rk, dt, dt_dev, scale,
-                       n_sub, c.status);
-    return hipGetLastError();
-}
-
-const NsOps kOps = {prims, sweep, sweep_vjp, sweep_frozen, face_speeds, glf, prims_vjp, cfl, transport, viscous, react,
+const NsOps kOps = {prims, sweep, sweep_vjp, sweep_frozen, face_speeds, glf, prims_vjp, cfl, transport, viscous, react_launch<NS>,
                     stage};
 
 }  // namespace

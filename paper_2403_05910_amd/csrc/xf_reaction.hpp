@@ -30,15 +30,91 @@ constexpr double kP0 = 101325.0;
 
 __device__ __forceinline__ double qss_alpha(double r) {
     if (r < 1e-3) return 0.5 + r * (1.0 / 12.0) - r * r * r * (1.0 / 720.0);
+    // past r = 40, e^-r < 2^-57, so 1 - e^-r rounds to 1 and alpha is 1 - 1/r
+    if (r > 40.0) return 1.0 - 1.0 / r;
     return 1.0 / (-expm1(-r)) - 1.0 / r;
 }
 
+// The mixture's internal energy and C_v at fixed Y as polynomials in T:
+// e(T) = sum_k E_k T^k (k = 0..5), C_v(T) = sum_k C_k T^k (k = 0..4), the
+// species tables weighted by Y once per solve, so that a Newton iteration
+// costs two Horner evaluations instead of one per species.
+struct MixPoly {
+    double E[6], C[5];
+    __device__ __forceinline__ double e(double T) const {
+        return ((((E[5] * T + E[4]) * T + E[3]) * T + E[2]) * T + E[1]) * T + E[0];
+    }
+    __device__ __forceinline__ double cv(double T) const {
+        return (((C[4] * T + C[3]) * T + C[2]) * T + C[1]) * T + C[0];
+    }
+};
+
+// The mechanism and the species tables are read through constant-address
+// pointers (scalar loads).  The table pointer is laundered on every call, so
+// that the table comes in where it is used instead of being held in scalar
+// registers across the sub-steps, where it would push the constants of the
+// exponentials out into vector registers.
+template <class T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+template <int NS>
+__device__ __forceinline__ void mix_poly(cptr<ThermoK<double>> thp, const double *Y, MixPoly &m) {
+    asm volatile("" : "+s"(thp));
+    const auto &th = *thp;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) m.E[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) m.C[k] = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) m.E[k] += Y[s] * th.e[s][k];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) m.C[k] += Y[s] * th.cv[s][k];
+    }
+}
+
+// Newton on e(T) = e (Eq. 21) from the start T (clamped into the bracket
+// where there is one): the bracket, the stop rule |dT| <= 1e-11 |T| and the
+// final update are those of newton_T; only the start differs, and the root
+// it converges to does not depend on it.
+__device__ __forceinline__ bool newton_poly(bool bracket, double T_lo, double T_hi, const MixPoly &m, double e,
+                                            double &T) {
+    double lo = T_lo, hi = T_hi;
+    if (bracket) T = T < lo ? lo : (T > hi ? hi : T);
+    for (int it = 0; it < kNewtonMaxIt; ++it) {
+        const double f = m.e(T) - e;
+        double Tn = T - f / m.cv(T);
+        if (bracket) {
+            if (f > 0.0)
+                hi = fmin(hi, T);
+            else
+                lo = fmax(lo, T);
+            if (Tn < lo || Tn > hi) Tn = 0.5 * (lo + hi);
+        }
+        const bool conv = fabs(Tn - T) <= kNewtonTol * fabs(T);
+        T = Tn;
+        if (conv) {
+            T = T - (m.e(T) - e) / m.cv(T);
+            return true;
+        }
+    }
+    return false;
+}
+
+// stoichiometric coefficient 0..3 as a double, chosen on the scalar unit
+__device__ __forceinline__ double coef(unsigned n) { return n == 1u ? 1.0 : (n == 2u ? 2.0 : (n == 3u ? 3.0 : 0.0)); }
+
 // production q_s and loss rate p_s (1/s) at (rho, Y, T); the species' Gibbs
 // functions enter only through each reaction's net sum, whose coefficients
-// the host folds (ReactK::G), so no per-species thermo table is held here
+// the host folds (ReactK::G), so no per-species thermo table is held here.
+// Each reaction's participants and coefficients come from three words read
+// once; only the participating species' concentrations are multiplied in
+// and only their q and p accumulate.  p_s = loss_s / [X_s] (= loss W_s /
+// (rho Y_s)), 0 where Y_s <= 0.
 template <int NS>
-__device__ __forceinline__ void qss_rates(const ReactK *__restrict__ rk, double rho, const double *Y, double T,
-                                          double *q, double *p) {
+__device__ __forceinline__ void qss_rates(cptr<ReactK> rk, double rho, const double *Y, double T, double *q,
+                                          double *p) {
     const double lt = log(T), iT = 1.0 / T, lt1 = lt - 1.0;
     const double lp = log(kP0 / (kRu * T));
     double conc[NS];
@@ -50,6 +126,7 @@ __device__ __forceinline__ void qss_rates(const ReactK *__restrict__ rk, double 
     }
     const int nr = rk->nr;
     for (int r = 0; r < nr; ++r) {
+        const unsigned part = rk->part[r], cf = rk->cf[r], cb = rk->cb[r];
         const double lkf = rk->lnA[r] + rk->B[r] * lt - rk->ER[r] * iT;
         double gam = 1.0;
         if (rk->third[r]) {
@@ -60,23 +137,50 @@ __device__ __forceinline__ void qss_rates(const ReactK *__restrict__ rk, double 
         double pf = 1.0, pb = 1.0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const int f = rk->nf[r][s], b = rk->nb[r][s];
-            for (int k = 0; k < f; ++k) pf *= conc[s];
-            for (int k = 0; k < b; ++k) pb *= conc[s];
+            if (part >> s & 1u) {
+                const unsigned f = cf >> (2 * s) & 3u, b = cb >> (2 * s) & 3u;
+                const double c = conc[s];
+                // uniform branches, one multiply each: the empty statements
+                // keep the compiler from turning them into per-lane selects
+                if (f) {
+                    asm volatile("");
+                    pf *= c;
+                }
+                if (f >> 1) {
+                    asm volatile("");
+                    pf *= c;
+                }
+                if (f == 3u) {
+                    asm volatile("");
+                    pf *= c;
+                }
+                if (b) {
+                    asm volatile("");
+                    pb *= c;
+                }
+                if (b >> 1) {
+                    asm volatile("");
+                    pb *= c;
+                }
+                if (b == 3u) {
+                    asm volatile("");
+                    pb *= c;
+                }
+            }
         }
         const double Rf = gam * exp(lkf) * pf;
         double Rb = 0.0;
         if (rk->rev[r]) {
-            const double *G = rk->G[r];
+            const auto *G = rk->G[r];
             const double dg = G[0] * lt1 + (((G[4] * T + G[3]) * T + G[2]) * T + G[1]) * T + G[5] * iT + G[6];
             Rb = gam * exp(lkf - (rk->dn[r] * lp + dg)) * pb;
         }
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const int f = rk->nf[r][s], b = rk->nb[r][s];
-            if (f | b) {
-                q[s] += b * Rf + f * Rb;
-                p[s] += f * Rf + b * Rb;
+            if (part >> s & 1u) {
+                const double fd = coef(cf >> (2 * s) & 3u), bd = coef(cb >> (2 * s) & 3u);
+                q[s] += bd * Rf + fd * Rb;
+                p[s] += fd * Rf + bd * Rb;
             }
         }
     }
@@ -84,20 +188,18 @@ __device__ __forceinline__ void qss_rates(const ReactK *__restrict__ rk, double 
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         q[s] *= rk->W[s] * ir;
-        const double l = p[s] * rk->W[s] * ir;
-        p[s] = Y[s] > 0.0 ? l / Y[s] : 0.0;
+        p[s] = conc[s] > 0.0 ? p[s] / conc[s] : 0.0;
     }
 }
 
 // The predictor's rates q0 and p0 wait out the corrector's rate evaluation in
 // LDS (one slot per thread, conflict-free rows of 256 doubles) instead of 2 NS
-// registers, and the kernel is held to 128 registers per lane (four waves per
-// SIMD) so that more waves hide the FP64 latency; at nine species that costs
-// a few hundred bytes of spill per lane and still wins over two or three waves.
+// registers.  Each temperature solve starts from the cell's previous one
+// (the first from e / C_v(T_ref)).
 template <int NS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_react(double *__restrict__ U, Geo g, ThermoK<double> th,
-                                               const ReactK *__restrict__ rk, double dt, const double *dt_dev,
-                                               double scale, int n_sub, unsigned *status) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_react(double *__restrict__ U, Geo g, const ReactK *__restrict__ rk,
+                                               double dt, const double *dt_dev, double scale, int n_sub,
+                                               unsigned *status) {
     __shared__ double held[2 * NS][256];
     const int t = threadIdx.x;
     const long long q = (long long)blockIdx.x * blockDim.x + t;
@@ -122,25 +224,49 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const double e = U[(NS + 3) * C + idx] * irho - 0.5 * (u * u + v * v + w * w);
     const double h = (dt_dev ? *dt_dev : dt) * scale / n_sub;
     unsigned flags = 0;
+    const cptr<ReactK> rc = (cptr<ReactK>)rk;
+    const cptr<ThermoK<double>> th = &rc->th;
+    const bool bracket = th->bracket;
+    const double T_lo = th->T_lo, T_hi = th->T_hi;
+    double T;
+    {
+        MixPoly m;
+        mix_poly<NS>(th, Y, m);
+        T = e / m.cv(th->T_ref);
+    }
     for (int it = 0; it < n_sub; ++it) {
-        double T0, Tp, qp[NS], pp[NS], Yp[NS];
+        double qp[NS], pp[NS];
         {
-            double q0[NS], p0[NS];
-            if (!newton_T<NS>(th, Y, e, T0)) flags |= XF_FLAG_NEWTON;
-            qss_rates<NS>(rk, rho, Y, T0, q0, p0);
+            double Yp[NS];
+            {
+                double q0[NS], p0[NS];
+                {
+                    MixPoly m;
+                    mix_poly<NS>(th, Y, m);
+                    if (!newton_poly(bracket, T_lo, T_hi, m, e, T)) flags |= XF_FLAG_NEWTON;
+                }
+                qss_rates<NS>(rc, rho, Y, T, q0, p0);
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const double a0 = qss_alpha(p0[s] * h);
-                Yp[s] = Y[s] + h * (q0[s] - p0[s] * Y[s]) / (1.0 + a0 * p0[s] * h);
-                held[s][t] = q0[s];
-                held[NS + s][t] = p0[s];
+                for (int s = 0; s < NS; ++s) {
+                    const double a0 = qss_alpha(p0[s] * h);
+                    Yp[s] = Y[s] + h * (q0[s] - p0[s] * Y[s]) / (1.0 + a0 * p0[s] * h);
+                    held[s][t] = q0[s];
+                    held[NS + s][t] = p0[s];
+                    // one species at a time: interleaving the nine alpha and
+                    // division chains would only raise the register count
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
+            // each thread reads back only its own slots; the fence keeps the
+            // compiler from carrying the stored values in registers instead
+            asm volatile("" ::: "memory");
+            {
+                MixPoly m;
+                mix_poly<NS>(th, Yp, m);
+                if (!newton_poly(bracket, T_lo, T_hi, m, e, T)) flags |= XF_FLAG_NEWTON;
+            }
+            qss_rates<NS>(rc, rho, Yp, T, qp, pp);
         }
-        // each thread reads back only its own slots; the fence keeps the
-        // compiler from carrying the stored values in registers instead
-        asm volatile("" ::: "memory");
-        if (!newton_T<NS>(th, Yp, e, Tp)) flags |= XF_FLAG_NEWTON;
-        qss_rates<NS>(rk, rho, Yp, Tp, qp, pp);
         asm volatile("" ::: "memory");
         double sum = 0.0;
 #pragma unroll
@@ -151,15 +277,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             const double ql = ab * qp[s] + (1.0 - ab) * q0;
             Y[s] = Y[s] + h * (ql - pb * Y[s]) / (1.0 + ab * pb * h);
             sum += Y[s];
+            __builtin_amdgcn_sched_barrier(0);
         }
         const double is = 1.0 / sum;
 #pragma unroll
         for (int s = 0; s < NS; ++s) Y[s] *= is;
     }
+    // the addresses are formed again here rather than held through the loop
+    long long o = idx;
+    asm volatile("" : "+v"(o));
     bool finite = true;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        U[s * C + idx] = rho * Y[s];
+        U[s * C + o] = rho * Y[s];
         finite = finite && isfinite(Y[s]);
     }
     if (!finite) flags |= XF_FLAG_NAN;
