@@ -845,6 +845,7 @@ int xf_set_reactions(xf_ctx *c, const xf_mechanism *m, int substeps, int splitti
         h.ER[r] = m->E[r] / xf::kRu;
     }
     h.th = c->lc.th64;
+    h.lp0 = std::log(xf::kP0 / xf::kRu);
     for (int s = 0; s < ns; ++s) {
         if (!std::isfinite(m->s0[s])) return XF_EINVAL;
         h.W[s] = c->W[s];

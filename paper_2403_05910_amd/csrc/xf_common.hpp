@@ -12,6 +12,7 @@
 namespace xf {
 
 constexpr double kRu = 8.314462618;      // J/(mol K)
+constexpr double kP0 = 101325.0;         // Pa, the reference pressure of the equilibrium constants
 constexpr int kMaxNs = XF_MAX_SPECIES;
 constexpr double kNewtonTol = 1e-11;
 constexpr int kNewtonMaxIt = 50;
@@ -85,6 +86,7 @@ struct ReactK {
     // nu'' in two bits per species (bits 2s, 2s + 1)
     unsigned part[kMaxReactions], cf[kMaxReactions], cb[kMaxReactions];
     ThermoK<double> th;   // the context's species tables, for the temperature solves
+    double lp0;           // ln(p0 / R_u)
 };
 
 // Step size seen by the sweeps, for the positivity blend: dt, or *dt_dev

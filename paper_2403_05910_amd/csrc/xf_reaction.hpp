@@ -26,13 +26,62 @@
 
 namespace xf {
 
-constexpr double kP0 = 101325.0;
+// The mechanism and the species tables are read through constant-address
+// pointers (scalar loads).
+template <class T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+// exp and expm1 of the rate evaluations.  x = k ln2 + r with k = rint(x /
+// ln2) and r reduced in two FMA steps against ln2 split into its double and
+// the remainder, so |r| <= ln2 / 2; e^r from its Taylor series through r^13
+// (truncation below 5e-18 relative), scaled by 2^k.  For expm1 the series
+// starts at r, P(r) = e^r - 1, and expm1(x) = 2^k P(r) + (2^k - 1), which is
+// P(r) itself wherever |x| < ln2 / 2 (k = 0), so small arguments keep their
+// relative accuracy.  The constants come by scalar loads from a table in
+// constant memory, read at every call (the pointer is laundered), so that
+// they enter the FMAs as scalar operands rather than being copied into
+// vector registers first.  Infinite or NaN arguments give NaN.
+__constant__ double kExpTab[17] = {
+    1.4426950408889634,                            // 1 / ln2
+    0.6931471805599453,    2.3190468138462996e-17,  // ln2 as a double, and the remainder
+    1.6059043836821613e-10, 2.08767569878681e-09,   // 1/13!, 1/12!
+    2.505210838544172e-08, 2.755731922398589e-07,   // 1/11!, 1/10!
+    2.7557319223985893e-06, 2.48015873015873e-05,   // 1/9!, 1/8!
+    0.0001984126984126984, 0.001388888888888889,    // 1/7!, 1/6!
+    0.008333333333333333,  0.041666666666666664,    // 1/5!, 1/4!
+    0.16666666666666666,   0.5,                     // 1/3!, 1/2!
+    1.0,                   1.0};                    // 1/1!, 1/0!
+
+__device__ __forceinline__ cptr<double> exp_table() {
+    cptr<double> c = (cptr<double>)kExpTab;
+    asm volatile("" : "+s"(c));
+    return c;
+}
+
+__device__ __forceinline__ double rx_exp(double x, cptr<double> c) {
+    const double k = rint(x * c[0]);
+    double r = fma(-k, c[1], x);
+    r = fma(-k, c[2], r);
+    double p = c[3];
+#pragma unroll
+    for (int i = 4; i < 17; ++i) p = fma(p, r, c[i]);
+    return ldexp(p, (int)k);
+}
+
+__device__ __forceinline__ double rx_expm1(double x, cptr<double> c) {
+    const double k = rint(x * c[0]);
+    double r = fma(-k, c[1], x);
+    r = fma(-k, c[2], r);
+    double q = c[3];
+#pragma unroll
+    for (int i = 4; i < 16; ++i) q = fma(q, r, c[i]);
+    const int ki = (int)k;
+    return fma(ldexp(r, ki), q, ldexp(1.0, ki) - 1.0);
+}
 
 __device__ __forceinline__ double qss_alpha(double r) {
     if (r < 1e-3) return 0.5 + r * (1.0 / 12.0) - r * r * r * (1.0 / 720.0);
-    // past r = 40, e^-r < 2^-57, so 1 - e^-r rounds to 1 and alpha is 1 - 1/r
-    if (r > 40.0) return 1.0 - 1.0 / r;
-    return 1.0 / (-expm1(-r)) - 1.0 / r;
+    return 1.0 / (-rx_expm1(-r, exp_table())) - 1.0 / r;
 }
 
 // The mixture's internal energy and C_v at fixed Y as polynomials in T:
@@ -49,13 +98,9 @@ struct MixPoly {
     }
 };
 
-// The mechanism and the species tables are read through constant-address
-// pointers (scalar loads).  The table pointer is laundered on every call, so
-// that the table comes in where it is used instead of being held in scalar
-// registers across the sub-steps, where it would push the constants of the
-// exponentials out into vector registers.
-template <class T>
-using cptr = const __attribute__((address_space(4))) T *;
+// The table pointer is laundered on every call, so that the table comes in
+// where it is used instead of being held in scalar registers across the
+// sub-steps, where it would crowd out everything else.
 
 template <int NS>
 __device__ __forceinline__ void mix_poly(cptr<ThermoK<double>> thp, const double *Y, MixPoly &m) {
@@ -115,8 +160,11 @@ __device__ __forceinline__ double coef(unsigned n) { return n == 1u ? 1.0 : (n =
 template <int NS>
 __device__ __forceinline__ void qss_rates(cptr<ReactK> rk, double rho, const double *Y, double T, double *q,
                                           double *p) {
+    // a fresh pointer per call: nothing read from the mechanism (W_s / rho,
+    // rho / W_s) is kept live across the sub-steps
+    asm volatile("" : "+s"(rk));
     const double lt = log(T), iT = 1.0 / T, lt1 = lt - 1.0;
-    const double lp = log(kP0 / (kRu * T));
+    const double lp = rk->lp0 - lt;   // ln(p0 / (R_u T))
     double conc[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -127,6 +175,7 @@ __device__ __forceinline__ void qss_rates(cptr<ReactK> rk, double rho, const dou
     const int nr = rk->nr;
     for (int r = 0; r < nr; ++r) {
         const unsigned part = rk->part[r], cf = rk->cf[r], cb = rk->cb[r];
+        const cptr<double> ec = exp_table();
         const double lkf = rk->lnA[r] + rk->B[r] * lt - rk->ER[r] * iT;
         double gam = 1.0;
         if (rk->third[r]) {
@@ -168,12 +217,12 @@ __device__ __forceinline__ void qss_rates(cptr<ReactK> rk, double rho, const dou
                 }
             }
         }
-        const double Rf = gam * exp(lkf) * pf;
+        const double Rf = gam * rx_exp(lkf, ec) * pf;
         double Rb = 0.0;
         if (rk->rev[r]) {
             const auto *G = rk->G[r];
             const double dg = G[0] * lt1 + (((G[4] * T + G[3]) * T + G[2]) * T + G[1]) * T + G[5] * iT + G[6];
-            Rb = gam * exp(lkf - (rk->dn[r] * lp + dg)) * pb;
+            Rb = gam * rx_exp(lkf - (rk->dn[r] * lp + dg), ec) * pb;
         }
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
