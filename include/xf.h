@@ -296,7 +296,8 @@ int xf_set_viscous(xf_ctx *ctx, const xf_transport *tr, int terms);
  * R(dt/2); XF_SPLIT_LIE: F(dt) R(dt) (F the SSP-RK3 flow step; with the
  * CFL variant dt comes from U^n before the first reaction step).  A NULL
  * mechanism or substeps = 0 switches reactions off.  Stoichiometric
- * coefficients 0..3; 1 <= nr <= XF_MAX_REACTIONS; every reaction must
+ * coefficients 0..3, at most seven molecules on each side of a reaction
+ * (sum_s nu' <= 7, sum_s nu'' <= 7); 1 <= nr <= XF_MAX_REACTIONS; every reaction must
  * conserve mass (sum_s W_s (nu'' - nu') = 0 within 1e-9 W_max).  Tables are
  * copied to the device (the first call allocates that copy and the call
  * synchronises).  The VJPs return XF_EUNSUPPORTED while reactions are on.

@@ -829,9 +829,18 @@ int xf_set_reactions(xf_ctx *c, const xf_mechanism *m, int substeps, int splitti
             if (!std::isfinite(e) || e < 0.0) return XF_EINVAL;
             h.nf[r][s] = f;
             h.nb[r][s] = b;
-            if (f | b) h.part[r] |= 1u << s;
-            h.cf[r] |= (unsigned)f << (2 * s);
-            h.cb[r] |= (unsigned)b << (2 * s);
+            h.fd[r][s] = f;
+            h.bd[r][s] = b;
+            for (int k = 0; k < f; ++k) {
+                const unsigned n = h.fl[r] & 7u;
+                if (n == 7u) return XF_EINVAL;   // more than seven reactant molecules
+                h.fl[r] = (h.fl[r] + 1u) | ((unsigned)s << (3 + 4 * n));
+            }
+            for (int k = 0; k < b; ++k) {
+                const unsigned n = h.bl[r] & 7u;
+                if (n == 7u) return XF_EINVAL;   // more than seven product molecules
+                h.bl[r] = (h.bl[r] + 1u) | ((unsigned)s << (3 + 4 * n));
+            }
             h.eff[r][s] = e;
             dn += b - f;
             dm += c->W[s] * (b - f);

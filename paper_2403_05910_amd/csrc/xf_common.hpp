@@ -81,10 +81,12 @@ struct ReactK {
     // dg = G0 (ln T - 1) + G1 T + G2 T^2 + G3 T^3 + G4 T^4 + G5 / T + G6
     double G[kMaxReactions][7];
     double W[kMaxNs], iW[kMaxNs];
-    // per reaction, for one scalar load ahead of the species loops: bit s of
-    // part is set where nu'_s or nu''_s is nonzero; cf and cb hold nu' and
-    // nu'' in two bits per species (bits 2s, 2s + 1)
-    unsigned part[kMaxReactions], cf[kMaxReactions], cb[kMaxReactions];
+    // per reaction, for scalar loads ahead of the species work: the reactant
+    // and product lists (the count in bits 0..2, then up to seven species
+    // indices of four bits each, a species listed nu times), and nu' and
+    // nu'' as doubles for the accumulation of q and p
+    unsigned fl[kMaxReactions], bl[kMaxReactions];
+    double fd[kMaxReactions][kMaxNs], bd[kMaxReactions][kMaxNs];
     ThermoK<double> th;   // the context's species tables, for the temperature solves
     double lp0;           // ln(p0 / R_u)
 };

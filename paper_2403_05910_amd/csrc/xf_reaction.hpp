@@ -52,6 +52,15 @@ __constant__ double kExpTab[17] = {
     0.16666666666666666,   0.5,                     // 1/3!, 1/2!
     1.0,                   1.0};                    // 1/1!, 1/0!
 
+// a * b + c with c in scalar registers, as one VOP3 instruction: written out
+// because the compiler otherwise copies c into the destination's vector
+// registers (two moves) to use the two-operand form
+__device__ __forceinline__ double fma_sc(double a, double b, double c) {
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+    return d;
+}
+
 __device__ __forceinline__ cptr<double> exp_table() {
     cptr<double> c = (cptr<double>)kExpTab;
     asm volatile("" : "+s"(c));
@@ -62,9 +71,9 @@ __device__ __forceinline__ double rx_exp(double x, cptr<double> c) {
     const double k = rint(x * c[0]);
     double r = fma(-k, c[1], x);
     r = fma(-k, c[2], r);
-    double p = c[3];
+    double p = fma_sc(r, c[3], c[4]);
 #pragma unroll
-    for (int i = 4; i < 17; ++i) p = fma(p, r, c[i]);
+    for (int i = 5; i < 17; ++i) p = fma_sc(p, r, c[i]);
     return ldexp(p, (int)k);
 }
 
@@ -72,9 +81,9 @@ __device__ __forceinline__ double rx_expm1(double x, cptr<double> c) {
     const double k = rint(x * c[0]);
     double r = fma(-k, c[1], x);
     r = fma(-k, c[2], r);
-    double q = c[3];
+    double q = fma_sc(r, c[3], c[4]);
 #pragma unroll
-    for (int i = 4; i < 16; ++i) q = fma(q, r, c[i]);
+    for (int i = 5; i < 16; ++i) q = fma_sc(q, r, c[i]);
     const int ki = (int)k;
     return fma(ldexp(r, ki), q, ldexp(1.0, ki) - 1.0);
 }
@@ -147,16 +156,14 @@ __device__ __forceinline__ bool newton_poly(bool bracket, double T_lo, double T_
     return false;
 }
 
-// stoichiometric coefficient 0..3 as a double, chosen on the scalar unit
-__device__ __forceinline__ double coef(unsigned n) { return n == 1u ? 1.0 : (n == 2u ? 2.0 : (n == 3u ? 3.0 : 0.0)); }
-
 // production q_s and loss rate p_s (1/s) at (rho, Y, T); the species' Gibbs
 // functions enter only through each reaction's net sum, whose coefficients
 // the host folds (ReactK::G), so no per-species thermo table is held here.
-// Each reaction's participants and coefficients come from three words read
-// once; only the participating species' concentrations are multiplied in
-// and only their q and p accumulate.  p_s = loss_s / [X_s] (= loss W_s /
-// (rho Y_s)), 0 where Y_s <= 0.
+// Each reaction's concentration products run over its reactant and product
+// lists (a uniform register index per molecule), and q and p accumulate over
+// all species with nu' and nu'' as scalar operands (zero for bystanders), so
+// that the per-reaction work has no per-species branches.  p_s = loss_s /
+// [X_s] (= loss W_s / (rho Y_s)), 0 where Y_s <= 0.
 template <int NS>
 __device__ __forceinline__ void qss_rates(cptr<ReactK> rk, double rho, const double *Y, double T, double *q,
                                           double *p) {
@@ -174,7 +181,7 @@ __device__ __forceinline__ void qss_rates(cptr<ReactK> rk, double rho, const dou
     }
     const int nr = rk->nr;
     for (int r = 0; r < nr; ++r) {
-        const unsigned part = rk->part[r], cf = rk->cf[r], cb = rk->cb[r];
+        const unsigned fl = rk->fl[r], bl = rk->bl[r];
         const cptr<double> ec = exp_table();
         const double lkf = rk->lnA[r] + rk->B[r] * lt - rk->ER[r] * iT;
         double gam = 1.0;
@@ -183,53 +190,37 @@ __device__ __forceinline__ void qss_rates(cptr<ReactK> rk, double rho, const dou
 #pragma unroll
             for (int s = 0; s < NS; ++s) gam += rk->eff[r][s] * conc[s];
         }
+        // the loops end at the list's count (a uniform branch; the empty
+        // statement keeps the compiler from running all seven slots under
+        // per-lane selects)
         double pf = 1.0, pb = 1.0;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            if (part >> s & 1u) {
-                const unsigned f = cf >> (2 * s) & 3u, b = cb >> (2 * s) & 3u;
-                const double c = conc[s];
-                // uniform branches, one multiply each: the empty statements
-                // keep the compiler from turning them into per-lane selects
-                if (f) {
-                    asm volatile("");
-                    pf *= c;
-                }
-                if (f >> 1) {
-                    asm volatile("");
-                    pf *= c;
-                }
-                if (f == 3u) {
-                    asm volatile("");
-                    pf *= c;
-                }
-                if (b) {
-                    asm volatile("");
-                    pb *= c;
-                }
-                if (b >> 1) {
-                    asm volatile("");
-                    pb *= c;
-                }
-                if (b == 3u) {
-                    asm volatile("");
-                    pb *= c;
-                }
-            }
+        for (unsigned k = 0; k < 7; ++k) {
+            if (k >= (fl & 7u)) break;
+            asm volatile("");
+            pf *= conc[fl >> (3 + 4 * k) & 15u];
+        }
+#pragma unroll
+        for (unsigned k = 0; k < 7; ++k) {
+            if (k >= (bl & 7u)) break;
+            asm volatile("");
+            pb *= conc[bl >> (3 + 4 * k) & 15u];
         }
         const double Rf = gam * rx_exp(lkf, ec) * pf;
-        double Rb = 0.0;
+        const auto *fd = rk->fd[r], *bd = rk->bd[r];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            q[s] = fma(bd[s], Rf, q[s]);
+            p[s] = fma(fd[s], Rf, p[s]);
+        }
         if (rk->rev[r]) {
             const auto *G = rk->G[r];
             const double dg = G[0] * lt1 + (((G[4] * T + G[3]) * T + G[2]) * T + G[1]) * T + G[5] * iT + G[6];
-            Rb = gam * rx_exp(lkf - (rk->dn[r] * lp + dg), ec) * pb;
-        }
+            const double Rb = gam * rx_exp(lkf - (rk->dn[r] * lp + dg), ec) * pb;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            if (part >> s & 1u) {
-                const double fd = coef(cf >> (2 * s) & 3u), bd = coef(cb >> (2 * s) & 3u);
-                q[s] += bd * Rf + fd * Rb;
-                p[s] += fd * Rf + bd * Rb;
+            for (int s = 0; s < NS; ++s) {
+                q[s] = fma(fd[s], Rb, q[s]);
+                p[s] = fma(bd[s], Rb, p[s]);
             }
         }
     }

@@ -169,6 +169,17 @@ def test_reaction_refusals():
     with pytest.raises(xf.XfError) as e:
         ctx.set_reactions(bad, 4)
     assert e.value.code == xf.XF_EINVAL
+    big = W.MechanismTable(mt.nu_f.copy(), mt.nu_b.copy(), mt.A, mt.B, mt.E, mt.third, mt.eff, mt.reversible, mt.s0)
+    big.nu_f[0] = 0
+    big.nu_b[0] = 0
+    big.nu_f[0, :3] = 3                                          # nine molecules on each side, mass conserved
+    big.nu_b[0, :3] = 3
+    with pytest.raises(xf.XfError) as e:
+        ctx.set_reactions(big, 4)
+    assert e.value.code == xf.XF_EINVAL
+    big.nu_f[0, 2] = 1                                           # seven on each side: accepted
+    big.nu_b[0, 2] = 1
+    ctx.set_reactions(big, 4)
     ctx.set_reactions(mt, 4)
     with pytest.raises(xf.XfError) as e:
         ctx.rhs_vjp(U, torch.ones_like(U))
