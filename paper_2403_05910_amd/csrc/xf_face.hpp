@@ -342,6 +342,19 @@ struct StencilT {
 };
 using Stencil = StencilT<double>;
 
+// Stencil values staged in LDS: field f of stencil cell m at
+// t[f * fs + base + m * step]; fields 0..NV-1 are U, NV..NV+3 the primitives
+// (T, p, c, 1/rho).  The pointer carries the LDS address space, so no
+// generic-address checks are generated.
+typedef __attribute__((address_space(3))) double lds_double;
+template <int NV>
+struct StencilLds {
+    const lds_double *t;
+    int base, step, fs;
+    XF_HD double u(int f, int m) const { return t[f * fs + base + m * step]; }
+    XF_HD double p(int k, int m) const { return t[(NV + k) * fs + base + m * step]; }
+};
+
 template <int DIR>
 struct Axes {
     // momentum component of the normal and of the two tangents

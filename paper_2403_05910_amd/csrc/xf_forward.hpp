@@ -275,10 +275,12 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(sweep_w
 template <typename R>
 struct TileShape {
     static constexpr int x = 32, s = 8;
+    static constexpr bool staged = false;
 };
 template <>
 struct TileShape<double> {
     static constexpr int x = 16, s = 16;
+    static constexpr bool staged = true;   // stencils from LDS (WENO5/CU6 without the blend)
 };
 
 template <int NS, typename R, int DIR, typename S, bool PP, int SPD, int REC>
@@ -287,27 +289,56 @@ k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, R *__restrict__ r
              int accumulate, StageArgs sa, unsigned *status, Dissip ds) {
     constexpr int NV = NS + 4;
     constexpr int kTileX = TileShape<R>::x, kTileS = TileShape<R>::s;
+    constexpr int RAD = stencil_radius(REC);
+    constexpr bool STAGE = TileShape<R>::staged && sizeof(S) == 8 && !PP && REC != kReconWeno7;
+    constexpr int kRows = kTileS + 2 * RAD - 1;        // stencil rows of the tile's faces
+    constexpr int TSZ = kRows * kTileX;                // staged cells
     __shared__ R sF[NV][kTileS][kTileX];
+    __shared__ double xf_ftile[STAGE ? (NV + 4) * TSZ : 1];
     unsigned bx, by, bz;
     xcd_block(bx, by, bz);
     const int tx = threadIdx.x, ts = threadIdx.y;
     const int x = bx * kTileX + tx;
-    const int j = by * (kTileS - 1) + ts;            // face j: between cells j-1 and j of the sweep axis
+    const int j0 = by * (kTileS - 1);                 // the tile's first face
+    const int j = j0 + ts;                            // face j: between cells j-1 and j of the sweep axis
     const int nsw = (DIR == 1) ? g.ny : g.nz;
     const bool valid = x < g.nx && j <= nsw;
     const long long step = (DIR == 1) ? g.sy : g.sz;
     const int gs = (DIR == 1) ? g.gy : g.gz;
-    const long long col = (long long)(g.gx + x) +
-                          ((DIR == 1) ? (long long)(g.gz + bz) * g.sz : (long long)(g.gy + bz) * g.sy);
+    const long long plane = (DIR == 1) ? (long long)(g.gz + bz) * g.sz : (long long)(g.gy + bz) * g.sy;
+    const long long col = (long long)(g.gx + x) + plane;
     unsigned flags = 0;
+    if constexpr (STAGE) {
+        // tile row r = padded sweep row gs + j0 - RAD + r, for the tile's x
+        // columns; rows past the padded extent and columns past the interior
+        // are never read
+        const int npad = nsw + 2 * gs;
+        for (int e = ts * kTileX + tx; e < TSZ; e += kTileX * kTileS) {
+            const int r = e / kTileX, cx = bx * kTileX + (e % kTileX);
+            const int row = gs + j0 - RAD + r;
+            if (cx >= g.nx || row >= npad) continue;
+            const long long cell = plane + g.gx + cx + (long long)row * step;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) xf_ftile[q * TSZ + e] = double(U[q * g.cells + cell]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) xf_ftile[(NV + k) * TSZ + e] = double(P[k * g.cells + cell]);
+        }
+        __syncthreads();
+    }
     if (valid) {
-        constexpr int RAD = stencil_radius(REC);
-        StencilT<S> st{U, P, col + (long long)(gs + j - RAD) * step, step, g.cells};
         if constexpr (SPD == kViscFrozen)   // y faces: i + nx (j + (ny + 1) k); z faces: i + nx (j + ny k)
             ds.fidx = DIR == 1 ? x + (long long)g.nx * (j + (long long)(g.ny + 1) * bz)
                                : x + (long long)g.nx * (bz + (long long)g.ny * j);
-        face_flux_to<NS, R, DIR, SweepTune<R>::fence_face, SPD, REC, !PP, SweepTune<R>::roll_tile>(
-            st, th, [&](int q, R v) { sF[q][ts][tx] = v; }, flags, ds);
+        StencilT<S> st{U, P, col + (long long)(gs + j - RAD) * step, step, g.cells};
+        if constexpr (STAGE) {
+            // stencil cell m of face j is tile row j - j0 + m
+            const StencilLds<NV> sl{(const lds_double *)xf_ftile, ts * kTileX + tx, kTileX, TSZ};
+            face_flux_to<NS, R, DIR, SweepTune<R>::fence_face, SPD, REC, !PP, SweepTune<R>::roll_tile>(
+                sl, th, [&](int q, R v) { sF[q][ts][tx] = v; }, flags, ds);
+        } else {
+            face_flux_to<NS, R, DIR, SweepTune<R>::fence_face, SPD, REC, !PP, SweepTune<R>::roll_tile>(
+                st, th, [&](int q, R v) { sF[q][ts][tx] = v; }, flags, ds);
+        }
         if constexpr (PP) {
             R Fq[NV];
 #pragma unroll

@@ -190,24 +190,12 @@ XF_HD R dcv_species(const ThermoK<R> &th, int s, R T) {
 // addresses differ: the accesses are volatile (LDS executes a wave's
 // instructions in order).  The pointer carries the LDS address space, so no
 // generic-address checks are generated.
-typedef __attribute__((address_space(3))) double lds_double;   // a pointer known to be LDS
 constexpr int kSinkP = 0, kSinkT = 1, kSinkRho = 2, kSinkExtra = 3;
 struct SinkLds {
     volatile lds_double *w;
     int W, off, mstep, pofs;   // window length, offset of stencil cell 0, cell stride, start of the extra rows
     XF_HD void u(int f, int m, double v) const { w[f * W + off + m * mstep] += v; }
     XF_HD void p(int k, int m, double v) const { w[pofs + k * W + off + m * mstep] += v; }
-};
-
-// Stencil values staged in LDS: field f of stencil cell m at
-// t[f * fs + base + m * step]; fields 0..NV-1 are U, NV..NV+3 the primitives
-// (T, p, c, 1/rho).
-template <int NV>
-struct StencilLds {
-    const lds_double *t;
-    int base, step, fs;
-    XF_HD double u(int f, int m) const { return t[f * fs + base + m * step]; }
-    XF_HD double p(int k, int m) const { return t[(NV + k) * fs + base + m * step]; }
 };
 
 // Cotangent of the face flux, (rbar_R - rbar_L) / dx of the residual's
