@@ -347,12 +347,12 @@ using Stencil = StencilT<double>;
 // (T, p, c, 1/rho).  The pointer carries the LDS address space, so no
 // generic-address checks are generated.
 typedef __attribute__((address_space(3))) double lds_double;
-template <int NV>
+template <int NV, typename T = double>
 struct StencilLds {
-    const lds_double *t;
+    const __attribute__((address_space(3))) T *t;
     int base, step, fs;
-    XF_HD double u(int f, int m) const { return t[f * fs + base + m * step]; }
-    XF_HD double p(int k, int m) const { return t[(NV + k) * fs + base + m * step]; }
+    XF_HD T u(int f, int m) const { return t[f * fs + base + m * step]; }
+    XF_HD T p(int k, int m) const { return t[(NV + k) * fs + base + m * step]; }
 };
 
 template <int DIR>

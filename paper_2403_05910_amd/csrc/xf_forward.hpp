@@ -164,9 +164,10 @@ __global__ __launch_bounds__(256) void k_stage_sum(double *Uout, const double *U
 // * the x sweeps run the species loops rolled (face_flux_to ROLL): FP64 at
 //   three waves per SIMD without spill (168 registers; 2.20 -> 2.00 ms per
 //   launch), FP32 1.74 -> 1.33 ms;
-// * the FP64 y/z tiles keep the unrolled form at two waves (rolled at three
-//   waves they took 2.76/3.02 ms against 2.72/2.91); the FP32 tiles roll
-//   (1.60/1.66 -> 1.56/1.62 ms);
+// * the y/z tiles roll their species loops too; staged in LDS (TileShape),
+//   the FP64 tiles need 154 registers and 72 KB of LDS per block, which
+//   allows two blocks (two waves per SIMD) per CU, the FP32 ones 94
+//   registers and 36 KB (four waves);
 // * the positivity-blend instances stay at two waves (at three the FP64
 //   blended step went from 37.5 to 47.7 ms), the FP64 WENO7 instances at
 //   one (at two they spilled 324-460 bytes per lane; at one they keep their
@@ -269,20 +270,20 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(sweep_w
 // Tiles that are neighbours along the sweep axis share six stencil rows and
 // are numbered to run on the same XCD.
 // ---------------------------------------------------------------------------
-// Tile shape per arithmetic type (measured at 256^3, nine species, among
-// 16 x 16, 32 x 8, 64 x 4, 64 x 8, 32 x 16): FP64 16 x 16 (y/z 2.78/2.96 ms;
-// the others 1-12 % slower); FP32 32 x 8 (1.61/1.67 ms against 1.72/1.81).
+// Tile shape per arithmetic type, and whether the tile stages its stencils
+// in LDS (WENO5/CU6 without the positivity blend): the block copies U and
+// the primitives of its (s + 5) x x stencil cells once, in whole rows, and
+// every face reads its six stencil points from there (a face's stencil is
+// six rows apart in memory, so unstaged each wave issues twice the loads of
+// the x sweep, one per row and field).  Measured at 256^3, nine species:
+// FP64 16 x 16 staged 2.10/2.19 ms (y/z) against 2.92/3.01 unstaged; FP32
+// 16 x 16 staged 1.18/1.18 ms against 1.36/1.37 for 32 x 16 or 32 x 8
+// staged and 1.43/1.49 for 32 x 8 unstaged.
 template <typename R>
 struct TileShape {
-    static constexpr int x = 32, s = 8;
-    static constexpr bool staged = false;
-};
-template <>
-struct TileShape<double> {
     static constexpr int x = 16, s = 16;
-    static constexpr bool staged = true;   // stencils from LDS (WENO5/CU6 without the blend)
+    static constexpr bool staged = true;
 };
-
 template <int NS, typename R, int DIR, typename S, bool PP, int SPD, int REC>
 __global__ __launch_bounds__(TileShape<R>::x *TileShape<R>::s) __attribute__((amdgpu_waves_per_eu(sweep_waves<R, REC, false, PP>()))) void
 k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, R *__restrict__ rhs, Geo g, ThermoK<R> th,
@@ -290,11 +291,11 @@ k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, R *__restrict__ r
     constexpr int NV = NS + 4;
     constexpr int kTileX = TileShape<R>::x, kTileS = TileShape<R>::s;
     constexpr int RAD = stencil_radius(REC);
-    constexpr bool STAGE = TileShape<R>::staged && sizeof(S) == 8 && !PP && REC != kReconWeno7;
+    constexpr bool STAGE = TileShape<R>::staged && !PP && REC != kReconWeno7;
     constexpr int kRows = kTileS + 2 * RAD - 1;        // stencil rows of the tile's faces
     constexpr int TSZ = kRows * kTileX;                // staged cells
     __shared__ R sF[NV][kTileS][kTileX];
-    __shared__ double xf_ftile[STAGE ? (NV + 4) * TSZ : 1];
+    __shared__ S xf_ftile[STAGE ? (NV + 4) * TSZ : 1];
     unsigned bx, by, bz;
     xcd_block(bx, by, bz);
     const int tx = threadIdx.x, ts = threadIdx.y;
@@ -319,9 +320,9 @@ k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, R *__restrict__ r
             if (cx >= g.nx || row >= npad) continue;
             const long long cell = plane + g.gx + cx + (long long)row * step;
 #pragma unroll
-            for (int q = 0; q < NV; ++q) xf_ftile[q * TSZ + e] = double(U[q * g.cells + cell]);
+            for (int q = 0; q < NV; ++q) xf_ftile[q * TSZ + e] = U[q * g.cells + cell];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) xf_ftile[(NV + k) * TSZ + e] = double(P[k * g.cells + cell]);
+            for (int k = 0; k < 4; ++k) xf_ftile[(NV + k) * TSZ + e] = P[k * g.cells + cell];
         }
         __syncthreads();
     }
@@ -332,7 +333,8 @@ k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, R *__restrict__ r
         StencilT<S> st{U, P, col + (long long)(gs + j - RAD) * step, step, g.cells};
         if constexpr (STAGE) {
             // stencil cell m of face j is tile row j - j0 + m
-            const StencilLds<NV> sl{(const lds_double *)xf_ftile, ts * kTileX + tx, kTileX, TSZ};
+            const StencilLds<NV, S> sl{(const __attribute__((address_space(3))) S *)xf_ftile, ts * kTileX + tx, kTileX,
+                                       TSZ};
             face_flux_to<NS, R, DIR, SweepTune<R>::fence_face, SPD, REC, !PP, SweepTune<R>::roll_tile>(
                 sl, th, [&](int q, R v) { sF[q][ts][tx] = v; }, flags, ds);
         } else {
