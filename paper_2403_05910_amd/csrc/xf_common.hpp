@@ -92,11 +92,22 @@ struct ReactK {
 };
 
 // Step size seen by the sweeps, for the positivity blend: dt, or *dt_dev
-// when dt_dev is set; pp switches the blend on.
+// when dt_dev is set; pp switches the blend on.  With Uout set, the x sweep
+// finishes the SSP-RK3 stage of Eq. 16 itself instead of writing its
+// residual: Uout = a U0 + b (Uin + h L), L = ((L_x + L_y) + L_z) + L_v with
+// its own L_x and the other terms read where their pointers are set (the
+// FP64 or the FP32 per-direction buffers, by the sweep's type), exactly as
+// the separate stage kernel sums them.
 struct StageArgs {
     double dt;
     const double *dt_dev;
     int pp;   // blend the face fluxes for positivity with the step dt (or *dt_dev)
+    double *Uout = nullptr;
+    const double *U0 = nullptr, *Uin = nullptr;
+    const double *Ly64 = nullptr, *Lz64 = nullptr;
+    const float *Ly32 = nullptr, *Lz32 = nullptr;
+    const double *Lv = nullptr;
+    double a = 0.0, b = 1.0;
 };
 
 // Everything a launch needs besides buffers.

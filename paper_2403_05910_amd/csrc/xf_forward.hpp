@@ -253,9 +253,28 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(sweep_w
     if (valid && t > 0 && i > 0) {
         const R id = R(g.idx);
         const long long cell = rowbase + i - 1;
+        if (sa.Uout) {
+            const double h = sa.dt_dev ? *sa.dt_dev : sa.dt;
 #pragma unroll
-        for (int q = 0; q < NV; ++q)
-            put_result(rhs, q * g.cells + cell, double((sF[q][t - 1] - sF[q][t]) * id), accumulate);
+            for (int q = 0; q < NV; ++q) {
+                const long long o = q * g.cells + cell;
+                double L = double((sF[q][t - 1] - sF[q][t]) * id);
+                if constexpr (sizeof(R) == 8) {
+                    if (sa.Ly64) L = L + sa.Ly64[o];
+                    if (sa.Lz64) L = L + sa.Lz64[o];
+                } else {
+                    if (sa.Ly32) L = L + (double)sa.Ly32[o];
+                    if (sa.Lz32) L = L + (double)sa.Lz32[o];
+                }
+                if (sa.Lv) L = L + sa.Lv[o];
+                const double v = sa.Uin[o] + h * L;
+                sa.Uout[o] = sa.a == 0.0 ? sa.b * v : sa.a * sa.U0[o] + sa.b * v;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NV; ++q)
+                put_result(rhs, q * g.cells + cell, double((sF[q][t - 1] - sF[q][t]) * id), accumulate);
+        }
     }
     if (flags) atomicOr(status, flags);
 }
