@@ -310,7 +310,7 @@ k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, R *__restrict__ r
     constexpr int NV = NS + 4;
     constexpr int kTileX = TileShape<R>::x, kTileS = TileShape<R>::s;
     constexpr int RAD = stencil_radius(REC);
-    constexpr bool STAGE = TileShape<R>::staged && !PP && REC != kReconWeno7;
+    constexpr bool STAGE = TileShape<R>::staged;
     constexpr int kRows = kTileS + 2 * RAD - 1;        // stencil rows of the tile's faces
     constexpr int TSZ = kRows * kTileX;                // staged cells
     __shared__ R sF[NV][kTileS][kTileX];
@@ -349,24 +349,24 @@ k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, R *__restrict__ r
         if constexpr (SPD == kViscFrozen)   // y faces: i + nx (j + (ny + 1) k); z faces: i + nx (j + ny k)
             ds.fidx = DIR == 1 ? x + (long long)g.nx * (j + (long long)(g.ny + 1) * bz)
                                : x + (long long)g.nx * (bz + (long long)g.ny * j);
-        StencilT<S> st{U, P, col + (long long)(gs + j - RAD) * step, step, g.cells};
-        if constexpr (STAGE) {
-            // stencil cell m of face j is tile row j - j0 + m
-            const StencilLds<NV, S> sl{(const __attribute__((address_space(3))) S *)xf_ftile, ts * kTileX + tx, kTileX,
-                                       TSZ};
-            face_flux_to<NS, R, DIR, SweepTune<R>::fence_face, SPD, REC, !PP, SweepTune<R>::roll_tile>(
-                sl, th, [&](int q, R v) { sF[q][ts][tx] = v; }, flags, ds);
-        } else {
+        auto face = [&](const auto &st) {
             face_flux_to<NS, R, DIR, SweepTune<R>::fence_face, SPD, REC, !PP, SweepTune<R>::roll_tile>(
                 st, th, [&](int q, R v) { sF[q][ts][tx] = v; }, flags, ds);
-        }
-        if constexpr (PP) {
-            R Fq[NV];
+            if constexpr (PP) {
+                R Fq[NV];
 #pragma unroll
-            for (int q = 0; q < NV; ++q) Fq[q] = sF[q][ts][tx];
-            pp_limit<NS, R, DIR, RAD>(st, pp_lambda<R>(g, sa, DIR == 1 ? g.idy : g.idz), Fq);
+                for (int q = 0; q < NV; ++q) Fq[q] = sF[q][ts][tx];
+                pp_limit<NS, R, DIR, RAD>(st, pp_lambda<R>(g, sa, DIR == 1 ? g.idy : g.idz), Fq);
 #pragma unroll
-            for (int q = 0; q < NV; ++q) sF[q][ts][tx] = Fq[q];
+                for (int q = 0; q < NV; ++q) sF[q][ts][tx] = Fq[q];
+            }
+        };
+        if constexpr (STAGE) {
+            // stencil cell m of face j is tile row j - j0 + m
+            face(StencilLds<NV, S>{(const __attribute__((address_space(3))) S *)xf_ftile, ts * kTileX + tx, kTileX,
+                                   TSZ});
+        } else {
+            face(StencilT<S>{U, P, col + (long long)(gs + j - RAD) * step, step, g.cells});
         }
     }
     __syncthreads();
