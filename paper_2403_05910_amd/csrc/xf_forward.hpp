@@ -134,28 +134,29 @@ __global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, dou
     if (flags) atomicOr(status, flags);
 }
 
-// SSP-RK3 stage of Eq. 16 on the interior cells, one thread per value
-// (field, cell): Uout = a U0 + b (Uin + h L), L = ((Lx + Ly) + Lz) + Lv.
+// SSP-RK3 stage of Eq. 16 on the interior cells: Uout = a U0 + b (Uin + h L),
+// L = ((Lx + Ly) + Lz) + Lv.  A block takes one interior row of one field
+// (blockIdx.x = j + ny k, blockIdx.y = field), its threads the cells along
+// x, so no index needs a 64-bit division.
 template <typename LT>
 __global__ __launch_bounds__(256) void k_stage_sum(double *Uout, const double *U0, const double *Uin, const LT *Lx,
-                                                   const LT *Ly, const LT *Lz, const double *Lv, Geo g, int nv,
-                                                   double a, double b, double dt, const double *dt_dev) {
-    const long long nint = (long long)g.nx * g.ny * g.nz;
-    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nint * nv) return;
-    const long long f = q / nint, r = q - f * nint;
-    const int i = (int)(r % g.nx);
-    const long long r2 = r / g.nx;
-    const int j = (int)(r2 % g.ny), k = (int)(r2 / g.ny);
-    const long long o = f * g.cells + (long long)(g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + (g.gx + i);
+                                                   const LT *Ly, const LT *Lz, const double *Lv, Geo g, double a,
+                                                   double b, double dt, const double *dt_dev) {
+    const int row = blockIdx.x;
+    const int j = row % g.ny, k = row / g.ny;
+    const long long base = (long long)blockIdx.y * g.cells + (long long)(g.gz + k) * g.sz +
+                           (long long)(g.gy + j) * g.sy + g.gx;
     const double h = dt_dev ? *dt_dev : dt;
-    double L = 0.0;
-    if (Lx) L = (double)Lx[o];
-    if (Ly) L = L + (double)Ly[o];
-    if (Lz) L = L + (double)Lz[o];
-    if (Lv) L = L + Lv[o];
-    const double v = Uin[o] + h * L;
-    Uout[o] = a == 0.0 ? b * v : a * U0[o] + b * v;
+    for (int i = threadIdx.x; i < g.nx; i += blockDim.x) {
+        const long long o = base + i;
+        double L = 0.0;
+        if (Lx) L = (double)Lx[o];
+        if (Ly) L = L + (double)Ly[o];
+        if (Lz) L = L + (double)Lz[o];
+        if (Lv) L = L + Lv[o];
+        const double v = Uin[o] + h * L;
+        Uout[o] = a == 0.0 ? b * v : a * U0[o] + b * v;
+    }
 }
 
 // ---------------------------------------------------------------------------

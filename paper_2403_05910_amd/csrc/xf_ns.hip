@@ -110,13 +110,13 @@ hipError_t sweep_frozen(const LaunchCtx &c, int dir, int accumulate, const doubl
 hipError_t stage(const LaunchCtx &c, double *Uout, const double *U0, const double *Uin, const double *const L64[3],
                  const float *const L32[3], const double *Lv, double a, double b, double dt, const double *dt_dev,
                  hipStream_t s) {
-    const long long m = (long long)c.g.nx * c.g.ny * c.g.nz * (NS + 4);
+    const dim3 grid((unsigned)c.g.ny * c.g.nz, NS + 4), block(256);
     if (c.precision == XF_PREC_MIXED)
-        hipLaunchKernelGGL(k_stage_sum<float>, dim3(blocks_for(m, 256)), dim3(256), 0, s, Uout, U0, Uin, L32[0],
-                           L32[1], L32[2], Lv, c.g, NS + 4, a, b, dt, dt_dev);
+        hipLaunchKernelGGL(k_stage_sum<float>, grid, block, 0, s, Uout, U0, Uin, L32[0], L32[1], L32[2], Lv, c.g, a,
+                           b, dt, dt_dev);
     else
-        hipLaunchKernelGGL(k_stage_sum<double>, dim3(blocks_for(m, 256)), dim3(256), 0, s, Uout, U0, Uin, L64[0],
-                           L64[1], L64[2], Lv, c.g, NS + 4, a, b, dt, dt_dev);
+        hipLaunchKernelGGL(k_stage_sum<double>, grid, block, 0, s, Uout, U0, Uin, L64[0], L64[1], L64[2], Lv, c.g, a,
+                           b, dt, dt_dev);
     return hipGetLastError();
 }
 
