@@ -62,15 +62,28 @@ def _footprint(n, direction):
     return m[0] * m[1] * m[2]
 
 
-def sweep_bytes(ns, n, direction, first=True, precision="fp64"):
+def sweep_bytes(ns, n, direction, first=True, precision="fp64", fused_stage=False):
     """algorithmic bytes of one sweep launch: U (N + 4 fields) and the four
     primitives of every cell its stencils read, once (FP32 copies in the
     mixed path), and the residual of every interior cell written once (read
-    as well when accumulated)"""
+    as well when accumulated; FP32 differences in the mixed path).  With
+    fused_stage (the mixed x sweep of an RK3 step, which finishes the stage
+    itself) the residual is not written; instead every interior value reads
+    Uin, the other two directions' residuals and, in two of the three
+    stages, U0, and writes Uout (FP64 state)"""
     nv = ns + 4
     cells = n[0] * n[1] * n[2]
     word = 4 if precision == "mixed" else 8
-    return word * (nv + 4) * _footprint(n, direction) + (8 if first else 16) * nv * cells
+    stencil = word * (nv + 4) * _footprint(n, direction)
+    if fused_stage:
+        return stencil + nv * cells * (8 + 2 * word + 8 + 8 * 2 / 3)
+    return stencil + (word if first else 2 * word) * nv * cells
+
+
+def stage_flops(ns, n):
+    """the stage sum of Eq. 16 per interior value: three adds of the
+    residuals, h L + Uin, and a U0 + b v"""
+    return (ns + 4) * n[0] * n[1] * n[2] * 7
 
 
 def vjp_bytes_per_cell(ns):
