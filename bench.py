@@ -119,22 +119,23 @@ def profile_data():
     return data if data.get("source_hash") == kernel_source_hash() else None
 
 
-def measured_counters(kernel_class, precision):
+def measured_counters(kernel_class, precision, workload):
     """counters per launch of a kernel class from the committed summary
     (calibrated FETCH_SIZE + WRITE_SIZE bytes, VALU instructions, executed
-    flops); None when the summary is missing or the kernels changed since"""
+    flops); None when the summary is missing, was taken on another workload,
+    or the kernels changed since"""
     data = profile_data()
-    if data is None:
+    if data is None or data.get("workload") != workload:
         return None
     return data.get("traffic_bytes_per_launch", {}).get(precision, {}).get(kernel_class)
 
 
-def measured_traffic(kernel_class, precision):
-    row = measured_counters(kernel_class, precision)
+def measured_traffic(kernel_class, precision, workload):
+    row = measured_counters(kernel_class, precision, workload)
     return None if row is None else row["fetch"] + row["write"]
 
 
-def roofline_of(kernels, case, precision):
+def roofline_of(kernels, case, precision, workload):
     """dominant sweep kernel by total time; flops per launch from the
     algorithmic count; achieved = flops per launch / average launch time.
     The path's arithmetic intensity (about 49 flop per algorithmic byte at
@@ -152,7 +153,7 @@ def roofline_of(kernels, case, precision):
     flops = pm.sweep_flops(ns, case.n, sweeps[name]) + (pm.stage_flops(ns, case.n) if fused else 0)
     achieved = flops / avg_s / 1e12
     peak = pm.PEAK["fp32_vector_TFLOPs" if precision == "mixed" else "fp64_vector_TFLOPs"]
-    traffic = measured_traffic(name, precision)
+    traffic = measured_traffic(name, precision, workload)
     alg_bytes = pm.sweep_bytes(ns, case.n, sweeps[name], first=True, precision=precision, fused_stage=fused)
     out = {"kernel": name + (" (with the stage)" if fused else ""), "bound": "alu", "achieved": achieved,
            "peak": peak, "unit": "TFLOP/s",
@@ -162,7 +163,7 @@ def roofline_of(kernels, case, precision):
            "hbm_frac_algorithmic": alg_bytes / avg_s / 1e9 / pm.PEAK["hbm_GBs"]}
     if traffic is not None:
         out["hbm_frac_measured"] = traffic / avg_s / 1e9 / pm.PEAK["hbm_GBs"]
-    cnt = measured_counters(name, precision)
+    cnt = measured_counters(name, precision, workload)
     if cnt is not None:
         # what limits the kernel: neither roof is reached, so report the VALU
         # issue fraction (wave instructions x 4 cycles over the 1024 SIMDs'
@@ -345,7 +346,7 @@ def mixed_part(torch, xf, case, ctx64, U0, a, secs64):
                  "Y_abs": [errs(Yb[k], Ya[k], 1.0) for k in range(ns)]}
     out = {"value": vm, "unit": "cell-RHS evals/s", "ms_per_step": secs / a.steps * 1e3,
            "ms_per_step_median": median(ts) * 1e3, "speedup_vs_fp64": secs64 / secs,
-           "state_err_after_steps": state_err, "roofline": roofline_of(kern, case, "mixed"),
+           "state_err_after_steps": state_err, "roofline": roofline_of(kern, case, "mixed", "nine_species_sbi_256"),
            "kernel_avg_ms": kernels_ms(kern), "status_flags": ctxm.status()}
     return ctxm, out
 
@@ -481,7 +482,7 @@ def inert_part(torch, xf, case, a):
     out = {"workload": "inert_sbi_128", "grid": list(case.n), "species": case.thermo.ns,
            "rhs_ms_median": median(trhs) * 1e3, "rhs_value": case.cells / median(trhs),
            "steps": 20, "ms_per_step": secs / 20 * 1e3, "value": 3 * case.cells * 20 / secs,
-           "unit": "cell-RHS evals/s", "roofline": roofline_of(kern, case, "fp64"), "status_flags": ctx.status()}
+           "unit": "cell-RHS evals/s", "roofline": roofline_of(kern, case, "fp64", "inert_sbi_128"), "status_flags": ctx.status()}
     ctx.close()
     return out
 
@@ -500,7 +501,7 @@ def large_part(torch, xf, case, a):
         secs = block_time(torch, step, 32)
         kern = kernel_pass(torch, ctx, step, 2)
         out[prec] = {"steps": 32, "ms_per_step": secs / 32 * 1e3, "value": 3 * case.cells * 32 / secs,
-                     "unit": "cell-RHS evals/s", "roofline": roofline_of(kern, case, prec),
+                     "unit": "cell-RHS evals/s", "roofline": roofline_of(kern, case, prec, "two_bubble_sbi_512x256x256"),
                      "status_flags": ctx.status()}
         log(f"[bench] large {prec}: {secs / 32 * 1e3:.2f} ms/step")
         ctx.close()
@@ -617,7 +618,7 @@ def main():
     value = 3 * cells * a.steps / secs
     log(f"[bench] fp64: {secs / a.steps * 1e3:.2f} ms/step (median {median(ts) * 1e3:.2f}), "
         f"{value:.3e} cell-RHS/s, flags={flags}")
-    roof = roofline_of(kern, case, "fp64")
+    roof = roofline_of(kern, case, "fp64", "nine_species_sbi_256")
     out = {
         "metric": METRIC,
         "value": value,
