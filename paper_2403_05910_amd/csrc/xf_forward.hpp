@@ -165,10 +165,8 @@ __global__ __launch_bounds__(256) void k_stage_sum(double *Uout, const double *U
 // * the x sweeps run the species loops rolled (face_flux_to ROLL): FP64 at
 //   three waves per SIMD without spill (168 registers; 2.20 -> 2.00 ms per
 //   launch), FP32 1.74 -> 1.33 ms;
-// * the y/z tiles roll their species loops too; staged in LDS (TileShape),
-//   the FP64 tiles need 154 registers and 72 KB of LDS per block, which
-//   allows two blocks (two waves per SIMD) per CU, the FP32 ones 94
-//   registers and 36 KB (four waves);
+// * the y/z tiles roll their species loops too (their shapes, LDS and
+//   waves per SIMD are at TileShape);
 // * the positivity-blend instances stay at two waves (at three the FP64
 //   blended step went from 37.5 to 47.7 ms), the FP64 WENO7 instances at
 //   one (at two they spilled 324-460 bytes per lane; at one they keep their
@@ -188,6 +186,7 @@ template <typename R, int REC, bool X, bool PP>
 constexpr int sweep_waves() {
     if (sizeof(R) == 4) return X ? 4 : 1;
     if (REC == kReconWeno7) return 1;
+    if (!X && !PP && REC == kReconWeno5) return 3;     // the exchanging FP64 tiles (CU6 spills at three)
     return (X && !PP && REC == kReconWeno5) ? 3 : 2;   // the rolled CU6 x face spills ~100 bytes at three
 }
 
@@ -282,39 +281,55 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(sweep_w
 
 // ---------------------------------------------------------------------------
 // Tiled y/z sweep: one face per thread, like the x sweep.  A block is a tile
-// of TileShape<R>::x x-columns by TileShape<R>::s consecutive faces along
-// the sweep axis (in one plane of the third axis); tiles overlap by one face
+// of TileShape::x x-columns by TileShape::s consecutive faces along the
+// sweep axis (in one plane of the third axis); tiles overlap by one face
 // along the sweep axis, so each finishes s - 1 cells per column.  Lanes run
-// along x, so every stencil load of a wave reads whole rows (one 128-byte
-// line: 16 doubles or 32 floats).
-// Tiles that are neighbours along the sweep axis share six stencil rows and
-// are numbered to run on the same XCD.
+// along x, so the staging loads of a wave read whole row segments.  Tiles
+// that are neighbours along x or the sweep axis share stencil rows and are
+// numbered to run on the same XCD.
 // ---------------------------------------------------------------------------
-// Tile shape per arithmetic type, and whether the tile stages its stencils
-// in LDS (WENO5/CU6 without the positivity blend): the block copies U and
-// the primitives of its (s + 5) x x stencil cells once, in whole rows, and
-// every face reads its six stencil points from there (a face's stencil is
-// six rows apart in memory, so unstaged each wave issues twice the loads of
-// the x sweep, one per row and field).  Measured at 256^3, nine species:
-// FP64 16 x 16 staged 2.10/2.19 ms (y/z) against 2.92/3.01 unstaged; FP32
-// 16 x 16 staged 1.18/1.18 ms against 1.36/1.37 for 32 x 16 or 32 x 8
-// staged and 1.43/1.49 for 32 x 8 unstaged.
-template <typename R>
+// Tile shape per instance.  Every tile stages its stencils in LDS: the block
+// copies U and the primitives of its (s + 2 RAD - 1) x x stencil cells once,
+// in whole rows, and every face reads its stencil from there (a face's
+// stencil is six rows apart in memory, so unstaged each wave issues twice
+// the loads of the x sweep, one per row and field).  The FP64 WENO5 tile
+// without the blend is 8 x 32 and exchanges its fluxes across lanes instead
+// of holding them in LDS (46.9 KB per block: three blocks, three waves per
+// SIMD, in 146 registers); the other instances are 16 x 16 with the fluxes
+// in LDS (FP64: 72 KB, two waves; the CU6 and WENO7 faces need more than
+// the 168 registers of three waves; FP32: 36 KB, four waves).  Measured at
+// 256^3, nine species, y/z: FP64 WENO5 2.92/3.01 ms unstaged, 2.10/2.19
+// staged at 16 x 16, 1.92/1.97 exchanging at 8 x 32 (CU6 and WENO7 ran 5 %
+// slower at 8 x 32 than at 16 x 16); FP32 1.43/1.49 unstaged at 32 x 8,
+// 1.36/1.37 staged at 32 x 8 or 32 x 16, 1.15/1.16 staged at 16 x 16.
+template <typename R, int REC, bool PP>
 struct TileShape {
-    static constexpr int x = 16, s = 16;
-    static constexpr bool staged = true;
+    static constexpr bool exchange = sizeof(R) == 8 && REC == kReconWeno5 && !PP;
+    static constexpr int x = exchange ? 8 : 16, s = exchange ? 32 : 16;
 };
+
 template <int NS, typename R, int DIR, typename S, bool PP, int SPD, int REC>
-__global__ __launch_bounds__(TileShape<R>::x *TileShape<R>::s) __attribute__((amdgpu_waves_per_eu(sweep_waves<R, REC, false, PP>()))) void
+__global__ __launch_bounds__((TileShape<R, REC, PP>::x * TileShape<R, REC, PP>::s)) __attribute__((amdgpu_waves_per_eu(sweep_waves<R, REC, false, PP>()))) void
 k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, R *__restrict__ rhs, Geo g, ThermoK<R> th,
              int accumulate, StageArgs sa, unsigned *status, Dissip ds) {
     constexpr int NV = NS + 4;
-    constexpr int kTileX = TileShape<R>::x, kTileS = TileShape<R>::s;
+    using Shape = TileShape<R, REC, PP>;
+    constexpr int kTileX = Shape::x, kTileS = Shape::s;
     constexpr int RAD = stencil_radius(REC);
-    constexpr bool STAGE = TileShape<R>::staged;
+    constexpr bool STAGE = true;
     constexpr int kRows = kTileS + 2 * RAD - 1;        // stencil rows of the tile's faces
     constexpr int TSZ = kRows * kTileX;                // staged cells
-    __shared__ R sF[NV][kTileS][kTileX];
+    // EXCH: each flux component goes to the cell below as soon as it is
+    // final, the neighbouring face's value taken across lanes (the face
+    // below is kTileX lanes down in the same wave); only the first and last
+    // face rows of each wave pass theirs through LDS, for the cell between
+    // two waves.  Otherwise (the blend, which limits the whole flux vector
+    // at once) the fluxes wait in LDS for the block.
+    constexpr bool EXCH = Shape::exchange;
+    constexpr int RPW = 64 / kTileX;                   // face rows per wave
+    constexpr int NWV = kTileS / RPW;                  // waves per block
+    __shared__ R sF[EXCH ? 1 : NV][EXCH ? 1 : kTileS][EXCH ? 1 : kTileX];
+    __shared__ R sEdge[2][EXCH ? NWV : 1][EXCH ? NV : 1][EXCH ? kTileX : 1];
     __shared__ S xf_ftile[STAGE ? (NV + 4) * TSZ : 1];
     unsigned bx, by, bz;
     xcd_block(bx, by, bz);
@@ -351,6 +366,22 @@ k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, R *__restrict__ r
             ds.fidx = DIR == 1 ? x + (long long)g.nx * (j + (long long)(g.ny + 1) * bz)
                                : x + (long long)g.nx * (bz + (long long)g.ny * j);
         auto face = [&](const auto &st) {
+            if constexpr (EXCH) {
+                const R id = R((DIR == 1) ? g.idy : g.idz);
+                const int r = ts % RPW, w = ts / RPW;
+                const long long below = col + (long long)(gs + j - 1) * step;
+                face_flux_to<NS, R, DIR, SweepTune<R>::fence_face, SPD, REC, !PP, SweepTune<R>::roll_tile>(
+                    st, th,
+                    [&](int q, R v) {
+                        // face j - 1 of this column, valid wherever face j is
+                        const R vb = __shfl_up(v, kTileX);
+                        if (r > 0) put_result(rhs, q * g.cells + below, double((vb - v) * id), accumulate);
+                        if (r == RPW - 1) sEdge[0][w][q][tx] = v;
+                        if (r == 0) sEdge[1][w][q][tx] = v;
+                    },
+                    flags, ds);
+                return;
+            }
             face_flux_to<NS, R, DIR, SweepTune<R>::fence_face, SPD, REC, !PP, SweepTune<R>::roll_tile>(
                 st, th, [&](int q, R v) { sF[q][ts][tx] = v; }, flags, ds);
             if constexpr (PP) {
@@ -371,7 +402,18 @@ k_sweep_tile(const S *__restrict__ U, const S *__restrict__ P, R *__restrict__ r
         }
     }
     __syncthreads();
-    if (valid && ts > 0) {
+    if constexpr (EXCH) {
+        // the cell between the last face row of wave w - 1 and the first of w
+        const int r = ts % RPW, w = ts / RPW;
+        if (valid && r == 0 && w > 0) {
+            const R id = R((DIR == 1) ? g.idy : g.idz);
+            const long long cell = col + (long long)(gs + j - 1) * step;
+#pragma unroll
+            for (int q = 0; q < NV; ++q)
+                put_result(rhs, q * g.cells + cell, double((sEdge[0][w - 1][q][tx] - sEdge[1][w][q][tx]) * id),
+                           accumulate);
+        }
+    } else if (valid && ts > 0) {
         const R id = R((DIR == 1) ? g.idy : g.idz);
         const long long cell = col + (long long)(gs + j - 1) * step;
 #pragma unroll

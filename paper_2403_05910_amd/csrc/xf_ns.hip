@@ -36,7 +36,7 @@ hipError_t launch_face_sweep(const LaunchCtx &c, const ThermoK<R> &th, int dir, 
     }
     const int ntr = dir == 1 ? g.nz : g.ny;
     const int nsw = dir == 1 ? g.ny : g.nz;
-    constexpr int TX = TileShape<R>::x, TS = TileShape<R>::s;
+    constexpr int TX = TileShape<R, REC, PP>::x, TS = TileShape<R, REC, PP>::s;
     const unsigned tiles = (unsigned)((nsw + TS - 2) / (TS - 1));
     dim3 grid((g.nx + TX - 1) / TX, tiles, ntr), block(TX, TS);
     if (dir == 1)
