@@ -65,6 +65,24 @@ __global__ __launch_bounds__(256) void k_fill(T *U, Geo g, int nv, int d) {
     }
 }
 
+// The x ghosts, one thread per ghost cell: a row's 2 ng ghost cells are
+// consecutive lanes, so one instruction touches each row's two ends once
+// (the per-row form of k_fill touches a different row in every lane).  The
+// sources are interior cells, so the copies are independent.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill_x(T *U, Geo g, int nv) {
+    const int ng = g.gx, w = 2 * ng;
+    const long long rows = (long long)g.py * g.pz;
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= rows * w * nv) return;
+    const int k = (int)(q % w);
+    const long long r = q / w;
+    const long long o = r % rows, f = r / rows;
+    const int sd = k / ng, l = k - sd * ng;
+    T *u = U + f * g.cells + (o / g.py) * g.sz + (o % g.py) * g.sy;
+    u[ghost_dst(sd, l, g.nx, ng)] = u[ghost_src(g.bc[sd], sd, l, g.nx, ng)];
+}
+
 // Adjoint of k_fill: every ghost cotangent is added to its source and zeroed,
 // in the reverse order of the forward copies.
 __global__ __launch_bounds__(256) void k_fill_vjp(double *Ub, Geo g, int nv, int d) {
@@ -215,7 +233,10 @@ hipError_t fill_ghosts_t(const LaunchCtx &c, int nv, T *U, hipStream_t s) {
     for (int d = 0; d < 3; ++d) {
         if (n[d] <= 1) continue;
         const long long no = d == 0 ? (long long)g.py * g.pz : (d == 1 ? (long long)g.px * g.pz : (long long)g.px * g.py);
-        hipLaunchKernelGGL(k_fill<T>, dim3(blocks_for(no * nv, 256)), dim3(256), 0, s, U, g, nv, d);
+        if (d == 0 && g.gx > 0)
+            hipLaunchKernelGGL(k_fill_x<T>, dim3(blocks_for(no * 2 * g.gx * nv, 256)), dim3(256), 0, s, U, g, nv);
+        else
+            hipLaunchKernelGGL(k_fill<T>, dim3(blocks_for(no * nv, 256)), dim3(256), 0, s, U, g, nv, d);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
