@@ -187,7 +187,7 @@ def adjoint_roofline(kv, case, precision):
     name = max(dirs, key=lambda k: kv[k][0])
     ms, launches = kv[name]
     d = dirs[name]
-    per_dir_s = ms / launches / 1e3   # one 'launch' of the timing table = the direction's six launch groups
+    per_dir_s = ms / launches / 1e3   # one 'launch' of the timing table = the direction's launch groups
     flops = pm.vjp_sweep_flops(ns, case.n, d, precision)
     peak = pm.PEAK["fp32_vector_TFLOPs" if precision == "mixed" else "fp64_vector_TFLOPs"]
     alg = pm.vjp_sweep_bytes(ns, case.n, d)

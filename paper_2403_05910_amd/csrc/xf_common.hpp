@@ -198,8 +198,8 @@ inline long long face_count(const Geo &g, int d) {
 }
 
 // Launch geometry of the face VJP in x: waves of 64 consecutive faces in
-// one z-plane, launch groups of every sixth wave, blocks of up to 4 waves.
-constexpr int kVjpGroups = 6;
+// one z-plane, launch groups of every second wave, blocks of up to 4 waves.
+constexpr int kVjpGroups = 2;
 inline long long vjp_x_waves_per_plane(const Geo &g) { return ((long long)(g.nx + 1) * g.ny + 63) / 64; }
 
 // Species-independent launches (xf_misc.hip).

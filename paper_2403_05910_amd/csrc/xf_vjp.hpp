@@ -649,7 +649,7 @@ constexpr bool vjp_staged() { return sizeof(R) == 8; }
 // cells, and the window accesses keep program order, so no atomics are
 // needed.  The window is then added to Ubar / Pbar with coalesced
 // read-modify-writes.  Runs of waves w and w + 1 can share up to five cells,
-// those of w and w + 2 cannot; launch `grp` takes the waves w = grp mod 6.
+// those of w and w + 2 cannot; launch `grp` takes the waves w = grp mod 2.
 // Staged (FP64): the wave first copies the run's U and primitives into a
 // second private LDS area of (NV + 4) W values.
 // ---------------------------------------------------------------------------
@@ -665,7 +665,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(vjp_waves<R
     const long long rowf = (long long)g.nx + 1;          // faces per row
     const long long nfp = rowf * g.ny;                   // faces per plane
     const long long wpp = (nfp + 63) / 64;               // waves per plane
-    const long long wid = 6 * ((long long)blockIdx.x * wpb + wv) + grp;
+    const long long wid = kVjpGroups * ((long long)blockIdx.x * wpb + wv) + grp;
     const long long C = g.cells;
     const long long zb = (long long)(g.gz + blockIdx.y) * g.sz + (long long)g.gy * g.sy;   // plane's first row
     double *w = xf_win + (size_t)wv * (NW + NT) * W;
@@ -733,8 +733,8 @@ constexpr size_t vjp_x_lds_per_wave(int W) {
 // one instruction its lanes address distinct cells); the block then adds,
 // for each of its 21 x 16 cells, the windows that cover it in wave order to
 // Ubar / Pbar (one coalesced read-modify-write per cell and field).  Blocks
-// b and b + 1 share six rows, blocks b and b + 6 none: launch `phase` takes
-// the blocks b = phase mod 6.  Staged (FP64): the block first copies the
+// b and b + 1 share five rows, blocks b and b + 2 none: launch `phase` takes
+// the blocks b = phase mod 2.  Staged (FP64): the block first copies the
 // U and primitives of its 21 x 16 cells into LDS.
 // ---------------------------------------------------------------------------
 constexpr int kVjpTX = 16, kVjpFB = 16, kVjpWin = kVjpTX * 9, kVjpRows = kVjpFB + 5;
