@@ -170,9 +170,9 @@ hipError_t launch_vjp_group(const LaunchCtx &c, const ThermoK<R> &th, int dir, i
     } else {
         const int nsw = dir == 1 ? g.ny : g.nz;
         const int xt = (g.nx + kVjpTX - 1) / kVjpTX;
-        const int nfb = (nsw + 1 + kVjpFB - 1) / kVjpFB;
+        const int nfb = (nsw + 1 + vjp_yz_faces<R>() - 1) / vjp_yz_faces<R>();
         const int nb = (nfb - grp + kVjpGroups - 1) / kVjpGroups;
-        dim3 grid((unsigned)(xt * nb), dir == 1 ? g.nz : g.ny), block(256);
+        dim3 grid((unsigned)(xt * nb), dir == 1 ? g.nz : g.ny), block(64 * vjp_yz_waves<R>());
         if (dir == 1)
             hipLaunchKernelGGL((k_face_vjp_yz<NS, R, 1, CU6>), grid, block, 0, s, U, P, rbar, Ubar, Pbar, g, th, grp,
                                ds);
@@ -192,7 +192,7 @@ hipError_t sweep_vjp_t(const LaunchCtx &c, const ThermoK<R> &th, int dir, const 
                        const double *rbar, double *Ubar, double *Pbar, const Dissip &ds, hipStream_t s) {
     const Geo &g = c.g;
     const int nsw = dir == 1 ? g.ny : g.nz;
-    const long long ngrp = dir == 0 ? vjp_x_waves_per_plane(g) : (nsw + 1 + kVjpFB - 1) / kVjpFB;
+    const long long ngrp = dir == 0 ? vjp_x_waves_per_plane(g) : (nsw + 1 + vjp_yz_faces<R>() - 1) / vjp_yz_faces<R>();
     for (int grp = 0; grp < kVjpGroups && grp < ngrp; ++grp) {
         const hipError_t e = ds.recon == kReconCu6
                                  ? launch_vjp_group<R, true>(c, th, dir, grp, U, P, rbar, Ubar, Pbar, ds, s)

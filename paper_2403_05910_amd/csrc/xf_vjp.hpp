@@ -725,29 +725,43 @@ constexpr size_t vjp_x_lds_per_wave(int W) {
 }
 
 // ---------------------------------------------------------------------------
-// y and z directions, blocked: a block takes 16 x-columns by 16 consecutive
-// faces j0..j0+15 of the sweep axis (j0 = 16 b) in one plane of the third
-// axis; wave w of the block takes faces j0+4w..j0+4w+3 (lane = 16 ts + tx),
-// so each stencil load of a wave reads four whole 128-byte rows.  Wave w
-// accumulates in a private LDS window of sweep rows j0+4w-3..j0+4w+5 (within
-// one instruction its lanes address distinct cells); the block then adds,
-// for each of its 21 x 16 cells, the windows that cover it in wave order to
-// Ubar / Pbar (one coalesced read-modify-write per cell and field).  Blocks
-// b and b + 1 share five rows, blocks b and b + 2 none: launch `phase` takes
-// the blocks b = phase mod 2.  Staged (FP64): the block first copies the
-// U and primitives of its 21 x 16 cells into LDS.
+// y and z directions, blocked: a block of WY waves takes 16 x-columns by
+// F = 4 WY consecutive faces j0..j0+F-1 of the sweep axis (j0 = F b) in one
+// plane of the third axis; wave w of the block takes faces j0+4w..j0+4w+3
+// (lane = 16 ts + tx), so each stencil load of a wave reads four whole
+// 128-byte rows.  Wave w accumulates in a private LDS window of sweep rows
+// j0+4w-3..j0+4w+5 (within one instruction its lanes address distinct
+// cells); the block then adds, for each of its (F + 5) x 16 cells, the
+// windows that cover it in wave order to Ubar / Pbar (one coalesced
+// read-modify-write per cell and field).  Blocks b and b + 1 share five
+// rows, blocks b and b + 2 none: launch `phase` takes the blocks
+// b = phase mod 2.  Staged (FP64): the block first copies the U and
+// primitives of its (F + 5) x 16 cells into LDS.
 // ---------------------------------------------------------------------------
-constexpr int kVjpTX = 16, kVjpFB = 16, kVjpWin = kVjpTX * 9, kVjpRows = kVjpFB + 5;
+constexpr int kVjpTX = 16, kVjpWin = kVjpTX * 9;
+// Waves per y/z block (four faces each): two in FP64, so that two blocks of
+// 65 KB share a CU and one block's staging and window merge overlap the
+// other's faces (RHS VJP at 256^3, nine species, 45.6 -> 44.8 ms against
+// four-wave blocks of 119 KB, one per CU); four in FP32, whose blocks hold
+// no staged tile (there two-wave blocks measured 35.3 -> 36.2 ms).  Blocks
+// of at least five faces keep next-but-one neighbours disjoint (two launch
+// groups).
+template <typename R>
+constexpr int vjp_yz_waves() { return sizeof(R) == 8 ? 2 : 4; }
+template <typename R>
+constexpr int vjp_yz_faces() { return 4 * vjp_yz_waves<R>(); }
+static_assert(vjp_yz_faces<double>() >= 5 && vjp_yz_faces<float>() >= 5, "windows of blocks b and b + 2 must not meet");
 
 template <int NS, typename R, int DIR, bool CU6>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(vjp_waves<R>()))) void k_face_vjp_yz(
+__global__ __launch_bounds__(64 * vjp_yz_waves<R>()) __attribute__((amdgpu_waves_per_eu(vjp_waves<R>()))) void k_face_vjp_yz(
     const double *__restrict__ U, const double *__restrict__ P, const double *__restrict__ rbar,
     double *__restrict__ Ubar, double *__restrict__ Pbar, Geo g, ThermoK<R> th, int phase, Dissip ds) {
     constexpr int NV = NS + 4;
     constexpr int NW = NV + kSinkExtra;                    // window rows
     constexpr int NT = vjp_staged<R>() ? NV + 4 : 0;       // staged rows
+    constexpr int WY = vjp_yz_waves<R>(), kVjpFB = vjp_yz_faces<R>(), kVjpRows = kVjpFB + 5;
     constexpr int TS = kVjpRows * kVjpTX;                  // staged cells
-    __shared__ double xf_wyz[4][NW * kVjpWin];
+    __shared__ double xf_wyz[WY][NW * kVjpWin];
     __shared__ double xf_tile[NT > 0 ? NT * TS : 1];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int tx = lane & (kVjpTX - 1), ts = lane / kVjpTX;
@@ -769,7 +783,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(vjp_waves<R
     for (int i = lane; i < NW * kVjpWin; i += 64) w[i] = 0.0;
     if constexpr (NT > 0) {
         // tile row r = sweep row j0 - 3 + r; cells past the padded extent are never read
-        for (int e = threadIdx.x; e < TS; e += 256) {
+        for (int e = threadIdx.x; e < TS; e += 64 * WY) {
             const int r = e / kVjpTX, cx = xi * kVjpTX + (e % kVjpTX);
             if (cx >= g.nx || j0 - 3 + r > nsw + 2) continue;
             const long long cell = col0 + cx + (long long)(j0 - 3 + r) * ss;
@@ -802,11 +816,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(vjp_waves<R
     }
     __syncthreads();
     // block rows r = 0..20 (sweep rows j0-3 .. j0+17); wave w covers r in [4w, 4w+9)
-    for (int c = threadIdx.x; c < kVjpTX * kVjpRows; c += 256) {
+    for (int c = threadIdx.x; c < kVjpTX * kVjpRows; c += 64 * WY) {
         const int r = c / kVjpTX, cx = xi * kVjpTX + (c % kVjpTX);
         const int row = j0 - 3 + r;                       // interior index along the sweep axis
         if (cx >= g.nx || row > nsw + 2) continue;
-        const int wlo = r >= 8 ? (r - 8 + 3) / 4 : 0, whi = min(3, r / 4);
+        const int wlo = r >= 8 ? (r - 8 + 3) / 4 : 0, whi = min(WY - 1, r / 4);
         const long long cell = col0 + cx + (long long)row * ss;
 #pragma unroll
         for (int q = 0; q < NW; ++q) {
