@@ -14,38 +14,37 @@ namespace xf {
 // ---------------------------------------------------------------------------
 // primitive variables and Newton temperature (always FP64)
 // ---------------------------------------------------------------------------
-template <int NS>
-XF_HD void mix_e_cv(const ThermoK<double> &th, const double *Y, double T, double &e,
-                                         double &cv) {
-    e = 0.0;
-    cv = 0.0;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        e += Y[s] * e_species(th, s, T);
-        cv += Y[s] * cv_species(th, s, T);
+// The mixture's internal energy and C_v at fixed Y as polynomials in T:
+// e(T) = sum_k E_k T^k (k = 0..5), C_v(T) = sum_k C_k T^k (k = 0..4), the
+// species tables weighted by Y once per solve, so that a Newton iteration
+// costs two Horner evaluations instead of one per species.
+struct MixPoly {
+    double E[6], C[5];
+    __device__ __forceinline__ double e(double T) const {
+        return ((((E[5] * T + E[4]) * T + E[3]) * T + E[2]) * T + E[1]) * T + E[0];
     }
-}
+    __device__ __forceinline__ double cv(double T) const {
+        return (((C[4] * T + C[3]) * T + C[2]) * T + C[1]) * T + C[0];
+    }
+};
 
-// Newton on e(T) = e (Eq. 21): T <- T + (e - e(T)) / C_v(T).  Cold start
-// T0 = e / C_v(T_ref) clamped into the bracket; with a bracket, every
-// evaluation narrows [lo, hi] (e(T) > e: hi = T, else lo = T) and a step that
-// leaves the closed bracket is replaced by bisection.  Stop when
-// |dT| <= 1e-11 |T|, then one more Newton update.  Returns false if not
-// converged in 50 iterations.
-template <int NS>
-XF_HD bool newton_T(const ThermoK<double> &th, const double *Y, double e, double &T) {
-    double ee, cv;
-    double cv0 = 0.0;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) cv0 += Y[s] * cv_species(th, s, th.T_ref);
-    T = e / cv0;
-    double lo = th.T_lo, hi = th.T_hi;
-    if (th.bracket) T = T < th.T_lo ? th.T_lo : (T > th.T_hi ? th.T_hi : T);
+// Newton on e(T) = e (Eq. 21) with the mixture polynomials m:
+// T <- T + (e - e(T)) / C_v(T) from the start T clamped into the bracket
+// [T_lo, T_hi] where there is one; every evaluation narrows the bracket
+// (e(T) > e: hi = T, else lo = T) and a step that leaves the closed bracket
+// is replaced by bisection.  Stop when |dT| <= 1e-11 |T|, then one more
+// Newton update.  Returns false if not converged in 50 iterations.  The
+// primitive pass starts from the cold start e / C_v(T_ref); the reaction
+// step from the cell's previous temperature (the root does not depend on
+// the start).
+__device__ __forceinline__ bool newton_poly(bool bracket, double T_lo, double T_hi, const MixPoly &m, double e,
+                                            double &T) {
+    double lo = T_lo, hi = T_hi;
+    if (bracket) T = T < lo ? lo : (T > hi ? hi : T);
     for (int it = 0; it < kNewtonMaxIt; ++it) {
-        mix_e_cv<NS>(th, Y, T, ee, cv);
-        const double f = ee - e;
-        double Tn = T - f / cv;
-        if (th.bracket) {
+        const double f = m.e(T) - e;
+        double Tn = T - f / m.cv(T);
+        if (bracket) {
             if (f > 0.0)
                 hi = fmin(hi, T);
             else
@@ -55,12 +54,78 @@ XF_HD bool newton_T(const ThermoK<double> &th, const double *Y, double e, double
         const bool conv = fabs(Tn - T) <= kNewtonTol * fabs(T);
         T = Tn;
         if (conv) {
-            mix_e_cv<NS>(th, Y, T, ee, cv);
-            T = T - (ee - e) / cv;
+            T = T - (m.e(T) - e) / m.cv(T);
             return true;
         }
     }
     return false;
+}
+
+// The fold of the species tables with Y (the table at hand, by value or
+// in kernel arguments).
+template <int NS>
+__device__ __forceinline__ void mix_poly_of(const ThermoK<double> &th, const double *Y, MixPoly &m) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) m.E[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) m.C[k] = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) m.E[k] += Y[s] * th.e[s][k];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) m.C[k] += Y[s] * th.cv[s][k];
+    }
+}
+
+// The primitive variables of one cell from its conserved values u(f)
+// (f = 0..N+3): T by Newton (Eq. 21) on the mixture polynomials,
+// p = rho Rbar T, c^2 = (1 + Rbar / C_v) Rbar T, 1/rho; returns the cell's
+// status flags.
+template <int NS, class Get>
+__device__ __forceinline__ unsigned cell_prims(const Get &u, const ThermoK<double> &th, double &T, double &p,
+                                               double &c, double &rinv) {
+    double Y[NS];
+    double rho = 0.0;
+    bool finite = true;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        Y[s] = u(s);
+        rho += Y[s];
+        finite = finite && isfinite(Y[s]);
+    }
+    rinv = 1.0 / rho;
+    unsigned flags = 0;
+    bool yneg = false;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        Y[s] *= rinv;
+        yneg = yneg || (Y[s] < -1e-12);
+    }
+    const double mx = u(NS), my = u(NS + 1), mz = u(NS + 2);
+    const double E = u(NS + 3);
+    finite = finite && isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(E);
+    const double uu = mx * rinv, v = my * rinv, w = mz * rinv;
+    const double e = E * rinv - 0.5 * (uu * uu + v * v + w * w);
+    // Newton on the mixture's folded polynomials from the cold start
+    // e / C_v(T_ref)
+    MixPoly m;
+    mix_poly_of<NS>(th, Y, m);
+    T = e / m.cv(th.T_ref);
+    const bool conv = newton_poly(th.bracket, th.T_lo, th.T_hi, m, e, T);
+    double Rb = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) Rb += Y[s] * th.Rs[s];
+    const double cv = m.cv(T);
+    p = rho * Rb * T;
+    c = sqrt((1.0 + Rb / cv) * Rb * T);
+    if (rho <= 0.0) flags |= XF_FLAG_RHO;
+    if (yneg) flags |= XF_FLAG_Y;
+    if (p <= 0.0 || T <= 0.0) flags |= XF_FLAG_P;
+    if (th.bracket && (T < th.T_lo || T > th.T_hi)) flags |= XF_FLAG_TRANGE;
+    if (!conv) flags |= XF_FLAG_NEWTON;
+    if (!finite || !isfinite(T) || !isfinite(c)) flags |= XF_FLAG_NAN;
+    return flags;
 }
 
 // P[0..3][cell] = (T, p, c, 1/rho) for every cell with at most one
@@ -81,44 +146,8 @@ __global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, dou
                    (z < g.gz || z >= g.gz + g.nz);
     if (ng > 1 && !all_cells) return;   // edge and corner ghosts: outside every stencil
     const long long C = g.cells;
-    double Y[NS];
-    double rho = 0.0;
-    bool finite = true;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        Y[s] = U[s * C + idx];
-        rho += Y[s];
-        finite = finite && isfinite(Y[s]);
-    }
-    const double rinv = 1.0 / rho;
-    unsigned flags = 0;
-    bool yneg = false;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        Y[s] *= rinv;
-        yneg = yneg || (Y[s] < -1e-12);
-    }
-    const double mx = U[NS * C + idx], my = U[(NS + 1) * C + idx], mz = U[(NS + 2) * C + idx];
-    const double E = U[(NS + 3) * C + idx];
-    finite = finite && isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(E);
-    const double u = mx * rinv, v = my * rinv, w = mz * rinv;
-    const double e = E * rinv - 0.5 * (u * u + v * v + w * w);
-    double T;
-    const bool conv = newton_T<NS>(th, Y, e, T);
-    double Rb = 0.0, cv = 0.0;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        Rb += Y[s] * th.Rs[s];
-        cv += Y[s] * cv_species(th, s, T);
-    }
-    const double p = rho * Rb * T;
-    const double c = sqrt((1.0 + Rb / cv) * Rb * T);
-    if (rho <= 0.0) flags |= XF_FLAG_RHO;
-    if (yneg) flags |= XF_FLAG_Y;
-    if (p <= 0.0 || T <= 0.0) flags |= XF_FLAG_P;
-    if (th.bracket && (T < th.T_lo || T > th.T_hi)) flags |= XF_FLAG_TRANGE;
-    if (!conv) flags |= XF_FLAG_NEWTON;
-    if (!finite || !isfinite(T) || !isfinite(c)) flags |= XF_FLAG_NAN;
+    double T, p, c, rinv;
+    const unsigned flags = cell_prims<NS>([&](int f) { return U[f * C + idx]; }, th, T, p, c, rinv);
     P[idx] = T;
     P[C + idx] = p;
     P[2 * C + idx] = c;

@@ -93,20 +93,6 @@ __device__ __forceinline__ double qss_alpha(double r) {
     return 1.0 / (-rx_expm1(-r, exp_table())) - 1.0 / r;
 }
 
-// The mixture's internal energy and C_v at fixed Y as polynomials in T:
-// e(T) = sum_k E_k T^k (k = 0..5), C_v(T) = sum_k C_k T^k (k = 0..4), the
-// species tables weighted by Y once per solve, so that a Newton iteration
-// costs two Horner evaluations instead of one per species.
-struct MixPoly {
-    double E[6], C[5];
-    __device__ __forceinline__ double e(double T) const {
-        return ((((E[5] * T + E[4]) * T + E[3]) * T + E[2]) * T + E[1]) * T + E[0];
-    }
-    __device__ __forceinline__ double cv(double T) const {
-        return (((C[4] * T + C[3]) * T + C[2]) * T + C[1]) * T + C[0];
-    }
-};
-
 // The table pointer is laundered on every call, so that the table comes in
 // where it is used instead of being held in scalar registers across the
 // sub-steps, where it would crowd out everything else.
@@ -126,34 +112,6 @@ __device__ __forceinline__ void mix_poly(cptr<ThermoK<double>> thp, const double
 #pragma unroll
         for (int k = 0; k < 5; ++k) m.C[k] += Y[s] * th.cv[s][k];
     }
-}
-
-// Newton on e(T) = e (Eq. 21) from the start T (clamped into the bracket
-// where there is one): the bracket, the stop rule |dT| <= 1e-11 |T| and the
-// final update are those of newton_T; only the start differs, and the root
-// it converges to does not depend on it.
-__device__ __forceinline__ bool newton_poly(bool bracket, double T_lo, double T_hi, const MixPoly &m, double e,
-                                            double &T) {
-    double lo = T_lo, hi = T_hi;
-    if (bracket) T = T < lo ? lo : (T > hi ? hi : T);
-    for (int it = 0; it < kNewtonMaxIt; ++it) {
-        const double f = m.e(T) - e;
-        double Tn = T - f / m.cv(T);
-        if (bracket) {
-            if (f > 0.0)
-                hi = fmin(hi, T);
-            else
-                lo = fmax(lo, T);
-            if (Tn < lo || Tn > hi) Tn = 0.5 * (lo + hi);
-        }
-        const bool conv = fabs(Tn - T) <= kNewtonTol * fabs(T);
-        T = Tn;
-        if (conv) {
-            T = T - (m.e(T) - e) / m.cv(T);
-            return true;
-        }
-    }
-    return false;
 }
 
 // production q_s and loss rate p_s (1/s) at (rho, Y, T); the species' Gibbs
