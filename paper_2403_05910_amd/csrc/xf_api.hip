@@ -266,10 +266,12 @@ const double *glf_of(const xf_ctx *c, const unsigned long long *mx, int d) {
     return c->lc.visc == XF_VISC_GLF ? reinterpret_cast<const double *>(mx + 1 + 3 * d) : nullptr;
 }
 
-hipError_t prims(xf_ctx *c, const double *U, const Prim &pb, hipStream_t s) {
+// p64 = false: the FP64 primitives are not needed (the FP32 copies are)
+hipError_t prims(xf_ctx *c, const double *U, const Prim &pb, hipStream_t s, bool p64 = true) {
     // viscous contexts: every padded cell (the tangential derivatives read edge ghosts)
-    hipError_t e = timed(c, XF_K_PRIMS, s,
-                         [&] { return c->ops->prims(c->lc, U, pb.P, pb.Uf, pb.Pf, c->viscous ? 1 : 0, s); });
+    hipError_t e = timed(c, XF_K_PRIMS, s, [&] {
+        return c->ops->prims(c->lc, U, p64 ? pb.P : nullptr, pb.Uf, pb.Pf, c->viscous ? 1 : 0, s);
+    });
     if (e == hipSuccess) e = glf_speeds(c, U, pb.P, pb.mx, s);
     return e;
 }
@@ -709,9 +711,12 @@ int flow_rk3_step(xf_ctx *c, double *U, double dt, const double *dt_in, double c
     double *out[3] = {S1, S2, U};
     const double a[3] = {0.0, 0.75, 1.0 / 3.0};
     const double b[3] = {1.0, 0.25, 2.0 / 3.0};
+    // a mixed step without viscous terms or GLF reads the FP64 primitives
+    // only for its step size (stage 1); later stages need the FP32 copies
+    const bool p64_later = !mixed || c->viscous || lc.visc == XF_VISC_GLF;
     for (int k = 0; k < 3; ++k) {
         XF_TRY(fill(c, in[k], s));
-        XF_TRY(prims(c, in[k], pb, s));
+        XF_TRY(prims(c, in[k], pb, s, k == 0 || p64_later));
         if (k == 0 && cfl > 0.0) {
             XF_TRY(timed(c, XF_K_CFL, s, [&] {
                 hipError_t e = xf::launch_cfl_reset(mx, s);

@@ -131,7 +131,8 @@ __device__ __forceinline__ unsigned cell_prims(const Get &u, const ThermoK<doubl
 // P[0..3][cell] = (T, p, c, 1/rho) for every cell with at most one
 // coordinate in a ghost layer (the cells axis-aligned stencils read).
 // Uf, Pf (optional): FP32 copies of U and of (T, p, c, 1/rho) for the
-// mixed-precision sweeps, written for the same cells.
+// mixed-precision sweeps, written for the same cells; P may be null when
+// only they are needed.
 template <int NS>
 __global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, double *__restrict__ P, Geo g,
                                                ThermoK<double> th, unsigned *status, float *__restrict__ Uf,
@@ -148,10 +149,12 @@ __global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, dou
     const long long C = g.cells;
     double T, p, c, rinv;
     const unsigned flags = cell_prims<NS>([&](int f) { return U[f * C + idx]; }, th, T, p, c, rinv);
-    P[idx] = T;
-    P[C + idx] = p;
-    P[2 * C + idx] = c;
-    P[3 * C + idx] = rinv;
+    if (P) {
+        P[idx] = T;
+        P[C + idx] = p;
+        P[2 * C + idx] = c;
+        P[3 * C + idx] = rinv;
+    }
     if (Uf) {
 #pragma unroll
         for (int f = 0; f < NS + 4; ++f) Uf[f * C + idx] = (float)U[f * C + idx];
