@@ -48,6 +48,57 @@ def reacting_case(name):
     return case, W.synthetic_mechanism([2.0, 1.0, 28.0], tab, 2, 4)
 
 
+def higher_order_case():
+    """four species of molar masses 1, 2, 3 and 4 g/mol and reactions with
+    two and three molecules of one species on a side: 3 A = C, 2 B = D (with
+    a third body), A + C = D and 2 A + B = D, all reversible; rate constants
+    of 10^2..10^4 SI units at 2000 K and entropy constants chosen as in the
+    synthetic mechanism (S/R - h/(R T) within +-2 at 2000 K)"""
+    Wg = [1.0, 2.0, 3.0, 4.0]
+    tab = W.with_formation_enthalpies(W.sampled_table(Wg, 5), 4)
+    case = W.random_smooth_state(tab, (11, 9, 7), seed=8, T0=2000.0)
+    nu_f = np.array([[3, 0, 0, 0], [0, 2, 0, 0], [1, 0, 1, 0], [2, 1, 0, 0]])
+    nu_b = np.array([[0, 0, 1, 0], [0, 0, 0, 1], [0, 0, 0, 1], [0, 0, 0, 1]])
+    rng = np.random.default_rng(9)
+    nr, ns, T_ref = 4, 4, 2000.0
+    k_ref = 10.0 ** rng.uniform(2.0, 4.0, nr)
+    B = rng.uniform(-1.0, 1.5, nr)
+    E = rng.uniform(0.0, 1.5e5, nr)
+    A = k_ref / (T_ref ** B * np.exp(-E / (W.R_UNIVERSAL * T_ref)))
+    third = np.array([False, True, False, False])
+    eff = rng.uniform(0.5, 3.0, (nr, ns))
+    a = np.asarray(tab.a)
+    T = T_ref
+    s_var = a[:, 0] * np.log(T) + a[:, 1] * T + a[:, 2] * T ** 2 / 2 + a[:, 3] * T ** 3 / 3 + a[:, 4] * T ** 4 / 4
+    h_RT = (a[:, 0] * T + a[:, 1] * T ** 2 / 2 + a[:, 2] * T ** 3 / 3 + a[:, 3] * T ** 4 / 4
+            + a[:, 4] * T ** 5 / 5 + a[:, 5]) / T
+    s0 = rng.uniform(-2.0, 2.0, ns) + h_RT - s_var
+    return case, W.MechanismTable(nu_f, nu_b, A, B, E, third, eff, np.ones(nr, dtype=bool), s0)
+
+
+@pytest.mark.parametrize("dt,n_sub", [(1e-6, 8), (1e-7, 1)])
+def test_higher_order_reactions_match_oracle(dt, n_sub):
+    """concentration products with a species two and three times on a side
+    (the molecule lists of the kernel) against the oracle's powers"""
+    xf = _xf()
+    case, mt = higher_order_case()
+    th, g = oracle_objects(case)
+    U0 = O.fill_ghosts(g, case.U)
+    ref = O.fill_ghosts(g, R.react(th, _omech(mt), g, U0, dt, n_sub))
+    ctx = xf.Context.from_case(case).set_reactions(mt, n_sub)
+    U = ctx.state_from_numpy(U0)
+    ctx.react(U, dt)
+    flags = ctx.status()
+    got = U.cpu().numpy()
+    ctx.close()
+    change = np.abs(ref[:th.ns] - U0[:th.ns]).max() / np.abs(U0[:th.ns]).max()
+    err = _state_err(got, ref)
+    print(f"[react] higher-order dt={dt:g} n_sub={n_sub} change {change:.2e} max err {err.max():.3e}", flush=True)
+    assert flags == 0
+    assert change > 1e-6
+    assert err.max() <= TOL, err
+
+
 def _state_err(U_gpu, U_ora):
     scale = np.abs(U_ora).reshape(U_ora.shape[0], -1).max(axis=1)
     return field_err(U_gpu, U_ora, scale)
