@@ -105,10 +105,10 @@ def vjp_sweep_bytes(ns, n, direction):
 # then the backward), counted with rocprofv3's per-type VALU counters on one
 # launch group of each direction at 256^3, nine species: 64 x (adds +
 # multiplies + transcendentals + 2 x fused multiply-adds) of the arithmetic
-# type over the group's faces (profiles/vjp_nine_species_sbi_256.md).  The
-# y/z kernels execute about 7 % more than the x kernel.  Measured at nine
-# species only: other species counts return None.
-VJP_FACE_OPS = {("fp64", 9): (10180, 10880, 10880), ("mixed", 9): (10363, 11030, 11030)}
+# type over the group's faces (profiles/vjp_nine_species_sbi_256.md; the
+# y/z figure from the group whose grid holds no idle threads).  Measured at
+# nine species only: other species counts return None.
+VJP_FACE_OPS = {("fp64", 9): (10178, 10226, 10226), ("mixed", 9): (10324, 10360, 10360)}
 
 # Operations per face of the forward sweeps as executed, counted the same way
 # (x sweep, nine species): FP64 3985, FP32 4155 -- about 19 % above the
