@@ -241,72 +241,156 @@ __device__ __forceinline__ void put_result(OT *__restrict__ rhs, long long o, do
 // ---------------------------------------------------------------------------
 // x sweep: faces linearised over interior rows (face i of row r = the face
 // between interior cells i-1 and i, i = 0..nx).  A block of 256 threads takes
-// 256 consecutive faces and blocks overlap by one face, so every cell whose
-// two faces lie in a block gets (F^_{i-1/2} - F^_{i+1/2}) / dx there; the
-// fluxes go straight to LDS as they are produced.
+// fpb <= 256 consecutive faces and blocks overlap by one face, so every cell
+// whose two faces lie in a block gets (F^_{i-1/2} - F^_{i+1/2}) / dx there.
+// The block first copies U and the primitives of its stencil cells to LDS,
+// row segment by row segment: the faces of one row need their own cells plus
+// 2 RAD - 1 more, so a block touching nseg rows stages fpb + nseg (2 RAD - 1)
+// cells.  Unstaged, the six overlapping stencil loads of each field went to
+// the caches, and at three blocks per CU the working set outgrew the L2:
+// 4.0 GB fetched per launch at 256^3, nine species, against 2.33 GB of
+// stencil inputs.  fpb is 256 whenever a row holds at least 255 faces; for
+// shorter rows the launch lowers it until the staged cells fit x_stage_cells.
+// The FP64 instances without the blend hand each flux component to the cell
+// below as soon as it is final, taking the neighbouring face's value from the
+// next lane down; the first lane of each wave takes it through LDS.  The
+// others keep the block's fluxes in LDS (the blend limits whole flux
+// vectors).  A mixed RK3 step's x sweep also finishes the stage (sa.Uout).
 // ---------------------------------------------------------------------------
 constexpr int kXBlock = 256;
+
+template <int RAD>
+constexpr int x_stage_cells() { return kXBlock + 2 * (2 * RAD - 1); }
+
+// Faces per x-sweep block for rows of nfx faces: the largest count whose
+// worst-case staging (a window of fpb faces spans at most
+// ceil((fpb - 1) / nfx) + 1 rows) fits x_stage_cells.
+template <int RAD>
+inline int x_faces_per_block(long long nfx) {
+    constexpr int gap = 2 * RAD - 1;
+    int fpb = kXBlock;
+    while (fpb > 2 && fpb + ((fpb - 1 + nfx - 1) / nfx + 1) * gap > x_stage_cells<RAD>()) --fpb;
+    return fpb;
+}
+
+template <typename R>
+struct XShape {
+    static constexpr bool exchange = sizeof(R) == 8;
+};
 
 template <int NS, typename R, typename S, bool PP, int SPD, int REC>
 __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(sweep_waves<R, REC, true, PP>()))) void k_sweep_x(
     const S *__restrict__ U, const S *__restrict__ P, R *__restrict__ rhs, Geo g, ThermoK<R> th, int accumulate,
-    StageArgs sa, unsigned *status, Dissip ds) {
+    StageArgs sa, unsigned *status, Dissip ds, int fpb) {
     constexpr int NV = NS + 4;
-    __shared__ R sF[NV][kXBlock];
+    constexpr int RAD = stencil_radius(REC);
+    constexpr int GAP = 2 * RAD - 1;
+    constexpr int XC = x_stage_cells<RAD>();
+    constexpr bool EXCH = XShape<R>::exchange && !PP;
+    constexpr int NW = kXBlock / 64;
+    __shared__ R sF[EXCH ? 1 : NV][EXCH ? 1 : kXBlock];
+    __shared__ R sEdge[2][EXCH ? NW : 1][EXCH ? NV : 1];
+    __shared__ S xf_xstage[(NV + 4) * XC];
+    unsigned lb, u1, u2;
+    xcd_block(lb, u1, u2);
     const int t = threadIdx.x;
     const long long nfx = (long long)g.nx + 1;
-    const long long f = (long long)blockIdx.x * (kXBlock - 1) + t;
     const long long nfaces = nfx * g.ny * g.nz;
-    const bool valid = f < nfaces;
+    const long long f0 = (long long)lb * (fpb - 1);
+    if (f0 >= nfaces) return;   // blocks that round the grid up to a multiple of 8
+    const long long flast = min(f0 + fpb - 1, nfaces - 1);
+    const long long row0 = f0 / nfx;
+    {
+        // staged cell e of row rho (row0 <= rho <= the last face's row) holds
+        // x index e + sbase - rho W - RAD of that row, W = nfx + GAP
+        const long long rowL = flast / nfx;
+        const int ncell = (int)(flast - f0 + 1) + (int)(rowL - row0 + 1) * GAP;
+        const long long W = nfx + GAP, sbase = f0 + row0 * GAP;
+        for (int e = t; e < ncell; e += kXBlock) {
+            long long rho = (e + sbase) / W;
+            if (rho < row0) rho = row0;
+            const int cx = (int)(e + sbase - rho * W) - RAD;
+            const long long j = rho % g.ny, k = rho / g.ny;
+            const long long cell = (g.gz + k) * g.sz + (g.gy + j) * g.sy + g.gx + cx;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) xf_xstage[q * XC + e] = U[q * g.cells + cell];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xf_xstage[(NV + q) * XC + e] = P[q * g.cells + cell];
+        }
+    }
+    __syncthreads();
+    const long long f = f0 + t;
+    const bool valid = t < fpb && f < nfaces;
+    const int lane = t & 63, w = t >> 6;
     long long row = 0;
     int i = 0;
     unsigned flags = 0;
     long long rowbase = 0;
+    const R id = R(g.idx);
+    // the result of interior cell `cell` from its flux difference L (x part)
+    auto emit = [&](int q, long long cell, double L) {
+        const long long o = q * g.cells + cell;
+        if (sa.Uout) {
+            const double h = sa.dt_dev ? *sa.dt_dev : sa.dt;
+            if constexpr (sizeof(R) == 8) {
+                if (sa.Ly64) L = L + sa.Ly64[o];
+                if (sa.Lz64) L = L + sa.Lz64[o];
+            } else {
+                if (sa.Ly32) L = L + (double)sa.Ly32[o];
+                if (sa.Lz32) L = L + (double)sa.Lz32[o];
+            }
+            if (sa.Lv) L = L + sa.Lv[o];
+            const double v = sa.Uin[o] + h * L;
+            sa.Uout[o] = sa.a == 0.0 ? sa.b * v : sa.a * sa.U0[o] + sa.b * v;
+        } else {
+            put_result(rhs, o, L, accumulate);
+        }
+    };
     if (valid) {
         row = f / nfx;
         i = (int)(f - row * nfx);
         const int j = (int)(row % g.ny), k = (int)(row / g.ny);
         rowbase = (long long)(g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + g.gx;
-        constexpr int RAD = stencil_radius(REC);
-        StencilT<S> st{U, P, rowbase + i - RAD, 1, g.cells};
+        // stencil cell m of face i (cell i - RAD + m of its row) is staged at
+        // t + (row - row0) GAP + m
+        StencilLds<NV, S> st{(const __attribute__((address_space(3))) S *)xf_xstage,
+                             t + (int)(row - row0) * GAP, 1, XC};
         if constexpr (SPD == kViscFrozen) ds.fidx = f;   // x faces: i + (nx + 1) (j + ny k)
-        face_flux_to<NS, R, 0, SweepTune<R>::fence_face, SPD, REC, !PP, true>(
-            st, th, [&](int q, R v) { sF[q][t] = v; }, flags, ds);
-        if constexpr (PP) {
-            R Fq[NV];
+        if constexpr (EXCH) {
+            face_flux_to<NS, R, 0, SweepTune<R>::fence_face, SPD, REC, true, true>(
+                st, th,
+                [&](int q, R v) {
+                    // face f - 1 is lane t - 1, valid wherever face f is
+                    const R vb = __shfl_up(v, 1);
+                    if (lane > 0 && i > 0) emit(q, rowbase + i - 1, double((vb - v) * id));
+                    if (lane == 63) sEdge[0][w][q] = v;
+                    if (lane == 0) sEdge[1][w][q] = v;
+                },
+                flags, ds);
+        } else {
+            face_flux_to<NS, R, 0, SweepTune<R>::fence_face, SPD, REC, !PP, true>(
+                st, th, [&](int q, R v) { sF[q][t] = v; }, flags, ds);
+            if constexpr (PP) {
+                R Fq[NV];
 #pragma unroll
-            for (int q = 0; q < NV; ++q) Fq[q] = sF[q][t];
-            pp_limit<NS, R, 0, RAD>(st, pp_lambda<R>(g, sa, g.idx), Fq);
+                for (int q = 0; q < NV; ++q) Fq[q] = sF[q][t];
+                pp_limit<NS, R, 0, RAD>(st, pp_lambda<R>(g, sa, g.idx), Fq);
 #pragma unroll
-            for (int q = 0; q < NV; ++q) sF[q][t] = Fq[q];
+                for (int q = 0; q < NV; ++q) sF[q][t] = Fq[q];
+            }
         }
     }
     __syncthreads();
-    if (valid && t > 0 && i > 0) {
-        const R id = R(g.idx);
-        const long long cell = rowbase + i - 1;
-        if (sa.Uout) {
-            const double h = sa.dt_dev ? *sa.dt_dev : sa.dt;
-#pragma unroll
-            for (int q = 0; q < NV; ++q) {
-                const long long o = q * g.cells + cell;
-                double L = double((sF[q][t - 1] - sF[q][t]) * id);
-                if constexpr (sizeof(R) == 8) {
-                    if (sa.Ly64) L = L + sa.Ly64[o];
-                    if (sa.Lz64) L = L + sa.Lz64[o];
-                } else {
-                    if (sa.Ly32) L = L + (double)sa.Ly32[o];
-                    if (sa.Lz32) L = L + (double)sa.Lz32[o];
-                }
-                if (sa.Lv) L = L + sa.Lv[o];
-                const double v = sa.Uin[o] + h * L;
-                sa.Uout[o] = sa.a == 0.0 ? sa.b * v : sa.a * sa.U0[o] + sa.b * v;
-            }
-        } else {
+    if constexpr (EXCH) {
+        // the cell between the last face of wave w - 1 and the first of w
+        if (valid && lane == 0 && w > 0 && i > 0) {
 #pragma unroll
             for (int q = 0; q < NV; ++q)
-                put_result(rhs, q * g.cells + cell, double((sF[q][t - 1] - sF[q][t]) * id), accumulate);
+                emit(q, rowbase + i - 1, double((sEdge[0][w - 1][q] - sEdge[1][w][q]) * id));
         }
+    } else if (valid && t > 0 && i > 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) emit(q, rowbase + i - 1, double((sF[q][t - 1] - sF[q][t]) * id));
     }
     if (flags) atomicOr(status, flags);
 }

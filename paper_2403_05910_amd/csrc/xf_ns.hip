@@ -28,10 +28,14 @@ hipError_t launch_face_sweep(const LaunchCtx &c, const ThermoK<R> &th, int dir, 
                              const S *P, R *rhs, const StageArgs &sa, const Dissip &ds, hipStream_t s) {
     const Geo &g = c.g;
     if (dir == 0) {
-        const long long nf = (long long)(g.nx + 1) * g.ny * g.nz;
-        const unsigned nb = (unsigned)((nf - 1 + (kXBlock - 2)) / (kXBlock - 1));   // blocks overlap by one face
+        const long long nfx = (long long)g.nx + 1, nf = nfx * g.ny * g.nz;
+        const int fpb = x_faces_per_block<stencil_radius(REC)>(nfx);
+        // blocks overlap by one face; the count is rounded up to a multiple
+        // of the XCD count so that each XCD takes one contiguous range
+        unsigned nb = (unsigned)((nf - 1 + (fpb - 2)) / (fpb - 1));
+        nb = (nb + kNumXcd - 1) / kNumXcd * kNumXcd;
         hipLaunchKernelGGL((k_sweep_x<NS, R, S, PP, SPD, REC>), dim3(nb), dim3(kXBlock), 0, s, U, P, rhs, g, th,
-                           accumulate, sa, c.status, ds);
+                           accumulate, sa, c.status, ds, fpb);
         return hipGetLastError();
     }
     const int ntr = dir == 1 ? g.nz : g.ny;
