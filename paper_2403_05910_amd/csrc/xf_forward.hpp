@@ -147,8 +147,18 @@ __global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, dou
                    (z < g.gz || z >= g.gz + g.nz);
     if (ng > 1 && !all_cells) return;   // edge and corner ghosts: outside every stencil
     const long long C = g.cells;
+    double u[NS + 4];
+#pragma unroll
+    for (int f = 0; f < NS + 4; ++f) u[f] = U[f * C + idx];
+    // the FP32 copies go out before the Newton solve, from the loaded values
+    // (read again after it, the state was partly evicted from the L2 and
+    // fetched twice: 2.43 against 1.92 GB per launch at 256^3, nine species)
+    if (Uf) {
+#pragma unroll
+        for (int f = 0; f < NS + 4; ++f) Uf[f * C + idx] = (float)u[f];
+    }
     double T, p, c, rinv;
-    const unsigned flags = cell_prims<NS>([&](int f) { return U[f * C + idx]; }, th, T, p, c, rinv);
+    const unsigned flags = cell_prims<NS>([&](int f) { return u[f]; }, th, T, p, c, rinv);
     if (P) {
         P[idx] = T;
         P[C + idx] = p;
@@ -156,8 +166,6 @@ __global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, dou
         P[3 * C + idx] = rinv;
     }
     if (Uf) {
-#pragma unroll
-        for (int f = 0; f < NS + 4; ++f) Uf[f * C + idx] = (float)U[f * C + idx];
         Pf[idx] = (float)T;
         Pf[C + idx] = (float)p;
         Pf[2 * C + idx] = (float)c;
@@ -408,19 +416,21 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(sweep_w
 // copies U and the primitives of its (s + 2 RAD - 1) x x stencil cells once,
 // in whole rows, and every face reads its stencil from there (a face's
 // stencil is six rows apart in memory, so unstaged each wave issues twice
-// the loads of the x sweep, one per row and field).  The FP64 WENO5 tile
-// without the blend is 8 x 32 and exchanges its fluxes across lanes instead
-// of holding them in LDS (46.9 KB per block: three blocks, three waves per
-// SIMD, in 146 registers); the other instances are 16 x 16 with the fluxes
-// in LDS (FP64: 72 KB, two waves; the CU6 and WENO7 faces need more than
-// the 168 registers of three waves; FP32: 36 KB, four waves).  Measured at
-// 256^3, nine species, y/z: FP64 WENO5 2.92/3.01 ms unstaged, 2.10/2.19
-// staged at 16 x 16, 1.92/1.97 exchanging at 8 x 32 (CU6 and WENO7 ran 5 %
-// slower at 8 x 32 than at 16 x 16); FP32 1.43/1.49 unstaged at 32 x 8,
-// 1.36/1.37 staged at 32 x 8 or 32 x 16, 1.15/1.16 staged at 16 x 16.
+// the loads of the x sweep, one per row and field).  The WENO5 tiles
+// without the blend are 8 x 32 and exchange their fluxes across lanes
+// instead of holding them in LDS (FP64: 46.9 KB per block, three blocks,
+// three waves per SIMD, in 146 registers; FP32: 23.5 KB, five waves in 95
+// registers); the other instances are 16 x 16 with the fluxes in LDS (FP64:
+// 72 KB, two waves; the CU6 and WENO7 faces need more than the 168
+// registers of three waves; FP32: 36 KB, four waves).  Measured at 256^3,
+// nine species, y/z: FP64 WENO5 2.92/3.01 ms unstaged, 2.10/2.19 staged at
+// 16 x 16, 1.92/1.97 exchanging at 8 x 32 (CU6 and WENO7 ran 5 % slower at
+// 8 x 32 than at 16 x 16); FP32 1.43/1.49 unstaged at 32 x 8, 1.36/1.37
+// staged at 32 x 8 or 32 x 16, 1.15/1.16 staged at 16 x 16, 1.12/1.11
+// exchanging at 8 x 32 (1.12/1.12 exchanging at 16 x 16).
 template <typename R, int REC, bool PP>
 struct TileShape {
-    static constexpr bool exchange = sizeof(R) == 8 && REC == kReconWeno5 && !PP;
+    static constexpr bool exchange = REC == kReconWeno5 && !PP;
     static constexpr int x = exchange ? 8 : 16, s = exchange ? 32 : 16;
 };
 
