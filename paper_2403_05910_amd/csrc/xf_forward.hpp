@@ -307,19 +307,34 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(sweep_w
     const long long f0 = (long long)lb * (fpb - 1);
     if (f0 >= nfaces) return;   // blocks that round the grid up to a multiple of 8
     const long long flast = min(f0 + fpb - 1, nfaces - 1);
+    // the block's first face: face i0 of row row0 = (j0, k0); its faces lie
+    // in rows row0 .. row0 + nseg - 1 (segment sg = row row0 + sg), so the
+    // per-cell and per-face indexing below needs 32-bit divisions only
     const long long row0 = f0 / nfx;
+    const int i0 = (int)(f0 - row0 * nfx);
+    const int j0 = (int)(row0 % g.ny);
+    const long long k0 = row0 / g.ny;
+    const int nfx32 = g.nx + 1;
+    auto row_base = [&](int sg) {
+        int j = j0 + sg;
+        long long k = k0;
+        if (j >= g.ny) {
+            k += j / g.ny;
+            j %= g.ny;
+        }
+        return (g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + g.gx;
+    };
     {
-        // staged cell e of row rho (row0 <= rho <= the last face's row) holds
-        // x index e + sbase - rho W - RAD of that row, W = nfx + GAP
-        const long long rowL = flast / nfx;
-        const int ncell = (int)(flast - f0 + 1) + (int)(rowL - row0 + 1) * GAP;
-        const long long W = nfx + GAP, sbase = f0 + row0 * GAP;
+        // staged cell e: segment sg = (e + i0) / W, W = nfx + GAP, x index
+        // e + i0 - sg W - RAD of that row (segment 0 starts at face i0, the
+        // others at face 0)
+        const int nseg = (int)(flast / nfx - row0) + 1;
+        const int ncell = (int)(flast - f0 + 1) + nseg * GAP;
+        const int W = nfx32 + GAP;
         for (int e = t; e < ncell; e += kXBlock) {
-            long long rho = (e + sbase) / W;
-            if (rho < row0) rho = row0;
-            const int cx = (int)(e + sbase - rho * W) - RAD;
-            const long long j = rho % g.ny, k = rho / g.ny;
-            const long long cell = (g.gz + k) * g.sz + (g.gy + j) * g.sy + g.gx + cx;
+            const int sg = (e + i0) / W;
+            const int cx = e + i0 - sg * W - RAD;
+            const long long cell = row_base(sg) + cx;
 #pragma unroll
             for (int q = 0; q < NV; ++q) xf_xstage[q * XC + e] = U[q * g.cells + cell];
 #pragma unroll
@@ -330,7 +345,6 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(sweep_w
     const long long f = f0 + t;
     const bool valid = t < fpb && f < nfaces;
     const int lane = t & 63, w = t >> 6;
-    long long row = 0;
     int i = 0;
     unsigned flags = 0;
     long long rowbase = 0;
@@ -355,14 +369,12 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(sweep_w
         }
     };
     if (valid) {
-        row = f / nfx;
-        i = (int)(f - row * nfx);
-        const int j = (int)(row % g.ny), k = (int)(row / g.ny);
-        rowbase = (long long)(g.gz + k) * g.sz + (long long)(g.gy + j) * g.sy + g.gx;
+        const int sg = (t + i0) / nfx32;
+        i = t + i0 - sg * nfx32;
+        rowbase = row_base(sg);
         // stencil cell m of face i (cell i - RAD + m of its row) is staged at
-        // t + (row - row0) GAP + m
-        StencilLds<NV, S> st{(const __attribute__((address_space(3))) S *)xf_xstage,
-                             t + (int)(row - row0) * GAP, 1, XC};
+        // t + sg GAP + m
+        StencilLds<NV, S> st{(const __attribute__((address_space(3))) S *)xf_xstage, t + sg * GAP, 1, XC};
         if constexpr (SPD == kViscFrozen) ds.fidx = f;   // x faces: i + (nx + 1) (j + ny k)
         if constexpr (EXCH) {
             face_flux_to<NS, R, 0, SweepTune<R>::fence_face, SPD, REC, true, true>(
