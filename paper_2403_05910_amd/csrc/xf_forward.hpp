@@ -259,11 +259,11 @@ __device__ __forceinline__ void put_result(OT *__restrict__ rhs, long long o, do
 // 4.0 GB fetched per launch at 256^3, nine species, against 2.33 GB of
 // stencil inputs.  fpb is 256 whenever a row holds at least 255 faces; for
 // shorter rows the launch lowers it until the staged cells fit x_stage_cells.
-// The FP64 instances without the blend hand each flux component to the cell
-// below as soon as it is final, taking the neighbouring face's value from the
-// next lane down; the first lane of each wave takes it through LDS.  The
-// others keep the block's fluxes in LDS (the blend limits whole flux
-// vectors).  A mixed RK3 step's x sweep also finishes the stage (sa.Uout).
+// The FP64 WENO5 instances without the blend hand each flux component to
+// the cell below as soon as it is final, taking the neighbouring face's
+// value from the next lane down; the first lane of each wave takes it
+// through LDS.  The others keep the block's fluxes in LDS (the blend limits
+// whole flux vectors).  A mixed RK3 step's x sweep also finishes the stage (sa.Uout).
 // ---------------------------------------------------------------------------
 constexpr int kXBlock = 256;
 
@@ -281,9 +281,12 @@ inline int x_faces_per_block(long long nfx) {
     return fpb;
 }
 
-template <typename R>
+// Exchanging x sweeps: FP64 WENO5 (three waves per SIMD).  The CU6 and
+// WENO7 faces (two and one waves per SIMD) took 3.09 ms per x sweep
+// exchanging against 2.62 and 2.65 ms with the fluxes in LDS.
+template <typename R, int REC>
 struct XShape {
-    static constexpr bool exchange = sizeof(R) == 8;
+    static constexpr bool exchange = sizeof(R) == 8 && REC == kReconWeno5;
 };
 
 template <int NS, typename R, typename S, bool PP, int SPD, int REC>
@@ -294,7 +297,7 @@ __global__ __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(sweep_w
     constexpr int RAD = stencil_radius(REC);
     constexpr int GAP = 2 * RAD - 1;
     constexpr int XC = x_stage_cells<RAD>();
-    constexpr bool EXCH = XShape<R>::exchange && !PP;
+    constexpr bool EXCH = XShape<R, REC>::exchange && !PP;
     constexpr int NW = kXBlock / 64;
     __shared__ R sF[EXCH ? 1 : NV][EXCH ? 1 : kXBlock];
     __shared__ R sEdge[2][EXCH ? NW : 1][EXCH ? NV : 1];
