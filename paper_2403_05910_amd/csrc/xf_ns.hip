@@ -255,7 +255,8 @@ hipError_t viscous(const LaunchCtx &c, int dir, const double *U, const double *P
     const Geo &g = c.g;
     if (dir == 0) {
         const long long nf = ((long long)g.nx + 3) * g.ny * g.nz;
-        const unsigned nb = (unsigned)((nf - 3 + (kViscXBlock - 4)) / (kViscXBlock - 3));   // blocks overlap by three
+        unsigned nb = (unsigned)((nf - 3 + (kViscXBlock - 4)) / (kViscXBlock - 3));   // blocks overlap by three
+        nb = (nb + kNumXcd - 1) / kNumXcd * kNumXcd;
         hipLaunchKernelGGL(k_visc_x<NS>, dim3(nb), dim3(kViscXBlock), 0, s, U, P, Q, G, rhs, g, c.th64, terms);
         return hipGetLastError();
     }

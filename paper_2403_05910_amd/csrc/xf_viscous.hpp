@@ -201,6 +201,9 @@ __device__ __forceinline__ void visc_point_flux(const double *__restrict__ U, co
 // x direction: point faces k = -1..nx+1 of every interior row, linearised
 // (nx + 3 per row); a block of 256 threads takes 256 consecutive faces and
 // blocks overlap by three, so each cell's four point faces meet in one block.
+// The block count is a multiple of the XCD count and each XCD takes one
+// contiguous range of faces (neighbouring blocks share their edge cells in
+// one L2).
 // The point fluxes go to LDS; a thread whose face closes a cell's window
 // (the cell's last point face) adds that cell's residual.
 // ---------------------------------------------------------------------------
@@ -217,10 +220,15 @@ __global__ __launch_bounds__(kViscXBlock) __attribute__((amdgpu_waves_per_eu(5))
                                                        int terms) {
     constexpr int NV = NS + 4;
     __shared__ double sF[NV][kViscXBlock];
+    unsigned lb, u1, u2;
+    xcd_block(lb, u1, u2);
     const int t = threadIdx.x;
     const long long per_row = (long long)g.nx + 3;
-    const long long f = (long long)blockIdx.x * (kViscXBlock - 3) + t;
-    const bool valid = f < per_row * g.ny * g.nz;
+    const long long nfaces = per_row * g.ny * g.nz;
+    const long long f0 = (long long)lb * (kViscXBlock - 3);
+    if (f0 >= nfaces) return;   // blocks that round the grid up to a multiple of 8
+    const long long f = f0 + t;
+    const bool valid = f < nfaces;
     long long row = 0, rowbase = 0;
     int kk = 0;
     if (valid) {
