@@ -90,6 +90,10 @@ def _cases():
         "periodic_mixture_24": W.periodic_mixture(24),
         "inert_sbi_32": W.inert_sbi(32),
         "nine_sbi_32": W.nine_species_sbi(32),
+        # rows of 4 x faces (the fewest three ghost layers allow): an x-sweep
+        # block then takes 116 faces over up to 30 rows
+        "thin_x3_n3": W.random_smooth_state(tp3, (3, 9, 7), seed=8, jump=True, bc=(1, 1, 0, 0, 0, 0)),
+        "thin_x3_n9": W.random_smooth_state(tp9, (3, 6, 5), seed=9),
     }
 
 
@@ -162,7 +166,7 @@ def test_cfl_dt_matches_oracle():
     assert abs(dt - ref) <= 1e-14 * ref
 
 
-@pytest.mark.parametrize("name,steps", [("inert_sbi_32", 5), ("wave1d_600", 10), ("n9_3d_mixed_bc", 3)])
+@pytest.mark.parametrize("name,steps", [("inert_sbi_32", 5), ("wave1d_600", 10), ("n9_3d_mixed_bc", 3), ("thin_x3_n9", 3)])
 def test_rk3_steps_match_oracle(name, steps):
     xf = _xf()
     case = CASES[name]
@@ -261,7 +265,7 @@ MIXED_STATE_TOL = 1e-5
 
 
 @pytest.mark.parametrize("name", ["ragged3d_n3_outflow_x", "n9_3d_mixed_bc", "inert_sbi_32", "nine_sbi_32",
-                                  "plane2d_n3", "z_only_n3"])
+                                  "plane2d_n3", "z_only_n3", "thin_x3_n3", "thin_x3_n9"])
 def test_rhs_mixed_within_fp32_bound(name):
     case = CASES[name]
     r_gpu, flags, _ = gpu_rhs(case, "mixed")
@@ -354,7 +358,7 @@ def test_rhs_glf_mixed_within_fp32_bound():
 
 
 @pytest.mark.parametrize("name", ["ragged3d_n3_outflow_x", "n9_3d_mixed_bc", "inert_sbi_32", "plane2d_n3",
-                                  "z_only_n3", "wave1d_600", "sod_400"])
+                                  "z_only_n3", "wave1d_600", "sod_400", "thin_x3_n3", "thin_x3_n9"])
 def test_rhs_cu6_matches_oracle(name):
     case = CASES[name]
     r_gpu, flags, _ = gpu_rhs(case, recon="CU6")
