@@ -29,6 +29,15 @@ struct Geo {
     int bc[6];
 };
 
+// Padded source index (along the ghost's axis) of ghost layer l on side sd
+// (0 low, 1 high), n interior cells, ng ghost layers per side: periodic wraps,
+// outflow copies the nearest interior cell (n >= ng, so every source is an
+// interior cell).
+__device__ __forceinline__ int ghost_src(int bc, int sd, int l, int n, int ng) {
+    if (sd == 0) return bc == XF_BC_PERIODIC ? n + l : ng;
+    return bc == XF_BC_PERIODIC ? ng + l : ng + n - 1;
+}
+
 // Species thermo in the form the kernels evaluate (Horner in T):
 //   cv_s(T) = sum_k cv[s][k] T^k  (k = 0..4),  C_v,s = C_p,s - R_s
 //   e_s(T)  = sum_k e[s][k] T^k   (k = 0..5),  e_s = h_s - R_s T
@@ -125,9 +134,12 @@ struct LaunchCtx {
 struct NsOps {
     // primitive variables (T, p, c, 1/rho) of every cell a stencil reads (of
     // every padded cell with all_cells); with Uf, Pf also FP32 copies of U
-    // and P for the mixed-precision sweeps
+    // and P for the mixed-precision sweeps.  With Ug (= U, all_cells 0) the
+    // face ghosts of U are filled on the way (each from its boundary source,
+    // as the ghost fill does; edge and corner ghosts, outside every stencil,
+    // are left)
     hipError_t (*prims)(const LaunchCtx &, const double *U, double *P, float *Uf, float *Pf, int all_cells,
-                        hipStream_t);
+                        double *Ug, hipStream_t);
     // one direction of the convective flux difference.  FP64 sweeps read U,
     // P and write rhs (accumulate: rhs +=, else rhs =); mixed-precision
     // sweeps read Uf, Pf and write the FP32 differences to rhs32 (no

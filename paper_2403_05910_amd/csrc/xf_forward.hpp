@@ -134,9 +134,9 @@ __device__ __forceinline__ unsigned cell_prims(const Get &u, const ThermoK<doubl
 // mixed-precision sweeps, written for the same cells; P may be null when
 // only they are needed.
 template <int NS>
-__global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, double *__restrict__ P, Geo g,
+__global__ __launch_bounds__(256) void k_prims(const double *U, double *__restrict__ P, Geo g,
                                                ThermoK<double> th, unsigned *status, float *__restrict__ Uf,
-                                               float *__restrict__ Pf, int all_cells) {
+                                               float *__restrict__ Pf, int all_cells, double *Ug) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= g.cells) return;
     const int x = (int)(idx % g.px);
@@ -147,9 +147,27 @@ __global__ __launch_bounds__(256) void k_prims(const double *__restrict__ U, dou
                    (z < g.gz || z >= g.gz + g.nz);
     if (ng > 1 && !all_cells) return;   // edge and corner ghosts: outside every stencil
     const long long C = g.cells;
+    // with Ug (= U): a face ghost takes its boundary source's state, written
+    // to the ghost as the ghost fill would (sources are interior cells, which
+    // this pass does not write)
+    long long src = idx;
+    if (Ug && ng == 1) {
+        const int d = (x < g.gx || x >= g.gx + g.nx) ? 0 : ((y < g.gy || y >= g.gy + g.ny) ? 1 : 2);
+        const int c = d == 0 ? x : (d == 1 ? y : z);
+        const int n = d == 0 ? g.nx : (d == 1 ? g.ny : g.nz);
+        const int gw = d == 0 ? g.gx : (d == 1 ? g.gy : g.gz);
+        const int sd = c < gw ? 0 : 1;
+        const int cs = ghost_src(g.bc[2 * d + sd], sd, sd == 0 ? c : c - gw - n, n, gw);
+        const long long stride = d == 0 ? 1 : (d == 1 ? (long long)g.px : (long long)g.px * g.py);
+        src = idx + (long long)(cs - c) * stride;
+    }
     double u[NS + 4];
 #pragma unroll
-    for (int f = 0; f < NS + 4; ++f) u[f] = U[f * C + idx];
+    for (int f = 0; f < NS + 4; ++f) u[f] = U[f * C + src];
+    if (src != idx) {
+#pragma unroll
+        for (int f = 0; f < NS + 4; ++f) Ug[f * C + idx] = u[f];
+    }
     // the FP32 copies go out before the Newton solve, from the loaded values
     // (read again after it, the state was partly evicted from the L2 and
     // fetched twice: 2.43 against 1.92 GB per launch at 256^3, nine species)

@@ -36,12 +36,6 @@ __device__ __forceinline__ long long others(const Geo &g, int d) {
     return d == 0 ? (long long)g.py * g.pz : (d == 1 ? (long long)g.px * g.pz : (long long)g.px * g.py);
 }
 
-// padded source index of ghost layer l on side sd (0 low, 1 high), n interior
-// cells, ng ghost layers per side (n >= ng, so periodic sources are interior)
-__device__ __forceinline__ int ghost_src(int bc, int sd, int l, int n, int ng) {
-    if (sd == 0) return bc == XF_BC_PERIODIC ? n + l : ng;
-    return bc == XF_BC_PERIODIC ? ng + l : ng + n - 1;
-}
 __device__ __forceinline__ int ghost_dst(int sd, int l, int n, int ng) { return sd == 0 ? l : ng + n + l; }
 __device__ __forceinline__ int ghost_width(const Geo &g, int d) { return d == 0 ? g.gx : (d == 1 ? g.gy : g.gz); }
 
