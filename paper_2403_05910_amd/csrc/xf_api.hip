@@ -267,7 +267,7 @@ const double *glf_of(const xf_ctx *c, const unsigned long long *mx, int d) {
 }
 
 // p64 = false: the FP64 primitives are not needed (the FP32 copies are).
-// Ug = U: the pass also fills the face ghosts of U (inviscid contexts)
+// Ug = U: the pass also fills the ghosts of U it covers
 hipError_t prims(xf_ctx *c, const double *U, const Prim &pb, hipStream_t s, bool p64 = true, double *Ug = nullptr) {
     // viscous contexts: every padded cell (the tangential derivatives read edge ghosts)
     hipError_t e = timed(c, XF_K_PRIMS, s, [&] {
@@ -715,12 +715,12 @@ int flow_rk3_step(xf_ctx *c, double *U, double dt, const double *dt_in, double c
     // a mixed step without viscous terms or GLF reads the FP64 primitives
     // only for its step size (stage 1); later stages need the FP32 copies
     const bool p64_later = !mixed || c->viscous || lc.visc == XF_VISC_GLF;
-    // without viscous terms the primitive pass fills the face ghosts of the
-    // stage input itself (no stencil reads an edge or corner ghost; the
-    // state's ghosts are filled in full at the end of the step)
+    // the primitive pass fills the ghosts of the stage input itself: the
+    // face ghosts, and with viscous terms (whose tangential derivatives read
+    // them) the edge and corner ghosts too; the state's ghosts are filled in
+    // full at the end of the step
     for (int k = 0; k < 3; ++k) {
-        if (c->viscous) XF_TRY(fill(c, in[k], s));
-        XF_TRY(prims(c, in[k], pb, s, k == 0 || p64_later, c->viscous ? nullptr : in[k]));
+        XF_TRY(prims(c, in[k], pb, s, k == 0 || p64_later, in[k]));
         if (k == 0 && cfl > 0.0) {
             XF_TRY(timed(c, XF_K_CFL, s, [&] {
                 hipError_t e = xf::launch_cfl_reset(mx, s);

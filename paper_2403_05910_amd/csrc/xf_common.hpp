@@ -134,10 +134,10 @@ struct LaunchCtx {
 struct NsOps {
     // primitive variables (T, p, c, 1/rho) of every cell a stencil reads (of
     // every padded cell with all_cells); with Uf, Pf also FP32 copies of U
-    // and P for the mixed-precision sweeps.  With Ug (= U, all_cells 0) the
-    // face ghosts of U are filled on the way (each from its boundary source,
-    // as the ghost fill does; edge and corner ghosts, outside every stencil,
-    // are left)
+    // and P for the mixed-precision sweeps.  With Ug (= U) the ghosts of U
+    // the pass covers are filled on the way, each from its boundary source as
+    // the ghost fill does (without all_cells: the face ghosts; the edge and
+    // corner ghosts lie outside every stencil and are left)
     hipError_t (*prims)(const LaunchCtx &, const double *U, double *P, float *Uf, float *Pf, int all_cells,
                         double *Ug, hipStream_t);
     // one direction of the convective flux difference.  FP64 sweeps read U,

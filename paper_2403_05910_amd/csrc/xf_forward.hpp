@@ -147,19 +147,21 @@ __global__ __launch_bounds__(256) void k_prims(const double *U, double *__restri
                    (z < g.gz || z >= g.gz + g.nz);
     if (ng > 1 && !all_cells) return;   // edge and corner ghosts: outside every stencil
     const long long C = g.cells;
-    // with Ug (= U): a face ghost takes its boundary source's state, written
-    // to the ghost as the ghost fill would (sources are interior cells, which
-    // this pass does not write)
+    // with Ug (= U): a ghost takes its boundary source's state, written to
+    // the ghost as the ghost fill would.  Each ghost coordinate maps to its
+    // source on its own axis (the axis-by-axis fill gives an edge or corner
+    // ghost the state of the interior cell all its coordinates map to);
+    // sources are interior cells, which this pass does not write.
     long long src = idx;
-    if (Ug && ng == 1) {
-        const int d = (x < g.gx || x >= g.gx + g.nx) ? 0 : ((y < g.gy || y >= g.gy + g.ny) ? 1 : 2);
-        const int c = d == 0 ? x : (d == 1 ? y : z);
-        const int n = d == 0 ? g.nx : (d == 1 ? g.ny : g.nz);
-        const int gw = d == 0 ? g.gx : (d == 1 ? g.gy : g.gz);
-        const int sd = c < gw ? 0 : 1;
-        const int cs = ghost_src(g.bc[2 * d + sd], sd, sd == 0 ? c : c - gw - n, n, gw);
-        const long long stride = d == 0 ? 1 : (d == 1 ? (long long)g.px : (long long)g.px * g.py);
-        src = idx + (long long)(cs - c) * stride;
+    if (Ug && ng > 0) {
+        auto map = [](int c, int n, int gw, int lo, int hi) {
+            if (c < gw) return ghost_src(lo, 0, c, n, gw);
+            if (c >= gw + n) return ghost_src(hi, 1, c - gw - n, n, gw);
+            return c;
+        };
+        const int sx = map(x, g.nx, g.gx, g.bc[0], g.bc[1]), sy = map(y, g.ny, g.gy, g.bc[2], g.bc[3]),
+                  sz = map(z, g.nz, g.gz, g.bc[4], g.bc[5]);
+        src = sx + (long long)g.px * (sy + (long long)g.py * sz);
     }
     double u[NS + 4];
 #pragma unroll
