@@ -267,11 +267,13 @@ const double *glf_of(const xf_ctx *c, const unsigned long long *mx, int d) {
 }
 
 // p64 = false: the FP64 primitives are not needed (the FP32 copies are).
-// Ug = U: the pass also fills the ghosts of U it covers
-hipError_t prims(xf_ctx *c, const double *U, const Prim &pb, hipStream_t s, bool p64 = true, double *Ug = nullptr) {
+// Ug = U: the pass also fills the ghosts of U it covers.  cfl: the pass also
+// takes the CFL maximum into *cfl (zeroed beforehand)
+hipError_t prims(xf_ctx *c, const double *U, const Prim &pb, hipStream_t s, bool p64 = true, double *Ug = nullptr,
+                 unsigned long long *cfl = nullptr) {
     // viscous contexts: every padded cell (the tangential derivatives read edge ghosts)
     hipError_t e = timed(c, XF_K_PRIMS, s, [&] {
-        return c->ops->prims(c->lc, U, p64 ? pb.P : nullptr, pb.Uf, pb.Pf, c->viscous ? 1 : 0, Ug, s);
+        return c->ops->prims(c->lc, U, p64 ? pb.P : nullptr, pb.Uf, pb.Pf, c->viscous ? 1 : 0, Ug, cfl, s);
     });
     if (e == hipSuccess) e = glf_speeds(c, U, pb.P, pb.mx, s);
     return e;
@@ -318,7 +320,7 @@ int rhs_vjp_into(xf_ctx *c, const double *U, const double *rbar, double *Ubar, d
                  unsigned long long *mx, hipStream_t s) {
     const LaunchCtx &lc = c->lc;
     const int n[3] = {lc.g.nx, lc.g.ny, lc.g.nz};
-    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(lc, U, P, nullptr, nullptr, 0, nullptr, s); }));
+    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(lc, U, P, nullptr, nullptr, 0, nullptr, nullptr, s); }));
     XF_TRY(glf_speeds(c, U, P, mx, s));
     XF_TRY(timed(c, XF_K_ZERO, s, [&] { return xf::launch_zero(3 * lc.g.cells, Pbar, s); }));
     for (int d = 0; d < 3; ++d) {
@@ -610,7 +612,7 @@ int xf_rhs_alpha(xf_ctx *c, const double *U, const double *alpha_in, double *alp
 int xf_primitives(xf_ctx *c, const double *U, double *prim, void *stream) {
     if (!c || !U || !prim || !aligned8(U) || !aligned8(prim)) return XF_EINVAL;
     const hipStream_t s = (hipStream_t)stream;
-    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, prim, nullptr, nullptr, 1, nullptr, s); }));
+    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, prim, nullptr, nullptr, 1, nullptr, nullptr, s); }));
     return XF_OK;
 }
 
@@ -620,7 +622,7 @@ int xf_cfl_dt(xf_ctx *c, const double *U, double cfl, double *dt_dev, void *ws, 
     const hipStream_t s = (hipStream_t)stream;
     double *P = at<double>(ws, l.P);
     unsigned long long *mx = at<unsigned long long>(ws, l.mx);
-    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, P, nullptr, nullptr, 0, nullptr, s); }));
+    XF_TRY(timed(c, XF_K_PRIMS, s, [&] { return c->ops->prims(c->lc, U, P, nullptr, nullptr, 0, nullptr, nullptr, s); }));
     XF_TRY(timed(c, XF_K_CFL, s, [&] {
         hipError_t e = xf::launch_cfl_reset(mx, s);
         if (e == hipSuccess) e = c->ops->cfl(c->lc, U, P, mx, s);
@@ -712,22 +714,20 @@ int flow_rk3_step(xf_ctx *c, double *U, double dt, const double *dt_in, double c
     double *out[3] = {S1, S2, U};
     const double a[3] = {0.0, 0.75, 1.0 / 3.0};
     const double b[3] = {1.0, 0.25, 2.0 / 3.0};
-    // a mixed step without viscous terms or GLF reads the FP64 primitives
-    // only for its step size (stage 1); later stages need the FP32 copies
-    const bool p64_later = !mixed || c->viscous || lc.visc == XF_VISC_GLF;
+    // a mixed step without viscous terms or GLF needs only the FP32 copies
+    // (the CFL maximum comes from the primitive pass itself)
+    const bool p64 = !mixed || c->viscous || lc.visc == XF_VISC_GLF;
     // the primitive pass fills the ghosts of the stage input itself: the
     // face ghosts, and with viscous terms (whose tangential derivatives read
     // them) the edge and corner ghosts too; the state's ghosts are filled in
     // full at the end of the step
+    // the CFL maximum of U^n (Eq. 17) is taken by the first primitive pass
     for (int k = 0; k < 3; ++k) {
-        XF_TRY(prims(c, in[k], pb, s, k == 0 || p64_later, in[k]));
-        if (k == 0 && cfl > 0.0) {
-            XF_TRY(timed(c, XF_K_CFL, s, [&] {
-                hipError_t e = xf::launch_cfl_reset(mx, s);
-                if (e == hipSuccess) e = c->ops->cfl(lc, U, P, mx, s);
-                if (e == hipSuccess) e = xf::launch_cfl_finish(mx, cfl, dt_out, s);
-                return e;
-            }));
+        const bool take_cfl = k == 0 && cfl > 0.0;
+        if (take_cfl) XF_TRY(timed(c, XF_K_CFL, s, [&] { return xf::launch_cfl_reset(mx, s); }));
+        XF_TRY(prims(c, in[k], pb, s, p64, in[k], take_cfl ? mx : nullptr));
+        if (take_cfl) {
+            XF_TRY(timed(c, XF_K_CFL, s, [&] { return xf::launch_cfl_finish(mx, cfl, dt_out, s); }));
             h = dt_out;
         }
         // the step size for the positivity blend.  In a mixed context without

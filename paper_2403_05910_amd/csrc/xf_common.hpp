@@ -138,8 +138,10 @@ struct NsOps {
     // the pass covers are filled on the way, each from its boundary source as
     // the ghost fill does (without all_cells: the face ghosts; the edge and
     // corner ghosts lie outside every stencil and are left)
+    // With cfl, the pass also folds the CFL rate of its interior cells
+    // (Eq. 17, as the cfl entry) into *cfl, which the caller has zeroed.
     hipError_t (*prims)(const LaunchCtx &, const double *U, double *P, float *Uf, float *Pf, int all_cells,
-                        double *Ug, hipStream_t);
+                        double *Ug, unsigned long long *cfl, hipStream_t);
     // one direction of the convective flux difference.  FP64 sweeps read U,
     // P and write rhs (accumulate: rhs +=, else rhs =); mixed-precision
     // sweeps read Uf, Pf and write the FP32 differences to rhs32 (no

@@ -136,62 +136,90 @@ __device__ __forceinline__ unsigned cell_prims(const Get &u, const ThermoK<doubl
 template <int NS>
 __global__ __launch_bounds__(256) void k_prims(const double *U, double *__restrict__ P, Geo g,
                                                ThermoK<double> th, unsigned *status, float *__restrict__ Uf,
-                                               float *__restrict__ Pf, int all_cells, double *Ug) {
+                                               float *__restrict__ Pf, int all_cells, double *Ug,
+                                               unsigned long long *cfl) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= g.cells) return;
-    const int x = (int)(idx % g.px);
-    const long long r = idx / g.px;
-    const int y = (int)(r % g.py);
-    const int z = (int)(r / g.py);
-    const int ng = (x < g.gx || x >= g.gx + g.nx) + (y < g.gy || y >= g.gy + g.ny) +
-                   (z < g.gz || z >= g.gz + g.nz);
-    if (ng > 1 && !all_cells) return;   // edge and corner ghosts: outside every stencil
-    const long long C = g.cells;
-    // with Ug (= U): a ghost takes its boundary source's state, written to
-    // the ghost as the ghost fill would.  Each ghost coordinate maps to its
-    // source on its own axis (the axis-by-axis fill gives an edge or corner
-    // ghost the state of the interior cell all its coordinates map to);
-    // sources are interior cells, which this pass does not write.
-    long long src = idx;
-    if (Ug && ng > 0) {
-        auto map = [](int c, int n, int gw, int lo, int hi) {
-            if (c < gw) return ghost_src(lo, 0, c, n, gw);
-            if (c >= gw + n) return ghost_src(hi, 1, c - gw - n, n, gw);
-            return c;
-        };
-        const int sx = map(x, g.nx, g.gx, g.bc[0], g.bc[1]), sy = map(y, g.ny, g.gy, g.bc[2], g.bc[3]),
-                  sz = map(z, g.nz, g.gz, g.bc[4], g.bc[5]);
-        src = sx + (long long)g.px * (sy + (long long)g.py * sz);
-    }
-    double u[NS + 4];
+    double sv = 0.0;   // with cfl: the cell's rate sum_d (|u_d| + c) / dx_d of Eq. 17 (interior cells)
+    if (idx < g.cells) {
+        const int x = (int)(idx % g.px);
+        const long long r = idx / g.px;
+        const int y = (int)(r % g.py);
+        const int z = (int)(r / g.py);
+        const int ng = (x < g.gx || x >= g.gx + g.nx) + (y < g.gy || y >= g.gy + g.ny) +
+                       (z < g.gz || z >= g.gz + g.nz);
+        // edge and corner ghosts lie outside every stencil
+        if (ng <= 1 || all_cells) {
+            const long long C = g.cells;
+            // with Ug (= U): a ghost takes its boundary source's state, written
+            // to the ghost as the ghost fill would.  Each ghost coordinate maps
+            // to its source on its own axis (the axis-by-axis fill gives an edge
+            // or corner ghost the state of the interior cell all its
+            // coordinates map to); sources are interior cells, which this pass
+            // does not write.
+            long long src = idx;
+            if (Ug && ng > 0) {
+                auto map = [](int c, int n, int gw, int lo, int hi) {
+                    if (c < gw) return ghost_src(lo, 0, c, n, gw);
+                    if (c >= gw + n) return ghost_src(hi, 1, c - gw - n, n, gw);
+                    return c;
+                };
+                const int sx = map(x, g.nx, g.gx, g.bc[0], g.bc[1]), sy = map(y, g.ny, g.gy, g.bc[2], g.bc[3]),
+                          sz = map(z, g.nz, g.gz, g.bc[4], g.bc[5]);
+                src = sx + (long long)g.px * (sy + (long long)g.py * sz);
+            }
+            double u[NS + 4];
 #pragma unroll
-    for (int f = 0; f < NS + 4; ++f) u[f] = U[f * C + src];
-    if (src != idx) {
+            for (int f = 0; f < NS + 4; ++f) u[f] = U[f * C + src];
+            if (src != idx) {
 #pragma unroll
-        for (int f = 0; f < NS + 4; ++f) Ug[f * C + idx] = u[f];
-    }
-    // the FP32 copies go out before the Newton solve, from the loaded values
-    // (read again after it, the state was partly evicted from the L2 and
-    // fetched twice: 2.43 against 1.92 GB per launch at 256^3, nine species)
-    if (Uf) {
+                for (int f = 0; f < NS + 4; ++f) Ug[f * C + idx] = u[f];
+            }
+            // the FP32 copies go out before the Newton solve, from the loaded
+            // values (read again after it, the state was partly evicted from
+            // the L2 and fetched twice: 2.43 against 1.92 GB per launch at
+            // 256^3, nine species)
+            if (Uf) {
 #pragma unroll
-        for (int f = 0; f < NS + 4; ++f) Uf[f * C + idx] = (float)u[f];
+                for (int f = 0; f < NS + 4; ++f) Uf[f * C + idx] = (float)u[f];
+            }
+            double T, p, c, rinv;
+            const unsigned flags = cell_prims<NS>([&](int f) { return u[f]; }, th, T, p, c, rinv);
+            if (P) {
+                P[idx] = T;
+                P[C + idx] = p;
+                P[2 * C + idx] = c;
+                P[3 * C + idx] = rinv;
+            }
+            if (Uf) {
+                Pf[idx] = (float)T;
+                Pf[C + idx] = (float)p;
+                Pf[2 * C + idx] = (float)c;
+                Pf[3 * C + idx] = (float)rinv;
+            }
+            if (cfl && ng == 0) {   // the same sum, in the same order, as k_cfl
+                double v = 0.0;
+                if (g.nx > 1) v += (fabs(u[NS] * rinv) + c) * g.idx;
+                if (g.ny > 1) v += (fabs(u[NS + 1] * rinv) + c) * g.idy;
+                if (g.nz > 1) v += (fabs(u[NS + 2] * rinv) + c) * g.idz;
+                if (v > sv) sv = v;   // NaN never wins (it is flagged)
+            }
+            if (flags) atomicOr(status, flags);
+        }
     }
-    double T, p, c, rinv;
-    const unsigned flags = cell_prims<NS>([&](int f) { return u[f]; }, th, T, p, c, rinv);
-    if (P) {
-        P[idx] = T;
-        P[C + idx] = p;
-        P[2 * C + idx] = c;
-        P[3 * C + idx] = rinv;
+    if (cfl) {
+        // block max, then one 64-bit atomicMax (positive doubles order like
+        // their bit patterns), skipped when the running max is already larger
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) sv = fmax(sv, __shfl_xor(sv, off, 64));
+        __shared__ double wmax[4];
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = sv;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(m);
+            if (bits > __atomic_load_n(cfl, __ATOMIC_RELAXED)) atomicMax(cfl, bits);
+        }
     }
-    if (Uf) {
-        Pf[idx] = (float)T;
-        Pf[C + idx] = (float)p;
-        Pf[2 * C + idx] = (float)c;
-        Pf[3 * C + idx] = (float)rinv;
-    }
-    if (flags) atomicOr(status, flags);
 }
 
 // SSP-RK3 stage of Eq. 16 on the interior cells: Uout = a U0 + b (Uin + h L),

@@ -17,10 +17,10 @@ constexpr int NS = XF_NS;
 unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 hipError_t prims(const LaunchCtx &c, const double *U, double *P, float *Uf, float *Pf, int all_cells, double *Ug,
-                 hipStream_t s) {
+                 unsigned long long *cfl, hipStream_t s) {
     if (Ug && Ug != U) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_prims<NS>, dim3(blocks_for(c.g.cells, 256)), dim3(256), 0, s, U, P, c.g, c.th64,
-                       c.status, Uf, Pf, all_cells, Ug);
+                       c.status, Uf, Pf, all_cells, Ug, cfl);
     return hipGetLastError();
 }
 
