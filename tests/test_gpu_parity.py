@@ -190,6 +190,31 @@ def test_rk3_steps_match_oracle(name, steps):
     assert err.max() <= 1e-12, err
 
 
+@pytest.mark.parametrize("name,precision", [("inert_sbi_32", "fp64"), ("n9_3d_mixed_bc", "fp64"),
+                                            ("thin_x3_n9", "fp64"), ("n9_3d_mixed_bc", "mixed")])
+def test_rk3_step_with_device_cfl_matches_oracle(name, precision):
+    """xf_rk3_step_cfl: the step takes the CFL maximum of U^n (Eq. 17) in its
+    first primitive pass; dt against the oracle's CFL dt, the state against
+    the oracle's step with that dt (FP64: 1e-12 of the field scale; mixed:
+    the FP32 bound of the mixed RK3 tests)"""
+    xf = _xf()
+    case = CASES[name]
+    th, g = oracle_objects(case)
+    Uo = O.fill_ghosts(g, case.U)
+    dt = O.cfl_dt(th, g, Uo, 0.45)
+    Uo = O.rk3_step(th, g, Uo, dt)
+    ctx = xf.Context.from_case(case, precision)
+    U = ctx.state_from_numpy(case.U)
+    dt_dev = ctx.rk3_step_cfl(U, 0.45)
+    rel = abs(float(dt_dev.item()) / dt - 1.0)
+    assert ctx.status() == 0
+    scale = np.abs(Uo).reshape(Uo.shape[0], -1).max(axis=1)
+    err = field_err(U.cpu().numpy(), Uo, scale)
+    print(f"[parity] rk3 cfl {name} {precision}: dt rel err {rel:.2e}, state max err {err.max():.3e}", flush=True)
+    assert rel <= 1e-14
+    assert err.max() <= (1e-12 if precision == "fp64" else MIXED_STATE_TOL), err
+
+
 def test_status_flags_match_oracle():
     xf = _xf()
     tab = W.sampled_table([2.0, 28.0, 40.0], 1)
